@@ -1,0 +1,338 @@
+// Oracle (test infrastructure only): plain, slow FP64 CPU implementation of
+// the CNOP hot path, exported as a C ABI on host pointers for the tests.
+// Nothing in the product path may link or call this library; it shares no
+// code with the GPU implementation.
+//
+// Calls (all arrays host, contiguous, members stacked; return 0 or < 0):
+//   rto_init_state     background + velocity perturbation -> U (Sec. 2.2, 3.1)
+//   rto_cfl_dt         CFL time step of each member (unclipped)
+//   rto_step           one step with a given dt per member (Sec. 2.1, 2.3)
+//   rto_integrate      adaptive-dt march to exactly T, optional dt log
+//   rto_kinetic_energy volume integral of Eq. 7
+//   rto_step_jvp       exact tangent of one step (forward-mode AD)
+//   rto_step_vjp       exact adjoint of one step (reverse-mode AD)
+//   rto_grad_u0        R = KE(T)/KE(0) and its exact gradient with respect to
+//                      the initial velocity field, by reverse-mode AD through
+//                      the whole discrete march with the time steps of the
+//                      forward run held fixed (Sec. 3.4)
+//   rto_project_to_constraint  scaling onto the constraint set (Eq. 11)
+//   rto_hllc, rto_wall_pressure  single-face fluxes for unit tests
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+#include "rto_ad.hpp"
+#include "rto_scheme.hpp"
+
+namespace rto {
+Tape& tape() {
+  static Tape t;
+  return t;
+}
+}  // namespace rto
+
+using rto::Dual;
+using rto::Problem;
+using rto::Rev;
+
+namespace {
+constexpr int kEInval = -1;
+constexpr int kENomem = -3;
+constexpr int kEUnphys = -4;
+
+bool valid(const Problem* P) {
+  return P && P->nx >= 3 && P->ny >= 2 && P->nb >= 1 && P->lx > 0 && P->ly > 0 && P->gamma > 1.0 &&
+         P->h > 0 && P->cfl > 0;
+}
+size_t cells(const Problem* P) { return static_cast<size_t>(P->nx) * P->ny; }
+
+// Reverse-mode adjoint of one step of one member: lam = (dUn/dU)^T lam_next.
+int vjp_member(const Problem& P, const double* U, double dt, const double* lam_next, double* lam) {
+  const size_t n4 = 4 * static_cast<size_t>(P.nx) * P.ny;
+  rto::Tape& tp = rto::tape();
+  tp.clear();
+  std::vector<Rev> x(n4), y(n4);
+  for (size_t k = 0; k < n4; ++k) x[k] = Rev::leaf(U[k]);
+  const int bad = rto::step_member<Rev>(P, x.data(), y.data(), dt);
+  tp.adj.assign(tp.nodes.size(), 0.0);
+  for (size_t k = 0; k < n4; ++k)
+    if (y[k].i >= 0) tp.adj[y[k].i] += lam_next[k];
+  tp.sweep();
+  for (size_t k = 0; k < n4; ++k) lam[k] = tp.adj[x[k].i];
+  tp.clear();
+  return bad;
+}
+
+// March one member to exactly T with the CFL step, the last step clipped.
+// Optionally records every state (states != nullptr, appended) and every dt.
+int integrate_member(const Problem& P, double* U, double T, double* t_out, int32_t* n_out,
+                     std::vector<double>* dts, std::vector<std::vector<double>>* states) {
+  const size_t n4 = 4 * cells(&P);
+  std::vector<double> Un(n4);
+  double t = 0.0;
+  int32_t n = 0;
+  bool last = false;
+  int bad = 0;
+  while (!last) {
+    double dt = P.cfl / rto::max_signal_speed(P, U);
+    const double rem = T - t;
+    if (dt >= rem) {
+      dt = rem;
+      last = true;
+    }
+    if (states) states->emplace_back(U, U + n4);
+    bad |= rto::step_member<double>(P, U, Un.data(), dt);
+    std::memcpy(U, Un.data(), n4 * sizeof(double));
+    t = last ? T : t + dt;
+    if (dts) dts->push_back(dt);
+    ++n;
+    if (bad) break;
+  }
+  if (t_out) *t_out = t;
+  if (n_out) *n_out = n;
+  return bad ? kEUnphys : 0;
+}
+}  // namespace
+
+extern "C" {
+
+int rto_init_state(const Problem* P, const double* uv0, double* U) {
+  if (!valid(P) || !uv0 || !U) return kEInval;
+  const size_t N = cells(P);
+  for (int b = 0; b < P->nb; ++b) rto::init_member<double>(*P, uv0 + 2 * N * b, U + 4 * N * b);
+  return 0;
+}
+
+int rto_cfl_dt(const Problem* P, const double* U, double* dt) {
+  if (!valid(P) || !U || !dt) return kEInval;
+  const size_t N = cells(P);
+  for (int b = 0; b < P->nb; ++b) dt[b] = P->cfl / rto::max_signal_speed(*P, U + 4 * N * b);
+  return 0;
+}
+
+int rto_step(const Problem* P, const double* U, double* Un, const double* dt) {
+  if (!valid(P) || !U || !Un || !dt || U == Un) return kEInval;
+  const size_t N = cells(P);
+  int bad = 0;
+  for (int b = 0; b < P->nb; ++b) bad |= rto::step_member<double>(*P, U + 4 * N * b, Un + 4 * N * b, dt[b]);
+  return bad ? kEUnphys : 0;
+}
+
+int rto_integrate(const Problem* P, double* U, double T, double* t_out, int32_t* nsteps, double* dt_log,
+                  int32_t cap) {
+  if (!valid(P) || !U || !(T > 0)) return kEInval;
+  const size_t N = cells(P);
+  int rc = 0;
+  for (int b = 0; b < P->nb; ++b) {
+    std::vector<double> dts;
+    int32_t n = 0;
+    const int r = integrate_member(*P, U + 4 * N * b, T, t_out ? t_out + b : nullptr, &n, &dts, nullptr);
+    if (nsteps) nsteps[b] = n;
+    if (dt_log) {
+      if (n > cap) return kENomem;
+      for (int32_t k = 0; k < n; ++k) dt_log[static_cast<size_t>(b) * cap + k] = dts[k];
+    }
+    if (r) rc = r;
+  }
+  return rc;
+}
+
+int rto_kinetic_energy(const Problem* P, const double* U, double* ke) {
+  if (!valid(P) || !U || !ke) return kEInval;
+  const size_t N = cells(P);
+  for (int b = 0; b < P->nb; ++b) ke[b] = rto::kinetic_energy<double>(*P, U + 4 * N * b);
+  return 0;
+}
+
+int rto_step_jvp(const Problem* P, const double* U, const double* dU, const double* dt, double* Un, double* dUn) {
+  if (!valid(P) || !U || !dU || !dt || !Un || !dUn) return kEInval;
+  const size_t n4 = 4 * cells(P);
+  std::vector<Dual> x(n4), y(n4);
+  int bad = 0;
+  for (int b = 0; b < P->nb; ++b) {
+    const size_t o = n4 * b;
+    for (size_t k = 0; k < n4; ++k) x[k] = Dual(U[o + k], dU[o + k]);
+    bad |= rto::step_member<Dual>(*P, x.data(), y.data(), dt[b]);
+    for (size_t k = 0; k < n4; ++k) {
+      Un[o + k] = y[k].v;
+      dUn[o + k] = y[k].d;
+    }
+  }
+  return bad ? kEUnphys : 0;
+}
+
+int rto_step_vjp(const Problem* P, const double* U, const double* dt, const double* lam_next, double* lam) {
+  if (!valid(P) || !U || !dt || !lam_next || !lam) return kEInval;
+  const size_t n4 = 4 * cells(P);
+  int bad = 0;
+  for (int b = 0; b < P->nb; ++b) bad |= vjp_member(*P, U + n4 * b, dt[b], lam_next + n4 * b, lam + n4 * b);
+  return bad ? kEUnphys : 0;
+}
+
+// R = KE(U^N)/KE(U^0) of each member and dR/d(u0, v0) (layout [2][ny][nx],
+// Euclidean gradient with respect to the array entries).  The time steps are
+// those of the forward run, held fixed while differentiating.  Every state
+// of the march is stored (the oracle does not checkpoint).  dt_log, if given,
+// receives each member's steps ([nb][cap]).
+int rto_grad_u0(const Problem* P, const double* uv0, double T, double* R, double* grad, int32_t* nsteps,
+                double* dt_log, int32_t cap) {
+  if (!valid(P) || !uv0 || !R || !grad || !(T > 0)) return kEInval;
+  const size_t N = cells(P), n4 = 4 * N;
+  rto::Tape& tp = rto::tape();
+  for (int b = 0; b < P->nb; ++b) {
+    const double* uv = uv0 + 2 * N * b;
+    std::vector<double> U(n4);
+    rto::init_member<double>(*P, uv, U.data());
+    const double ke0 = rto::kinetic_energy<double>(*P, U.data());
+    if (!(ke0 > 0.0)) return kEInval;
+    std::vector<double> dts;
+    std::vector<std::vector<double>> states;
+    int32_t n = 0;
+    const int rc = integrate_member(*P, U.data(), T, nullptr, &n, &dts, &states);
+    if (rc) return rc;
+    if (nsteps) nsteps[b] = n;
+    if (dt_log) {
+      if (n > cap) return kENomem;
+      for (int32_t k = 0; k < n; ++k) dt_log[static_cast<size_t>(b) * cap + k] = dts[k];
+    }
+    const double keN = rto::kinetic_energy<double>(*P, U.data());
+    R[b] = keN / ke0;
+
+    // Terminal adjoint: d(KE(U^N)/KE0)/dU^N with KE0 held fixed.
+    std::vector<double> lam(n4), lam_prev(n4);
+    {
+      tp.clear();
+      std::vector<Rev> x(n4);
+      for (size_t k = 0; k < n4; ++k) x[k] = Rev::leaf(U[k]);
+      const Rev r = rto::kinetic_energy<Rev>(*P, x.data()) / ke0;
+      tp.adj.assign(tp.nodes.size(), 0.0);
+      tp.adj[r.i] = 1.0;
+      tp.sweep();
+      for (size_t k = 0; k < n4; ++k) lam[k] = tp.adj[x[k].i];
+      tp.clear();
+    }
+    // Reverse sweep through the stored states.
+    for (int32_t s = n - 1; s >= 0; --s) {
+      if (vjp_member(*P, states[s].data(), dts[s], lam.data(), lam_prev.data())) return kEUnphys;
+      lam.swap(lam_prev);
+    }
+    // Initial adjoint: through U^0(uv0) and through KE0(uv0) in R = KE_N/KE0.
+    {
+      tp.clear();
+      std::vector<Rev> q(2 * N), U0(n4);
+      for (size_t k = 0; k < 2 * N; ++k) q[k] = Rev::leaf(uv[k]);
+      rto::init_member<Rev>(*P, q.data(), U0.data());
+      Rev f = keN / rto::kinetic_energy<Rev>(*P, U0.data());
+      for (size_t k = 0; k < n4; ++k) f = f + lam[k] * U0[k];
+      tp.adj.assign(tp.nodes.size(), 0.0);
+      tp.adj[f.i] = 1.0;
+      tp.sweep();
+      for (size_t k = 0; k < 2 * N; ++k) grad[2 * N * b + k] = tp.adj[q[k].i];
+      tp.clear();
+    }
+  }
+  return 0;
+}
+
+// KE ratio of a march that uses a given dt sequence (the frozen schedule of
+// a previous run) instead of the CFL step: the map that rto_grad_u0
+// differentiates.  dt_log is [nb][cap]; nsteps[b] steps are taken.
+int rto_ke_ratio_frozen(const Problem* P, const double* uv0, const double* dt_log, const int32_t* nsteps,
+                        int32_t cap, double* R) {
+  if (!valid(P) || !uv0 || !dt_log || !nsteps || !R) return kEInval;
+  const size_t N = cells(P), n4 = 4 * N;
+  std::vector<double> U(n4), Un(n4);
+  for (int b = 0; b < P->nb; ++b) {
+    Problem Q = *P;
+    Q.nb = 1;
+    rto::init_member<double>(Q, uv0 + 2 * N * b, U.data());
+    const double ke0 = rto::kinetic_energy<double>(Q, U.data());
+    for (int32_t s = 0; s < nsteps[b]; ++s) {
+      if (rto::step_member<double>(Q, U.data(), Un.data(), dt_log[static_cast<size_t>(b) * cap + s]))
+        return kEUnphys;
+      U.swap(Un);
+    }
+    R[b] = rto::kinetic_energy<double>(Q, U.data()) / ke0;
+  }
+  return 0;
+}
+
+// Scale each member's perturbation onto the constraint set (Eq. 11).
+//   norm 0: (sum (u^2+v^2) dx dy)^(1/2)       (velocity L2 norm)
+//   norm 1: (mean over cells of u^2+v^2)^(1/2) (RMS)
+//   norm 2: C = sum rho0 (u^2+v^2)/2 dx dy     (Eq. 9); delta plays epsilon
+//   set 0: sphere (always scaled to the bound); set 1: ball (scaled only
+//   when outside, Eq. 11).  Components switched off by comp_mask are zeroed.
+// norm_out[b] receives the norm (or C) before scaling.
+int rto_project_to_constraint(const Problem* P, double* uv, double delta, int32_t norm, int32_t set,
+                              double* norm_out) {
+  if (!valid(P) || !uv || !(delta > 0) || norm < 0 || norm > 2 || set < 0 || set > 1) return kEInval;
+  const int nx = P->nx, ny = P->ny;
+  const size_t N = cells(P);
+  const double dV = rto::dx_of(*P) * rto::dy_of(*P);
+  for (int b = 0; b < P->nb; ++b) {
+    double* u = uv + 2 * N * b;
+    double* v = u + N;
+    if (!(P->comp_mask & 1))
+      for (size_t c = 0; c < N; ++c) u[c] = 0.0;
+    if (!(P->comp_mask & 2))
+      for (size_t c = 0; c < N; ++c) v[c] = 0.0;
+    double s = 0.0;
+    for (int j = 0; j < ny; ++j) {
+      const double w = norm == 2 ? 0.5 * rto::rho0_at(*P, rto::yc(*P, j)) : 1.0;
+      for (int i = 0; i < nx; ++i) {
+        const size_t c = static_cast<size_t>(j) * nx + i;
+        s += w * (u[c] * u[c] + v[c] * v[c]);
+      }
+    }
+    double m, scale;
+    if (norm == 0) {
+      m = std::sqrt(s * dV);
+      scale = delta / m;
+    } else if (norm == 1) {
+      m = std::sqrt(s / static_cast<double>(N));
+      scale = delta / m;
+    } else {
+      m = s * dV;
+      scale = std::sqrt(delta / m);
+    }
+    if (norm_out) norm_out[b] = m;
+    if (set == 1 && m <= delta) continue;
+    if (!(m > 0.0)) return kEInval;
+    for (size_t c = 0; c < 2 * N; ++c) u[c] *= scale;
+  }
+  return 0;
+}
+
+// Single-face HLLC flux in face-normal order (mass, normal momentum,
+// tangential momentum, energy); states are (rho, normal vel., tangential
+// vel., p).
+int rto_hllc(double gamma, const double* L, const double* Rr, double* flux) {
+  Problem P{};
+  P.gamma = gamma;
+  const std::array<double, 4> f =
+      rto::hllc<double>(P, rto::FaceState<double>{L[0], L[1], L[2], L[3]},
+                        rto::FaceState<double>{Rr[0], Rr[1], Rr[2], Rr[3]});
+  for (int k = 0; k < 4; ++k) flux[k] = f[k];
+  return 0;
+}
+
+double rto_wall_pressure(double gamma, const double* w, int32_t interior_left) {
+  Problem P{};
+  P.gamma = gamma;
+  return rto::wall_pressure<double>(P, rto::FaceState<double>{w[0], w[1], w[2], w[3]}, interior_left != 0);
+}
+
+// Background profiles at the cell centres of row j (Eq. 5 and the
+// hydrostatic integral), for tests.
+int rto_background(const Problem* P, double* rho0, double* p0) {
+  if (!valid(P) || !rho0 || !p0) return kEInval;
+  for (int j = 0; j < P->ny; ++j) {
+    rho0[j] = rto::rho0_at(*P, rto::yc(*P, j));
+    p0[j] = rto::p0_at(*P, rto::yc(*P, j));
+  }
+  return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,179 @@
+/*
+ * rtcnop.h - C ABI of the MI355X (gfx950) hot path of the CNOP search for
+ * the most dangerous initial velocity perturbation in 2-D compressible
+ * Rayleigh-Taylor instability (Ji & Shi, "The Most Dangerous Seed").
+ *
+ * What the library computes
+ *   - The forward map F_t of Sec. 3.1: the 2-D compressible Euler equations
+ *     with uniform gravity (Sec. 2.1, Eqs. 1-4) on a uniform grid, by a
+ *     finite-volume Godunov-type scheme with an HLLC Riemann solver and a
+ *     gravity source (Sec. 2.3).  The paper leaves reconstruction and time
+ *     integrator open; this is unsplit MUSCL-Hancock with monotonized-central
+ *     limited slopes of (rho, u, v, p), plain HLLC with Davis wave speeds,
+ *     and a gravity source that conserves total energy including the
+ *     potential energy.  x is periodic; the y boundaries are reflecting walls
+ *     whose ghost pressure is extrapolated hydrostatically (dp/dy = rho g,
+ *     Sec. 2.1), with the wall flux equal to the wall pressure of the
+ *     mirrored Riemann problem.  dt = CFL / max over cells of
+ *     max((|u|+c)/dx, (|v|+c)/dy), the last step clipped to end at T.
+ *   - The initial state: the two-layer tanh atmosphere of Eq. 5 in
+ *     hydrostatic balance (Sec. 2.2), plus a velocity perturbation (u0, v0).
+ *   - The kinetic energy KE = sum (m_x^2 + m_y^2)/(2 rho) dx dy (Eq. 7
+ *     integrated) and the growth ratio R = KE(U(T)) / KE(U(0)).
+ *   - The exact gradient of R with respect to the initial velocity field by a
+ *     hand-written discrete adjoint of the step (the paper uses reverse-mode
+ *     AD of the discrete march, Sec. 2.3 and 3.4), with the time steps of the
+ *     forward run held fixed, and checkpointing to bound memory (Sec. 3.4).
+ *   - The constraint projection of Eq. 11 (sphere or ball, in the velocity L2
+ *     norm, the RMS norm or the energy norm C of Eq. 9).
+ *
+ * Conventions
+ *   - Arrays are FP64, contiguous, in DEVICE memory owned by the caller
+ *     (unless stated), 8-byte aligned at least; 256-byte alignment is best.
+ *     State U is [B][4][ny][nx] with variables (rho, m_x, m_y, E), x fastest.
+ *     Velocity fields (perturbation, gradient) are [B][2][ny][nx], (u, v).
+ *   - The library never allocates device memory: all scratch lives in the
+ *     workspace the caller hands to rt_set_workspace, and the checkpoint pool
+ *     is handed in with each gradient call.
+ *   - Calls are asynchronous on the context's stream (a hipStream_t passed
+ *     as void*; NULL = the default stream) unless stated.  rt_integrate and
+ *     rt_grad_u0 synchronise that stream (they read device step counters).
+ *   - A context is not thread-safe; distinct contexts are independent.
+ *   - Return value: 0 on success or a negative rt_status; rt_last_error()
+ *     gives a message for the calling thread's last failure.
+ */
+#ifndef RTCNOP_H
+#define RTCNOP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum rt_status {
+  RT_OK = 0,
+  RT_EINVAL = -1,   /* bad shape, null pointer, T <= 0, zero KE(0), ...     */
+  RT_EHIP = -2,     /* a HIP runtime call failed                             */
+  RT_ENOMEM = -3,   /* workspace, step-log or checkpoint pool too small      */
+  RT_EUNPHYS = -4,  /* rho <= 0, p <= 0 or a non-finite value was produced   */
+  RT_ESTATE = -5    /* call order violated (e.g. no workspace set)           */
+} rt_status;
+
+/* Grid: nx x ny cells on [0, lx] x [0, ly]; batch independent members. */
+typedef struct rt_grid {
+  int32_t nx, ny, batch, reserved;
+  double lx, ly;
+} rt_grid;
+
+/* Physics.  g_y < 0 points down.  The background is
+ * rho0(y) = (rho_h + rho_l)/2 + (rho_h - rho_l)/2 tanh((y - y0)/h) (Eq. 5)
+ * with p0 from dp0/dy = rho0 g_y and p0(y0) = p_int.  comp_mask: bit 0 = u
+ * is perturbed, bit 1 = v (the paper perturbs v only, Sec. 3.1). */
+typedef struct rt_phys {
+  double gamma, g_y, rho_h, rho_l, y0, h, p_int, cfl;
+  int32_t comp_mask, reserved;
+} rt_phys;
+
+typedef struct rt_ctx rt_ctx;
+
+/* Checkpoint policy of rt_grad_u0 (Sec. 3.4: checkpoints re-computed from a
+ * sparse set of saved states).  kind: 0 store every state, 1 a snapshot every
+ * `interval` steps with re-computation inside each interval, 2 binomial
+ * (revolve) schedule using as many snapshots as `pool_bytes` holds.  The pool
+ * is caller-owned device memory. */
+typedef struct rt_ckpt_policy {
+  int32_t kind, interval;
+  void* pool;
+  size_t pool_bytes;
+} rt_ckpt_policy;
+
+enum { RT_CKPT_STORE_ALL = 0, RT_CKPT_UNIFORM = 1, RT_CKPT_REVOLVE = 2 };
+enum { RT_NORM_L2 = 0, RT_NORM_RMS = 1, RT_NORM_RHO_KE = 2 };
+enum { RT_SET_SPHERE = 0, RT_SET_BALL = 1 };
+
+/* Create a context for one grid / physics / stream.  Validates the numbers
+ * (nx >= 3, ny >= 2, batch >= 1, positive lengths, gamma > 1, h > 0,
+ * cfl > 0).  No device work. */
+int rt_create(const rt_grid* grid, const rt_phys* phys, void* stream, rt_ctx** out);
+int rt_destroy(rt_ctx* ctx);
+int rt_set_stream(rt_ctx* ctx, void* stream);
+
+/* Bytes of device workspace needed for marches of up to max_steps steps per
+ * member (the step log of the gradient needs one double per step). */
+int rt_workspace_bytes(const rt_ctx* ctx, int32_t max_steps, size_t* bytes);
+/* Hand the context its workspace (device, >= rt_workspace_bytes, 256-byte
+ * aligned).  The context uses it until the next rt_set_workspace or
+ * rt_destroy; the caller frees it afterwards. */
+int rt_set_workspace(rt_ctx* ctx, void* dev, size_t bytes, int32_t max_steps);
+
+/* Initial state (Sec. 2.2 and 3.1): U = background + velocity perturbation
+ * uv0 ([B][2][ny][nx]) at cell centres; masked components are taken as 0. */
+int rt_init_state(rt_ctx* ctx, const double* uv0, double* U);
+
+/* CFL time step of each member's state (unclipped): dt[B] on the device. */
+int rt_cfl_dt(rt_ctx* ctx, const double* U, double* dt);
+
+/* One step U_out = Phi_dt(U_in) with the per-member step dt[B] (device).
+ * U_in and U_out must not overlap.  If dt_next is not NULL it receives the
+ * unclipped CFL step of U_out.  Unphysical states are reported on the next
+ * rt_check_error or synchronising call. */
+int rt_step(rt_ctx* ctx, const double* U_in, double* U_out, const double* dt, double* dt_next);
+
+/* March every member from its state U (in/out) to exactly time T with its
+ * own CFL step, all members advancing in one batched launch per step.
+ * t_out[B], nsteps[B] (int32) receive the end time and step count; dt_log,
+ * if not NULL, receives each member's steps, [B][dt_log_cap] (device).
+ * Synchronises the stream.  RT_EUNPHYS if any member became unphysical,
+ * RT_ENOMEM if a member needs more steps than the workspace allows. */
+int rt_integrate(rt_ctx* ctx, double* U, double T, double* t_out, int32_t* nsteps, double* dt_log,
+                 int32_t dt_log_cap);
+
+/* Kinetic energy of each member, ke[B] (device). */
+int rt_kinetic_energy(rt_ctx* ctx, const double* U, double* ke);
+
+/* Adjoint of one step: lam = (d Phi_dt / dU)(U)^T lam_next with dt[B]
+ * (device) held fixed.  Arrays are states [B][4][ny][nx]; lam must not
+ * overlap lam_next. */
+int rt_step_adjoint(rt_ctx* ctx, const double* U, const double* dt, const double* lam_next, double* lam);
+
+/* R[B] = KE(U(T))/KE(U(0)) for the initial perturbation uv0, and its
+ * gradient dR/d(u0, v0) ([B][2][ny][nx], Euclidean, with respect to the
+ * array entries) by the discrete adjoint with the forward run's time steps
+ * held fixed.  nsteps[B] (device, may be NULL) receives the step counts.
+ * Synchronises the stream.  RT_ENOMEM if the pool cannot hold the policy's
+ * snapshots; RT_EINVAL if KE(0) = 0. */
+int rt_grad_u0(rt_ctx* ctx, const double* uv0, double T, const rt_ckpt_policy* policy, double* R,
+               double* grad, int32_t* nsteps);
+
+/* Bytes of checkpoint pool that `kind`/`interval` needs for marches of
+ * nsteps_max steps (RT_CKPT_REVOLVE: the minimum, two snapshots). */
+int rt_pool_bytes(const rt_ctx* ctx, int32_t kind, int32_t interval, int32_t nsteps_max, size_t* bytes);
+
+/* Eq. 11: scale each member of uv ([B][2][ny][nx], in place) onto the
+ * constraint set of radius delta in norm `norm`; set = sphere (always) or
+ * ball (only when outside).  For RT_NORM_RHO_KE the bound is the energy
+ * epsilon of Eq. 9 and the scale is (epsilon / C)^(1/2).  Masked components
+ * are zeroed.  norm_out[B] (device, may be NULL) receives the norm (or C)
+ * before scaling. */
+int rt_project_to_constraint(rt_ctx* ctx, double* uv, double delta, int32_t norm, int32_t set,
+                             double* norm_out);
+
+/* Per-member inner products of velocity fields: out[B] = sum_cells a . b
+ * (device).  Used by the spectral projected-gradient step. */
+int rt_dot(rt_ctx* ctx, const double* a, const double* b, double* out);
+
+/* out = x + alpha[b] * y per member (alpha device [B]); out may alias x. */
+int rt_axpy(rt_ctx* ctx, const double* x, const double* alpha, const double* y, double* out);
+
+/* Synchronise the stream and report a device-side error flag (RT_EUNPHYS)
+ * raised by earlier asynchronous calls; clears the flag. */
+int rt_check_error(rt_ctx* ctx);
+
+const char* rt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RTCNOP_H */

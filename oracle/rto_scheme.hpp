@@ -16,7 +16,8 @@
 //     gravity source (Sec. 2.3).  The paper names neither the reconstruction
 //     nor the time integrator; this is the unsplit primitive-variable
 //     MUSCL-Hancock scheme with piecewise-linear, monotonized-central (MC)
-//     limited slopes, and the plain HLLC flux with Davis wave-speed bounds
+//     limited slopes (differences below 1e-10 of the local scale count as
+//     zero), and the plain HLLC flux with Davis wave-speed bounds
 //     (the "hybrid" qualifier in Sec. 2.3 is not explained there, so no HLL
 //     switch is applied).
 //   * Gravity source, second order in time and chosen so that total energy
@@ -93,24 +94,44 @@ bool bad_state(const Prim<T>& w) {
   return !(r > 0.0) || !(p > 0.0) || !std::isfinite(val(w.u)) || !std::isfinite(val(w.v));
 }
 
+// Relative tolerance below which a difference counts as zero when the scheme
+// takes a discrete decision (limiter case, upwind side, wave-speed choice).
+// Decisions on differences at the level of round-off would otherwise be
+// taken at random and make the discrete derivative of the march erratic:
+// the linearisation of the compressive limiter branches amplifies grid-scale
+// perturbations, so two correct implementations that differ by one ulp in a
+// quiescent region would produce different gradients.  The forward state
+// changes by at most this tolerance, relative.
+constexpr double kTieTol = 1e-10;
+
 // Monotonized-central limited slope of one variable from its backward and
-// forward differences a, b: zero at an extremum (a*b <= 0), else the central
-// difference (a+b)/2 when it does not exceed 2|a| and 2|b|, else 2a if
-// |a| <= |b|, else 2b.
-template <class T>
-T mc_slope(const T& a, const T& b) {
-  if (val(a) * val(b) <= 0.0) return T(0.0);
+// forward differences a, b: zero at an extremum (a*b <= 0) or when either
+// difference is negligible (`small(a)`), else the central difference (a+b)/2
+// when it does not exceed 2|a| and 2|b|, else 2a if |a| <= |b|, else 2b.
+template <class T, class Small>
+T mc_slope(const T& a, const T& b, Small small) {
+  const double va = val(a), vb = val(b);
+  if (va * vb <= 0.0 || small(va) || small(vb)) return T(0.0);
   const T c = 0.5 * (a + b);
-  const double ac = std::fabs(val(c)), aa = std::fabs(val(a)), ab = std::fabs(val(b));
+  const double ac = std::fabs(val(c)), aa = std::fabs(va), ab = std::fabs(vb);
   if (ac <= 2.0 * aa && ac <= 2.0 * ab) return c;
   if (aa <= ab) return 2.0 * a;
   return 2.0 * b;
 }
 
+// Slopes of the four primitives.  A difference is negligible below kTieTol
+// times the cell's own density (density slope), pressure (pressure slope)
+// or sound speed c = sqrt(gamma p / rho) (velocity slopes; compared as
+// d^2 rho <= kTieTol^2 gamma p).
 template <class T>
-Prim<T> mc_slope(const Prim<T>& wm, const Prim<T>& w, const Prim<T>& wp) {
-  return Prim<T>{mc_slope(w.r - wm.r, wp.r - w.r), mc_slope(w.u - wm.u, wp.u - w.u),
-                 mc_slope(w.v - wm.v, wp.v - w.v), mc_slope(w.p - wm.p, wp.p - w.p)};
+Prim<T> mc_slope(const Problem& P, const Prim<T>& wm, const Prim<T>& w, const Prim<T>& wp) {
+  const double r = val(w.r), p = val(w.p);
+  const double tr = kTieTol * r, tp = kTieTol * p, tv2 = kTieTol * kTieTol * P.gamma * p;
+  auto small_r = [tr](double d) { return std::fabs(d) <= tr; };
+  auto small_p = [tp](double d) { return std::fabs(d) <= tp; };
+  auto small_v = [tv2, r](double d) { return d * d * r <= tv2; };
+  return Prim<T>{mc_slope(w.r - wm.r, wp.r - w.r, small_r), mc_slope(w.u - wm.u, wp.u - w.u, small_v),
+                 mc_slope(w.v - wm.v, wp.v - w.v, small_v), mc_slope(w.p - wm.p, wp.p - w.p, small_p)};
 }
 
 // Face-normal Riemann data: n is the normal velocity, t the tangential one.
@@ -123,16 +144,18 @@ struct FaceState {
 // velocity n.  Returns (mass, normal momentum, tangential momentum, energy).
 // Davis estimates S_L = min(n_L - c_L, n_R - c_R), S_R = max(n_L + c_L,
 // n_R + c_R); contact speed S*; four cases S_L >= 0, S* >= 0, S_R > 0, else
-// (a tie at S* = 0 takes the left star state).
+// (a tie at S* = 0, within the tie tolerance, takes the left star state).
 template <class T>
 std::array<T, 4> hllc(const Problem& P, const FaceState<T>& L, const FaceState<T>& R) {
   const double gm = P.gamma;
   const T cL = sqrt(gm * L.p / L.r);
   const T cR = sqrt(gm * R.p / R.r);
+  // Near-ties (within kTieTol of the sound speeds) resolve to the left state.
+  const double tie = kTieTol * (val(cL) + val(cR));
   const T aL = L.n - cL, bL = R.n - cR;
-  const T SL = val(aL) <= val(bL) ? aL : bL;
+  const T SL = val(aL) <= val(bL) + tie ? aL : bL;
   const T aR = L.n + cL, bR = R.n + cR;
-  const T SR = val(aR) >= val(bR) ? aR : bR;
+  const T SR = val(aR) >= val(bR) - tie ? aR : bR;
   const T EL = L.p / (gm - 1.0) + 0.5 * L.r * (L.n * L.n + L.t * L.t);
   const T ER = R.p / (gm - 1.0) + 0.5 * R.r * (R.n * R.n + R.t * R.t);
   const T SS = (R.p - L.p + L.r * L.n * (SL - L.n) - R.r * R.n * (SR - R.n)) /
@@ -140,7 +163,7 @@ std::array<T, 4> hllc(const Problem& P, const FaceState<T>& L, const FaceState<T
   const std::array<T, 4> FL = {L.r * L.n, L.r * L.n * L.n + L.p, L.r * L.n * L.t, L.n * (EL + L.p)};
   const std::array<T, 4> FR = {R.r * R.n, R.r * R.n * R.n + R.p, R.r * R.n * R.t, R.n * (ER + R.p)};
   if (val(SL) >= 0.0) return FL;
-  if (val(SS) >= 0.0) {
+  if (val(SS) >= -tie) {
     const T f = L.r * (SL - L.n) / (SL - SS);
     const std::array<T, 4> Us = {f, f * SS, f * L.t,
                                  f * (EL / L.r + (SS - L.n) * (SS + L.p / (L.r * (SL - L.n))))};
@@ -167,7 +190,8 @@ std::array<T, 4> hllc(const Problem& P, const FaceState<T>& L, const FaceState<T
 template <class T>
 T wall_pressure(const Problem& P, const FaceState<T>& w, bool interior_left) {
   const T c = sqrt(P.gamma * w.p / w.r);
-  const T an = fabs(w.n);
+  // |n|, with normal speeds within the tie tolerance of zero taken as >= 0
+  const T an = val(w.n) < -kTieTol * val(c) ? -w.n : w.n;
   if (interior_left) return w.p + w.r * w.n * (an + c + w.n);
   return w.p - w.r * w.n * (an + c - w.n);
 }
@@ -203,8 +227,8 @@ int step_member(const Problem& P, const T* U, T* Un, double dt) {
   for (int j = 0; j < ny; ++j)
     for (int i = 0; i < nx; ++i) {
       const Prim<T>& w = Wat(i, j);
-      const Prim<T> sx = mc_slope(Wat((i + nx - 1) % nx, j), w, Wat((i + 1) % nx, j));
-      const Prim<T> sy = mc_slope(Wat(i, j - 1), w, Wat(i, j + 1));
+      const Prim<T> sx = mc_slope(P, Wat((i + nx - 1) % nx, j), w, Wat((i + 1) % nx, j));
+      const Prim<T> sy = mc_slope(P, Wat(i, j - 1), w, Wat(i, j + 1));
       const double hx = 0.5 * dt / dx, hy = 0.5 * dt / dy;
       Prim<T> q;
       q.r = w.r - hx * (w.u * sx.r + w.r * sx.u) - hy * (w.v * sy.r + w.r * sy.v);

@@ -1,0 +1,577 @@
+// C ABI of the MI355X hot path (declared in include/rtcnop.h): context and
+// workspace management, the batched CFL march, and the checkpointed discrete
+// adjoint driver.  All device memory is the caller's; this file only carves
+// the workspace and launches kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/rtcnop.h"
+#include "rt_kernels.h"
+#include "rt_revolve.h"
+
+using rtk::Ctl;
+using rtk::Flags;
+using rtk::Params;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define RT_HIP(call)                                                                        \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess) return fail(RT_EHIP, "%s: %s", #call, hipGetErrorString(e_));    \
+  } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+struct rt_ctx {
+  Params P;
+  hipStream_t stream;
+  int tile;
+  int red_blocks;
+  // workspace
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  int32_t max_steps = 0;
+  double *S0 = nullptr, *S1 = nullptr, *L0 = nullptr, *L1 = nullptr, *Z = nullptr;
+  int32_t* codes = nullptr;
+  double* partial = nullptr;
+  uint32_t* counter = nullptr;
+  Ctl* ctl = nullptr;
+  Flags* flags = nullptr;
+  double* dt_log = nullptr;
+  int32_t* nsteps = nullptr;
+  double* scal = nullptr;  // [8][B]: 0 max speed, 1 ke0, 2 keN, 3 dt, 4 norm, 5 dot
+  size_t cells() const { return (size_t)P.nx * P.ny; }
+  size_t state_elems() const { return 4 * cells() * P.nb; }
+  double* sc(int k) const { return scal + (size_t)k * P.nb; }
+};
+
+namespace {
+
+struct Layout {
+  size_t S0, S1, L0, L1, Z, codes, partial, counter, ctl, flags, dt_log, nsteps, scal, total;
+};
+
+Layout layout(const rt_ctx* c, int32_t max_steps) {
+  Layout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align256(bytes);
+    return o;
+  };
+  const size_t se = c->state_elems() * sizeof(double);
+  int maxblk = c->red_blocks;
+  for (int t = 0; t < rtk::TILE_COUNT; ++t) maxblk = std::max(maxblk, rtk::step_blocks(c->P, t));
+  L.S0 = take(se);
+  L.S1 = take(se);
+  L.L0 = take(se);
+  L.L1 = take(se);
+  L.Z = take(3 * se);
+  L.codes = take(c->cells() * c->P.nb * sizeof(int32_t));
+  L.partial = take((size_t)maxblk * c->P.nb * sizeof(double));
+  L.counter = take((size_t)c->P.nb * sizeof(uint32_t));
+  L.ctl = take((size_t)c->P.nb * sizeof(Ctl));
+  L.flags = take(sizeof(Flags));
+  L.dt_log = take((size_t)c->P.nb * std::max<int32_t>(max_steps, 1) * sizeof(double));
+  L.nsteps = take((size_t)c->P.nb * sizeof(int32_t));
+  L.scal = take((size_t)8 * c->P.nb * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+int need_ws(const rt_ctx* c) {
+  if (!c) return fail(RT_EINVAL, "null context");
+  if (!c->ws) return fail(RT_ESTATE, "no workspace set (call rt_set_workspace)");
+  return 0;
+}
+
+// Read the device flags (synchronising) and turn them into a status.
+int read_flags(rt_ctx* c, Flags* host, bool clear) {
+  RT_HIP(hipMemcpyAsync(host, c->flags, sizeof(Flags), hipMemcpyDeviceToHost, c->stream));
+  RT_HIP(hipStreamSynchronize(c->stream));
+  if (clear && (host->err_unphys || host->err_overflow)) {
+    RT_HIP(rtk::launch_fill_i32(reinterpret_cast<int32_t*>(c->flags), 0, 2, c->stream));
+  }
+  return 0;
+}
+
+int flags_status(const Flags& f) {
+  if (f.err_unphys) return fail(RT_EUNPHYS, "unphysical state (rho <= 0, p <= 0 or non-finite)");
+  if (f.err_overflow) return fail(RT_ENOMEM, "step log or checkpoint pool overflow");
+  return 0;
+}
+
+rtk::StepArgs adaptive_args(rt_ctx* c, const double* src, double* dst, double* pool, int interval, int slots) {
+  rtk::StepArgs a{};
+  a.U = src;
+  a.Un = dst;
+  a.ctl = c->ctl;
+  a.partial = c->partial;
+  a.counter = c->counter;
+  a.dt_log = c->dt_log;
+  a.dt_log_cap = c->max_steps;
+  a.pool = pool;
+  a.snap_interval = interval > 0 ? interval : 1;
+  a.snap_slots = slots;
+  a.flags = c->flags;
+  return a;
+}
+
+// Adaptive march of all members from S0 to T.  On return (stream synced)
+// ctl holds per-member step counts; the final state of member b is in S0 if
+// its step count is even, else in S1.  Snapshots of U^n go to `pool` every
+// `interval` steps when pool is not null.
+int march(rt_ctx* c, double T, double* pool, int interval, int slots) {
+  Params& P = c->P;
+  RT_HIP(rtk::launch_reduce(P, 0, c->S0, nullptr, c->partial, c->red_blocks, c->sc(0), c->stream));
+  RT_HIP(rtk::launch_march_begin(P, c->sc(0), T, c->ctl, c->flags, c->stream));
+  std::vector<Ctl> h(P.nb);
+  RT_HIP(hipMemcpyAsync(h.data(), c->ctl, sizeof(Ctl) * P.nb, hipMemcpyDeviceToHost, c->stream));
+  RT_HIP(hipStreamSynchronize(c->stream));
+  double dtmin = INFINITY;
+  for (const Ctl& x : h) dtmin = std::min(dtmin, x.dt);
+  if (!(dtmin > 0.0) || !std::isfinite(dtmin)) return fail(RT_EUNPHYS, "initial CFL step is %g", dtmin);
+  const double est = std::ceil(T / dtmin);
+  const long nest = est > 1e9 ? 1000000000L : (long)est;
+  long launched = 0;
+  long target = nest;
+  Flags f{};
+  for (;;) {
+    while (launched < target) {
+      const double* src = (launched & 1) ? c->S1 : c->S0;
+      double* dst = (launched & 1) ? c->S0 : c->S1;
+      rtk::StepArgs a = adaptive_args(c, src, dst, pool, interval, slots);
+      RT_HIP(rtk::launch_step(P, c->tile, a, c->stream));
+      ++launched;
+    }
+    if (int rc = read_flags(c, &f, false)) return rc;
+    if (f.n_active == 0 || f.err_unphys || f.err_overflow) break;
+    if (launched > (long)c->max_steps + 2) {
+      return fail(RT_ENOMEM, "march needs more than %d steps (workspace max_steps)", c->max_steps);
+    }
+    target = launched + std::max<long>(8, nest / 32);
+  }
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rt_last_error(void) { return g_err.c_str(); }
+
+int rt_create(const rt_grid* grid, const rt_phys* phys, void* stream, rt_ctx** out) {
+  if (!grid || !phys || !out) return fail(RT_EINVAL, "null argument");
+  if (grid->nx < 3 || grid->ny < 2 || grid->batch < 1) return fail(RT_EINVAL, "grid must be at least 3 x 2 with batch >= 1");
+  if ((size_t)grid->nx * grid->ny > (size_t)1 << 30) return fail(RT_EINVAL, "grid too large");
+  if (!(grid->lx > 0) || !(grid->ly > 0)) return fail(RT_EINVAL, "domain lengths must be positive");
+  if (!(phys->gamma > 1.0) || !(phys->h > 0) || !(phys->cfl > 0) || !(phys->rho_h > 0) || !(phys->rho_l > 0))
+    return fail(RT_EINVAL, "need gamma > 1, h > 0, cfl > 0, positive densities");
+  if (phys->comp_mask < 1 || phys->comp_mask > 3) return fail(RT_EINVAL, "comp_mask must be 1, 2 or 3");
+  rt_ctx* c = new rt_ctx();
+  Params& P = c->P;
+  P.nx = grid->nx;
+  P.ny = grid->ny;
+  P.nb = grid->batch;
+  P.comp_mask = phys->comp_mask;
+  P.dx = grid->lx / grid->nx;
+  P.dy = grid->ly / grid->ny;
+  P.inv_dx = 1.0 / P.dx;
+  P.inv_dy = 1.0 / P.dy;
+  P.gamma = phys->gamma;
+  P.gm1 = phys->gamma - 1.0;
+  P.inv_gm1 = 1.0 / P.gm1;
+  P.g_y = phys->g_y;
+  P.cfl = phys->cfl;
+  P.rho_h = phys->rho_h;
+  P.rho_l = phys->rho_l;
+  P.y0 = phys->y0;
+  P.h = phys->h;
+  P.p_int = phys->p_int;
+  c->stream = reinterpret_cast<hipStream_t>(stream);
+  c->tile = P.nx >= 64 ? rtk::TILE_64x4 : (P.nx >= 32 ? rtk::TILE_32x8 : rtk::TILE_16x16);
+  const size_t n = c->cells();
+  c->red_blocks = (int)std::min<size_t>(256, std::max<size_t>(1, n / 2048));
+  *out = c;
+  return 0;
+}
+
+int rt_destroy(rt_ctx* c) {
+  delete c;
+  return 0;
+}
+
+int rt_set_stream(rt_ctx* c, void* stream) {
+  if (!c) return fail(RT_EINVAL, "null context");
+  c->stream = reinterpret_cast<hipStream_t>(stream);
+  return 0;
+}
+
+// Internal tuning hook: choose the tile shape of the step / adjoint kernels.
+int rt_set_tile(rt_ctx* c, int32_t tile) {
+  if (!c || tile < 0 || tile >= rtk::TILE_COUNT) return fail(RT_EINVAL, "bad tile id");
+  c->tile = tile;
+  return 0;
+}
+
+int rt_get_tile(const rt_ctx* c, int32_t* tile) {
+  if (!c || !tile) return fail(RT_EINVAL, "null argument");
+  *tile = c->tile;
+  return 0;
+}
+
+int rt_workspace_bytes(const rt_ctx* c, int32_t max_steps, size_t* bytes) {
+  if (!c || !bytes || max_steps < 1) return fail(RT_EINVAL, "bad argument");
+  *bytes = layout(c, max_steps).total;
+  return 0;
+}
+
+int rt_set_workspace(rt_ctx* c, void* dev, size_t bytes, int32_t max_steps) {
+  if (!c || !dev || max_steps < 1) return fail(RT_EINVAL, "bad argument");
+  if (reinterpret_cast<uintptr_t>(dev) & 255) return fail(RT_EINVAL, "workspace must be 256-byte aligned");
+  const Layout L = layout(c, max_steps);
+  if (bytes < L.total) return fail(RT_ENOMEM, "workspace of %zu bytes < %zu needed", bytes, L.total);
+  char* w = static_cast<char*>(dev);
+  c->ws = w;
+  c->ws_bytes = bytes;
+  c->max_steps = max_steps;
+  c->S0 = reinterpret_cast<double*>(w + L.S0);
+  c->S1 = reinterpret_cast<double*>(w + L.S1);
+  c->L0 = reinterpret_cast<double*>(w + L.L0);
+  c->L1 = reinterpret_cast<double*>(w + L.L1);
+  c->Z = reinterpret_cast<double*>(w + L.Z);
+  c->codes = reinterpret_cast<int32_t*>(w + L.codes);
+  c->partial = reinterpret_cast<double*>(w + L.partial);
+  c->counter = reinterpret_cast<uint32_t*>(w + L.counter);
+  c->ctl = reinterpret_cast<Ctl*>(w + L.ctl);
+  c->flags = reinterpret_cast<Flags*>(w + L.flags);
+  c->dt_log = reinterpret_cast<double*>(w + L.dt_log);
+  c->nsteps = reinterpret_cast<int32_t*>(w + L.nsteps);
+  c->scal = reinterpret_cast<double*>(w + L.scal);
+  RT_HIP(rtk::launch_fill_i32(reinterpret_cast<int32_t*>(c->counter), 0, c->P.nb, c->stream));
+  RT_HIP(rtk::launch_fill_i32(reinterpret_cast<int32_t*>(c->flags), 0, sizeof(Flags) / 4, c->stream));
+  return 0;
+}
+
+int rt_init_state(rt_ctx* c, const double* uv0, double* U) {
+  if (!c || !uv0 || !U) return fail(RT_EINVAL, "null argument");
+  RT_HIP(rtk::launch_init_state(c->P, uv0, U, c->stream));
+  return 0;
+}
+
+int rt_cfl_dt(rt_ctx* c, const double* U, double* dt) {
+  if (int rc = need_ws(c)) return rc;
+  if (!U || !dt) return fail(RT_EINVAL, "null argument");
+  RT_HIP(rtk::launch_reduce(c->P, 0, U, nullptr, c->partial, c->red_blocks, c->sc(0), c->stream));
+  RT_HIP(rtk::launch_cfl_from_speed(c->P, c->sc(0), dt, c->stream));
+  return 0;
+}
+
+int rt_step(rt_ctx* c, const double* U_in, double* U_out, const double* dt, double* dt_next) {
+  if (int rc = need_ws(c)) return rc;
+  if (!U_in || !U_out || U_in == U_out) return fail(RT_EINVAL, "need distinct non-null U_in, U_out");
+  if (!dt) {
+    if (int rc = rt_cfl_dt(c, U_in, c->sc(3))) return rc;
+    dt = c->sc(3);
+  }
+  rtk::StepArgs a{};
+  a.U = U_in;
+  a.Un = U_out;
+  a.dt = dt;
+  a.dt_stride = 1;
+  a.dt_index = 0;
+  a.partial = c->partial;
+  a.counter = c->counter;
+  a.dt_next = dt_next;
+  a.flags = c->flags;
+  RT_HIP(rtk::launch_step(c->P, c->tile, a, c->stream));
+  return 0;
+}
+
+int rt_integrate(rt_ctx* c, double* U, double T, double* t_out, int32_t* nsteps, double* dt_log, int32_t cap) {
+  if (int rc = need_ws(c)) return rc;
+  if (!U || !(T > 0) || !std::isfinite(T)) return fail(RT_EINVAL, "need U and 0 < T < inf");
+  if (dt_log && cap < 1) return fail(RT_EINVAL, "dt_log needs cap >= 1");
+  RT_HIP(rtk::launch_copy(U, c->S0, c->state_elems(), c->stream));
+  if (int rc = march(c, T, nullptr, 1, 0)) return rc;
+  RT_HIP(rtk::launch_copy_final(c->P, c->ctl, c->S0, c->S1, U, t_out, nsteps, c->dt_log, c->max_steps, dt_log, cap,
+                                c->stream));
+  Flags f{};
+  if (int rc = read_flags(c, &f, true)) return rc;
+  if (int rc = flags_status(f)) return rc;
+  if (dt_log) {
+    std::vector<Ctl> h(c->P.nb);
+    RT_HIP(hipMemcpy(h.data(), c->ctl, sizeof(Ctl) * c->P.nb, hipMemcpyDeviceToHost));
+    for (const Ctl& x : h)
+      if (x.nsteps > cap) return fail(RT_ENOMEM, "dt_log capacity %d < %d steps", cap, x.nsteps);
+  }
+  return 0;
+}
+
+int rt_kinetic_energy(rt_ctx* c, const double* U, double* ke) {
+  if (int rc = need_ws(c)) return rc;
+  if (!U || !ke) return fail(RT_EINVAL, "null argument");
+  RT_HIP(rtk::launch_reduce(c->P, 1, U, nullptr, c->partial, c->red_blocks, ke, c->stream));
+  return 0;
+}
+
+int rt_step_adjoint(rt_ctx* c, const double* U, const double* dt, const double* lam_next, double* lam) {
+  if (int rc = need_ws(c)) return rc;
+  if (!U || !dt || !lam_next || !lam || lam == lam_next) return fail(RT_EINVAL, "bad argument");
+  rtk::AdjArgs a{};
+  a.U = U;
+  a.lam_next = lam_next;
+  a.lam = lam;
+  a.Z = c->Z;
+  a.codes = c->codes;
+  a.dt = dt;
+  a.dt_stride = 1;
+  a.dt_index = 0;
+  a.flags = c->flags;
+  RT_HIP(rtk::launch_adjoint(c->P, c->tile, a, c->stream));
+  return 0;
+}
+
+int rt_pool_bytes(const rt_ctx* c, int32_t kind, int32_t interval, int32_t nsteps_max, size_t* bytes) {
+  if (!c || !bytes || nsteps_max < 1) return fail(RT_EINVAL, "bad argument");
+  const size_t se = c->state_elems() * sizeof(double);
+  if (kind == RT_CKPT_STORE_ALL) {
+    *bytes = se * (size_t)nsteps_max;
+  } else if (kind == RT_CKPT_UNIFORM) {
+    if (interval < 1) return fail(RT_EINVAL, "interval must be >= 1");
+    *bytes = se * ((size_t)(nsteps_max + interval - 1) / interval + (interval - 1));
+  } else if (kind == RT_CKPT_REVOLVE) {
+    *bytes = se * 2;
+  } else {
+    return fail(RT_EINVAL, "unknown checkpoint kind %d", kind);
+  }
+  return 0;
+}
+
+int rt_grad_u0(rt_ctx* c, const double* uv0, double T, const rt_ckpt_policy* pol, double* R, double* grad,
+               int32_t* nsteps_out) {
+  if (int rc = need_ws(c)) return rc;
+  if (!uv0 || !pol || !R || !grad || !(T > 0) || !std::isfinite(T)) return fail(RT_EINVAL, "bad argument");
+  if (!pol->pool) return fail(RT_EINVAL, "checkpoint pool is null");
+  Params& P = c->P;
+  hipStream_t s = c->stream;
+  const size_t se = c->state_elems();
+  const size_t slots_total = pol->pool_bytes / (se * sizeof(double));
+  double* pool = static_cast<double*>(pol->pool);
+  auto state_slot = [&](size_t k) { return pool + k * se; };
+
+  // forward: U^0, KE(U^0)
+  RT_HIP(rtk::launch_init_state(P, uv0, c->S0, s));
+  RT_HIP(rtk::launch_reduce(P, 1, c->S0, nullptr, c->partial, c->red_blocks, c->sc(1), s));
+
+  int interval = 1;
+  size_t snap_slots = 0;
+  double* seg = nullptr;
+  if (pol->kind == RT_CKPT_STORE_ALL || pol->kind == RT_CKPT_UNIFORM) {
+    interval = pol->kind == RT_CKPT_STORE_ALL ? 1 : pol->interval;
+    if (interval < 1) return fail(RT_EINVAL, "interval must be >= 1");
+    if (slots_total < (size_t)interval) return fail(RT_ENOMEM, "pool holds %zu states, need > %d", slots_total, interval - 1);
+    snap_slots = slots_total - (interval - 1);
+    seg = state_slot(snap_slots);
+    if (int rc = march(c, T, pool, interval, (int)std::min<size_t>(snap_slots, 1u << 30))) return rc;
+  } else if (pol->kind == RT_CKPT_REVOLVE) {
+    if (slots_total < 2) return fail(RT_ENOMEM, "revolve needs a pool of at least 2 states");
+    // Counting pass: the step count decides the binomial schedule.  The
+    // initial state is kept in slot 0 for the restart.
+    RT_HIP(rtk::launch_copy(c->S0, state_slot(0), se, s));
+    if (int rc = march(c, T, nullptr, 1, 0)) return rc;
+  } else {
+    return fail(RT_EINVAL, "unknown checkpoint kind %d", pol->kind);
+  }
+  Flags f{};
+  if (int rc = read_flags(c, &f, true)) return rc;
+  if (int rc = flags_status(f)) return rc;
+
+  // step counts and final state
+  RT_HIP(rtk::launch_copy_final(P, c->ctl, c->S0, c->S1, c->L1, nullptr, c->nsteps, nullptr, 0, nullptr, 0, s));
+  if (nsteps_out) RT_HIP(hipMemcpyAsync(nsteps_out, c->nsteps, sizeof(int32_t) * P.nb, hipMemcpyDeviceToDevice, s));
+  std::vector<int32_t> hn(P.nb);
+  std::vector<double> hke0(P.nb);
+  RT_HIP(hipMemcpyAsync(hn.data(), c->nsteps, sizeof(int32_t) * P.nb, hipMemcpyDeviceToHost, s));
+  RT_HIP(hipMemcpyAsync(hke0.data(), c->sc(1), sizeof(double) * P.nb, hipMemcpyDeviceToHost, s));
+  RT_HIP(hipStreamSynchronize(s));
+  for (double k : hke0)
+    if (!(k > 0.0)) return fail(RT_EINVAL, "KE(0) = %g: the perturbation is zero", k);
+  const int nmax = *std::max_element(hn.begin(), hn.end());
+
+  // terminal adjoint lambda^N into L0 (from U^N in L1)
+  RT_HIP(rtk::launch_reduce(P, 1, c->L1, nullptr, c->partial, c->red_blocks, c->sc(2), s));
+  RT_HIP(rtk::launch_terminal_adjoint(P, c->L1, c->sc(1), c->L0, s));
+  double* lam = c->L0;
+  double* lam_other = c->L1;
+
+  auto step_given = [&](const double* src, double* dst, int n) -> int {
+    rtk::StepArgs a{};
+    a.U = src;
+    a.Un = dst;
+    a.dt = c->dt_log;
+    a.dt_stride = c->max_steps;
+    a.dt_index = n;
+    a.nsteps_limit = c->nsteps;
+    a.flags = c->flags;
+    RT_HIP(rtk::launch_step(P, c->tile, a, s));
+    return 0;
+  };
+  auto adjoint = [&](const double* Un, int n) -> int {
+    rtk::AdjArgs a{};
+    a.U = Un;
+    a.lam_next = lam;
+    a.lam = lam_other;
+    a.Z = c->Z;
+    a.codes = c->codes;
+    a.dt = c->dt_log;
+    a.dt_stride = c->max_steps;
+    a.dt_index = n;
+    a.nsteps_limit = c->nsteps;
+    a.flags = c->flags;
+    RT_HIP(rtk::launch_adjoint(P, c->tile, a, s));
+    std::swap(lam, lam_other);
+    return 0;
+  };
+
+  if (pol->kind != RT_CKPT_REVOLVE) {
+    const int K = (nmax + interval - 1) / interval;
+    for (int k = K - 1; k >= 0; --k) {
+      const int base = k * interval, hi = std::min(base + interval, nmax);
+      auto st = [&](int n) -> double* { return n == base ? state_slot(k) : seg + (size_t)(n - base - 1) * se; };
+      for (int n = base; n < hi - 1; ++n)
+        if (int rc = step_given(st(n), st(n + 1), n)) return rc;
+      for (int n = hi - 1; n >= base; --n)
+        if (int rc = adjoint(st(n), n)) return rc;
+    }
+  } else {
+    // Binomial checkpointing over slots [0, slots_total): slot 0 holds U^0.
+    const int snaps = (int)std::min<size_t>(slots_total, 1u << 20);
+    std::vector<rtrev::Action> plan = rtrev::schedule(nmax, snaps);
+    std::vector<int> slot_step(snaps, -1);
+    slot_step[0] = 0;
+    double* cur = c->S0;   // working state of the schedule
+    int cur_step = 0;
+    RT_HIP(rtk::launch_copy(state_slot(0), cur, se, s));
+    for (const rtrev::Action& act : plan) {
+      switch (act.kind) {
+        case rtrev::Action::TAKESHOT:
+          RT_HIP(rtk::launch_copy(cur, state_slot(act.slot), se, s));
+          slot_step[act.slot] = cur_step;
+          break;
+        case rtrev::Action::RESTORE:
+          RT_HIP(rtk::launch_copy(state_slot(act.slot), cur, se, s));
+          cur_step = slot_step[act.slot];
+          break;
+        case rtrev::Action::ADVANCE:
+          for (int n = cur_step; n < act.to; ++n) {
+            double* dst = (cur == c->S0) ? c->S1 : c->S0;
+            if (int rc = step_given(cur, dst, n)) return rc;
+            cur = dst;
+          }
+          cur_step = act.to;
+          break;
+        case rtrev::Action::REVERSE:
+          if (int rc = adjoint(cur, cur_step)) return rc;
+          break;
+      }
+    }
+  }
+
+  // initial adjoint -> R, gradient
+  RT_HIP(rtk::launch_initial_adjoint(P, uv0, lam, c->sc(1), c->sc(2), R, grad, s));
+  if (int rc = read_flags(c, &f, true)) return rc;
+  return flags_status(f);
+}
+
+int rt_project_to_constraint(rt_ctx* c, double* uv, double delta, int32_t norm, int32_t set, double* norm_out) {
+  if (int rc = need_ws(c)) return rc;
+  if (!uv || !(delta > 0) || norm < 0 || norm > 2 || set < 0 || set > 1) return fail(RT_EINVAL, "bad argument");
+  double* m = norm_out ? norm_out : c->sc(4);
+  RT_HIP(rtk::launch_reduce(c->P, 2 + norm, uv, nullptr, c->partial, c->red_blocks, m, c->stream));
+  RT_HIP(rtk::launch_scale_project(c->P, uv, m, delta, norm, set, c->stream));
+  return 0;
+}
+
+int rt_dot(rt_ctx* c, const double* a, const double* b, double* out) {
+  if (int rc = need_ws(c)) return rc;
+  if (!a || !b || !out) return fail(RT_EINVAL, "null argument");
+  RT_HIP(rtk::launch_reduce(c->P, 5, a, b, c->partial, c->red_blocks, out, c->stream));
+  return 0;
+}
+
+int rt_axpy(rt_ctx* c, const double* x, const double* alpha, const double* y, double* out) {
+  if (!c || !x || !alpha || !y || !out) return fail(RT_EINVAL, "null argument");
+  RT_HIP(rtk::launch_axpy(c->P, x, alpha, y, out, c->stream));
+  return 0;
+}
+
+int rt_check_error(rt_ctx* c) {
+  if (int rc = need_ws(c)) return rc;
+  Flags f{};
+  if (int rc = read_flags(c, &f, true)) return rc;
+  return flags_status(f);
+}
+
+// Host-only check of the binomial schedule (no GPU): builds the schedule for
+// nsteps steps and `slots` slots, replays it on step indices and verifies that
+// every step is reversed exactly once, in decreasing order, from the right
+// state, using only slots [0, slots).  Returns its forward-step count and
+// the closed-form minimum.
+int rt_revolve_stats(int32_t nsteps, int32_t slots, int64_t* forward, int64_t* optimum) {
+  if (nsteps < 1 || slots < 1 || !forward || !optimum) return fail(RT_EINVAL, "bad argument");
+  const std::vector<rtrev::Action> plan = rtrev::schedule(nsteps, slots);
+  std::vector<int> slot_step(slots, -1);
+  slot_step[0] = 0;
+  int cur = 0, next_rev = nsteps - 1;
+  int64_t fw = 0;
+  for (const rtrev::Action& a : plan) {
+    switch (a.kind) {
+      case rtrev::Action::ADVANCE:
+        if (a.to < cur) return fail(RT_EINVAL, "schedule advances backwards");
+        fw += a.to - cur;
+        cur = a.to;
+        break;
+      case rtrev::Action::TAKESHOT:
+        if (a.slot < 0 || a.slot >= slots) return fail(RT_EINVAL, "slot out of range");
+        slot_step[a.slot] = cur;
+        break;
+      case rtrev::Action::RESTORE:
+        if (a.slot < 0 || a.slot >= slots || slot_step[a.slot] < 0) return fail(RT_EINVAL, "restore of empty slot");
+        cur = slot_step[a.slot];
+        break;
+      case rtrev::Action::REVERSE:
+        if (a.to != next_rev || cur != a.to) return fail(RT_EINVAL, "reverse out of order at %d", a.to);
+        --next_rev;
+        break;
+    }
+  }
+  if (next_rev != -1) return fail(RT_EINVAL, "schedule left %d steps unreversed", next_rev + 1);
+  *forward = fw;
+  *optimum = rtrev::min_forward_steps(nsteps, slots);
+  return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,897 @@
+// HIP kernels for gfx950: the fused forward step, the two-kernel discrete
+// adjoint of the step, and the small elementwise / reduction kernels around
+// them.  All arithmetic is FP64.
+//
+// Fused step (one launch per time step for all members):
+//   block = one tile of TX x TY cells of one member, 256 threads;
+//   phase A  primitives of the tile plus a 2-cell halo into LDS (x periodic,
+//            y ghost rows from the wall boundary condition);
+//   phase B  MC slopes and the MUSCL-Hancock predictor of the tile plus a
+//            1-cell cross-shaped halo into LDS;
+//   phase C  HLLC fluxes of every face of the tile, each computed once;
+//   phase D  conservative update with the gravity source, store, optional
+//            snapshot of U^n, and the largest signal speed of U^{n+1};
+//   epilogue per-block maxima -> the last block to finish reduces them into
+//            the member's next CFL step (no extra launch, no host sync).
+// Adjoint of one step (frozen dt): kernel A recomputes phases A-C, runs the
+// HLLC / wall-flux adjoints on every face of the tile and the predictor
+// adjoint of every tile cell; kernel B gathers the limiter adjoints of the
+// five slope stencils touching a cell and applies the primitive-variable
+// adjoint and the direct (identity + gravity) terms.
+#include <hip/hip_runtime.h>
+
+#include "rt_kernels.h"
+
+namespace rtk {
+
+namespace {
+
+__device__ __forceinline__ int wrapx(int i, int nx) {
+  i %= nx;
+  return i < 0 ? i + nx : i;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <int NT>
+__device__ double block_max(double v, double* red) {
+  v = wave_max(v);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) red[w] = v;
+  __syncthreads();
+  double m = red[0];
+#pragma unroll
+  for (int k = 1; k < NT / 64; ++k) m = fmax(m, red[k]);
+  return m;
+}
+
+template <int NT>
+__device__ double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) red[w] = v;
+  __syncthreads();
+  double s = red[0];
+#pragma unroll
+  for (int k = 1; k < NT / 64; ++k) s += red[k];
+  return s;
+}
+
+__device__ __forceinline__ double load_coherent(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ double rho0_at(const Params& P, double y) {
+  return 0.5 * (P.rho_h + P.rho_l) + 0.5 * (P.rho_h - P.rho_l) * tanh((y - P.y0) / P.h);
+}
+
+__device__ __forceinline__ double p0_at(const Params& P, double y) {
+  const double z = (y - P.y0) / P.h;
+  const double az = fabs(z);
+  const double lc = az + log1p(exp(-2.0 * az)) - 0.69314718055994530942;
+  return P.p_int + P.g_y * (0.5 * (P.rho_h + P.rho_l) * (y - P.y0) + 0.5 * (P.rho_h - P.rho_l) * P.h * lc);
+}
+
+// ----------------------------------------------------------------- LDS tile
+template <int TX, int TY>
+struct TileLDS {
+  static constexpr int AX = TX + 4, AY = TY + 4;  // primitives, halo 2
+  static constexpr int QX = TX + 2, QY = TY + 2;  // predictor, halo 1
+  double W[4][AY][AX];
+  double Q[12][QY][QX];  // q (4), sx (4), sy (4)
+};
+
+// Phase A: primitives of the tile + halo 2.  Returns nonzero on an
+// unphysical interior state.
+template <int TX, int TY, int NT>
+__device__ int tile_prims(const Params& P, const double* U, size_t N, int x0, int y0, TileLDS<TX, TY>& S) {
+  constexpr int AX = TileLDS<TX, TY>::AX, AY = TileLDS<TX, TY>::AY;
+  int bad = 0;
+  for (int k = threadIdx.x; k < AX * AY; k += NT) {
+    const int lx = k % AX, ly = k / AX;
+    const int gx = wrapx(x0 - 2 + lx, P.nx);
+    const int gy = y0 - 2 + ly;
+    W4 w{1.0, 0.0, 0.0, 1.0};
+    if (gy >= -1 && gy <= P.ny) {
+      const int sy = gy < 0 ? 0 : (gy >= P.ny ? P.ny - 1 : gy);
+      const size_t c = (size_t)sy * P.nx + gx;
+      w = cons_to_prim(P, U[c], U[N + c], U[2 * N + c], U[3 * N + c]);
+      if (gy >= 0 && gy < P.ny) bad |= unphysical(w);
+      if (gy < 0) w = ghost_bottom(P, w);
+      else if (gy >= P.ny) w = ghost_top(P, w);
+    }
+    S.W[0][ly][lx] = w.r;
+    S.W[1][ly][lx] = w.u;
+    S.W[2][ly][lx] = w.v;
+    S.W[3][ly][lx] = w.p;
+  }
+  return bad;
+}
+
+template <int TX, int TY>
+__device__ __forceinline__ W4 ldW(const TileLDS<TX, TY>& S, int x, int y) {
+  return W4{S.W[0][y][x], S.W[1][y][x], S.W[2][y][x], S.W[3][y][x]};
+}
+template <int TX, int TY>
+__device__ __forceinline__ W4 ldQ(const TileLDS<TX, TY>& S, int k, int x, int y) {
+  return W4{S.Q[4 * k + 0][y][x], S.Q[4 * k + 1][y][x], S.Q[4 * k + 2][y][x], S.Q[4 * k + 3][y][x]};
+}
+
+// Phase B: slopes and predictor on the cross-shaped halo-1 region.  If
+// codes_out is given, the MC cases of the tile cells are stored there.
+template <int TX, int TY, int NT>
+__device__ int tile_predict(const Params& P, double dt, int x0, int y0, TileLDS<TX, TY>& S, int32_t* codes_out) {
+  constexpr int QX = TileLDS<TX, TY>::QX, QY = TileLDS<TX, TY>::QY;
+  const double hx = 0.5 * dt * P.inv_dx, hy = 0.5 * dt * P.inv_dy, hg = 0.5 * dt * P.g_y;
+  int bad = 0;
+  for (int k = threadIdx.x; k < QX * QY; k += NT) {
+    const int lx = k % QX, ly = k / QX;
+    if ((lx == 0 || lx == QX - 1) && (ly == 0 || ly == QY - 1)) continue;
+    const int gy = y0 - 1 + ly;
+    if (gy < 0 || gy >= P.ny) continue;
+    const W4 wc = ldW(S, lx + 1, ly + 1);
+    int cx, cy;
+    const W4 sx = mc4(P, ldW(S, lx, ly + 1), wc, ldW(S, lx + 2, ly + 1), cx);
+    const W4 sy = mc4(P, ldW(S, lx + 1, ly), wc, ldW(S, lx + 1, ly + 2), cy);
+    const W4 q = predict(P, wc, sx, sy, hx, hy, hg);
+    S.Q[0][ly][lx] = q.r;
+    S.Q[1][ly][lx] = q.u;
+    S.Q[2][ly][lx] = q.v;
+    S.Q[3][ly][lx] = q.p;
+    S.Q[4][ly][lx] = sx.r;
+    S.Q[5][ly][lx] = sx.u;
+    S.Q[6][ly][lx] = sx.v;
+    S.Q[7][ly][lx] = sx.p;
+    S.Q[8][ly][lx] = sy.r;
+    S.Q[9][ly][lx] = sy.u;
+    S.Q[10][ly][lx] = sy.v;
+    S.Q[11][ly][lx] = sy.p;
+    const double hr = 0.5 * fabs(sx.r), hp = 0.5 * fabs(sx.p), vr = 0.5 * fabs(sy.r), vp = 0.5 * fabs(sy.p);
+    bad |= !(q.r - hr > 0.0) || !(q.p - hp > 0.0) || !(q.r - vr > 0.0) || !(q.p - vp > 0.0);
+    if (codes_out && lx >= 1 && lx <= TX && ly >= 1 && ly <= TY) {
+      const int gx = x0 - 1 + lx;
+      if (gx < P.nx) codes_out[(size_t)gy * P.nx + gx] = cx | (cy << 8);
+    }
+  }
+  return bad;
+}
+
+// Face states from the predictor region: x faces in (r, n = u, t = v, p),
+// y faces in (r, n = v, t = u, p).
+template <int TX, int TY>
+__device__ __forceinline__ FS xface_right_of(const TileLDS<TX, TY>& S, int x, int y) {  // state at the cell's right face
+  return FS{S.Q[0][y][x] + 0.5 * S.Q[4][y][x], S.Q[1][y][x] + 0.5 * S.Q[5][y][x], S.Q[2][y][x] + 0.5 * S.Q[6][y][x],
+            S.Q[3][y][x] + 0.5 * S.Q[7][y][x]};
+}
+template <int TX, int TY>
+__device__ __forceinline__ FS xface_left_of(const TileLDS<TX, TY>& S, int x, int y) {
+  return FS{S.Q[0][y][x] - 0.5 * S.Q[4][y][x], S.Q[1][y][x] - 0.5 * S.Q[5][y][x], S.Q[2][y][x] - 0.5 * S.Q[6][y][x],
+            S.Q[3][y][x] - 0.5 * S.Q[7][y][x]};
+}
+template <int TX, int TY>
+__device__ __forceinline__ FS yface_top_of(const TileLDS<TX, TY>& S, int x, int y) {
+  return FS{S.Q[0][y][x] + 0.5 * S.Q[8][y][x], S.Q[2][y][x] + 0.5 * S.Q[10][y][x], S.Q[1][y][x] + 0.5 * S.Q[9][y][x],
+            S.Q[3][y][x] + 0.5 * S.Q[11][y][x]};
+}
+template <int TX, int TY>
+__device__ __forceinline__ FS yface_bottom_of(const TileLDS<TX, TY>& S, int x, int y) {
+  return FS{S.Q[0][y][x] - 0.5 * S.Q[8][y][x], S.Q[2][y][x] - 0.5 * S.Q[10][y][x], S.Q[1][y][x] - 0.5 * S.Q[9][y][x],
+            S.Q[3][y][x] - 0.5 * S.Q[11][y][x]};
+}
+
+// ----------------------------------------------------------------- step
+template <int TX, int TY>
+__global__ __launch_bounds__(TX* TY) void k_step(Params P, StepArgs a) {
+  constexpr int NT = TX * TY;
+  __shared__ TileLDS<TX, TY> S;
+  __shared__ double sF[4][TY][TX + 1];
+  __shared__ double sG[4][TY + 1][TX];
+  __shared__ double sRed[NT / 64];
+  __shared__ int sLast;
+
+  const int b = blockIdx.z;
+  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+  const int tid = threadIdx.x;
+  const int nx = P.nx, ny = P.ny;
+  const size_t N = (size_t)nx * ny;
+  const double* U = a.U + (size_t)b * 4 * N;
+
+  double dt;
+  int nstep = 0;
+  if (a.ctl) {
+    if (a.ctl[b].done) return;
+    dt = a.ctl[b].dt;
+    nstep = a.ctl[b].nsteps;
+  } else {
+    if (a.nsteps_limit && a.dt_index >= a.nsteps_limit[b]) return;
+    dt = a.dt[(size_t)b * a.dt_stride + a.dt_index];
+  }
+
+  int bad = tile_prims<TX, TY, NT>(P, U, N, x0, y0, S);
+  __syncthreads();
+  bad |= tile_predict<TX, TY, NT>(P, dt, x0, y0, S, nullptr);
+  __syncthreads();
+
+  // phase C: fluxes
+  for (int k = tid; k < (TX + 1) * TY; k += NT) {
+    const int fx = k % (TX + 1), fy = k / (TX + 1);
+    if (y0 + fy >= ny) continue;
+    double F[4];
+    hllc(P, xface_right_of(S, fx, fy + 1), xface_left_of(S, fx + 1, fy + 1), F);
+    sF[0][fy][fx] = F[0];
+    sF[1][fy][fx] = F[1];
+    sF[2][fy][fx] = F[2];
+    sF[3][fy][fx] = F[3];
+  }
+  for (int k = tid; k < TX * (TY + 1); k += NT) {
+    const int fx = k % TX, fy = k / TX;
+    const int j = y0 + fy;
+    if (j > ny) continue;
+    double G0 = 0.0, G1 = 0.0, G2, G3 = 0.0;
+    if (j == 0) {
+      G2 = wall_pressure(P, yface_bottom_of(S, fx + 1, fy + 1), false);
+    } else if (j == ny) {
+      G2 = wall_pressure(P, yface_top_of(S, fx + 1, fy), true);
+    } else {
+      double f[4];
+      hllc(P, yface_top_of(S, fx + 1, fy), yface_bottom_of(S, fx + 1, fy + 1), f);
+      G0 = f[0];
+      G1 = f[2];
+      G2 = f[1];
+      G3 = f[3];
+    }
+    sG[0][fy][fx] = G0;
+    sG[1][fy][fx] = G1;
+    sG[2][fy][fx] = G2;
+    sG[3][fy][fx] = G3;
+  }
+  __syncthreads();
+
+  // phase D: update
+  const int tx = tid % TX, ty = tid / TX;
+  const int gx = x0 + tx, gy = y0 + ty;
+  double smax = 0.0;
+  if (gx < nx && gy < ny) {
+    const size_t c = (size_t)gy * nx + gx;
+    const double u0 = U[c], u1 = U[N + c], u2 = U[2 * N + c], u3 = U[3 * N + c];
+    const double ax = dt * P.inv_dx, ay = dt * P.inv_dy;
+    double n0 = u0 - ax * (sF[0][ty][tx + 1] - sF[0][ty][tx]) - ay * (sG[0][ty + 1][tx] - sG[0][ty][tx]);
+    double n1 = u1 - ax * (sF[1][ty][tx + 1] - sF[1][ty][tx]) - ay * (sG[1][ty + 1][tx] - sG[1][ty][tx]);
+    double n2 = u2 - ax * (sF[2][ty][tx + 1] - sF[2][ty][tx]) - ay * (sG[2][ty + 1][tx] - sG[2][ty][tx]);
+    double n3 = u3 - ax * (sF[3][ty][tx + 1] - sF[3][ty][tx]) - ay * (sG[3][ty + 1][tx] - sG[3][ty][tx]);
+    const double dtg = dt * P.g_y;
+    n2 = n2 + dtg * 0.5 * (u0 + n0);
+    n3 = n3 + dtg * 0.5 * (sG[0][ty][tx] + sG[0][ty + 1][tx]);
+    double* Un = a.Un + (size_t)b * 4 * N;
+    Un[c] = n0;
+    Un[N + c] = n1;
+    Un[2 * N + c] = n2;
+    Un[3 * N + c] = n3;
+    if (a.pool && (nstep % a.snap_interval) == 0) {
+      const int slot = nstep / a.snap_interval;
+      if (slot < a.snap_slots) {
+        double* s = a.pool + ((size_t)slot * P.nb + b) * 4 * N;
+        s[c] = u0;
+        s[N + c] = u1;
+        s[2 * N + c] = u2;
+        s[3 * N + c] = u3;
+      } else if (tid == 0) {
+        atomicOr(&a.flags->err_overflow, 1);
+      }
+    }
+    const W4 w = cons_to_prim(P, n0, n1, n2, n3);
+    bad |= unphysical(w);
+    const double cs = sqrt(P.gamma * w.p / w.r);
+    const double sx = (fabs(w.u) + cs) * P.inv_dx, sy = (fabs(w.v) + cs) * P.inv_dy;
+    smax = sx > sy ? sx : sy;
+  }
+  if (bad) atomicOr(&a.flags->err_unphys, 1);
+
+  if (a.ctl == nullptr && a.dt_next == nullptr) return;
+  // epilogue: CFL step of U^{n+1}
+  const double bm = block_max<NT>(smax, sRed);
+  const int nblk = gridDim.x * gridDim.y;
+  if (tid == 0) {
+    a.partial[(size_t)b * nblk + blockIdx.y * gridDim.x + blockIdx.x] = bm;
+    __threadfence();
+    const unsigned prev = atomicAdd(&a.counter[b], 1u);
+    sLast = prev == (unsigned)(nblk - 1);
+  }
+  __syncthreads();
+  if (!sLast) return;
+  __threadfence();
+  double m = 0.0;
+  for (int k = tid; k < nblk; k += NT) m = fmax(m, load_coherent(&a.partial[(size_t)b * nblk + k]));
+  m = block_max<NT>(m, sRed);
+  if (tid != 0) return;
+  a.counter[b] = 0u;
+  if (a.ctl == nullptr) {
+    a.dt_next[b] = P.cfl / m;
+    return;
+  }
+  Ctl cl = a.ctl[b];
+  const double dtn = cl.dt;
+  if (a.dt_log) {
+    if (cl.nsteps < a.dt_log_cap) a.dt_log[(size_t)b * a.dt_log_cap + cl.nsteps] = dtn;
+    else atomicOr(&a.flags->err_overflow, 1);
+  }
+  cl.nsteps += 1;
+  if (cl.last) {
+    cl.t = cl.T;
+    cl.done = 1;
+    atomicSub(&a.flags->n_active, 1);
+  } else {
+    cl.t = cl.t + dtn;
+    double d = P.cfl / m;
+    const double rem = cl.T - cl.t;
+    if (d >= rem) {
+      d = rem;
+      cl.last = 1;
+    }
+    cl.dt = d;
+  }
+  a.ctl[b] = cl;
+}
+
+// ----------------------------------------------------------------- adjoint A
+template <int TX, int TY>
+__global__ __launch_bounds__(TX* TY) void k_adj_a(Params P, AdjArgs a) {
+  constexpr int NT = TX * TY;
+  constexpr int QX = TileLDS<TX, TY>::QX, QY = TileLDS<TX, TY>::QY;
+  __shared__ TileLDS<TX, TY> S;
+  __shared__ double sL[4][QY][QX];            // lambda-tilde on the halo-1 region
+  __shared__ double sXL[4][TY][TX + 1];       // x faces: cotangent of the left state (r,u,v,p)
+  __shared__ double sXR[4][TY][TX + 1];       // x faces: cotangent of the right state
+  __shared__ double sYB[4][TY + 1][TX];       // y faces: cotangent of the state below
+  __shared__ double sYT[4][TY + 1][TX];       // y faces: cotangent of the state above
+
+  const int b = blockIdx.z;
+  if (a.nsteps_limit && a.dt_index >= a.nsteps_limit[b]) return;
+  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+  const int tid = threadIdx.x;
+  const int nx = P.nx, ny = P.ny;
+  const size_t N = (size_t)nx * ny;
+  const double* U = a.U + (size_t)b * 4 * N;
+  const double* Lm = a.lam_next + (size_t)b * 4 * N;
+  const double dt = a.dt[(size_t)b * a.dt_stride + a.dt_index];
+  const double hdtg = 0.5 * dt * P.g_y;
+
+  int bad = tile_prims<TX, TY, NT>(P, U, N, x0, y0, S);
+  for (int k = tid; k < QX * QY; k += NT) {
+    const int lx = k % QX, ly = k / QX;
+    const int gy = y0 - 1 + ly;
+    double l0 = 0.0, l1 = 0.0, l2 = 0.0, l3 = 0.0;
+    if (gy >= 0 && gy < ny) {
+      const size_t c = (size_t)gy * nx + wrapx(x0 - 1 + lx, nx);
+      l0 = Lm[c];
+      l1 = Lm[N + c];
+      l2 = Lm[2 * N + c];
+      l3 = Lm[3 * N + c];
+    }
+    sL[0][ly][lx] = l0 + hdtg * l2;
+    sL[1][ly][lx] = l1;
+    sL[2][ly][lx] = l2;
+    sL[3][ly][lx] = l3;
+  }
+  __syncthreads();
+  bad |= tile_predict<TX, TY, NT>(P, dt, x0, y0, S, a.codes + (size_t)b * N);
+  __syncthreads();
+
+  const double ax = dt * P.inv_dx, ay = dt * P.inv_dy;
+  for (int k = tid; k < (TX + 1) * TY; k += NT) {
+    const int fx = k % (TX + 1), fy = k / (TX + 1);
+    FS Lb{0, 0, 0, 0}, Rb{0, 0, 0, 0};
+    if (y0 + fy < ny) {
+      // face between halo-1 cells (fx, fy+1) [left] and (fx+1, fy+1) [right]
+      const double Fb[4] = {ax * (sL[0][fy + 1][fx + 1] - sL[0][fy + 1][fx]),
+                            ax * (sL[1][fy + 1][fx + 1] - sL[1][fy + 1][fx]),
+                            ax * (sL[2][fy + 1][fx + 1] - sL[2][fy + 1][fx]),
+                            ax * (sL[3][fy + 1][fx + 1] - sL[3][fy + 1][fx])};
+      hllc_adj(P, xface_right_of(S, fx, fy + 1), xface_left_of(S, fx + 1, fy + 1), Fb, Lb, Rb);
+    }
+    // x-frame (r, n = u, t = v, p) is the primitive order
+    sXL[0][fy][fx] = Lb.r;
+    sXL[1][fy][fx] = Lb.n;
+    sXL[2][fy][fx] = Lb.t;
+    sXL[3][fy][fx] = Lb.p;
+    sXR[0][fy][fx] = Rb.r;
+    sXR[1][fy][fx] = Rb.n;
+    sXR[2][fy][fx] = Rb.t;
+    sXR[3][fy][fx] = Rb.p;
+  }
+  for (int k = tid; k < TX * (TY + 1); k += NT) {
+    const int fx = k % TX, fy = k / TX;
+    const int j = y0 + fy;
+    FS Bb{0, 0, 0, 0}, Tb{0, 0, 0, 0};
+    // below = halo-1 cell (fx+1, fy), above = (fx+1, fy+1)
+    if (j == 0) {
+      wall_pressure_adj(P, yface_bottom_of(S, fx + 1, fy + 1), false, ay * sL[2][fy + 1][fx + 1], Tb);
+    } else if (j == ny) {
+      wall_pressure_adj(P, yface_top_of(S, fx + 1, fy), true, -ay * sL[2][fy][fx + 1], Bb);
+    } else if (j < ny) {
+      const double g0 = ay * (sL[0][fy + 1][fx + 1] - sL[0][fy][fx + 1]) + hdtg * (sL[3][fy + 1][fx + 1] + sL[3][fy][fx + 1]);
+      const double g1 = ay * (sL[1][fy + 1][fx + 1] - sL[1][fy][fx + 1]);
+      const double g2 = ay * (sL[2][fy + 1][fx + 1] - sL[2][fy][fx + 1]);
+      const double g3 = ay * (sL[3][fy + 1][fx + 1] - sL[3][fy][fx + 1]);
+      const double Fb[4] = {g0, g2, g1, g3};  // y frame: normal momentum is m_y
+      hllc_adj(P, yface_top_of(S, fx + 1, fy), yface_bottom_of(S, fx + 1, fy + 1), Fb, Bb, Tb);
+    }
+    // y-frame (r, n = v, t = u, p) -> primitive order (r, u, v, p)
+    sYB[0][fy][fx] = Bb.r;
+    sYB[1][fy][fx] = Bb.t;
+    sYB[2][fy][fx] = Bb.n;
+    sYB[3][fy][fx] = Bb.p;
+    sYT[0][fy][fx] = Tb.r;
+    sYT[1][fy][fx] = Tb.t;
+    sYT[2][fy][fx] = Tb.n;
+    sYT[3][fy][fx] = Tb.p;
+  }
+  __syncthreads();
+
+  const int tx = tid % TX, ty = tid / TX;
+  const int gx = x0 + tx, gy = y0 + ty;
+  if (gx < nx && gy < ny) {
+    const int lx = tx + 1, ly = ty + 1;
+    const W4 xl{sXR[0][ty][tx], sXR[1][ty][tx], sXR[2][ty][tx], sXR[3][ty][tx]};
+    const W4 xr{sXL[0][ty][tx + 1], sXL[1][ty][tx + 1], sXL[2][ty][tx + 1], sXL[3][ty][tx + 1]};
+    const W4 yb{sYT[0][ty][tx], sYT[1][ty][tx], sYT[2][ty][tx], sYT[3][ty][tx]};
+    const W4 yt{sYB[0][ty + 1][tx], sYB[1][ty + 1][tx], sYB[2][ty + 1][tx], sYB[3][ty + 1][tx]};
+    const W4 qb{xl.r + xr.r + yb.r + yt.r, xl.u + xr.u + yb.u + yt.u, xl.v + xr.v + yb.v + yt.v,
+                xl.p + xr.p + yb.p + yt.p};
+    W4 sxb{0.5 * (xr.r - xl.r), 0.5 * (xr.u - xl.u), 0.5 * (xr.v - xl.v), 0.5 * (xr.p - xl.p)};
+    W4 syb{0.5 * (yt.r - yb.r), 0.5 * (yt.u - yb.u), 0.5 * (yt.v - yb.v), 0.5 * (yt.p - yb.p)};
+    W4 wb{0.0, 0.0, 0.0, 0.0};
+    const W4 w = ldW(S, lx + 1, ly + 1);
+    const W4 sx = ldQ(S, 1, lx, ly), sy = ldQ(S, 2, lx, ly);
+    predict_adj(P, w, sx, sy, 0.5 * dt * P.inv_dx, 0.5 * dt * P.inv_dy, qb, wb, sxb, syb);
+    double* Z = a.Z + (size_t)b * 12 * N;
+    const size_t c = (size_t)gy * nx + gx;
+    Z[c] = wb.r;
+    Z[N + c] = wb.u;
+    Z[2 * N + c] = wb.v;
+    Z[3 * N + c] = wb.p;
+    Z[4 * N + c] = sxb.r;
+    Z[5 * N + c] = sxb.u;
+    Z[6 * N + c] = sxb.v;
+    Z[7 * N + c] = sxb.p;
+    Z[8 * N + c] = syb.r;
+    Z[9 * N + c] = syb.u;
+    Z[10 * N + c] = syb.v;
+    Z[11 * N + c] = syb.p;
+  }
+  if (bad) atomicOr(&a.flags->err_unphys, 1);
+}
+
+// ----------------------------------------------------------------- adjoint B
+__device__ __forceinline__ void add_slope_terms(double sb[4], int code, double scale_a, double scale_b, double out[4]) {
+  // out += (scale_a * wa + scale_b * wb) * sb, per variable with its own case
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    double wa, wb;
+    mc_weights((code >> (2 * v)) & 3, wa, wb);
+    out[v] += (scale_a * wa + scale_b * wb) * sb[v];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_adj_b(Params P, AdjArgs a) {
+  const int nx = P.nx, ny = P.ny;
+  const size_t N = (size_t)nx * ny;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y;
+  if (idx >= N) return;
+  const double* Lm = a.lam_next + (size_t)b * 4 * N;
+  double* Lo = a.lam + (size_t)b * 4 * N;
+  if (a.nsteps_limit && a.dt_index >= a.nsteps_limit[b]) {
+    Lo[idx] = Lm[idx];
+    Lo[N + idx] = Lm[N + idx];
+    Lo[2 * N + idx] = Lm[2 * N + idx];
+    Lo[3 * N + idx] = Lm[3 * N + idx];
+    return;
+  }
+  const int i = (int)(idx % nx), j = (int)(idx / nx);
+  const double dt = a.dt[(size_t)b * a.dt_stride + a.dt_index];
+  const double* Z = a.Z + (size_t)b * 12 * N;
+  const int32_t* codes = a.codes + (size_t)b * N;
+  const double* U = a.U + (size_t)b * 4 * N;
+
+  double wb[4] = {Z[idx], Z[N + idx], Z[2 * N + idx], Z[3 * N + idx]};
+  // x slopes at d = c-1, c, c+1
+  {
+    const size_t cm = (size_t)j * nx + (i == 0 ? nx - 1 : i - 1);
+    const size_t cp = (size_t)j * nx + (i == nx - 1 ? 0 : i + 1);
+    double sm[4] = {Z[4 * N + cm], Z[5 * N + cm], Z[6 * N + cm], Z[7 * N + cm]};
+    double s0[4] = {Z[4 * N + idx], Z[5 * N + idx], Z[6 * N + idx], Z[7 * N + idx]};
+    double sp[4] = {Z[4 * N + cp], Z[5 * N + cp], Z[6 * N + cp], Z[7 * N + cp]};
+    add_slope_terms(sm, codes[cm] & 0xff, 0.0, 1.0, wb);    // c is d+1: +wb
+    add_slope_terms(s0, codes[idx] & 0xff, 1.0, -1.0, wb);  // c is d: wa - wb
+    add_slope_terms(sp, codes[cp] & 0xff, -1.0, 0.0, wb);   // c is d-1: -wa
+  }
+  // y slopes
+  {
+    const int c0 = codes[idx] >> 8;
+    double s0[4] = {Z[8 * N + idx], Z[9 * N + idx], Z[10 * N + idx], Z[11 * N + idx]};
+    add_slope_terms(s0, c0, 1.0, -1.0, wb);
+    if (j > 0) {
+      const size_t cm = idx - nx;
+      double sm[4] = {Z[8 * N + cm], Z[9 * N + cm], Z[10 * N + cm], Z[11 * N + cm]};
+      add_slope_terms(sm, codes[cm] >> 8, 0.0, 1.0, wb);
+    }
+    if (j < ny - 1) {
+      const size_t cp = idx + nx;
+      double sp[4] = {Z[8 * N + cp], Z[9 * N + cp], Z[10 * N + cp], Z[11 * N + cp]};
+      add_slope_terms(sp, codes[cp] >> 8, -1.0, 0.0, wb);
+    }
+    // the wall ghost cell is a function of this cell
+    if (j == 0 || j == ny - 1) {
+      double gb[4] = {0.0, 0.0, 0.0, 0.0};
+      if (j == 0) add_slope_terms(s0, c0, -1.0, 0.0, gb);       // ghost below: a = W - Wg
+      if (j == ny - 1) add_slope_terms(s0, c0, 0.0, 1.0, gb);   // ghost above: b = Wg - W
+      // (for ny == 1 both apply; ny >= 2 is required)
+      const double sgn = j == 0 ? -1.0 : 1.0;
+      wb[0] += gb[0] + sgn * P.g_y * P.dy * gb[3];
+      wb[1] += gb[1];
+      wb[2] -= gb[2];
+      wb[3] += gb[3];
+    }
+  }
+  const W4 w = cons_to_prim(P, U[idx], U[N + idx], U[2 * N + idx], U[3 * N + idx]);
+  double ub[4];
+  prim_adj(P, w, W4{wb[0], wb[1], wb[2], wb[3]}, ub);
+  const double l0 = Lm[idx], l1 = Lm[N + idx], l2 = Lm[2 * N + idx], l3 = Lm[3 * N + idx];
+  Lo[idx] = ub[0] + l0 + dt * P.g_y * l2;
+  Lo[N + idx] = ub[1] + l1;
+  Lo[2 * N + idx] = ub[2] + l2;
+  Lo[3 * N + idx] = ub[3] + l3;
+}
+
+// ----------------------------------------------------------------- small kernels
+__global__ void k_init_state(Params P, const double* uv0, double* U) {
+  const size_t N = (size_t)P.nx * P.ny;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y;
+  if (idx >= N) return;
+  const int j = (int)(idx / P.nx);
+  const double y = (j + 0.5) * P.dy;
+  const double r = rho0_at(P, y), p = p0_at(P, y);
+  const double* q = uv0 + (size_t)b * 2 * N;
+  const double u = (P.comp_mask & 1) ? q[idx] : 0.0;
+  const double v = (P.comp_mask & 2) ? q[N + idx] : 0.0;
+  double* o = U + (size_t)b * 4 * N;
+  o[idx] = r;
+  o[N + idx] = r * u;
+  o[2 * N + idx] = r * v;
+  o[3 * N + idx] = p * P.inv_gm1 + 0.5 * r * (u * u + v * v);
+}
+
+// Per-member reduction, pass 1.  kind: 0 max signal speed of a state;
+// 1 kinetic energy sum of a state; 2/3/4 weighted |uv|^2 of a velocity field
+// (weights 1, 1, rho0/2) honouring comp_mask; 5 dot product of two velocity
+// fields.
+__global__ __launch_bounds__(256) void k_reduce_partial(Params P, int kind, const double* A, const double* Bv,
+                                                        double* partial) {
+  __shared__ double red[4];
+  const size_t N = (size_t)P.nx * P.ny;
+  const int b = blockIdx.y;
+  const int nblk = gridDim.x;
+  double acc = 0.0;
+  if (kind == 0 || kind == 1) {
+    const double* U = A + (size_t)b * 4 * N;
+    for (size_t c = (size_t)blockIdx.x * 256 + threadIdx.x; c < N; c += (size_t)nblk * 256) {
+      if (kind == 0) {
+        acc = fmax(acc, signal_speed(P, U[c], U[N + c], U[2 * N + c], U[3 * N + c]));
+      } else {
+        const double mx = U[N + c], my = U[2 * N + c];
+        acc += 0.5 * (mx * mx + my * my) / U[c];
+      }
+    }
+  } else if (kind <= 4) {
+    const double* q = A + (size_t)b * 2 * N;
+    const bool mu = (P.comp_mask & 1) != 0, mv = (P.comp_mask & 2) != 0;
+    for (size_t c = (size_t)blockIdx.x * 256 + threadIdx.x; c < N; c += (size_t)nblk * 256) {
+      const double u = mu ? q[c] : 0.0, v = mv ? q[N + c] : 0.0;
+      double w = 1.0;
+      if (kind == 4) w = 0.5 * rho0_at(P, ((int)(c / P.nx) + 0.5) * P.dy);
+      acc += w * (u * u + v * v);
+    }
+  } else {
+    const double* x = A + (size_t)b * 2 * N;
+    const double* y = Bv + (size_t)b * 2 * N;
+    for (size_t c = (size_t)blockIdx.x * 256 + threadIdx.x; c < 2 * N; c += (size_t)nblk * 256) acc += x[c] * y[c];
+  }
+  const double r = kind == 0 ? block_max<256>(acc, red) : block_sum<256>(acc, red);
+  if (threadIdx.x == 0) partial[(size_t)b * nblk + blockIdx.x] = r;
+}
+
+// Pass 2: one block per member combines the partials in a fixed order.
+__global__ __launch_bounds__(256) void k_reduce_final(Params P, int kind, const double* partial, int nblk,
+                                                      double* out) {
+  __shared__ double red[4];
+  const int b = blockIdx.x;
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < nblk; k += 256) {
+    const double v = partial[(size_t)b * nblk + k];
+    acc = kind == 0 ? fmax(acc, v) : acc + v;
+  }
+  const double r = kind == 0 ? block_max<256>(acc, red) : block_sum<256>(acc, red);
+  if (threadIdx.x != 0) return;
+  const double dV = P.dx * P.dy;
+  const double N = (double)P.nx * (double)P.ny;
+  switch (kind) {
+    case 0: out[b] = r; break;             // max signal speed
+    case 1: out[b] = r * dV; break;        // kinetic energy
+    case 2: out[b] = sqrt(r * dV); break;  // velocity L2 norm
+    case 3: out[b] = sqrt(r / N); break;   // RMS
+    case 4: out[b] = r * dV; break;        // energy C of Eq. 9
+    default: out[b] = r; break;            // dot product
+  }
+}
+
+__global__ void k_march_begin(Params P, const double* ms, double T, Ctl* ctl, Flags* flags) {
+  const int b = threadIdx.x + blockIdx.x * blockDim.x;
+  if (b == 0) flags->n_active = P.nb;
+  if (b >= P.nb) return;
+  Ctl c;
+  c.t = 0.0;
+  c.T = T;
+  c.nsteps = 0;
+  c.done = 0;
+  c.last = 0;
+  c.pad = 0;
+  double d = P.cfl / ms[b];
+  if (d >= T) {
+    d = T;
+    c.last = 1;
+  }
+  c.dt = d;
+  ctl[b] = c;
+}
+
+__global__ void k_cfl_from_speed(Params P, const double* ms, double* dt) {
+  const int b = threadIdx.x + blockIdx.x * blockDim.x;
+  if (b < P.nb) dt[b] = P.cfl / ms[b];
+}
+
+__global__ void k_copy_final(Params P, const Ctl* ctl, const double* A, const double* Bb, double* U) {
+  const size_t N4 = (size_t)4 * P.nx * P.ny;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y;
+  if (idx >= N4) return;
+  const double* src = (ctl[b].nsteps & 1) ? Bb : A;
+  U[(size_t)b * N4 + idx] = src[(size_t)b * N4 + idx];
+}
+
+__global__ void k_copy_meta(Params P, const Ctl* ctl, double* t_out, int32_t* n_out, const double* ls, int32_t lcap,
+                            double* ld, int32_t dcap) {
+  const int b = blockIdx.x;
+  const int n = ctl[b].nsteps;
+  if (threadIdx.x == 0) {
+    if (t_out) t_out[b] = ctl[b].t;
+    if (n_out) n_out[b] = n;
+  }
+  if (ld && ls) {
+    const int m = n < dcap ? n : dcap;
+    for (int k = threadIdx.x; k < m; k += blockDim.x) ld[(size_t)b * dcap + k] = ls[(size_t)b * lcap + k];
+  }
+}
+
+__global__ void k_copy(const double* src, double* dst, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+__global__ void k_fill_i32(int32_t* p, int32_t v, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// lambda^N = dR/dU^N = (1/KE0) (-|m|^2/(2 rho^2), m_x/rho, m_y/rho, 0) dV.
+__global__ void k_terminal_adjoint(Params P, const double* U, const double* ke0, double* lam) {
+  const size_t N = (size_t)P.nx * P.ny;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y;
+  if (idx >= N) return;
+  const double* u = U + (size_t)b * 4 * N;
+  double* l = lam + (size_t)b * 4 * N;
+  const double s = P.dx * P.dy / ke0[b];
+  const double ri = 1.0 / u[idx];
+  const double vx = u[N + idx] * ri, vy = u[2 * N + idx] * ri;
+  l[idx] = -0.5 * (vx * vx + vy * vy) * s;
+  l[N + idx] = vx * s;
+  l[2 * N + idx] = vy * s;
+  l[3 * N + idx] = 0.0;
+}
+
+// grad_u = rho0 (lam_mx + u0 lam_E) - (R/KE0) rho0 u0 dV (and v), R = KE_N/KE0.
+__global__ void k_initial_adjoint(Params P, const double* uv0, const double* lam0, const double* ke0,
+                                  const double* keN, double* R, double* grad) {
+  const size_t N = (size_t)P.nx * P.ny;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y;
+  if (idx >= N) return;
+  const double Rb = keN[b] / ke0[b];
+  if (idx == 0 && R) R[b] = Rb;
+  const int j = (int)(idx / P.nx);
+  const double r0 = rho0_at(P, (j + 0.5) * P.dy);
+  const double* q = uv0 + (size_t)b * 2 * N;
+  const double* l = lam0 + (size_t)b * 4 * N;
+  double* g = grad + (size_t)b * 2 * N;
+  const double k = Rb / ke0[b] * P.dx * P.dy;
+  const double u = (P.comp_mask & 1) ? q[idx] : 0.0;
+  const double v = (P.comp_mask & 2) ? q[N + idx] : 0.0;
+  g[idx] = (P.comp_mask & 1) ? r0 * (l[N + idx] + u * l[3 * N + idx]) - k * r0 * u : 0.0;
+  g[N + idx] = (P.comp_mask & 2) ? r0 * (l[2 * N + idx] + v * l[3 * N + idx]) - k * r0 * v : 0.0;
+}
+
+__global__ void k_scale_project(Params P, double* uv, const double* m, double delta, int norm, int set) {
+  const size_t N = (size_t)P.nx * P.ny;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y;
+  if (idx >= N) return;
+  const double mb = m[b];
+  double s = norm == 2 ? sqrt(delta / mb) : delta / mb;
+  if (set == 1 && mb <= delta) s = 1.0;
+  double* q = uv + (size_t)b * 2 * N;
+  q[idx] = (P.comp_mask & 1) ? q[idx] * s : 0.0;
+  q[N + idx] = (P.comp_mask & 2) ? q[N + idx] * s : 0.0;
+}
+
+__global__ void k_axpy(Params P, const double* x, const double* alpha, const double* y, double* out) {
+  const size_t N2 = (size_t)2 * P.nx * P.ny;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y;
+  if (idx >= N2) return;
+  const size_t o = (size_t)b * N2 + idx;
+  out[o] = x[o] + alpha[b] * y[o];
+}
+
+__global__ void k_ratio(int nb, const double* num, const double* den, double* out) {
+  const int b = threadIdx.x + blockIdx.x * blockDim.x;
+  if (b < nb) out[b] = num[b] / den[b];
+}
+
+inline dim3 cells_grid(const Params& P, size_t per_member) {
+  return dim3((unsigned)((per_member + 255) / 256), (unsigned)P.nb, 1);
+}
+
+}  // namespace
+
+void tile_dims(int tile, int* tx, int* ty) {
+  switch (tile) {
+    case TILE_32x8: *tx = 32; *ty = 8; break;
+    case TILE_64x4: *tx = 64; *ty = 4; break;
+    default: *tx = 16; *ty = 16; break;
+  }
+}
+
+int step_blocks(const Params& P, int tile) {
+  int tx, ty;
+  tile_dims(tile, &tx, &ty);
+  return ((P.nx + tx - 1) / tx) * ((P.ny + ty - 1) / ty);
+}
+
+template <int TX, int TY>
+static hipError_t launch_step_t(const Params& P, const StepArgs& a, hipStream_t s) {
+  dim3 grid((P.nx + TX - 1) / TX, (P.ny + TY - 1) / TY, P.nb);
+  hipLaunchKernelGGL((k_step<TX, TY>), grid, dim3(TX * TY), 0, s, P, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_step(const Params& P, int tile, const StepArgs& a, hipStream_t s) {
+  switch (tile) {
+    case TILE_32x8: return launch_step_t<32, 8>(P, a, s);
+    case TILE_64x4: return launch_step_t<64, 4>(P, a, s);
+    default: return launch_step_t<16, 16>(P, a, s);
+  }
+}
+
+template <int TX, int TY>
+static hipError_t launch_adj_t(const Params& P, const AdjArgs& a, hipStream_t s) {
+  dim3 grid((P.nx + TX - 1) / TX, (P.ny + TY - 1) / TY, P.nb);
+  hipLaunchKernelGGL((k_adj_a<TX, TY>), grid, dim3(TX * TY), 0, s, P, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const size_t N = (size_t)P.nx * P.ny;
+  hipLaunchKernelGGL(k_adj_b, cells_grid(P, N), dim3(256), 0, s, P, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint(const Params& P, int tile, const AdjArgs& a, hipStream_t s) {
+  switch (tile) {
+    case TILE_32x8: return launch_adj_t<32, 8>(P, a, s);
+    case TILE_64x4: return launch_adj_t<64, 4>(P, a, s);
+    default: return launch_adj_t<16, 16>(P, a, s);
+  }
+}
+
+hipError_t launch_init_state(const Params& P, const double* uv0, double* U, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_state, cells_grid(P, (size_t)P.nx * P.ny), dim3(256), 0, s, P, uv0, U);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(const Params& P, int kind, const double* a, const double* b, double* partial, int nblk,
+                         double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_partial, dim3(nblk, P.nb), dim3(256), 0, s, P, kind, a, b, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_reduce_final, dim3(P.nb), dim3(256), 0, s, P, kind, partial, nblk, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_march_begin(const Params& P, const double* ms, double T, Ctl* ctl, Flags* flags, hipStream_t s) {
+  hipLaunchKernelGGL(k_march_begin, dim3((P.nb + 63) / 64), dim3(64), 0, s, P, ms, T, ctl, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_cfl_from_speed(const Params& P, const double* ms, double* dt, hipStream_t s) {
+  hipLaunchKernelGGL(k_cfl_from_speed, dim3((P.nb + 63) / 64), dim3(64), 0, s, P, ms, dt);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_final(const Params& P, const Ctl* ctl, const double* A, const double* Bbuf, double* U,
+                             double* t_out, int32_t* nsteps_out, const double* log_src, int32_t log_src_cap,
+                             double* log_dst, int32_t log_dst_cap, hipStream_t s) {
+  if (U) {
+    hipLaunchKernelGGL(k_copy_final, cells_grid(P, (size_t)4 * P.nx * P.ny), dim3(256), 0, s, P, ctl, A, Bbuf, U);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_copy_meta, dim3(P.nb), dim3(256), 0, s, P, ctl, t_out, nsteps_out, log_src, log_src_cap,
+                     log_dst, log_dst_cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const double* src, double* dst, size_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t* p, int32_t v, size_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_terminal_adjoint(const Params& P, const double* U, const double* ke0, double* lam, hipStream_t s) {
+  hipLaunchKernelGGL(k_terminal_adjoint, cells_grid(P, (size_t)P.nx * P.ny), dim3(256), 0, s, P, U, ke0, lam);
+  return hipGetLastError();
+}
+
+hipError_t launch_initial_adjoint(const Params& P, const double* uv0, const double* lam0, const double* ke0,
+                                  const double* keN, double* R, double* grad, hipStream_t s) {
+  hipLaunchKernelGGL(k_initial_adjoint, cells_grid(P, (size_t)P.nx * P.ny), dim3(256), 0, s, P, uv0, lam0, ke0,
+                     keN, R, grad);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_project(const Params& P, double* uv, const double* m, double delta, int norm, int set,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_project, cells_grid(P, (size_t)P.nx * P.ny), dim3(256), 0, s, P, uv, m, delta, norm,
+                     set);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy(const Params& P, const double* x, const double* alpha, const double* y, double* out,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_axpy, cells_grid(P, (size_t)2 * P.nx * P.ny), dim3(256), 0, s, P, x, alpha, y, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_ratio(int nb, const double* num, const double* den, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_ratio, dim3((nb + 63) / 64), dim3(64), 0, s, nb, num, den, out);
+  return hipGetLastError();
+}
+
+}  // namespace rtk

@@ -1,0 +1,321 @@
+"""Thin Python binding of ``librtcnop.so`` (the C ABI of include/rtcnop.h).
+
+Argument marshalling only: torch supplies device memory and the stream, and
+every step of the hot path runs in the library's HIP kernels.  There is no
+CPU fallback: :func:`load` raises if the library is missing, and every call
+raises :class:`RTError` on a non-zero status.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+from .config import (CKPT_REVOLVE, CKPT_STORE_ALL, CKPT_UNIFORM, NORM_L2, SET_SPHERE, RTConfig)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librtcnop.so")
+
+STATUS = {0: "RT_OK", -1: "RT_EINVAL", -2: "RT_EHIP", -3: "RT_ENOMEM", -4: "RT_EUNPHYS", -5: "RT_ESTATE"}
+TILES = {"16x16": 0, "32x8": 1, "64x4": 2}
+
+
+class RTError(RuntimeError):
+    def __init__(self, code: int, call: str, msg: str):
+        super().__init__(f"{call}: {STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class RtGrid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("batch", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("lx", ctypes.c_double), ("ly", ctypes.c_double)]
+
+
+class RtPhys(ctypes.Structure):
+    _fields_ = [("gamma", ctypes.c_double), ("g_y", ctypes.c_double), ("rho_h", ctypes.c_double),
+                ("rho_l", ctypes.c_double), ("y0", ctypes.c_double), ("h", ctypes.c_double),
+                ("p_int", ctypes.c_double), ("cfl", ctypes.c_double), ("comp_mask", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class RtCkptPolicy(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("interval", ctypes.c_int32), ("pool", ctypes.c_void_p),
+                ("pool_bytes", ctypes.c_size_t)]
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+
+
+def load():
+    """Load the HIP library (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2608_04085_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "rt_create": [ctypes.POINTER(RtGrid), ctypes.POINTER(RtPhys), _vp, ctypes.POINTER(_vp)],
+        "rt_destroy": [_vp],
+        "rt_set_stream": [_vp, _vp],
+        "rt_set_tile": [_vp, _i32],
+        "rt_get_tile": [_vp, ctypes.POINTER(_i32)],
+        "rt_workspace_bytes": [_vp, _i32, ctypes.POINTER(ctypes.c_size_t)],
+        "rt_set_workspace": [_vp, _vp, ctypes.c_size_t, _i32],
+        "rt_init_state": [_vp, _vp, _vp],
+        "rt_cfl_dt": [_vp, _vp, _vp],
+        "rt_step": [_vp, _vp, _vp, _vp, _vp],
+        "rt_integrate": [_vp, _vp, ctypes.c_double, _vp, _vp, _vp, _i32],
+        "rt_kinetic_energy": [_vp, _vp, _vp],
+        "rt_step_adjoint": [_vp, _vp, _vp, _vp, _vp],
+        "rt_grad_u0": [_vp, _vp, ctypes.c_double, ctypes.POINTER(RtCkptPolicy), _vp, _vp, _vp],
+        "rt_pool_bytes": [_vp, _i32, _i32, _i32, ctypes.POINTER(ctypes.c_size_t)],
+        "rt_project_to_constraint": [_vp, _vp, ctypes.c_double, _i32, _i32, _vp],
+        "rt_dot": [_vp, _vp, _vp, _vp],
+        "rt_axpy": [_vp, _vp, _vp, _vp, _vp],
+        "rt_check_error": [_vp],
+        "rt_revolve_stats": [_i32, _i32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    L.rt_last_error.argtypes = []
+    L.rt_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+EXPORTED = ["rt_create", "rt_destroy", "rt_set_stream", "rt_workspace_bytes", "rt_set_workspace",
+            "rt_init_state", "rt_cfl_dt", "rt_step", "rt_integrate", "rt_kinetic_energy", "rt_step_adjoint",
+            "rt_grad_u0", "rt_pool_bytes", "rt_project_to_constraint", "rt_dot", "rt_axpy", "rt_check_error",
+            "rt_last_error"]
+
+
+def _check(rc: int, call: str):
+    if rc != 0:
+        msg = load().rt_last_error()
+        raise RTError(rc, call, msg.decode() if msg else "")
+
+
+def _ptr(t: torch.Tensor | None):
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous CUDA/HIP tensors"
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def revolve_stats(nsteps: int, slots: int):
+    """(forward steps of the library's binomial schedule, the closed-form
+    minimum) for reversing `nsteps` steps with `slots` checkpoint slots; the
+    call also checks the schedule's consistency (host only, no GPU)."""
+    fw = ctypes.c_int64()
+    opt = ctypes.c_int64()
+    _check(load().rt_revolve_stats(nsteps, slots, ctypes.byref(fw), ctypes.byref(opt)), "rt_revolve_stats")
+    return fw.value, opt.value
+
+
+@dataclass
+class Policy:
+    kind: int = CKPT_UNIFORM
+    interval: int = 32
+    pool_bytes: int | None = None  # None: what the policy needs for max_steps
+
+
+class Context:
+    """One grid / physics / stream; owns its workspace tensor."""
+
+    def __init__(self, cfg: RTConfig, max_steps: int = 65536, device: str | int = "cuda", tile: str | None = None):
+        self.cfg = cfg
+        self.device = torch.device(device)
+        self.max_steps = int(max_steps)
+        L = load()
+        grid = RtGrid(cfg.nx, cfg.ny, cfg.batch, 0, cfg.lx, cfg.ly)
+        phys = RtPhys(cfg.gamma, cfg.g_y, cfg.rho_h, cfg.rho_l, cfg.y0, cfg.h, cfg.p_int, cfg.cfl, cfg.comp_mask, 0)
+        h = ctypes.c_void_p()
+        _check(L.rt_create(ctypes.byref(grid), ctypes.byref(phys), self._stream(), ctypes.byref(h)), "rt_create")
+        self._h = h
+        if tile is not None:
+            _check(L.rt_set_tile(h, TILES[tile]), "rt_set_tile")
+        n = ctypes.c_size_t()
+        _check(L.rt_workspace_bytes(h, self.max_steps, ctypes.byref(n)), "rt_workspace_bytes")
+        self.ws = torch.empty(n.value + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.ws.data_ptr()) % 256
+        self._ws_ptr = ctypes.c_void_p(self.ws.data_ptr() + off)
+        _check(L.rt_set_workspace(h, self._ws_ptr, n.value, self.max_steps), "rt_set_workspace")
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None) is not None and _lib is not None:
+                _lib.rt_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+    def _stream(self):
+        if not torch.cuda.is_available():
+            return None
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def _sync_stream(self):
+        _check(load().rt_set_stream(self._h, self._stream()), "rt_set_stream")
+
+    # ---------------------------------------------------------------- shapes
+    @property
+    def shape_u(self):
+        return (self.cfg.batch, 4, self.cfg.ny, self.cfg.nx)
+
+    @property
+    def shape_uv(self):
+        return (self.cfg.batch, 2, self.cfg.ny, self.cfg.nx)
+
+    def _f64(self, shape):
+        return torch.empty(shape, dtype=torch.float64, device=self.device)
+
+    def as_dev(self, a) -> torch.Tensor:
+        if isinstance(a, torch.Tensor):
+            return a.to(device=self.device, dtype=torch.float64).contiguous()
+        return torch.as_tensor(a, dtype=torch.float64, device=self.device).contiguous()
+
+    @property
+    def tile(self) -> str:
+        t = ctypes.c_int32()
+        _check(load().rt_get_tile(self._h, ctypes.byref(t)), "rt_get_tile")
+        return {v: k for k, v in TILES.items()}[t.value]
+
+    def set_tile(self, name: str):
+        _check(load().rt_set_tile(self._h, TILES[name]), "rt_set_tile")
+
+    # ---------------------------------------------------------------- calls
+    def init_state(self, uv0) -> torch.Tensor:
+        self._sync_stream()
+        uv0 = self.as_dev(uv0).reshape(self.shape_uv)
+        U = self._f64(self.shape_u)
+        _check(load().rt_init_state(self._h, _ptr(uv0), _ptr(U)), "rt_init_state")
+        return U
+
+    def cfl_dt(self, U) -> torch.Tensor:
+        self._sync_stream()
+        U = self.as_dev(U)
+        dt = self._f64((self.cfg.batch,))
+        _check(load().rt_cfl_dt(self._h, _ptr(U), _ptr(dt)), "rt_cfl_dt")
+        return dt
+
+    def step(self, U, dt=None, want_next: bool = False):
+        self._sync_stream()
+        U = self.as_dev(U)
+        Un = torch.empty_like(U)
+        dtp = None
+        if dt is not None:
+            dtp = self.as_dev(torch.as_tensor(dt, dtype=torch.float64).expand(self.cfg.batch).clone())
+        nxt = self._f64((self.cfg.batch,)) if want_next else None
+        _check(load().rt_step(self._h, _ptr(U), _ptr(Un), _ptr(dtp), _ptr(nxt)), "rt_step")
+        return (Un, nxt) if want_next else Un
+
+    def integrate(self, U, T: float, log_cap: int = 0):
+        """(U(T), t, nsteps, dt_log or None); U is not modified."""
+        self._sync_stream()
+        U = self.as_dev(U).clone()
+        t = self._f64((self.cfg.batch,))
+        n = torch.empty((self.cfg.batch,), dtype=torch.int32, device=self.device)
+        log = self._f64((self.cfg.batch, log_cap)) if log_cap > 0 else None
+        _check(load().rt_integrate(self._h, _ptr(U), float(T), _ptr(t), _ptr(n), _ptr(log), int(log_cap)),
+               "rt_integrate")
+        return U, t, n, log
+
+    def kinetic_energy(self, U) -> torch.Tensor:
+        self._sync_stream()
+        U = self.as_dev(U)
+        ke = self._f64((self.cfg.batch,))
+        _check(load().rt_kinetic_energy(self._h, _ptr(U), _ptr(ke)), "rt_kinetic_energy")
+        return ke
+
+    def step_adjoint(self, U, dt, lam_next) -> torch.Tensor:
+        self._sync_stream()
+        U = self.as_dev(U)
+        lam_next = self.as_dev(lam_next)
+        dtp = self.as_dev(torch.as_tensor(dt, dtype=torch.float64).expand(self.cfg.batch).clone())
+        lam = torch.empty_like(lam_next)
+        _check(load().rt_step_adjoint(self._h, _ptr(U), _ptr(dtp), _ptr(lam_next), _ptr(lam)), "rt_step_adjoint")
+        return lam
+
+    def pool_bytes(self, kind: int, interval: int, nsteps_max: int) -> int:
+        n = ctypes.c_size_t()
+        _check(load().rt_pool_bytes(self._h, kind, interval, nsteps_max, ctypes.byref(n)), "rt_pool_bytes")
+        return n.value
+
+    def grad_u0(self, uv0, T: float, policy: Policy | None = None, pool: torch.Tensor | None = None):
+        """(R[B], grad[B][2][ny][nx], nsteps[B]) on the device."""
+        self._sync_stream()
+        policy = policy or Policy()
+        uv0 = self.as_dev(uv0).reshape(self.shape_uv)
+        if pool is None:
+            nbytes = policy.pool_bytes or self.pool_bytes(policy.kind, policy.interval, self.max_steps)
+            pool = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-pool.data_ptr()) % 256
+        pol = RtCkptPolicy(policy.kind, policy.interval, ctypes.c_void_p(pool.data_ptr() + off),
+                           pool.numel() - off)
+        R = self._f64((self.cfg.batch,))
+        g = self._f64(self.shape_uv)
+        n = torch.empty((self.cfg.batch,), dtype=torch.int32, device=self.device)
+        _check(load().rt_grad_u0(self._h, _ptr(uv0), float(T), ctypes.byref(pol), _ptr(R), _ptr(g), _ptr(n)),
+               "rt_grad_u0")
+        return R, g, n
+
+    def project_to_constraint(self, uv, delta: float, norm: int = NORM_L2, kind: int = SET_SPHERE):
+        """In-place on a copy: returns (projected uv, norm before scaling)."""
+        self._sync_stream()
+        uv = self.as_dev(uv).reshape(self.shape_uv).clone()
+        m = self._f64((self.cfg.batch,))
+        _check(load().rt_project_to_constraint(self._h, _ptr(uv), float(delta), int(norm), int(kind), _ptr(m)),
+               "rt_project_to_constraint")
+        return uv, m
+
+    def dot(self, a, b) -> torch.Tensor:
+        self._sync_stream()
+        a = self.as_dev(a)
+        b = self.as_dev(b)
+        out = self._f64((self.cfg.batch,))
+        _check(load().rt_dot(self._h, _ptr(a), _ptr(b), _ptr(out)), "rt_dot")
+        return out
+
+    def axpy(self, x, alpha, y) -> torch.Tensor:
+        self._sync_stream()
+        x = self.as_dev(x)
+        y = self.as_dev(y)
+        al = self.as_dev(torch.as_tensor(alpha, dtype=torch.float64).expand(self.cfg.batch).clone())
+        out = torch.empty_like(x)
+        _check(load().rt_axpy(self._h, _ptr(x), _ptr(al), _ptr(y), _ptr(out)), "rt_axpy")
+        return out
+
+    def check_error(self):
+        _check(load().rt_check_error(self._h), "rt_check_error")
+
+
+class KERatio(torch.autograd.Function):
+    """R = KE(U(T)) / KE(U(0)) as a differentiable function of the initial
+    velocity perturbation; backward runs the library's discrete adjoint."""
+
+    @staticmethod
+    def forward(fctx, uv0: torch.Tensor, rt: Context, T: float, policy: Policy | None = None):
+        U0 = rt.init_state(uv0)
+        ke0 = rt.kinetic_energy(U0)
+        UT, _, _, _ = rt.integrate(U0, T)
+        keT = rt.kinetic_energy(UT)
+        fctx.save_for_backward(uv0)
+        fctx.rt, fctx.T, fctx.policy = rt, T, policy
+        return keT / ke0
+
+    @staticmethod
+    def backward(fctx, gout):
+        (uv0,) = fctx.saved_tensors
+        _, g, _ = fctx.rt.grad_u0(uv0, fctx.T, fctx.policy)
+        return g * gout.reshape(-1, 1, 1, 1), None, None, None
+
+
+__all__ = ["Context", "Policy", "KERatio", "RTError", "load", "revolve_stats", "EXPORTED",
+           "CKPT_STORE_ALL", "CKPT_UNIFORM", "CKPT_REVOLVE"]

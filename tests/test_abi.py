@@ -1,0 +1,77 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every call that
+include/rtcnop.h declares, rejects bad arguments without touching a GPU, and
+its binomial checkpoint schedule is optimal (against a brute-force dynamic
+program) and consistent."""
+import ctypes
+import functools
+import os
+import re
+
+import pytest
+
+from paper_2608_04085_amd import rtcnop
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "rtcnop.h")).read()
+    return sorted(set(re.findall(r"\b(rt_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_calls_are_exported():
+    L = rtcnop.load()
+    names = _declared()
+    assert "rt_grad_u0" in names and "rt_integrate" in names
+    for n in names:
+        assert hasattr(L, n), n
+    for n in rtcnop.EXPORTED:
+        assert n in names, n
+
+
+def test_create_rejects_bad_grid_without_gpu():
+    L = rtcnop.load()
+    h = ctypes.c_void_p()
+    g = rtcnop.RtGrid(2, 8, 1, 0, 0.5, 1.0)
+    p = rtcnop.RtPhys(1.4, -0.1, 2.0, 1.0, 0.5, 0.01, 2.5, 0.4, 3, 0)
+    assert L.rt_create(ctypes.byref(g), ctypes.byref(p), None, ctypes.byref(h)) == -1
+    assert b"grid" in L.rt_last_error()
+    g = rtcnop.RtGrid(8, 8, 1, 0, 0.5, 1.0)
+    p.gamma = 1.0
+    assert L.rt_create(ctypes.byref(g), ctypes.byref(p), None, ctypes.byref(h)) == -1
+    p.gamma = 1.4
+    assert L.rt_create(ctypes.byref(g), ctypes.byref(p), None, ctypes.byref(h)) == 0
+    # calls that need a workspace refuse to run without one
+    assert L.rt_kinetic_energy(h, ctypes.c_void_p(8), ctypes.c_void_p(8)) == -5
+    n = ctypes.c_size_t()
+    assert L.rt_workspace_bytes(h, 100, ctypes.byref(n)) == 0 and n.value > 8 * 8 * 4 * 8 * 4
+    assert L.rt_destroy(h) == 0
+
+
+@functools.lru_cache(maxsize=None)
+def _dp(l, c):
+    # Brute force over recursive schedules: advance m steps, snapshot, reverse
+    # the right part with one slot fewer, then the left part.
+    if l <= 1:
+        return 0
+    if c <= 1:
+        return l * (l - 1) // 2
+    return min(m + _dp(l - m, c - 1) + _dp(m, c) for m in range(1, l))
+
+
+@pytest.mark.parametrize("c", [1, 2, 3, 4, 5, 6])
+def test_revolve_is_optimal_against_brute_force(c):
+    for l in range(1, 41):
+        fw, opt = rtcnop.revolve_stats(l, c)
+        assert opt == _dp(l, c), (l, c)
+        assert fw == opt, (l, c, fw, opt)
+
+
+def test_revolve_large_schedules_are_consistent():
+    # the march lengths of the benchmark workloads
+    for l, c in [(1210, 8), (4838, 119), (19350, 119), (29024, 953), (5000, 2)]:
+        fw, opt = rtcnop.revolve_stats(l, c)
+        assert fw == opt
+    # with as many slots as steps nothing is recomputed beyond one pass
+    fw, _ = rtcnop.revolve_stats(100, 100)
+    assert fw == 99

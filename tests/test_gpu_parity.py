@@ -1,0 +1,254 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs, plus the bitwise invariants of the GPU path itself.
+
+Tolerances (normwise per field, max|a-b| / max|b|): state after 100 steps
+1e-10, KE ratio at T = 2 1e-8, gradient 1e-9 (against the oracle adjoint),
+finite differences 1e-5.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle.rto import Oracle
+from paper_2608_04085_amd import inputs
+from paper_2608_04085_amd.config import (CKPT_REVOLVE, CKPT_STORE_ALL, CKPT_UNIFORM, NORM_L2, NORM_RHO_KE,
+                                         NORM_RMS, SET_BALL, SET_SPHERE, RTConfig)
+
+pytestmark = pytest.mark.gpu
+
+
+def rt():
+    from paper_2608_04085_amd import rtcnop
+    return rtcnop
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def normwise(a, b, axis_field=1):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    errs = []
+    for k in range(a.shape[axis_field]):
+        x = np.take(a, k, axis=axis_field)
+        y = np.take(b, k, axis=axis_field)
+        errs.append(np.max(np.abs(x - y)) / max(np.max(np.abs(y)), 1e-300))
+    return max(errs)
+
+
+CASES = [
+    RTConfig(nx=64, ny=128),           # forward workload grid
+    RTConfig(nx=70, ny=37),            # ragged in x and y for every tile shape
+    RTConfig(nx=5, ny=9),              # smaller than one tile, wrap-around halo
+    RTConfig(nx=48, ny=40, batch=3),   # batched
+]
+
+
+@pytest.mark.parametrize("cfg", CASES, ids=lambda c: f"{c.nx}x{c.ny}x{c.batch}")
+def test_init_and_cfl_match_oracle(cfg):
+    r = rt().Context(cfg, max_steps=64)
+    o = Oracle.from_config(cfg)
+    uv = inputs.seed_batch(cfg, range(cfg.batch), rms=1e-3)
+    U = r.init_state(uv)
+    Uo = o.init_state(uv)
+    assert normwise(host(U), Uo) <= 1e-14
+    dt = host(r.cfl_dt(U))
+    np.testing.assert_allclose(dt, o.cfl_dt(Uo), rtol=1e-14)
+    ke = host(r.kinetic_energy(U))
+    np.testing.assert_allclose(ke, o.kinetic_energy(Uo), rtol=1e-13)
+
+
+@pytest.mark.parametrize("tile", ["16x16", "32x8", "64x4"])
+@pytest.mark.parametrize("cfg", CASES, ids=lambda c: f"{c.nx}x{c.ny}x{c.batch}")
+def test_one_step_matches_oracle(cfg, tile):
+    r = rt().Context(cfg, max_steps=64, tile=tile)
+    o = Oracle.from_config(cfg)
+    Uo = o.init_state(inputs.seed_batch(cfg, range(cfg.batch), rms=3e-2))
+    for _ in range(3):
+        Uo = o.step(Uo, o.cfl_dt(Uo))
+    dt = o.cfl_dt(Uo)
+    Un, nxt = r.step(torch.from_numpy(Uo), torch.from_numpy(dt), want_next=True)
+    Uno = o.step(Uo, dt)
+    assert normwise(host(Un), Uno) <= 1e-13
+    np.testing.assert_allclose(host(nxt), o.cfl_dt(Uno), rtol=1e-13)
+
+
+def test_hundred_steps_match_oracle_at_256x512():
+    # the gradient workload's grid, launch configuration of the benchmark
+    cfg = RTConfig(nx=256, ny=512)
+    r = rt().Context(cfg, max_steps=256)
+    o = Oracle.from_config(cfg)
+    uv = inputs.seed_batch(cfg, [0], rms=1e-3)
+    Uo = o.init_state(uv)
+    U = r.init_state(uv)
+    for _ in range(100):
+        dto = o.cfl_dt(Uo)
+        Uo = o.step(Uo, dto)
+        U = r.step(U)
+    assert normwise(host(U), Uo) <= 1e-10
+
+
+def test_integrate_to_T2_matches_oracle_at_64x128():
+    cfg = RTConfig(nx=64, ny=128)
+    r = rt().Context(cfg, max_steps=4096)
+    o = Oracle.from_config(cfg)
+    uv = inputs.seed_batch(cfg, [0], rms=1e-3)
+    U0 = r.init_state(uv)
+    UT, t, n, log = r.integrate(U0, 2.0, log_cap=4096)
+    Uo0 = o.init_state(uv)
+    UoT, to, no, logo = o.integrate(Uo0, 2.0, cap=4096)
+    assert int(host(n)[0]) == int(no[0])
+    assert host(t)[0] == 2.0
+    np.testing.assert_allclose(host(log)[0, : no[0]], logo[0, : no[0]], rtol=1e-10)
+    R = host(r.kinetic_energy(UT)) / host(r.kinetic_energy(U0))
+    Ro = o.kinetic_energy(UoT) / o.kinetic_energy(Uo0)
+    assert abs(R[0] - Ro[0]) / abs(Ro[0]) <= 1e-8
+
+
+def test_tile_shapes_are_bitwise_identical():
+    cfg = RTConfig(nx=70, ny=45, batch=2)
+    uv = inputs.seed_batch(cfg, [1, 2], rms=1e-2)
+    outs, adjs = [], []
+    lam = torch.from_numpy(np.random.default_rng(5).standard_normal((2, 4, 45, 70)))
+    for tile in ["16x16", "32x8", "64x4"]:
+        r = rt().Context(cfg, max_steps=512, tile=tile)
+        U, _, n, _ = r.integrate(r.init_state(uv), 0.2)
+        outs.append(host(U))
+        adjs.append(host(r.step_adjoint(U, 1e-3, lam)))
+    for k in range(1, 3):
+        np.testing.assert_array_equal(outs[k], outs[0])
+        np.testing.assert_array_equal(adjs[k], adjs[0])
+
+
+def test_batch_member_equals_solo_run_bitwise():
+    cfg = RTConfig(nx=64, ny=96, batch=4)
+    uv = inputs.seed_batch(cfg, [0, 1, 2, 3], rms=1e-3)
+    r = rt().Context(cfg, max_steps=4096)
+    U, t, n, _ = r.integrate(r.init_state(uv), 0.5)
+    solo = rt().Context(cfg.with_(batch=1), max_steps=4096)
+    for b in [0, 3]:
+        Us, ts, ns, _ = solo.integrate(solo.init_state(uv[b : b + 1]), 0.5)
+        np.testing.assert_array_equal(host(Us)[0], host(U)[b])
+        assert int(host(ns)[0]) == int(host(n)[b])
+
+
+def test_periodic_shift_equivariance_bitwise():
+    cfg = RTConfig(nx=64, ny=64)
+    uv = inputs.seed_batch(cfg, [3], rms=1e-2)
+    r = rt().Context(cfg, max_steps=4096)
+    U0 = r.init_state(uv)
+    A, _, _, _ = r.integrate(U0, 0.3)
+    B, _, _, _ = r.integrate(torch.roll(U0, 13, dims=3), 0.3)
+    np.testing.assert_array_equal(np.roll(host(A), 13, axis=3), host(B))
+
+
+@pytest.mark.parametrize("cfg", [RTConfig(nx=32, ny=48), RTConfig(nx=21, ny=19, batch=2)],
+                         ids=lambda c: f"{c.nx}x{c.ny}x{c.batch}")
+def test_step_adjoint_matches_oracle(cfg):
+    o = Oracle.from_config(cfg)
+    Uo = o.init_state(inputs.seed_batch(cfg, range(cfg.batch), rms=3e-2))
+    for _ in range(3):
+        Uo = o.step(Uo, o.cfl_dt(Uo))
+    dt = o.cfl_dt(Uo)
+    lam_next = np.random.default_rng(7).standard_normal(Uo.shape)
+    ref = o.step_vjp(Uo, dt, lam_next)
+    for tile in ["16x16", "64x4"]:
+        r = rt().Context(cfg, max_steps=64, tile=tile)
+        lam = r.step_adjoint(torch.from_numpy(Uo), torch.from_numpy(dt), torch.from_numpy(lam_next))
+        assert normwise(host(lam), ref) <= 1e-12
+
+
+@pytest.mark.parametrize("cfg,T", [(RTConfig(nx=32, ny=64), 0.1), (RTConfig(nx=24, ny=30, batch=2), 0.08)],
+                         ids=["32x64", "24x30x2"])
+def test_gradient_matches_oracle_and_policies_agree_bitwise(cfg, T):
+    o = Oracle.from_config(cfg)
+    uv = inputs.seed_batch(cfg, range(cfg.batch), rms=1e-3)
+    Ro, go, no, _ = o.grad_u0(uv, T)
+    r = rt().Context(cfg, max_steps=1024)
+    results = []
+    for pol in [rt().Policy(CKPT_STORE_ALL, 1), rt().Policy(CKPT_UNIFORM, 7), rt().Policy(CKPT_UNIFORM, 32),
+                rt().Policy(CKPT_REVOLVE, 1, pool_bytes=3 * 8 * 4 * cfg.cells * cfg.batch)]:
+        R, g, n = r.grad_u0(uv, T, pol)
+        results.append((host(R), host(g), host(n)))
+    R, g, n = results[0]
+    np.testing.assert_array_equal(n, no)
+    np.testing.assert_allclose(R, Ro, rtol=1e-12)
+    assert normwise(g, go) <= 1e-9
+    for Rk, gk, nk in results[1:]:
+        np.testing.assert_array_equal(gk, g)
+        np.testing.assert_array_equal(Rk, R)
+
+
+def test_gradient_matches_finite_differences_on_gpu():
+    # central differences of the frozen-schedule march, GPU only
+    cfg = RTConfig(nx=64, ny=128)
+    T = 0.3
+    r = rt().Context(cfg, max_steps=4096)
+    uv = inputs.seed_batch(cfg, [0], rms=1e-3)
+    R, g, n = r.grad_u0(uv, T, rt().Policy(CKPT_UNIFORM, 32))
+    _, _, n2, log = r.integrate(r.init_state(uv), T, log_cap=4096)
+    steps = int(host(n2)[0])
+    logt = log[:, :steps].clone()
+
+    def frozen(u):
+        U = r.init_state(u)
+        ke0 = r.kinetic_energy(U)
+        for k in range(steps):
+            U = r.step(U, logt[:, k])
+        return float(host(r.kinetic_energy(U) / ke0)[0])
+
+    assert frozen(uv) == float(host(R)[0])
+    delta = float(np.sqrt(np.sum(uv * uv) * cfg.dx * cfg.dy))
+    gh = host(g)
+    for s in range(1000, 1004):
+        d = inputs.direction_batch(cfg, [s], delta)
+        an = float(np.sum(gh * d))
+        errs = []
+        for h in (1e-5, 1e-6):
+            fd = (frozen(uv + h * d) - frozen(uv - h * d)) / (2 * h)
+            errs.append(abs(fd - an) / abs(an))
+        assert min(errs) <= 1e-5, (s, errs)
+
+
+def test_projection_dot_axpy_match_oracle():
+    cfg = RTConfig(nx=40, ny=50, batch=2)
+    o = Oracle.from_config(cfg)
+    r = rt().Context(cfg, max_steps=16)
+    uv = inputs.seed_batch(cfg, [4, 5], rms=1.0)
+    for norm in (NORM_L2, NORM_RMS, NORM_RHO_KE):
+        for kind in (SET_SPHERE, SET_BALL):
+            delta = 1e-6 if norm == NORM_RHO_KE else 1e-3
+            out, m = r.project_to_constraint(uv, delta, norm, kind)
+            outo, mo = o.project_to_constraint(uv, delta, norm, kind)
+            np.testing.assert_allclose(host(m), mo, rtol=1e-13)
+            assert normwise(host(out), outo) <= 1e-14
+    d = host(r.dot(uv, uv[::-1].copy()))
+    np.testing.assert_allclose(d, np.sum(uv * uv[::-1], axis=(1, 2, 3)), rtol=1e-13)
+    z = host(r.axpy(uv, np.array([0.5, -2.0]), uv))
+    np.testing.assert_allclose(z, uv * np.array([1.5, -1.0])[:, None, None, None], rtol=1e-15)
+
+
+def test_unphysical_state_is_reported():
+    cfg = RTConfig(nx=32, ny=32)
+    r = rt().Context(cfg, max_steps=64)
+    U = r.init_state(inputs.seed_batch(cfg, [0]))
+    U[0, 3, 10, 10] = -1.0  # negative energy -> negative pressure, forced from the host
+    with pytest.raises(rt().RTError) as e:
+        r.integrate(U, 0.01)
+    assert e.value.code == -4
+    # the context stays usable
+    U = r.init_state(inputs.seed_batch(cfg, [0]))
+    r.integrate(U, 0.01)
+
+
+def test_pool_too_small_and_zero_perturbation_are_rejected():
+    cfg = RTConfig(nx=32, ny=32)
+    r = rt().Context(cfg, max_steps=4096)
+    uv = inputs.seed_batch(cfg, [0])
+    with pytest.raises(rt().RTError) as e:
+        r.grad_u0(uv, 0.5, rt().Policy(CKPT_STORE_ALL, 1, pool_bytes=10 * 8 * 4 * cfg.cells))
+    assert e.value.code == -3
+    with pytest.raises(rt().RTError) as e:
+        r.grad_u0(np.zeros_like(uv), 0.1)
+    assert e.value.code == -1

@@ -1,0 +1,228 @@
+"""Benchmark of the CNOP hot path on one MI355X.
+
+One step = one projected-gradient iteration of the CNOP search on the
+gradient workload (256 x 512 FP64 cells, T = 2, about 4.8k CFL steps, a
+snapshot every 32 steps with re-computation in between):
+    u+ = P(u + alpha g)                   (constraint projection, Eq. 11)
+    R, g+ = KE ratio and its gradient     (init_state, CFL march with
+                                           snapshots, kinetic energy, adjoint
+                                           sweep, initial adjoint)
+    alpha = <s,s>/|<s,y>|                 (dot products for the next step)
+All of it runs in the library's HIP kernels; torch provides memory and the
+stream.  Inputs are seeded synthetic velocity fields (envelope-masked
+Gaussian noise); the paper uses no dataset.
+
+value = (forward + adjoint) cell-updates per second of the whole iteration:
+2 * N_t * nx * ny / (seconds per iteration).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "FP64 cell-updates/s (fwd, adjoint) and CNOP grad iters/s vs FD-gradient, % HBM"
+HBM_PEAK_GBS = 8000.0
+FWD_BYTES_PER_CELL = 64.0   # read U^n, write U^{n+1}
+ADJ_BYTES_PER_CELL = 96.0   # read U^n and lambda^{n+1}, write lambda^n
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--nx", type=int, default=256)
+    ap.add_argument("--ny", type=int, default=512)
+    ap.add_argument("--T", type=float, default=2.0)
+    ap.add_argument("--interval", type=int, default=32)
+    ap.add_argument("--tile", default=None)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--kernel-launches", type=int, default=300)
+    return ap.parse_args()
+
+
+def time_kernel(fn, n, stream):
+    """Average duration of fn() (one library call) over n calls, HIP events
+    recorded on the stream the library launches on."""
+    import torch
+
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(n)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(n)]
+    for k in range(n):
+        starts[k].record(stream)
+        fn()
+        ends[k].record(stream)
+    torch.cuda.synchronize()
+    ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
+    return float(np.mean(ms)) * 1e-3, float(np.median(ms)) * 1e-3
+
+
+def cpu_baseline(cfg, T, seconds):
+    """The oracle as it stands (single-threaded C++), timed on a bounded
+    sample of the same workload: forward steps and reverse-mode adjoint steps
+    on the same grid from the same seed."""
+    from oracle.rto import Oracle
+    from paper_2608_04085_amd import inputs
+
+    o = Oracle.from_config(cfg)
+    U = o.init_state(inputs.seed_batch(cfg, [0], rms=1e-3))
+    cells = cfg.nx * cfg.ny
+    t0 = time.perf_counter()
+    nf = 0
+    while time.perf_counter() - t0 < 0.6 * seconds:
+        U = o.step(U, o.cfl_dt(U))
+        nf += 1
+    tf = (time.perf_counter() - t0) / (nf * cells)
+    lam = np.ones_like(U) * 1e-3
+    t1 = time.perf_counter()
+    na = 0
+    dt = o.cfl_dt(U)
+    while time.perf_counter() - t1 < 0.4 * seconds or na == 0:
+        lam = o.step_vjp(U, dt, lam)
+        na += 1
+    ta = (time.perf_counter() - t1) / (na * cells)
+    return {
+        "value": 2.0 / (tf + ta),
+        "unit": "cell-updates/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"{nf} forward steps + {na} adjoint steps of the {cfg.nx}x{cfg.ny} grid from the same seed; "
+                  f"value = 2/(t_fwd + t_adj) per cell (forward {1.0 / tf:.3e}, adjoint {1.0 / ta:.3e} cell-updates/s)",
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the independent members of a "
+              f"batch shard across GPUs without communication, see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2608_04085_amd import inputs
+    from paper_2608_04085_amd.config import CKPT_UNIFORM, NORM_L2, SET_SPHERE, RTConfig
+    from paper_2608_04085_amd.rtcnop import Context, Policy
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    cfg = RTConfig(nx=args.nx, ny=args.ny)
+    T = args.T
+    ctx = Context(cfg, max_steps=16384, tile=args.tile)
+    stream = torch.cuda.current_stream()
+    cells = cfg.nx * cfg.ny
+
+    # seed and step count
+    u = torch.from_numpy(inputs.seed_batch(cfg, [0], rms=1e-3)).cuda()
+    delta = float(math.sqrt(float((u * u).sum()) * cfg.dx * cfg.dy))
+    U0 = ctx.init_state(u)
+    _, _, n, log = ctx.integrate(U0, T, log_cap=16384)
+    nt = int(n.item())
+    pol = Policy(CKPT_UNIFORM, args.interval)
+    pool = torch.empty(ctx.pool_bytes(CKPT_UNIFORM, args.interval, nt + 64) + 256, dtype=torch.uint8, device="cuda")
+    R, g, _ = ctx.grad_u0(u, T, pol, pool=pool)
+    alpha = 0.1 * delta / float(g.norm() * math.sqrt(cfg.dx * cfg.dy))
+
+    def iteration(u, g, alpha):
+        ut = ctx.axpy(u, alpha, g)
+        ut, _ = ctx.project_to_constraint(ut, delta, NORM_L2, SET_SPHERE)
+        R, gt, n = ctx.grad_u0(ut, T, pol, pool=pool)
+        s = ctx.axpy(ut, -1.0, u)
+        y = ctx.axpy(gt, -1.0, g)
+        ss, sy = ctx.dot(s, s), ctx.dot(s, y)
+        a = float(ss.item()) / max(abs(float(sy.item())), 1e-300)
+        return ut, gt, min(max(a, 1e-10 * alpha), 1e10 * alpha), R, n
+
+    for _ in range(args.warmup):
+        u, g, alpha, R, n = iteration(u, g, alpha)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nsteps_total = 0
+    for _ in range(args.steps):
+        u, g, alpha, R, n = iteration(u, g, alpha)
+        nsteps_total += int(n.item())
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    per_iter = elapsed / args.steps
+    nt_mean = nsteps_total / args.steps
+    value = 2.0 * nt_mean * cells / per_iter
+
+    # forward-only march (adaptive CFL, one launch per step, no snapshots)
+    torch.cuda.synchronize()
+    tf0 = time.perf_counter()
+    _, _, nf, _ = ctx.integrate(U0, T)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - tf0
+    fwd_rate = int(nf.item()) * cells / t_fwd
+
+    # per-kernel durations with HIP events on the library's stream
+    Uk = ctx.integrate(U0, 0.5)[0]
+    dtk = ctx.cfl_dt(Uk)
+    Un = torch.empty_like(Uk)
+    lam = torch.randn_like(Uk) * 1e-3
+    t_step, t_step_med = time_kernel(lambda: ctx.step(Uk, dtk), args.kernel_launches, stream)
+    t_adj, t_adj_med = time_kernel(lambda: ctx.step_adjoint(Uk, dtk, lam), args.kernel_launches, stream)
+    # forward launches per iteration ~ nt (march) + nt*(interval-1)/interval
+    # (re-computation); adjoint launches (pairs) nt
+    fw_share = t_step * nt_mean * (2 - 1.0 / args.interval)
+    adj_share = t_adj * nt_mean
+    if adj_share >= fw_share:
+        dom = {"kernel": "adjoint step (k_adj_a + k_adj_b)", "bytes_per_cell": ADJ_BYTES_PER_CELL, "t": t_adj}
+    else:
+        dom = {"kernel": "fused forward step (k_step)", "bytes_per_cell": FWD_BYTES_PER_CELL, "t": t_step}
+    achieved = dom["bytes_per_cell"] * cells / dom["t"] / 1e9
+    roofline = {
+        "bound": "hbm",
+        "achieved": round(achieved, 2),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 5),
+        "traffic": None,
+        "kernel": dom["kernel"],
+        "launch_us": round(dom["t"] * 1e6, 3),
+        "fwd_step_us": round(t_step * 1e6, 3),
+        "adj_step_us": round(t_adj * 1e6, 3),
+    }
+    n_dof = 2 * cells
+    fd_iter_s = (n_dof + 1) * nt_mean * cells / fwd_rate  # one-sided differences, batched forwards
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": per_iter * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"grad_{cfg.nx}x{cfg.ny}: forward + discrete-adjoint gradient of KE(T)/KE(0), T={T}, "
+                        f"snapshot every {args.interval} steps, one projected-gradient iteration per step",
+            "nx": cfg.nx, "ny": cfg.ny, "batch": 1, "T": T, "nsteps": nt_mean, "tile": ctx.tile,
+        },
+        "grad_iters_per_s": 1.0 / per_iter,
+        "fwd_cell_updates_per_s": fwd_rate,
+        "fd_grad_iters_per_s_extrapolated": 1.0 / fd_iter_s,
+        "R": float(R.item()),
+        "roofline": roofline,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(cfg, T, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

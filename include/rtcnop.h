@@ -164,8 +164,27 @@ int rt_project_to_constraint(rt_ctx* ctx, double* uv, double delta, int32_t norm
  * (device).  Used by the spectral projected-gradient step. */
 int rt_dot(rt_ctx* ctx, const double* a, const double* b, double* out);
 
+/* Per-member largest magnitude of a velocity field: out[B] = max |a|
+ * (device); the infinity norm of the stationarity measure of the search. */
+int rt_max_abs(rt_ctx* ctx, const double* a, double* out);
+
 /* out = x + alpha[b] * y per member (alpha device [B]); out may alias x. */
 int rt_axpy(rt_ctx* ctx, const double* x, const double* alpha, const double* y, double* out);
+
+/* Kernel variants.  The fused step and adjoint kernels come in tile shapes
+ * 16x16, 32x8, 64x4 (256 threads) and 16x16, 32x8 (576 threads, one pass
+ * per phase); ids 0..4 in that order.  Every variant gives bitwise-identical
+ * results.  rt_set_tile selects one variant for both kernels;
+ * rt_autotune times every variant on the state U (device) with `reps`
+ * launches each on the context's stream, keeps the fastest step and
+ * adjoint variants (returned in step_tile / adj_tile, may be NULL) and
+ * synchronises the stream.  The workspace buffers serve as scratch. */
+int rt_set_tile(rt_ctx* ctx, int32_t tile);
+/* The adaptive march replays captured HIP graphs of 48 steps (on = 1, the
+ * default) or launches step by step (on = 0); results are identical. */
+int rt_set_graphs(rt_ctx* ctx, int32_t on);
+int rt_get_tiles(const rt_ctx* ctx, int32_t* step_tile, int32_t* adj_tile);
+int rt_autotune(rt_ctx* ctx, const double* U, int32_t reps, int32_t* step_tile, int32_t* adj_tile);
 
 /* Synchronise the stream and report a device-side error flag (RT_EUNPHYS)
  * raised by earlier asynchronous calls; clears the flag. */

@@ -1,0 +1,127 @@
+"""CNOP search: spectral projected-gradient ascent on the constraint sphere.
+
+The paper maximises its objective over the perturbations that satisfy the
+energy constraint (Sec. 3.1, Eq. 10) with a projected quasi-Newton method, a
+projection that rescales a trial point onto the constraint (Eq. 11) and a
+non-monotone Armijo line search that allows temporary decreases (Sec. 3.4).
+This driver does the same with the spectral (Barzilai-Borwein) projected
+gradient method:
+
+    u+ = P(u_k + lam * alpha_k * g_k)              trial point on the sphere
+    accept if R(u+) >= min(R of the last M accepted iterates)
+                       + c * <g_k, u+ - u_k>       (non-monotone, ascent form)
+    else lam <- lam / 2
+    alpha_{k+1} = <s, s> / |<s, y>|,  s = u+ - u_k, y = g+ - g_k
+
+and logs the stationarity measure chi_k = ||P(u_k + g_k) - u_k||_inf of
+Appendix A (written for ascent).  Every member of the batch is an independent
+restart; all members advance in the same launches.  The host only decides
+acceptance and step sizes from per-member scalars; every field operation is
+a library call (projection, axpy, dot products, forward march, gradient).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from .config import NORM_L2, SET_SPHERE
+from .rtcnop import Context, Policy
+
+
+@dataclass
+class SPGLog:
+    R: list = field(default_factory=list)          # [iter][B] accepted objective
+    grad_norm: list = field(default_factory=list)  # [iter][B] ||g|| (L2 dV)
+    chi: list = field(default_factory=list)        # [iter][B] stationarity measure
+    backtracks: list = field(default_factory=list) # [iter][B]
+    evals: int = 0                                 # forward evaluations
+    grads: int = 0                                 # gradient evaluations
+
+
+def _l2dv(rt: Context, x: torch.Tensor) -> np.ndarray:
+    return np.sqrt(rt.dot(x, x).cpu().numpy() * rt.cfg.dx * rt.cfg.dy)
+
+
+def ke_ratio(rt: Context, uv: torch.Tensor, T: float) -> torch.Tensor:
+    """R = KE(T)/KE(0) of every member (forward march only)."""
+    U0 = rt.init_state(uv)
+    ke0 = rt.kinetic_energy(U0)
+    UT, _, _, _ = rt.integrate(U0, T)
+    return rt.kinetic_energy(UT) / ke0
+
+
+def spg(rt: Context, uv0, T: float, delta: float, iters: int, policy: Policy | None = None,
+        pool: torch.Tensor | None = None, memory: int = 10, c_armijo: float = 1e-4, max_backtracks: int = 8,
+        log: SPGLog | None = None):
+    """Run `iters` SPG iterations from uv0 (projected onto ||u|| = delta).
+    Returns (u, R, g, log)."""
+    log = log or SPGLog()
+    B = rt.cfg.batch
+    u, _ = rt.project_to_constraint(rt.as_dev(uv0), delta, NORM_L2, SET_SPHERE)
+    R, g, _ = rt.grad_u0(u, T, policy, pool=pool)
+    log.grads += 1
+    Rh = R.cpu().numpy().copy()
+    hist = [Rh.copy()]
+    gn = _l2dv(rt, g)
+    alpha = 0.1 * delta / np.maximum(gn, 1e-300)
+    for _ in range(iters):
+        lam = np.ones(B)
+        accepted = np.zeros(B, dtype=bool)
+        u_new = torch.empty_like(u)
+        R_new = np.zeros(B)
+        ref = np.min(np.stack(hist[-memory:]), axis=0)
+        nback = np.zeros(B, dtype=int)
+        for bt in range(max_backtracks + 1):
+            trial = rt.axpy(u, lam * alpha, g)
+            trial, _ = rt.project_to_constraint(trial, delta, NORM_L2, SET_SPHERE)
+            Rt = ke_ratio(rt, trial, T).cpu().numpy()
+            log.evals += 1
+            d = rt.axpy(trial, -1.0, u)
+            gd = rt.dot(g, d).cpu().numpy()
+            ok = (Rt >= ref + c_armijo * gd) | (bt == max_backtracks)
+            for b in range(B):
+                if not accepted[b] and ok[b]:
+                    accepted[b] = True
+                    u_new[b] = trial[b]
+                    R_new[b] = Rt[b]
+            if accepted.all():
+                break
+            nback += ~accepted
+            lam = np.where(accepted, lam, 0.5 * lam)
+        R2, g2, _ = rt.grad_u0(u_new, T, policy, pool=pool)
+        log.grads += 1
+        s = rt.axpy(u_new, -1.0, u)
+        y = rt.axpy(g2, -1.0, g)
+        ss = rt.dot(s, s).cpu().numpy()
+        sy = rt.dot(s, y).cpu().numpy()
+        gn = _l2dv(rt, g2)
+        base = delta / np.maximum(gn, 1e-300)
+        alpha = np.clip(ss / np.maximum(np.abs(sy), 1e-300), 1e-10 * base, 1e10 * base)
+        # stationarity measure chi = ||P(u + g) - u||_inf
+        pg, _ = rt.project_to_constraint(rt.axpy(u_new, 1.0, g2), delta, NORM_L2, SET_SPHERE)
+        chi = rt.max_abs(rt.axpy(pg, -1.0, u_new)).cpu().numpy()
+        u, g = u_new, g2
+        Rh = R2.cpu().numpy().copy()
+        hist.append(Rh)
+        log.R.append(Rh.tolist())
+        log.grad_norm.append(gn.tolist())
+        log.chi.append(chi.tolist())
+        log.backtracks.append(nback.tolist())
+    return u, torch.as_tensor(Rh), g, log
+
+
+def spectrum_top5(v_row: np.ndarray) -> float:
+    """Energy fraction of the 5 strongest horizontal modes n >= 1 of one row
+    (Sec. 4.2, Eq. 12: E_n = |u_n|^2 / sum over the positive modes)."""
+    c = np.fft.rfft(v_row)
+    e = np.abs(c[1:]) ** 2
+    e = e / np.sum(e)
+    return float(np.sum(np.sort(e)[-5:]))
+
+
+def peak_row(v: np.ndarray) -> int:
+    """Row whose rms along x is largest (lowest index on ties)."""
+    return int(np.argmax(np.sqrt(np.mean(v * v, axis=1))))

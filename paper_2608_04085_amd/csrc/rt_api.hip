@@ -47,7 +47,8 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 struct rt_ctx {
   Params P;
   hipStream_t stream;
-  int tile;
+  int tile;      // tile variant of the step kernel
+  int tile_adj;  // tile variant of the adjoint kernel
   int red_blocks;
   // workspace
   char* ws = nullptr;
@@ -56,8 +57,20 @@ struct rt_ctx {
   double *S0 = nullptr, *S1 = nullptr, *L0 = nullptr, *L1 = nullptr, *Z = nullptr;
   int32_t* codes = nullptr;
   double* partial = nullptr;
-  uint32_t* counter = nullptr;
-  Ctl* ctl = nullptr;
+  uint64_t* acc = nullptr;  // [3][B] signal-speed accumulators of the march
+  Ctl* ctl = nullptr;       // [2][B] march control, double buffered
+  long last_launch = 0;     // launches of the last march (final ctl in ctl[last_launch & 1])
+  // Graph of a chunk of kGraphChunk march steps (captured once per set of
+  // kernel arguments, replayed on the caller's stream).
+  bool use_graphs = true;
+  hipStream_t capture_stream = nullptr;
+  hipGraphExec_t chunk_exec = nullptr;
+  const double* chunk_pool = nullptr;
+  int chunk_interval = 0, chunk_slots = 0, chunk_tile = -1;
+  ~rt_ctx() {
+    if (chunk_exec) (void)hipGraphExecDestroy(chunk_exec);
+    if (capture_stream) (void)hipStreamDestroy(capture_stream);
+  }
   Flags* flags = nullptr;
   double* dt_log = nullptr;
   int32_t* nsteps = nullptr;
@@ -70,7 +83,7 @@ struct rt_ctx {
 namespace {
 
 struct Layout {
-  size_t S0, S1, L0, L1, Z, codes, partial, counter, ctl, flags, dt_log, nsteps, scal, total;
+  size_t S0, S1, L0, L1, Z, codes, partial, acc, ctl, flags, dt_log, nsteps, scal, total;
 };
 
 Layout layout(const rt_ctx* c, int32_t max_steps) {
@@ -91,8 +104,8 @@ Layout layout(const rt_ctx* c, int32_t max_steps) {
   L.Z = take(3 * se);
   L.codes = take(c->cells() * c->P.nb * sizeof(int32_t));
   L.partial = take((size_t)maxblk * c->P.nb * sizeof(double));
-  L.counter = take((size_t)c->P.nb * sizeof(uint32_t));
-  L.ctl = take((size_t)c->P.nb * sizeof(Ctl));
+  L.acc = take((size_t)4 * c->P.nb * sizeof(uint64_t));
+  L.ctl = take((size_t)2 * c->P.nb * sizeof(Ctl));
   L.flags = take(sizeof(Flags));
   L.dt_log = take((size_t)c->P.nb * std::max<int32_t>(max_steps, 1) * sizeof(double));
   L.nsteps = take((size_t)c->P.nb * sizeof(int32_t));
@@ -123,13 +136,14 @@ int flags_status(const Flags& f) {
   return 0;
 }
 
-rtk::StepArgs adaptive_args(rt_ctx* c, const double* src, double* dst, double* pool, int interval, int slots) {
+rtk::StepArgs adaptive_args(rt_ctx* c, const double* src, double* dst, long launch, double* pool, int interval,
+                            int slots) {
   rtk::StepArgs a{};
   a.U = src;
   a.Un = dst;
   a.ctl = c->ctl;
-  a.partial = c->partial;
-  a.counter = c->counter;
+  a.acc = c->acc;
+  a.launch = (int32_t)launch;
   a.dt_log = c->dt_log;
   a.dt_log_cap = c->max_steps;
   a.pool = pool;
@@ -139,36 +153,95 @@ rtk::StepArgs adaptive_args(rt_ctx* c, const double* src, double* dst, double* p
   return a;
 }
 
-// Adaptive march of all members from S0 to T.  On return (stream synced)
-// ctl holds per-member step counts; the final state of member b is in S0 if
-// its step count is even, else in S1.  Snapshots of U^n go to `pool` every
-// `interval` steps when pool is not null.
+// Control records after the last march.
+const Ctl* final_ctl(const rt_ctx* c) { return c->ctl + (size_t)(c->last_launch & 1) * c->P.nb; }
+
+// Steps per captured graph: a multiple of 6 so that the launch index enters
+// the kernels only through L mod 2 and L mod 3.
+constexpr long kGraphChunk = 48;
+
+// (Re)capture the graph of kGraphChunk adaptive steps starting at an even
+// launch index (S0 -> S1 -> S0 ...).
+int ensure_chunk_graph(rt_ctx* c, double* pool, int interval, int slots) {
+  if (c->chunk_exec && c->chunk_pool == pool && c->chunk_interval == interval && c->chunk_slots == slots &&
+      c->chunk_tile == c->tile)
+    return 0;
+  if (c->chunk_exec) {
+    RT_HIP(hipGraphExecDestroy(c->chunk_exec));
+    c->chunk_exec = nullptr;
+  }
+  if (!c->capture_stream) RT_HIP(hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
+  hipGraph_t g = nullptr;
+  RT_HIP(hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
+  hipError_t e = hipSuccess;
+  for (long k = 0; k < kGraphChunk && e == hipSuccess; ++k) {
+    const double* src = (k & 1) ? c->S1 : c->S0;
+    double* dst = (k & 1) ? c->S0 : c->S1;
+    rtk::StepArgs a = adaptive_args(c, src, dst, k, pool, interval, slots);
+    e = rtk::launch_step(c->P, c->tile, a, c->capture_stream);
+  }
+  const hipError_t e2 = hipStreamEndCapture(c->capture_stream, &g);
+  if (e != hipSuccess || e2 != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return fail(RT_EHIP, "graph capture failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+  }
+  e = hipGraphInstantiate(&c->chunk_exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    c->chunk_exec = nullptr;
+    return fail(RT_EHIP, "graph instantiate failed: %s", hipGetErrorString(e));
+  }
+  c->chunk_pool = pool;
+  c->chunk_interval = interval;
+  c->chunk_slots = slots;
+  c->chunk_tile = c->tile;
+  return 0;
+}
+
+// Adaptive march of all members from S0 to T, one launch per step for the
+// whole batch (captured in graphs of kGraphChunk steps).  Members that are
+// done skip their blocks; the host checks the number of active members once
+// per round of launches.  On return (stream synced) final_ctl(c) holds the
+// per-member step counts; the final state of member b is in S0 if its step
+// count is even, else in S1.  Snapshots of U^n go to `pool` every `interval`
+// steps when pool is not null.
 int march(rt_ctx* c, double T, double* pool, int interval, int slots) {
   Params& P = c->P;
   RT_HIP(rtk::launch_reduce(P, 0, c->S0, nullptr, c->partial, c->red_blocks, c->sc(0), c->stream));
-  RT_HIP(rtk::launch_march_begin(P, c->sc(0), T, c->ctl, c->flags, c->stream));
-  std::vector<Ctl> h(P.nb);
-  RT_HIP(hipMemcpyAsync(h.data(), c->ctl, sizeof(Ctl) * P.nb, hipMemcpyDeviceToHost, c->stream));
+  RT_HIP(rtk::launch_march_begin(P, c->sc(0), T, c->ctl, c->acc, c->flags, c->stream));
+  std::vector<double> ms(P.nb);
+  RT_HIP(hipMemcpyAsync(ms.data(), c->sc(0), sizeof(double) * P.nb, hipMemcpyDeviceToHost, c->stream));
   RT_HIP(hipStreamSynchronize(c->stream));
-  double dtmin = INFINITY;
-  for (const Ctl& x : h) dtmin = std::min(dtmin, x.dt);
+  double msmax = 0.0;
+  for (double m : ms) msmax = std::max(msmax, m);
+  const double dtmin = P.cfl / msmax;
   if (!(dtmin > 0.0) || !std::isfinite(dtmin)) return fail(RT_EUNPHYS, "initial CFL step is %g", dtmin);
   const double est = std::ceil(T / dtmin);
   const long nest = est > 1e9 ? 1000000000L : (long)est;
+  const bool graphs = c->use_graphs;
+  if (graphs) {
+    if (int rc = ensure_chunk_graph(c, pool, interval, slots)) return rc;
+  }
   long launched = 0;
   long target = nest;
   Flags f{};
   for (;;) {
     while (launched < target) {
+      if (graphs) {
+        RT_HIP(hipGraphLaunch(c->chunk_exec, c->stream));
+        launched += kGraphChunk;
+        continue;
+      }
       const double* src = (launched & 1) ? c->S1 : c->S0;
       double* dst = (launched & 1) ? c->S0 : c->S1;
-      rtk::StepArgs a = adaptive_args(c, src, dst, pool, interval, slots);
+      rtk::StepArgs a = adaptive_args(c, src, dst, launched, pool, interval, slots);
       RT_HIP(rtk::launch_step(P, c->tile, a, c->stream));
       ++launched;
     }
+    c->last_launch = launched;
     if (int rc = read_flags(c, &f, false)) return rc;
     if (f.n_active == 0 || f.err_unphys || f.err_overflow) break;
-    if (launched > (long)c->max_steps + 2) {
+    if (launched > (long)c->max_steps + kGraphChunk + 2) {
       return fail(RT_ENOMEM, "march needs more than %d steps (workspace max_steps)", c->max_steps);
     }
     target = launched + std::max<long>(8, nest / 32);
@@ -211,7 +284,12 @@ int rt_create(const rt_grid* grid, const rt_phys* phys, void* stream, rt_ctx** o
   P.h = phys->h;
   P.p_int = phys->p_int;
   c->stream = reinterpret_cast<hipStream_t>(stream);
-  c->tile = P.nx >= 64 ? rtk::TILE_64x4 : (P.nx >= 32 ? rtk::TILE_32x8 : rtk::TILE_16x16);
+  // Small grids fill the chip with one round of blocks, so the single-pass
+  // 576-thread tiles (shorter critical path) win; large grids are throughput
+  // bound and prefer 256-thread tiles.  rt_autotune measures instead.
+  const bool small = (size_t)P.nx * P.ny * P.nb < ((size_t)1 << 20);
+  c->tile = small ? rtk::TILE_16x16W : rtk::TILE_32x8;
+  c->tile_adj = small ? rtk::TILE_16x16W : rtk::TILE_32x8;
   const size_t n = c->cells();
   c->red_blocks = (int)std::min<size_t>(256, std::max<size_t>(1, n / 2048));
   *out = c;
@@ -233,6 +311,7 @@ int rt_set_stream(rt_ctx* c, void* stream) {
 int rt_set_tile(rt_ctx* c, int32_t tile) {
   if (!c || tile < 0 || tile >= rtk::TILE_COUNT) return fail(RT_EINVAL, "bad tile id");
   c->tile = tile;
+  c->tile_adj = tile;
   return 0;
 }
 
@@ -240,6 +319,88 @@ int rt_get_tile(const rt_ctx* c, int32_t* tile) {
   if (!c || !tile) return fail(RT_EINVAL, "null argument");
   *tile = c->tile;
   return 0;
+}
+
+// Replay the march in captured graphs (1, default) or launch step by step (0).
+int rt_set_graphs(rt_ctx* c, int32_t on) {
+  if (!c) return fail(RT_EINVAL, "null context");
+  c->use_graphs = on != 0;
+  return 0;
+}
+
+int rt_get_tiles(const rt_ctx* c, int32_t* step_tile, int32_t* adj_tile) {
+  if (!c || !step_tile || !adj_tile) return fail(RT_EINVAL, "null argument");
+  *step_tile = c->tile;
+  *adj_tile = c->tile_adj;
+  return 0;
+}
+
+// Autotuner: times every tile variant of the step and adjoint kernels on
+// the caller's state U (device, [B][4][ny][nx]) with HIP events on the
+// context's stream and keeps the fastest of each.  All variants give
+// bitwise-identical results, so this changes speed only.  Uses the
+// workspace buffers as scratch.  Synchronises the stream.
+int rt_autotune(rt_ctx* c, const double* U, int32_t reps, int32_t* step_tile, int32_t* adj_tile) {
+  if (int rc = need_ws(c)) return rc;
+  if (!U || reps < 1) return fail(RT_EINVAL, "bad argument");
+  hipStream_t s = c->stream;
+  const size_t se = c->state_elems();
+  if (int rc = rt_cfl_dt(c, U, c->sc(3))) return rc;
+  RT_HIP(rtk::launch_copy(U, c->L0, se, s));  // any finite cotangent will do
+  hipEvent_t e0, e1;
+  RT_HIP(hipEventCreate(&e0));
+  RT_HIP(hipEventCreate(&e1));
+  float best_s = 1e30f, best_a = 1e30f;
+  int bs = c->tile, ba = c->tile_adj;
+  int rc = 0;
+  for (int t = 0; t < rtk::TILE_COUNT && rc == 0; ++t) {
+    rtk::StepArgs a{};
+    a.U = U;
+    a.Un = c->S1;
+    a.dt = c->sc(3);
+    a.dt_stride = 1;
+    a.flags = c->flags;
+    rtk::AdjArgs j{};
+    j.U = U;
+    j.lam_next = c->L0;
+    j.lam = c->L1;
+    j.Z = c->Z;
+    j.codes = c->codes;
+    j.dt = c->sc(3);
+    j.dt_stride = 1;
+    j.flags = c->flags;
+    float ms_s = 0.f, ms_a = 0.f;
+    if (rtk::launch_step(c->P, t, a, s) != hipSuccess || rtk::launch_adjoint(c->P, t, j, s) != hipSuccess) {
+      rc = fail(RT_EHIP, "autotune launch failed");
+      break;
+    }
+    hipError_t e = hipEventRecord(e0, s);
+    for (int k = 0; k < reps && e == hipSuccess; ++k) e = rtk::launch_step(c->P, t, a, s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms_s, e0, e1);
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    for (int k = 0; k < reps && e == hipSuccess; ++k) e = rtk::launch_adjoint(c->P, t, j, s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms_a, e0, e1);
+    if (e != hipSuccess) {
+      rc = fail(RT_EHIP, "autotune: %s", hipGetErrorString(e));
+      break;
+    }
+    if (ms_s < best_s) { best_s = ms_s; bs = t; }
+    if (ms_a < best_a) { best_a = ms_a; ba = t; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  RT_HIP(hipGetLastError());
+  c->tile = bs;
+  c->tile_adj = ba;
+  if (step_tile) *step_tile = bs;
+  if (adj_tile) *adj_tile = ba;
+  Flags f{};
+  return read_flags(c, &f, true);
 }
 
 int rt_workspace_bytes(const rt_ctx* c, int32_t max_steps, size_t* bytes) {
@@ -254,6 +415,10 @@ int rt_set_workspace(rt_ctx* c, void* dev, size_t bytes, int32_t max_steps) {
   const Layout L = layout(c, max_steps);
   if (bytes < L.total) return fail(RT_ENOMEM, "workspace of %zu bytes < %zu needed", bytes, L.total);
   char* w = static_cast<char*>(dev);
+  if (c->chunk_exec) {
+    RT_HIP(hipGraphExecDestroy(c->chunk_exec));
+    c->chunk_exec = nullptr;
+  }
   c->ws = w;
   c->ws_bytes = bytes;
   c->max_steps = max_steps;
@@ -264,13 +429,13 @@ int rt_set_workspace(rt_ctx* c, void* dev, size_t bytes, int32_t max_steps) {
   c->Z = reinterpret_cast<double*>(w + L.Z);
   c->codes = reinterpret_cast<int32_t*>(w + L.codes);
   c->partial = reinterpret_cast<double*>(w + L.partial);
-  c->counter = reinterpret_cast<uint32_t*>(w + L.counter);
+  c->acc = reinterpret_cast<uint64_t*>(w + L.acc);
   c->ctl = reinterpret_cast<Ctl*>(w + L.ctl);
   c->flags = reinterpret_cast<Flags*>(w + L.flags);
   c->dt_log = reinterpret_cast<double*>(w + L.dt_log);
   c->nsteps = reinterpret_cast<int32_t*>(w + L.nsteps);
   c->scal = reinterpret_cast<double*>(w + L.scal);
-  RT_HIP(rtk::launch_fill_i32(reinterpret_cast<int32_t*>(c->counter), 0, c->P.nb, c->stream));
+  RT_HIP(rtk::launch_fill_i32(reinterpret_cast<int32_t*>(c->acc), 0, 8 * c->P.nb, c->stream));
   RT_HIP(rtk::launch_fill_i32(reinterpret_cast<int32_t*>(c->flags), 0, sizeof(Flags) / 4, c->stream));
   return 0;
 }
@@ -302,11 +467,14 @@ int rt_step(rt_ctx* c, const double* U_in, double* U_out, const double* dt, doub
   a.dt = dt;
   a.dt_stride = 1;
   a.dt_index = 0;
-  a.partial = c->partial;
-  a.counter = c->counter;
-  a.dt_next = dt_next;
   a.flags = c->flags;
+  uint64_t* acc_out = c->acc + 3 * (size_t)c->P.nb;  // the fourth accumulator row
+  if (dt_next) {
+    RT_HIP(rtk::launch_fill_i32(reinterpret_cast<int32_t*>(acc_out), 0, 2 * c->P.nb, c->stream));
+    a.acc_out = acc_out;
+  }
   RT_HIP(rtk::launch_step(c->P, c->tile, a, c->stream));
+  if (dt_next) RT_HIP(rtk::launch_cfl_from_bits(c->P, acc_out, dt_next, c->stream));
   return 0;
 }
 
@@ -316,14 +484,14 @@ int rt_integrate(rt_ctx* c, double* U, double T, double* t_out, int32_t* nsteps,
   if (dt_log && cap < 1) return fail(RT_EINVAL, "dt_log needs cap >= 1");
   RT_HIP(rtk::launch_copy(U, c->S0, c->state_elems(), c->stream));
   if (int rc = march(c, T, nullptr, 1, 0)) return rc;
-  RT_HIP(rtk::launch_copy_final(c->P, c->ctl, c->S0, c->S1, U, t_out, nsteps, c->dt_log, c->max_steps, dt_log, cap,
-                                c->stream));
+  RT_HIP(rtk::launch_copy_final(c->P, final_ctl(c), c->S0, c->S1, U, t_out, nsteps, c->dt_log, c->max_steps, dt_log,
+                                cap, c->stream));
   Flags f{};
   if (int rc = read_flags(c, &f, true)) return rc;
   if (int rc = flags_status(f)) return rc;
   if (dt_log) {
     std::vector<Ctl> h(c->P.nb);
-    RT_HIP(hipMemcpy(h.data(), c->ctl, sizeof(Ctl) * c->P.nb, hipMemcpyDeviceToHost));
+    RT_HIP(hipMemcpy(h.data(), final_ctl(c), sizeof(Ctl) * c->P.nb, hipMemcpyDeviceToHost));
     for (const Ctl& x : h)
       if (x.nsteps > cap) return fail(RT_ENOMEM, "dt_log capacity %d < %d steps", cap, x.nsteps);
   }
@@ -350,7 +518,7 @@ int rt_step_adjoint(rt_ctx* c, const double* U, const double* dt, const double* 
   a.dt_stride = 1;
   a.dt_index = 0;
   a.flags = c->flags;
-  RT_HIP(rtk::launch_adjoint(c->P, c->tile, a, c->stream));
+  RT_HIP(rtk::launch_adjoint(c->P, c->tile_adj, a, c->stream));
   return 0;
 }
 
@@ -410,7 +578,7 @@ int rt_grad_u0(rt_ctx* c, const double* uv0, double T, const rt_ckpt_policy* pol
   if (int rc = flags_status(f)) return rc;
 
   // step counts and final state
-  RT_HIP(rtk::launch_copy_final(P, c->ctl, c->S0, c->S1, c->L1, nullptr, c->nsteps, nullptr, 0, nullptr, 0, s));
+  RT_HIP(rtk::launch_copy_final(P, final_ctl(c), c->S0, c->S1, c->L1, nullptr, c->nsteps, nullptr, 0, nullptr, 0, s));
   if (nsteps_out) RT_HIP(hipMemcpyAsync(nsteps_out, c->nsteps, sizeof(int32_t) * P.nb, hipMemcpyDeviceToDevice, s));
   std::vector<int32_t> hn(P.nb);
   std::vector<double> hke0(P.nb);
@@ -451,7 +619,7 @@ int rt_grad_u0(rt_ctx* c, const double* uv0, double T, const rt_ckpt_policy* pol
     a.dt_index = n;
     a.nsteps_limit = c->nsteps;
     a.flags = c->flags;
-    RT_HIP(rtk::launch_adjoint(P, c->tile, a, s));
+    RT_HIP(rtk::launch_adjoint(P, c->tile_adj, a, s));
     std::swap(lam, lam_other);
     return 0;
   };
@@ -519,6 +687,13 @@ int rt_dot(rt_ctx* c, const double* a, const double* b, double* out) {
   if (int rc = need_ws(c)) return rc;
   if (!a || !b || !out) return fail(RT_EINVAL, "null argument");
   RT_HIP(rtk::launch_reduce(c->P, 5, a, b, c->partial, c->red_blocks, out, c->stream));
+  return 0;
+}
+
+int rt_max_abs(rt_ctx* c, const double* a, double* out) {
+  if (int rc = need_ws(c)) return rc;
+  if (!a || !out) return fail(RT_EINVAL, "null argument");
+  RT_HIP(rtk::launch_reduce(c->P, 6, a, nullptr, c->partial, c->red_blocks, out, c->stream));
   return 0;
 }
 

@@ -10,16 +10,15 @@
 
 namespace rtk {
 
-// Per-member march control, device resident.  Written by the step kernel's
-// last block (or by march_begin), read by the next step.
+// Per-member march control, device resident and double buffered: the step
+// launched with index L reads ctl[L & 1] and its block (0, 0) writes
+// ctl[(L + 1) & 1], so no block can see a half-updated record.
 struct Ctl {
   double t;        // time reached
-  double dt;       // step to take next
   double T;        // end time
+  double dt_last;  // step taken by the launch that wrote this record
   int32_t nsteps;  // steps taken
   int32_t done;    // 1 once t == T
-  int32_t last;    // 1 if dt was clipped to end exactly at T
-  int32_t pad;
 };
 
 // Flags shared by all members (device).
@@ -34,21 +33,28 @@ struct Flags {
 struct StepArgs {
   const double* U;     // U^n       [B][4][ny][nx]
   double* Un;          // U^{n+1}
-  // time step: adaptive (ctl != nullptr) or given (dt[b * dt_stride + dt_index])
-  Ctl* ctl;
-  const double* dt;
-  int32_t dt_stride, dt_index;
-  const int32_t* nsteps_limit;  // given-dt mode: members with dt_index >= limit[b] are skipped
-  // CFL epilogue: per-block max signal speed of U^{n+1}
-  double* partial;              // [B][nblk]
-  uint32_t* counter;            // [B] last-block counters (self-resetting)
-  double* dt_next;              // given-dt mode: unclipped CFL step of U^{n+1} (may be null)
-  double* dt_log;               // adaptive mode: step log [B][dt_log_cap]
+  // Adaptive mode (ctl != nullptr).  The largest signal speed of each
+  // member's state is kept as the bit pattern of a non-negative double
+  // (ordered like the unsigned integer) in acc[3][B]: launch L reads
+  // acc[L % 3] (speeds of U^n) to form its CFL step, folds the speeds of
+  // U^{n+1} into acc[(L + 1) % 3] with one atomic max per block, and clears
+  // acc[(L + 2) % 3] for the next launch.
+  Ctl* ctl;                     // [2][B]
+  uint64_t* acc;                // [3][B]
+  int32_t launch;
+  double* dt_log;               // step log [B][dt_log_cap]
   int32_t dt_log_cap;
-  // snapshots (adaptive mode): U^n copied to pool[slot][B][4][ny][nx] when
+  // snapshots: U^n copied to pool[slot][B][4][ny][nx] when
   // nsteps % snap_interval == 0, slot = nsteps / snap_interval
   double* pool;
   int32_t snap_interval, snap_slots;
+  // Given-dt mode: dt = dt[b * dt_stride + dt_index]; members with
+  // dt_index >= nsteps_limit[b] are skipped.  acc_out (may be null) receives
+  // the largest signal speed of U^{n+1} (bit pattern, must start at 0).
+  const double* dt;
+  int32_t dt_stride, dt_index;
+  const int32_t* nsteps_limit;
+  uint64_t* acc_out;
   Flags* flags;
 };
 
@@ -64,26 +70,25 @@ struct AdjArgs {
   Flags* flags;
 };
 
-struct Launch {
-  int tile;   // tile shape id
-  int red_blocks;
-};
-
-// Tile shapes of the fused step / adjoint kernels (TX x TY cells, 256 threads).
-enum TileId { TILE_16x16 = 0, TILE_32x8 = 1, TILE_64x4 = 2, TILE_COUNT = 3 };
-void tile_dims(int tile, int* tx, int* ty);
+// Tile shapes of the fused step / adjoint kernels: TX x TY cells with 256
+// threads, or with 576 threads ("W" variants: one pass per phase).  All
+// variants produce bitwise-identical results.
+enum TileId { TILE_16x16 = 0, TILE_32x8 = 1, TILE_64x4 = 2, TILE_16x16W = 3, TILE_32x8W = 4, TILE_COUNT = 5 };
+void tile_dims(int tile, int* tx, int* ty, int* nt);
 int step_blocks(const Params& P, int tile);  // blocks per member
 
 hipError_t launch_init_state(const Params& P, const double* uv0, double* U, hipStream_t s);
 hipError_t launch_step(const Params& P, int tile, const StepArgs& a, hipStream_t s);
 hipError_t launch_adjoint(const Params& P, int tile, const AdjArgs& a, hipStream_t s);
 // Per-member reductions: kind 0 = max signal speed, 1 = kinetic energy,
-// 2.. = weighted |uv|^2 for the projection (norm id = kind - 2), 5 = dot.
+// 2.. = weighted |uv|^2 for the projection (norm id = kind - 2), 5 = dot,
+// 6 = max |x| of a velocity field.
 hipError_t launch_reduce(const Params& P, int kind, const double* a, const double* b, double* partial,
                          int nblk, double* out, hipStream_t s);
-hipError_t launch_march_begin(const Params& P, const double* maxspeed, double T, Ctl* ctl, Flags* flags,
-                              hipStream_t s);
+hipError_t launch_march_begin(const Params& P, const double* maxspeed, double T, Ctl* ctl, uint64_t* acc,
+                              Flags* flags, hipStream_t s);
 hipError_t launch_cfl_from_speed(const Params& P, const double* maxspeed, double* dt, hipStream_t s);
+hipError_t launch_cfl_from_bits(const Params& P, const uint64_t* acc, double* dt, hipStream_t s);
 hipError_t launch_copy_final(const Params& P, const Ctl* ctl, const double* A, const double* Bbuf, double* U,
                              double* t_out, int32_t* nsteps_out, const double* log_src, int32_t log_src_cap,
                              double* log_dst, int32_t log_dst_cap, hipStream_t s);

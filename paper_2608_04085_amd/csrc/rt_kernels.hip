@@ -3,7 +3,9 @@
 // them.  All arithmetic is FP64.
 //
 // Fused step (one launch per time step for all members):
-//   block = one tile of TX x TY cells of one member, 256 threads;
+//   block = one tile of TX x TY cells of one member; 256 threads, or 576
+//            threads so that every phase of a 16x16 or 32x8 tile is a single
+//            pass (shorter critical path when the grid is small);
 //   phase A  primitives of the tile plus a 2-cell halo into LDS (x periodic,
 //            y ghost rows from the wall boundary condition);
 //   phase B  MC slopes and the MUSCL-Hancock predictor of the tile plus a
@@ -84,20 +86,12 @@ __device__ __forceinline__ double p0_at(const Params& P, double y) {
   return P.p_int + P.g_y * (0.5 * (P.rho_h + P.rho_l) * (y - P.y0) + 0.5 * (P.rho_h - P.rho_l) * P.h * lc);
 }
 
-// ----------------------------------------------------------------- LDS tile
-template <int TX, int TY>
-struct TileLDS {
-  static constexpr int AX = TX + 4, AY = TY + 4;  // primitives, halo 2
-  static constexpr int QX = TX + 2, QY = TY + 2;  // predictor, halo 1
-  double W[4][AY][AX];
-  double Q[12][QY][QX];  // q (4), sx (4), sy (4)
-};
-
+// ----------------------------------------------------------------- LDS tile helpers
 // Phase A: primitives of the tile + halo 2.  Returns nonzero on an
 // unphysical interior state.
-template <int TX, int TY, int NT>
-__device__ int tile_prims(const Params& P, const double* U, size_t N, int x0, int y0, TileLDS<TX, TY>& S) {
-  constexpr int AX = TileLDS<TX, TY>::AX, AY = TileLDS<TX, TY>::AY;
+template <int TX, int TY, int NT, class LDS>
+__device__ int tile_prims(const Params& P, const double* U, size_t N, int x0, int y0, LDS& S) {
+  constexpr int AX = TX + 4, AY = TY + 4;
   int bad = 0;
   for (int k = threadIdx.x; k < AX * AY; k += NT) {
     const int lx = k % AX, ly = k / AX;
@@ -120,20 +114,20 @@ __device__ int tile_prims(const Params& P, const double* U, size_t N, int x0, in
   return bad;
 }
 
-template <int TX, int TY>
-__device__ __forceinline__ W4 ldW(const TileLDS<TX, TY>& S, int x, int y) {
+template <class LDS>
+__device__ __forceinline__ W4 ldW(const LDS& S, int x, int y) {
   return W4{S.W[0][y][x], S.W[1][y][x], S.W[2][y][x], S.W[3][y][x]};
 }
-template <int TX, int TY>
-__device__ __forceinline__ W4 ldQ(const TileLDS<TX, TY>& S, int k, int x, int y) {
+template <class LDS>
+__device__ __forceinline__ W4 ldQ(const LDS& S, int k, int x, int y) {
   return W4{S.Q[4 * k + 0][y][x], S.Q[4 * k + 1][y][x], S.Q[4 * k + 2][y][x], S.Q[4 * k + 3][y][x]};
 }
 
 // Phase B: slopes and predictor on the cross-shaped halo-1 region.  If
 // codes_out is given, the MC cases of the tile cells are stored there.
-template <int TX, int TY, int NT>
-__device__ int tile_predict(const Params& P, double dt, int x0, int y0, TileLDS<TX, TY>& S, int32_t* codes_out) {
-  constexpr int QX = TileLDS<TX, TY>::QX, QY = TileLDS<TX, TY>::QY;
+template <int TX, int TY, int NT, class LDS>
+__device__ int tile_predict(const Params& P, double dt, int x0, int y0, LDS& S, int32_t* codes_out) {
+  constexpr int QX = TX + 2, QY = TY + 2;
   const double hx = 0.5 * dt * P.inv_dx, hy = 0.5 * dt * P.inv_dy, hg = 0.5 * dt * P.g_y;
   int bad = 0;
   for (int k = threadIdx.x; k < QX * QY; k += NT) {
@@ -170,36 +164,49 @@ __device__ int tile_predict(const Params& P, double dt, int x0, int y0, TileLDS<
 
 // Face states from the predictor region: x faces in (r, n = u, t = v, p),
 // y faces in (r, n = v, t = u, p).
-template <int TX, int TY>
-__device__ __forceinline__ FS xface_right_of(const TileLDS<TX, TY>& S, int x, int y) {  // state at the cell's right face
+template <class LDS>
+__device__ __forceinline__ FS xface_right_of(const LDS& S, int x, int y) {  // state at the cell's right face
   return FS{S.Q[0][y][x] + 0.5 * S.Q[4][y][x], S.Q[1][y][x] + 0.5 * S.Q[5][y][x], S.Q[2][y][x] + 0.5 * S.Q[6][y][x],
             S.Q[3][y][x] + 0.5 * S.Q[7][y][x]};
 }
-template <int TX, int TY>
-__device__ __forceinline__ FS xface_left_of(const TileLDS<TX, TY>& S, int x, int y) {
+template <class LDS>
+__device__ __forceinline__ FS xface_left_of(const LDS& S, int x, int y) {
   return FS{S.Q[0][y][x] - 0.5 * S.Q[4][y][x], S.Q[1][y][x] - 0.5 * S.Q[5][y][x], S.Q[2][y][x] - 0.5 * S.Q[6][y][x],
             S.Q[3][y][x] - 0.5 * S.Q[7][y][x]};
 }
-template <int TX, int TY>
-__device__ __forceinline__ FS yface_top_of(const TileLDS<TX, TY>& S, int x, int y) {
+template <class LDS>
+__device__ __forceinline__ FS yface_top_of(const LDS& S, int x, int y) {
   return FS{S.Q[0][y][x] + 0.5 * S.Q[8][y][x], S.Q[2][y][x] + 0.5 * S.Q[10][y][x], S.Q[1][y][x] + 0.5 * S.Q[9][y][x],
             S.Q[3][y][x] + 0.5 * S.Q[11][y][x]};
 }
-template <int TX, int TY>
-__device__ __forceinline__ FS yface_bottom_of(const TileLDS<TX, TY>& S, int x, int y) {
+template <class LDS>
+__device__ __forceinline__ FS yface_bottom_of(const LDS& S, int x, int y) {
   return FS{S.Q[0][y][x] - 0.5 * S.Q[8][y][x], S.Q[2][y][x] - 0.5 * S.Q[10][y][x], S.Q[1][y][x] - 0.5 * S.Q[9][y][x],
             S.Q[3][y][x] - 0.5 * S.Q[11][y][x]};
 }
 
 // ----------------------------------------------------------------- step
+// LDS of the step kernel: the flux arrays reuse the primitive tile, which is
+// dead once the predictor has run.
 template <int TX, int TY>
-__global__ __launch_bounds__(TX* TY) void k_step(Params P, StepArgs a) {
-  constexpr int NT = TX * TY;
-  __shared__ TileLDS<TX, TY> S;
-  __shared__ double sF[4][TY][TX + 1];
-  __shared__ double sG[4][TY + 1][TX];
+struct StepLDS {
+  static constexpr int AX = TX + 4, AY = TY + 4;
+  static constexpr int QX = TX + 2, QY = TY + 2;
+  union {
+    double W[4][AY][AX];
+    struct {
+      double F[4][TY][TX + 1];
+      double G[4][TY + 1][TX];
+    } fg;
+  };
+  double Q[12][QY][QX];
+};
+
+template <int TX, int TY, int NT>
+__global__ __launch_bounds__(NT) void k_step(Params P, StepArgs a) {
+  static_assert(NT >= TX * TY && NT % 64 == 0, "one thread per tile cell at least");
+  __shared__ StepLDS<TX, TY> S;
   __shared__ double sRed[NT / 64];
-  __shared__ int sLast;
 
   const int b = blockIdx.z;
   const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
@@ -207,73 +214,175 @@ __global__ __launch_bounds__(TX* TY) void k_step(Params P, StepArgs a) {
   const int nx = P.nx, ny = P.ny;
   const size_t N = (size_t)nx * ny;
   const double* U = a.U + (size_t)b * 4 * N;
+  const bool first_block = blockIdx.x == 0 && blockIdx.y == 0;
 
+  // time step of this member
   double dt;
   int nstep = 0;
+  bool last = false;
+  const Ctl* cin = nullptr;
+  Ctl* cout = nullptr;
   if (a.ctl) {
-    if (a.ctl[b].done) return;
-    dt = a.ctl[b].dt;
-    nstep = a.ctl[b].nsteps;
+    const int L = a.launch;
+    cin = a.ctl + (size_t)(L & 1) * P.nb + b;
+    cout = a.ctl + (size_t)((L + 1) & 1) * P.nb + b;
+    if (cin->done) {
+      if (first_block && tid == 0) *cout = *cin;
+      return;
+    }
+    const double ms = __longlong_as_double((long long)a.acc[(size_t)(L % 3) * P.nb + b]);
+    const double t = cin->t, rem = cin->T - t;
+    dt = P.cfl / ms;
+    if (dt >= rem) {
+      dt = rem;
+      last = true;
+    }
+    nstep = cin->nsteps;
   } else {
     if (a.nsteps_limit && a.dt_index >= a.nsteps_limit[b]) return;
     dt = a.dt[(size_t)b * a.dt_stride + a.dt_index];
   }
 
-  int bad = tile_prims<TX, TY, NT>(P, U, N, x0, y0, S);
-  __syncthreads();
-  bad |= tile_predict<TX, TY, NT>(P, dt, x0, y0, S, nullptr);
-  __syncthreads();
-
-  // phase C: fluxes
-  for (int k = tid; k < (TX + 1) * TY; k += NT) {
-    const int fx = k % (TX + 1), fy = k / (TX + 1);
-    if (y0 + fy >= ny) continue;
-    double F[4];
-    hllc(P, xface_right_of(S, fx, fy + 1), xface_left_of(S, fx + 1, fy + 1), F);
-    sF[0][fy][fx] = F[0];
-    sF[1][fy][fx] = F[1];
-    sF[2][fy][fx] = F[2];
-    sF[3][fy][fx] = F[3];
-  }
-  for (int k = tid; k < TX * (TY + 1); k += NT) {
-    const int fx = k % TX, fy = k / TX;
-    const int j = y0 + fy;
-    if (j > ny) continue;
-    double G0 = 0.0, G1 = 0.0, G2, G3 = 0.0;
-    if (j == 0) {
-      G2 = wall_pressure(P, yface_bottom_of(S, fx + 1, fy + 1), false);
-    } else if (j == ny) {
-      G2 = wall_pressure(P, yface_top_of(S, fx + 1, fy), true);
-    } else {
-      double f[4];
-      hllc(P, yface_top_of(S, fx + 1, fy), yface_bottom_of(S, fx + 1, fy + 1), f);
-      G0 = f[0];
-      G1 = f[2];
-      G2 = f[1];
-      G3 = f[3];
-    }
-    sG[0][fy][fx] = G0;
-    sG[1][fy][fx] = G1;
-    sG[2][fy][fx] = G2;
-    sG[3][fy][fx] = G3;
-  }
-  __syncthreads();
-
-  // phase D: update
+  // prefetch this thread's own cell for the update
   const int tx = tid % TX, ty = tid / TX;
   const int gx = x0 + tx, gy = y0 + ty;
+  const bool own = tid < TX * TY && gx < nx && gy < ny;
+  const size_t c = own ? (size_t)gy * nx + gx : 0;
+  double u0 = 0.0, u1 = 0.0, u2 = 0.0, u3 = 0.0;
+  if (own) {
+    u0 = U[c];
+    u1 = U[N + c];
+    u2 = U[2 * N + c];
+    u3 = U[3 * N + c];
+  }
+
+  // phase A: primitives of the tile + halo 2
+  constexpr int AX = StepLDS<TX, TY>::AX, AY = StepLDS<TX, TY>::AY;
+  constexpr int QX = StepLDS<TX, TY>::QX, QY = StepLDS<TX, TY>::QY;
+  int bad = 0;
+#pragma unroll
+  for (int it = 0; it < (AX * AY + NT - 1) / NT; ++it) {
+    const int k = tid + it * NT;
+    if (k < AX * AY) {
+      const int lx = k % AX, ly = k / AX;
+      const int hx = wrapx(x0 - 2 + lx, nx);
+      const int hy = y0 - 2 + ly;
+      W4 w{1.0, 0.0, 0.0, 1.0};
+      if (hy >= -1 && hy <= ny) {
+        const int sy = hy < 0 ? 0 : (hy >= ny ? ny - 1 : hy);
+        const size_t h = (size_t)sy * nx + hx;
+        w = cons_to_prim(P, U[h], U[N + h], U[2 * N + h], U[3 * N + h]);
+        if (hy >= 0 && hy < ny) bad |= unphysical(w);
+        if (hy < 0) w = ghost_bottom(P, w);
+        else if (hy >= ny) w = ghost_top(P, w);
+      }
+      S.W[0][ly][lx] = w.r;
+      S.W[1][ly][lx] = w.u;
+      S.W[2][ly][lx] = w.v;
+      S.W[3][ly][lx] = w.p;
+    }
+  }
+  __syncthreads();
+
+  // phase B: slopes and predictor on the cross-shaped halo-1 region
+  {
+    const double hx = 0.5 * dt * P.inv_dx, hy = 0.5 * dt * P.inv_dy, hg = 0.5 * dt * P.g_y;
+    for (int k = tid; k < QX * QY; k += NT) {
+      const int lx = k % QX, ly = k / QX;
+      if ((lx == 0 || lx == QX - 1) && (ly == 0 || ly == QY - 1)) continue;
+      const int qy = y0 - 1 + ly;
+      if (qy < 0 || qy >= ny) continue;
+      const W4 wc{S.W[0][ly + 1][lx + 1], S.W[1][ly + 1][lx + 1], S.W[2][ly + 1][lx + 1], S.W[3][ly + 1][lx + 1]};
+      const W4 wl{S.W[0][ly + 1][lx], S.W[1][ly + 1][lx], S.W[2][ly + 1][lx], S.W[3][ly + 1][lx]};
+      const W4 wr{S.W[0][ly + 1][lx + 2], S.W[1][ly + 1][lx + 2], S.W[2][ly + 1][lx + 2], S.W[3][ly + 1][lx + 2]};
+      const W4 wd{S.W[0][ly][lx + 1], S.W[1][ly][lx + 1], S.W[2][ly][lx + 1], S.W[3][ly][lx + 1]};
+      const W4 wu{S.W[0][ly + 2][lx + 1], S.W[1][ly + 2][lx + 1], S.W[2][ly + 2][lx + 1], S.W[3][ly + 2][lx + 1]};
+      int cx, cy;
+      const W4 sx = mc4(P, wl, wc, wr, cx);
+      const W4 sy = mc4(P, wd, wc, wu, cy);
+      const W4 q = predict(P, wc, sx, sy, hx, hy, hg);
+      S.Q[0][ly][lx] = q.r;
+      S.Q[1][ly][lx] = q.u;
+      S.Q[2][ly][lx] = q.v;
+      S.Q[3][ly][lx] = q.p;
+      S.Q[4][ly][lx] = sx.r;
+      S.Q[5][ly][lx] = sx.u;
+      S.Q[6][ly][lx] = sx.v;
+      S.Q[7][ly][lx] = sx.p;
+      S.Q[8][ly][lx] = sy.r;
+      S.Q[9][ly][lx] = sy.u;
+      S.Q[10][ly][lx] = sy.v;
+      S.Q[11][ly][lx] = sy.p;
+      const double hr = 0.5 * fabs(sx.r), hp = 0.5 * fabs(sx.p), vr = 0.5 * fabs(sy.r), vp = 0.5 * fabs(sy.p);
+      bad |= !(q.r - hr > 0.0) || !(q.p - hp > 0.0) || !(q.r - vr > 0.0) || !(q.p - vp > 0.0);
+    }
+  }
+  __syncthreads();
+
+  // phase C: every face of the tile once (x faces, then y faces)
+  constexpr int NXF = (TX + 1) * TY, NYF = TX * (TY + 1);
+  for (int k = tid; k < NXF + NYF; k += NT) {
+    if (k < NXF) {
+      const int fx = k % (TX + 1), fy = k / (TX + 1);
+      if (y0 + fy >= ny) continue;
+      const int l = fx, r = fx + 1, y = fy + 1;
+      const FS L{S.Q[0][y][l] + 0.5 * S.Q[4][y][l], S.Q[1][y][l] + 0.5 * S.Q[5][y][l],
+                 S.Q[2][y][l] + 0.5 * S.Q[6][y][l], S.Q[3][y][l] + 0.5 * S.Q[7][y][l]};
+      const FS R{S.Q[0][y][r] - 0.5 * S.Q[4][y][r], S.Q[1][y][r] - 0.5 * S.Q[5][y][r],
+                 S.Q[2][y][r] - 0.5 * S.Q[6][y][r], S.Q[3][y][r] - 0.5 * S.Q[7][y][r]};
+      double F[4];
+      hllc(P, L, R, F);
+      S.fg.F[0][fy][fx] = F[0];
+      S.fg.F[1][fy][fx] = F[1];
+      S.fg.F[2][fy][fx] = F[2];
+      S.fg.F[3][fy][fx] = F[3];
+    } else {
+      const int kk = k - NXF;
+      const int fx = kk % TX, fy = kk / TX;
+      const int j = y0 + fy;
+      if (j > ny) continue;
+      const int x = fx + 1, d = fy, u = fy + 1;  // halo-1 cells below / above the face
+      double G0 = 0.0, G1 = 0.0, G2, G3 = 0.0;
+      if (j == 0) {
+        const FS A{S.Q[0][u][x] - 0.5 * S.Q[8][u][x], S.Q[2][u][x] - 0.5 * S.Q[10][u][x],
+                   S.Q[1][u][x] - 0.5 * S.Q[9][u][x], S.Q[3][u][x] - 0.5 * S.Q[11][u][x]};
+        G2 = wall_pressure(P, A, false);
+      } else if (j == ny) {
+        const FS Bs{S.Q[0][d][x] + 0.5 * S.Q[8][d][x], S.Q[2][d][x] + 0.5 * S.Q[10][d][x],
+                    S.Q[1][d][x] + 0.5 * S.Q[9][d][x], S.Q[3][d][x] + 0.5 * S.Q[11][d][x]};
+        G2 = wall_pressure(P, Bs, true);
+      } else {
+        const FS Bs{S.Q[0][d][x] + 0.5 * S.Q[8][d][x], S.Q[2][d][x] + 0.5 * S.Q[10][d][x],
+                    S.Q[1][d][x] + 0.5 * S.Q[9][d][x], S.Q[3][d][x] + 0.5 * S.Q[11][d][x]};
+        const FS A{S.Q[0][u][x] - 0.5 * S.Q[8][u][x], S.Q[2][u][x] - 0.5 * S.Q[10][u][x],
+                   S.Q[1][u][x] - 0.5 * S.Q[9][u][x], S.Q[3][u][x] - 0.5 * S.Q[11][u][x]};
+        double f[4];
+        hllc(P, Bs, A, f);
+        G0 = f[0];
+        G1 = f[2];
+        G2 = f[1];
+        G3 = f[3];
+      }
+      S.fg.G[0][fy][fx] = G0;
+      S.fg.G[1][fy][fx] = G1;
+      S.fg.G[2][fy][fx] = G2;
+      S.fg.G[3][fy][fx] = G3;
+    }
+  }
+  __syncthreads();
+
+  // phase D: update with the gravity source
+  const bool need_speed = a.ctl != nullptr || a.acc_out != nullptr;
   double smax = 0.0;
-  if (gx < nx && gy < ny) {
-    const size_t c = (size_t)gy * nx + gx;
-    const double u0 = U[c], u1 = U[N + c], u2 = U[2 * N + c], u3 = U[3 * N + c];
+  if (own) {
     const double ax = dt * P.inv_dx, ay = dt * P.inv_dy;
-    double n0 = u0 - ax * (sF[0][ty][tx + 1] - sF[0][ty][tx]) - ay * (sG[0][ty + 1][tx] - sG[0][ty][tx]);
-    double n1 = u1 - ax * (sF[1][ty][tx + 1] - sF[1][ty][tx]) - ay * (sG[1][ty + 1][tx] - sG[1][ty][tx]);
-    double n2 = u2 - ax * (sF[2][ty][tx + 1] - sF[2][ty][tx]) - ay * (sG[2][ty + 1][tx] - sG[2][ty][tx]);
-    double n3 = u3 - ax * (sF[3][ty][tx + 1] - sF[3][ty][tx]) - ay * (sG[3][ty + 1][tx] - sG[3][ty][tx]);
+    double n0 = u0 - ax * (S.fg.F[0][ty][tx + 1] - S.fg.F[0][ty][tx]) - ay * (S.fg.G[0][ty + 1][tx] - S.fg.G[0][ty][tx]);
+    double n1 = u1 - ax * (S.fg.F[1][ty][tx + 1] - S.fg.F[1][ty][tx]) - ay * (S.fg.G[1][ty + 1][tx] - S.fg.G[1][ty][tx]);
+    double n2 = u2 - ax * (S.fg.F[2][ty][tx + 1] - S.fg.F[2][ty][tx]) - ay * (S.fg.G[2][ty + 1][tx] - S.fg.G[2][ty][tx]);
+    double n3 = u3 - ax * (S.fg.F[3][ty][tx + 1] - S.fg.F[3][ty][tx]) - ay * (S.fg.G[3][ty + 1][tx] - S.fg.G[3][ty][tx]);
     const double dtg = dt * P.g_y;
     n2 = n2 + dtg * 0.5 * (u0 + n0);
-    n3 = n3 + dtg * 0.5 * (sG[0][ty][tx] + sG[0][ty + 1][tx]);
+    n3 = n3 + dtg * 0.5 * (S.fg.G[0][ty][tx] + S.fg.G[0][ty + 1][tx]);
     double* Un = a.Un + (size_t)b * 4 * N;
     Un[c] = n0;
     Un[N + c] = n1;
@@ -282,80 +391,85 @@ __global__ __launch_bounds__(TX* TY) void k_step(Params P, StepArgs a) {
     if (a.pool && (nstep % a.snap_interval) == 0) {
       const int slot = nstep / a.snap_interval;
       if (slot < a.snap_slots) {
-        double* s = a.pool + ((size_t)slot * P.nb + b) * 4 * N;
-        s[c] = u0;
-        s[N + c] = u1;
-        s[2 * N + c] = u2;
-        s[3 * N + c] = u3;
-      } else if (tid == 0) {
-        atomicOr(&a.flags->err_overflow, 1);
+        double* sp = a.pool + ((size_t)slot * P.nb + b) * 4 * N;
+        sp[c] = u0;
+        sp[N + c] = u1;
+        sp[2 * N + c] = u2;
+        sp[3 * N + c] = u3;
+      } else {
+        bad |= 2;  // overflow, reported below
       }
     }
-    const W4 w = cons_to_prim(P, n0, n1, n2, n3);
-    bad |= unphysical(w);
-    const double cs = sqrt(P.gamma * w.p / w.r);
-    const double sx = (fabs(w.u) + cs) * P.inv_dx, sy = (fabs(w.v) + cs) * P.inv_dy;
-    smax = sx > sy ? sx : sy;
+    if (need_speed) {
+      const W4 w = cons_to_prim(P, n0, n1, n2, n3);
+      bad |= unphysical(w);
+      const double cs = sqrt(P.gamma * w.p / w.r);
+      const double sx = (fabs(w.u) + cs) * P.inv_dx, sy = (fabs(w.v) + cs) * P.inv_dy;
+      smax = sx > sy ? sx : sy;
+    }
   }
-  if (bad) atomicOr(&a.flags->err_unphys, 1);
+  if (bad & 2) atomicOr(&a.flags->err_overflow, 1);
+  if (bad & 1) atomicOr(&a.flags->err_unphys, 1);
+  if (!need_speed) return;
 
-  if (a.ctl == nullptr && a.dt_next == nullptr) return;
-  // epilogue: CFL step of U^{n+1}
+  // epilogue: fold the block's largest signal speed of U^{n+1} into the
+  // member's accumulator (non-negative doubles order like their bits)
   const double bm = block_max<NT>(smax, sRed);
-  const int nblk = gridDim.x * gridDim.y;
-  if (tid == 0) {
-    a.partial[(size_t)b * nblk + blockIdx.y * gridDim.x + blockIdx.x] = bm;
-    __threadfence();
-    const unsigned prev = atomicAdd(&a.counter[b], 1u);
-    sLast = prev == (unsigned)(nblk - 1);
-  }
-  __syncthreads();
-  if (!sLast) return;
-  __threadfence();
-  double m = 0.0;
-  for (int k = tid; k < nblk; k += NT) m = fmax(m, load_coherent(&a.partial[(size_t)b * nblk + k]));
-  m = block_max<NT>(m, sRed);
   if (tid != 0) return;
-  a.counter[b] = 0u;
   if (a.ctl == nullptr) {
-    a.dt_next[b] = P.cfl / m;
+    atomicMax((unsigned long long*)(a.acc_out + b), (unsigned long long)__double_as_longlong(bm));
     return;
   }
-  Ctl cl = a.ctl[b];
-  const double dtn = cl.dt;
+  const int L = a.launch;
+  atomicMax((unsigned long long*)(a.acc + (size_t)((L + 1) % 3) * P.nb + b),
+            (unsigned long long)__double_as_longlong(bm));
+  if (!first_block) return;
+  a.acc[(size_t)((L + 2) % 3) * P.nb + b] = 0ull;
   if (a.dt_log) {
-    if (cl.nsteps < a.dt_log_cap) a.dt_log[(size_t)b * a.dt_log_cap + cl.nsteps] = dtn;
+    if (nstep < a.dt_log_cap) a.dt_log[(size_t)b * a.dt_log_cap + nstep] = dt;
     else atomicOr(&a.flags->err_overflow, 1);
   }
-  cl.nsteps += 1;
-  if (cl.last) {
-    cl.t = cl.T;
-    cl.done = 1;
-    atomicSub(&a.flags->n_active, 1);
-  } else {
-    cl.t = cl.t + dtn;
-    double d = P.cfl / m;
-    const double rem = cl.T - cl.t;
-    if (d >= rem) {
-      d = rem;
-      cl.last = 1;
-    }
-    cl.dt = d;
-  }
-  a.ctl[b] = cl;
+  Ctl o;
+  o.T = cin->T;
+  o.t = last ? cin->T : cin->t + dt;
+  o.dt_last = dt;
+  o.nsteps = nstep + 1;
+  o.done = last ? 1 : 0;
+  *cout = o;
+  if (last) atomicSub(&a.flags->n_active, 1);
 }
 
 // ----------------------------------------------------------------- adjoint A
+// LDS of adjoint kernel A: the face cotangents reuse the primitive tile,
+// which is dead once the predictor has run (the tile cell's own primitives
+// are recomputed from registers for the predictor adjoint).
 template <int TX, int TY>
-__global__ __launch_bounds__(TX* TY) void k_adj_a(Params P, AdjArgs a) {
-  constexpr int NT = TX * TY;
-  constexpr int QX = TileLDS<TX, TY>::QX, QY = TileLDS<TX, TY>::QY;
-  __shared__ TileLDS<TX, TY> S;
-  __shared__ double sL[4][QY][QX];            // lambda-tilde on the halo-1 region
-  __shared__ double sXL[4][TY][TX + 1];       // x faces: cotangent of the left state (r,u,v,p)
-  __shared__ double sXR[4][TY][TX + 1];       // x faces: cotangent of the right state
-  __shared__ double sYB[4][TY + 1][TX];       // y faces: cotangent of the state below
-  __shared__ double sYT[4][TY + 1][TX];       // y faces: cotangent of the state above
+struct AdjLDS {
+  static constexpr int AX = TX + 4, AY = TY + 4;
+  static constexpr int QX = TX + 2, QY = TY + 2;
+  union {
+    double W[4][AY][AX];
+    struct {
+      double XL[4][TY][TX + 1];  // x faces: cotangent of the left state (r, u, v, p)
+      double XR[4][TY][TX + 1];  // x faces: cotangent of the right state
+      double YB[4][TY + 1][TX];  // y faces: cotangent of the state below
+      double YT[4][TY + 1][TX];  // y faces: cotangent of the state above
+    } f;
+  };
+  double Q[12][QY][QX];
+  double L[4][QY][QX];  // lambda-tilde on the halo-1 region
+};
+
+template <int TX, int TY, int NT>
+__global__ __launch_bounds__(NT) void k_adj_a(Params P, AdjArgs a) {
+  static_assert(NT >= TX * TY && NT % 64 == 0, "one thread per tile cell at least");
+  constexpr int QX = AdjLDS<TX, TY>::QX, QY = AdjLDS<TX, TY>::QY;
+  __shared__ AdjLDS<TX, TY> S;
+  double(&sL)[4][QY][QX] = S.L;
+  double(&sXL)[4][TY][TX + 1] = S.f.XL;
+  double(&sXR)[4][TY][TX + 1] = S.f.XR;
+  double(&sYB)[4][TY + 1][TX] = S.f.YB;
+  double(&sYT)[4][TY + 1][TX] = S.f.YT;
 
   const int b = blockIdx.z;
   if (a.nsteps_limit && a.dt_index >= a.nsteps_limit[b]) return;
@@ -367,6 +481,17 @@ __global__ __launch_bounds__(TX* TY) void k_adj_a(Params P, AdjArgs a) {
   const double* Lm = a.lam_next + (size_t)b * 4 * N;
   const double dt = a.dt[(size_t)b * a.dt_stride + a.dt_index];
   const double hdtg = 0.5 * dt * P.g_y;
+  const int tx = tid % TX, ty = tid / TX;
+  const int gx = x0 + tx, gy = y0 + ty;
+  const bool own = tid < TX * TY && gx < nx && gy < ny;
+  const size_t c = own ? (size_t)gy * nx + gx : 0;
+  double u0 = 1.0, u1 = 0.0, u2 = 0.0, u3 = 1.0;
+  if (own) {
+    u0 = U[c];
+    u1 = U[N + c];
+    u2 = U[2 * N + c];
+    u3 = U[3 * N + c];
+  }
 
   int bad = tile_prims<TX, TY, NT>(P, U, N, x0, y0, S);
   for (int k = tid; k < QX * QY; k += NT) {
@@ -440,9 +565,7 @@ __global__ __launch_bounds__(TX* TY) void k_adj_a(Params P, AdjArgs a) {
   }
   __syncthreads();
 
-  const int tx = tid % TX, ty = tid / TX;
-  const int gx = x0 + tx, gy = y0 + ty;
-  if (gx < nx && gy < ny) {
+  if (own) {
     const int lx = tx + 1, ly = ty + 1;
     const W4 xl{sXR[0][ty][tx], sXR[1][ty][tx], sXR[2][ty][tx], sXR[3][ty][tx]};
     const W4 xr{sXL[0][ty][tx + 1], sXL[1][ty][tx + 1], sXL[2][ty][tx + 1], sXL[3][ty][tx + 1]};
@@ -453,11 +576,10 @@ __global__ __launch_bounds__(TX* TY) void k_adj_a(Params P, AdjArgs a) {
     W4 sxb{0.5 * (xr.r - xl.r), 0.5 * (xr.u - xl.u), 0.5 * (xr.v - xl.v), 0.5 * (xr.p - xl.p)};
     W4 syb{0.5 * (yt.r - yb.r), 0.5 * (yt.u - yb.u), 0.5 * (yt.v - yb.v), 0.5 * (yt.p - yb.p)};
     W4 wb{0.0, 0.0, 0.0, 0.0};
-    const W4 w = ldW(S, lx + 1, ly + 1);
+    const W4 w = cons_to_prim(P, u0, u1, u2, u3);
     const W4 sx = ldQ(S, 1, lx, ly), sy = ldQ(S, 2, lx, ly);
     predict_adj(P, w, sx, sy, 0.5 * dt * P.inv_dx, 0.5 * dt * P.inv_dy, qb, wb, sxb, syb);
     double* Z = a.Z + (size_t)b * 12 * N;
-    const size_t c = (size_t)gy * nx + gx;
     Z[c] = wb.r;
     Z[N + c] = wb.u;
     Z[2 * N + c] = wb.v;
@@ -578,7 +700,7 @@ __global__ void k_init_state(Params P, const double* uv0, double* U) {
 // Per-member reduction, pass 1.  kind: 0 max signal speed of a state;
 // 1 kinetic energy sum of a state; 2/3/4 weighted |uv|^2 of a velocity field
 // (weights 1, 1, rho0/2) honouring comp_mask; 5 dot product of two velocity
-// fields.
+// fields; 6 largest magnitude of a velocity field.
 __global__ __launch_bounds__(256) void k_reduce_partial(Params P, int kind, const double* A, const double* Bv,
                                                         double* partial) {
   __shared__ double red[4];
@@ -605,12 +727,17 @@ __global__ __launch_bounds__(256) void k_reduce_partial(Params P, int kind, cons
       if (kind == 4) w = 0.5 * rho0_at(P, ((int)(c / P.nx) + 0.5) * P.dy);
       acc += w * (u * u + v * v);
     }
-  } else {
+  } else if (kind == 5) {
     const double* x = A + (size_t)b * 2 * N;
     const double* y = Bv + (size_t)b * 2 * N;
     for (size_t c = (size_t)blockIdx.x * 256 + threadIdx.x; c < 2 * N; c += (size_t)nblk * 256) acc += x[c] * y[c];
+  } else {
+    const double* x = A + (size_t)b * 2 * N;
+    for (size_t c = (size_t)blockIdx.x * 256 + threadIdx.x; c < 2 * N; c += (size_t)nblk * 256)
+      acc = fmax(acc, fabs(x[c]));
   }
-  const double r = kind == 0 ? block_max<256>(acc, red) : block_sum<256>(acc, red);
+  const bool is_max = kind == 0 || kind == 6;
+  const double r = is_max ? block_max<256>(acc, red) : block_sum<256>(acc, red);
   if (threadIdx.x == 0) partial[(size_t)b * nblk + blockIdx.x] = r;
 }
 
@@ -620,11 +747,12 @@ __global__ __launch_bounds__(256) void k_reduce_final(Params P, int kind, const 
   __shared__ double red[4];
   const int b = blockIdx.x;
   double acc = 0.0;
+  const bool is_max = kind == 0 || kind == 6;
   for (int k = threadIdx.x; k < nblk; k += 256) {
     const double v = partial[(size_t)b * nblk + k];
-    acc = kind == 0 ? fmax(acc, v) : acc + v;
+    acc = is_max ? fmax(acc, v) : acc + v;
   }
-  const double r = kind == 0 ? block_max<256>(acc, red) : block_sum<256>(acc, red);
+  const double r = is_max ? block_max<256>(acc, red) : block_sum<256>(acc, red);
   if (threadIdx.x != 0) return;
   const double dV = P.dx * P.dy;
   const double N = (double)P.nx * (double)P.ny;
@@ -638,24 +766,25 @@ __global__ __launch_bounds__(256) void k_reduce_final(Params P, int kind, const 
   }
 }
 
-__global__ void k_march_begin(Params P, const double* ms, double T, Ctl* ctl, Flags* flags) {
+__global__ void k_march_begin(Params P, const double* ms, double T, Ctl* ctl, uint64_t* acc, Flags* flags) {
   const int b = threadIdx.x + blockIdx.x * blockDim.x;
   if (b == 0) flags->n_active = P.nb;
   if (b >= P.nb) return;
   Ctl c;
   c.t = 0.0;
   c.T = T;
+  c.dt_last = 0.0;
   c.nsteps = 0;
   c.done = 0;
-  c.last = 0;
-  c.pad = 0;
-  double d = P.cfl / ms[b];
-  if (d >= T) {
-    d = T;
-    c.last = 1;
-  }
-  c.dt = d;
   ctl[b] = c;
+  acc[b] = (uint64_t)__double_as_longlong(ms[b]);
+  acc[P.nb + b] = 0ull;
+  acc[2 * P.nb + b] = 0ull;
+}
+
+__global__ void k_cfl_from_bits(Params P, const uint64_t* acc, double* dt) {
+  const int b = threadIdx.x + blockIdx.x * blockDim.x;
+  if (b < P.nb) dt[b] = P.cfl / __longlong_as_double((long long)acc[b]);
 }
 
 __global__ void k_cfl_from_speed(Params P, const double* ms, double* dt) {
@@ -681,7 +810,8 @@ __global__ void k_copy_meta(Params P, const Ctl* ctl, double* t_out, int32_t* n_
     if (n_out) n_out[b] = n;
   }
   if (ld && ls) {
-    const int m = n < dcap ? n : dcap;
+    int m = n < dcap ? n : dcap;
+    m = m < lcap ? m : lcap;
     for (int k = threadIdx.x; k < m; k += blockDim.x) ld[(size_t)b * dcap + k] = ls[(size_t)b * lcap + k];
   }
 }
@@ -767,39 +897,47 @@ inline dim3 cells_grid(const Params& P, size_t per_member) {
 
 }  // namespace
 
-void tile_dims(int tile, int* tx, int* ty) {
+void tile_dims(int tile, int* tx, int* ty, int* nt) {
+  int a = 16, b = 16, t = 256;
   switch (tile) {
-    case TILE_32x8: *tx = 32; *ty = 8; break;
-    case TILE_64x4: *tx = 64; *ty = 4; break;
-    default: *tx = 16; *ty = 16; break;
+    case TILE_32x8: a = 32; b = 8; break;
+    case TILE_64x4: a = 64; b = 4; break;
+    case TILE_16x16W: t = 576; break;
+    case TILE_32x8W: a = 32; b = 8; t = 576; break;
+    default: break;
   }
+  *tx = a;
+  *ty = b;
+  if (nt) *nt = t;
 }
 
 int step_blocks(const Params& P, int tile) {
   int tx, ty;
-  tile_dims(tile, &tx, &ty);
+  tile_dims(tile, &tx, &ty, nullptr);
   return ((P.nx + tx - 1) / tx) * ((P.ny + ty - 1) / ty);
 }
 
-template <int TX, int TY>
+template <int TX, int TY, int NT>
 static hipError_t launch_step_t(const Params& P, const StepArgs& a, hipStream_t s) {
   dim3 grid((P.nx + TX - 1) / TX, (P.ny + TY - 1) / TY, P.nb);
-  hipLaunchKernelGGL((k_step<TX, TY>), grid, dim3(TX * TY), 0, s, P, a);
+  hipLaunchKernelGGL((k_step<TX, TY, NT>), grid, dim3(NT), 0, s, P, a);
   return hipGetLastError();
 }
 
 hipError_t launch_step(const Params& P, int tile, const StepArgs& a, hipStream_t s) {
   switch (tile) {
-    case TILE_32x8: return launch_step_t<32, 8>(P, a, s);
-    case TILE_64x4: return launch_step_t<64, 4>(P, a, s);
-    default: return launch_step_t<16, 16>(P, a, s);
+    case TILE_32x8: return launch_step_t<32, 8, 256>(P, a, s);
+    case TILE_64x4: return launch_step_t<64, 4, 256>(P, a, s);
+    case TILE_16x16W: return launch_step_t<16, 16, 576>(P, a, s);
+    case TILE_32x8W: return launch_step_t<32, 8, 576>(P, a, s);
+    default: return launch_step_t<16, 16, 256>(P, a, s);
   }
 }
 
-template <int TX, int TY>
+template <int TX, int TY, int NT>
 static hipError_t launch_adj_t(const Params& P, const AdjArgs& a, hipStream_t s) {
   dim3 grid((P.nx + TX - 1) / TX, (P.ny + TY - 1) / TY, P.nb);
-  hipLaunchKernelGGL((k_adj_a<TX, TY>), grid, dim3(TX * TY), 0, s, P, a);
+  hipLaunchKernelGGL((k_adj_a<TX, TY, NT>), grid, dim3(NT), 0, s, P, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const size_t N = (size_t)P.nx * P.ny;
@@ -809,9 +947,11 @@ static hipError_t launch_adj_t(const Params& P, const AdjArgs& a, hipStream_t s)
 
 hipError_t launch_adjoint(const Params& P, int tile, const AdjArgs& a, hipStream_t s) {
   switch (tile) {
-    case TILE_32x8: return launch_adj_t<32, 8>(P, a, s);
-    case TILE_64x4: return launch_adj_t<64, 4>(P, a, s);
-    default: return launch_adj_t<16, 16>(P, a, s);
+    case TILE_32x8: return launch_adj_t<32, 8, 256>(P, a, s);
+    case TILE_64x4: return launch_adj_t<64, 4, 256>(P, a, s);
+    case TILE_16x16W: return launch_adj_t<16, 16, 576>(P, a, s);
+    case TILE_32x8W: return launch_adj_t<32, 8, 576>(P, a, s);
+    default: return launch_adj_t<16, 16, 256>(P, a, s);
   }
 }
 
@@ -829,8 +969,14 @@ hipError_t launch_reduce(const Params& P, int kind, const double* a, const doubl
   return hipGetLastError();
 }
 
-hipError_t launch_march_begin(const Params& P, const double* ms, double T, Ctl* ctl, Flags* flags, hipStream_t s) {
-  hipLaunchKernelGGL(k_march_begin, dim3((P.nb + 63) / 64), dim3(64), 0, s, P, ms, T, ctl, flags);
+hipError_t launch_march_begin(const Params& P, const double* ms, double T, Ctl* ctl, uint64_t* acc, Flags* flags,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_march_begin, dim3((P.nb + 63) / 64), dim3(64), 0, s, P, ms, T, ctl, acc, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_cfl_from_bits(const Params& P, const uint64_t* acc, double* dt, hipStream_t s) {
+  hipLaunchKernelGGL(k_cfl_from_bits, dim3((P.nb + 63) / 64), dim3(64), 0, s, P, acc, dt);
   return hipGetLastError();
 }
 

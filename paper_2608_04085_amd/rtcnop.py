@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librtcnop.so")
 
 STATUS = {0: "RT_OK", -1: "RT_EINVAL", -2: "RT_EHIP", -3: "RT_ENOMEM", -4: "RT_EUNPHYS", -5: "RT_ESTATE"}
-TILES = {"16x16": 0, "32x8": 1, "64x4": 2}
+TILES = {"16x16": 0, "32x8": 1, "64x4": 2, "16x16w": 3, "32x8w": 4}
 
 
 class RTError(RuntimeError):
@@ -64,6 +64,8 @@ def load():
         "rt_set_stream": [_vp, _vp],
         "rt_set_tile": [_vp, _i32],
         "rt_get_tile": [_vp, ctypes.POINTER(_i32)],
+        "rt_get_tiles": [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)],
+        "rt_autotune": [_vp, _vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32)],
         "rt_workspace_bytes": [_vp, _i32, ctypes.POINTER(ctypes.c_size_t)],
         "rt_set_workspace": [_vp, _vp, ctypes.c_size_t, _i32],
         "rt_init_state": [_vp, _vp, _vp],
@@ -76,6 +78,8 @@ def load():
         "rt_pool_bytes": [_vp, _i32, _i32, _i32, ctypes.POINTER(ctypes.c_size_t)],
         "rt_project_to_constraint": [_vp, _vp, ctypes.c_double, _i32, _i32, _vp],
         "rt_dot": [_vp, _vp, _vp, _vp],
+        "rt_max_abs": [_vp, _vp, _vp],
+        "rt_set_graphs": [_vp, _i32],
         "rt_axpy": [_vp, _vp, _vp, _vp, _vp],
         "rt_check_error": [_vp],
         "rt_revolve_stats": [_i32, _i32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
@@ -93,7 +97,7 @@ def load():
 EXPORTED = ["rt_create", "rt_destroy", "rt_set_stream", "rt_workspace_bytes", "rt_set_workspace",
             "rt_init_state", "rt_cfl_dt", "rt_step", "rt_integrate", "rt_kinetic_energy", "rt_step_adjoint",
             "rt_grad_u0", "rt_pool_bytes", "rt_project_to_constraint", "rt_dot", "rt_axpy", "rt_check_error",
-            "rt_last_error"]
+            "rt_last_error", "rt_set_tile", "rt_get_tiles", "rt_autotune", "rt_max_abs", "rt_set_graphs"]
 
 
 def _check(rc: int, call: str):
@@ -183,12 +187,25 @@ class Context:
 
     @property
     def tile(self) -> str:
-        t = ctypes.c_int32()
-        _check(load().rt_get_tile(self._h, ctypes.byref(t)), "rt_get_tile")
-        return {v: k for k, v in TILES.items()}[t.value]
+        """Tile variants in use, "step/adjoint"."""
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        _check(load().rt_get_tiles(self._h, ctypes.byref(a), ctypes.byref(b)), "rt_get_tiles")
+        names = {v: k for k, v in TILES.items()}
+        return f"{names[a.value]}/{names[b.value]}"
 
     def set_tile(self, name: str):
         _check(load().rt_set_tile(self._h, TILES[name]), "rt_set_tile")
+
+    def set_graphs(self, on: bool):
+        _check(load().rt_set_graphs(self._h, 1 if on else 0), "rt_set_graphs")
+
+    def autotune(self, U, reps: int = 20) -> str:
+        """Time every kernel variant on U and keep the fastest (bitwise-identical results)."""
+        self._sync_stream()
+        U = self.as_dev(U)
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        _check(load().rt_autotune(self._h, _ptr(U), int(reps), ctypes.byref(a), ctypes.byref(b)), "rt_autotune")
+        return self.tile
 
     # ---------------------------------------------------------------- calls
     def init_state(self, uv0) -> torch.Tensor:
@@ -281,6 +298,13 @@ class Context:
         b = self.as_dev(b)
         out = self._f64((self.cfg.batch,))
         _check(load().rt_dot(self._h, _ptr(a), _ptr(b), _ptr(out)), "rt_dot")
+        return out
+
+    def max_abs(self, a) -> torch.Tensor:
+        self._sync_stream()
+        a = self.as_dev(a)
+        out = self._f64((self.cfg.batch,))
+        _check(load().rt_max_abs(self._h, _ptr(a), _ptr(out)), "rt_max_abs")
         return out
 
     def axpy(self, x, alpha, y) -> torch.Tensor:

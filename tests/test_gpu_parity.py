@@ -59,7 +59,10 @@ def test_init_and_cfl_match_oracle(cfg):
     np.testing.assert_allclose(ke, o.kinetic_energy(Uo), rtol=1e-13)
 
 
-@pytest.mark.parametrize("tile", ["16x16", "32x8", "64x4"])
+TILE_NAMES = ["16x16", "32x8", "64x4", "16x16w", "32x8w"]
+
+
+@pytest.mark.parametrize("tile", TILE_NAMES)
 @pytest.mark.parametrize("cfg", CASES, ids=lambda c: f"{c.nx}x{c.ny}x{c.batch}")
 def test_one_step_matches_oracle(cfg, tile):
     r = rt().Context(cfg, max_steps=64, tile=tile)
@@ -111,12 +114,12 @@ def test_tile_shapes_are_bitwise_identical():
     uv = inputs.seed_batch(cfg, [1, 2], rms=1e-2)
     outs, adjs = [], []
     lam = torch.from_numpy(np.random.default_rng(5).standard_normal((2, 4, 45, 70)))
-    for tile in ["16x16", "32x8", "64x4"]:
+    for tile in TILE_NAMES:
         r = rt().Context(cfg, max_steps=512, tile=tile)
         U, _, n, _ = r.integrate(r.init_state(uv), 0.2)
         outs.append(host(U))
         adjs.append(host(r.step_adjoint(U, 1e-3, lam)))
-    for k in range(1, 3):
+    for k in range(1, len(TILE_NAMES)):
         np.testing.assert_array_equal(outs[k], outs[0])
         np.testing.assert_array_equal(adjs[k], adjs[0])
 
@@ -153,7 +156,7 @@ def test_step_adjoint_matches_oracle(cfg):
     dt = o.cfl_dt(Uo)
     lam_next = np.random.default_rng(7).standard_normal(Uo.shape)
     ref = o.step_vjp(Uo, dt, lam_next)
-    for tile in ["16x16", "64x4"]:
+    for tile in ["16x16", "64x4", "32x8w"]:
         r = rt().Context(cfg, max_steps=64, tile=tile)
         lam = r.step_adjoint(torch.from_numpy(Uo), torch.from_numpy(dt), torch.from_numpy(lam_next))
         assert normwise(host(lam), ref) <= 1e-12
@@ -264,3 +267,50 @@ def test_pool_too_small_and_zero_perturbation_are_rejected():
     with pytest.raises(rt().RTError) as e:
         r.grad_u0(np.zeros_like(uv), 0.1)
     assert e.value.code == -1
+
+
+def test_graph_replays_match_eager_launches_bitwise():
+    # The march replays a captured graph of 48 steps; every replay must give
+    # the eager (step-by-step) result, with other work between replays.
+    cfg = RTConfig(nx=48, ny=64, batch=2)
+    r = rt().Context(cfg, max_steps=4096)
+    uvs = [inputs.seed_batch(cfg, [2 * k, 2 * k + 1], rms=1e-2) for k in range(3)]
+    eager = []
+    r.set_graphs(False)
+    for uv in uvs:
+        U, t, n, _ = r.integrate(r.init_state(uv), 0.25)
+        eager.append((host(U), host(n)))
+    r.set_graphs(True)
+    for rep in range(2):
+        for k, uv in enumerate(uvs):
+            U, t, n, _ = r.integrate(r.init_state(uv), 0.25)
+            r.kinetic_energy(U)  # eager work between replays
+            np.testing.assert_array_equal(host(U), eager[k][0])
+            np.testing.assert_array_equal(host(n), eager[k][1])
+    R1, g1, _ = r.grad_u0(uvs[0], 0.1, rt().Policy(CKPT_UNIFORM, 8, pool_bytes=64 * 8 * 4 * cfg.cells * 2))
+    r.set_graphs(False)
+    R0, g0, _ = r.grad_u0(uvs[0], 0.1, rt().Policy(CKPT_UNIFORM, 8, pool_bytes=64 * 8 * 4 * cfg.cells * 2))
+    np.testing.assert_array_equal(host(g1), host(g0))
+
+
+def test_spg_search_keeps_the_constraint_and_ascends():
+    from paper_2608_04085_amd import cnop
+
+    cfg = RTConfig(nx=32, ny=64, batch=2)
+    T = 0.3
+    r = rt().Context(cfg, max_steps=4096)
+    uv = inputs.seed_batch(cfg, [0, 1], rms=1e-3)
+    delta = 1e-3
+    pol = rt().Policy(CKPT_UNIFORM, 16, pool_bytes=48 * 8 * 4 * cfg.cells * cfg.batch)
+    u0, _ = r.project_to_constraint(uv, delta, NORM_L2, SET_SPHERE)
+    R0 = host(cnop.ke_ratio(r, u0, T))
+    u, R, g, log = cnop.spg(r, uv, T, delta, iters=4, policy=pol)
+    norms = np.sqrt(host(r.dot(u, u)) * cfg.dx * cfg.dy)
+    np.testing.assert_allclose(norms, delta, rtol=1e-12)
+    Rs = np.array([R0] + log.R)  # [iter+1][B]
+    # non-monotone acceptance: the minimum over the memory window (here the
+    # whole short history) never decreases, and the search ends above its start
+    wmin = np.minimum.accumulate(Rs[::-1], axis=0)[::-1]
+    assert np.all(np.diff(np.minimum.accumulate(Rs, axis=0), axis=0) >= -1e-15)
+    assert np.all(Rs[-1] >= Rs[0]), Rs
+    assert np.all(np.isfinite(np.array(log.chi)))

@@ -7,9 +7,9 @@
 // source, Sec. 2.3; the rest is this implementation's reading):
 //   * primitive variables W = (rho, u, v, p), p = (gamma-1)(E - |m|^2/(2 rho));
 //   * monotonized-central (MC) limited slopes: zero if a*b <= 0 or a
-//     difference is negligible (below 1e-10 of the local scale), else the
-//     central difference (a+b)/2 if it does not exceed 2|a| and 2|b|, else
-//     2a if |a| <= |b|, else 2b;
+//     difference is negligible (below 1e-10 of the local scale), else
+//     sign(a) min(2|a|, 2|b|, |a+b|/2) -- the central difference when it does
+//     not exceed 2|a| and 2|b|, else 2a if |a| <= |b|, else 2b;
 //   * unsplit MUSCL-Hancock half step in primitive variables with gravity
 //     added to v, face states W^{n+1/2} -/+ dW/2;
 //   * HLLC (Toro-Spruce-Speares) with Davis speeds; near-ties of the Davis
@@ -21,6 +21,14 @@
 //     rho^{n+1})/2 and E += dt g_y (G_rho,bottom + G_rho,top)/2, which makes
 //     E + rho*phi (phi = -g_y y) conserved.
 // All branches are evaluated as selects, so a wavefront never diverges.
+//
+// Arithmetic: the gfx950 reciprocal and reciprocal-square-root estimates
+// (v_rcp_f64, v_rsq_f64) are good to about 2^-24; two Newton steps bring
+// them to within an ulp or two of the correctly rounded result.  Divisions
+// are products with shared reciprocals, and the HLLC star flux is rearranged
+// so that E/rho and p/m need no division.  The forward kernel and the
+// adjoint's recomputation call the same functions, so both see the same
+// values and take the same decisions.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -33,20 +41,53 @@ struct Params {
   double rho_h, rho_l, y0, h, p_int;
 };
 
+// Primitive state plus the reciprocal density, which later steps reuse.
 struct W4 {
-  double r, u, v, p;
+  double r, u, v, p, ri;
 };
 
 #define RT_DEV __device__ __forceinline__
 
+// 1/b for a normal b: hardware estimate + two Newton steps.
+RT_DEV double rcp(double b) {
+  double r = __builtin_amdgcn_rcp(b);
+  double e = fma(-b, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-b, r, 1.0);
+  return fma(r, e, r);
+}
+
+// sqrt(x) and 1/sqrt(x) for a positive normal x: reciprocal square-root
+// estimate, then two coupled Newton (Goldschmidt) steps on both.
+RT_DEV void sqrt_rsqrt(double x, double& s, double& rs) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double h = 0.5 * y;
+  double g = x * y;
+  double e = fma(-g, h, 0.5);  // 1/2 - x y^2 / 2
+  g = fma(g, e, g);
+  h = fma(h, e, h);
+  e = fma(-g, h, 0.5);
+  g = fma(g, e, g);
+  h = fma(h, e, h);
+  s = g;
+  rs = 2.0 * h;
+}
+
+RT_DEV double sqrt_fast(double x) {
+  double s, rs;
+  sqrt_rsqrt(x, s, rs);
+  return s;
+}
+
 RT_DEV W4 cons_to_prim(const Params& P, double r, double mx, double my, double E) {
-  const double ri = 1.0 / r;
+  const double ri = rcp(r);
   const double u = mx * ri, v = my * ri;
   W4 w;
   w.r = r;
   w.u = u;
   w.v = v;
   w.p = P.gm1 * (E - 0.5 * (mx * u + my * v));
+  w.ri = ri;
   return w;
 }
 
@@ -57,7 +98,7 @@ RT_DEV bool unphysical(const W4& w) {
 
 // Adjoint of cons_to_prim: W-bar -> U-bar at the state (r, u, v).
 RT_DEV void prim_adj(const Params& P, const W4& w, const W4& wb, double ub[4]) {
-  const double ri = 1.0 / w.r;
+  const double ri = w.ri;
   ub[0] = wb.r - (w.u * wb.u + w.v * wb.v) * ri + 0.5 * P.gm1 * (w.u * w.u + w.v * w.v) * wb.p;
   ub[1] = wb.u * ri - P.gm1 * w.u * wb.p;
   ub[2] = wb.v * ri - P.gm1 * w.v * wb.p;
@@ -72,17 +113,24 @@ RT_DEV void prim_adj(const Params& P, const W4& w, const W4& wb, double ub[4]) {
 // forward state changes by at most this tolerance, relative.
 constexpr double kTieTol = 1e-10;
 
-// MC-limited slope and its case: 0 zero, 1 central, 2 -> 2a, 3 -> 2b.  The
-// zero case also covers a negligible difference (small_a / small_b).
-RT_DEV double mc(double a, double b, bool small_a, bool small_b, int& code) {
+// MC-limited slope: zero if a*b <= 0 or a difference is negligible, else
+// sign(a) min(2|a|, 2|b|, |a+b|/2), which equals the value of the case
+// (central, 2a or 2b) that the limiter selects.
+RT_DEV double mc_value(double a, double b, bool small_a, bool small_b) {
+  const bool zero = (a * b <= 0.0) || small_a || small_b;
+  const double m = fmin(fmin(2.0 * fabs(a), 2.0 * fabs(b)), fabs(0.5 * (a + b)));
+  return zero ? 0.0 : copysign(m, a);
+}
+
+// The limiter's case, for the adjoint: 0 zero, 1 central, 2 -> 2a, 3 -> 2b.
+// Where two cases give the same value the central one, then 2a, is taken.
+RT_DEV int mc_code(double a, double b, bool small_a, bool small_b) {
   const double c = 0.5 * (a + b);
   const double aa = fabs(a), ab = fabs(b), ac = fabs(c);
   const bool zero = (a * b <= 0.0) || small_a || small_b;
   const bool central = (ac <= 2.0 * aa) && (ac <= 2.0 * ab);
   const bool left = aa <= ab;
-  const double s = zero ? 0.0 : (central ? c : (left ? 2.0 * a : 2.0 * b));
-  code = zero ? 0 : (central ? 1 : (left ? 2 : 3));
-  return s;
+  return zero ? 0 : (central ? 1 : (left ? 2 : 3));
 }
 
 // Weights (d s/d a, d s/d b) of an MC case.
@@ -91,22 +139,30 @@ RT_DEV void mc_weights(int code, double& wa, double& wb) {
   wb = code == 1 ? 0.5 : (code == 3 ? 2.0 : 0.0);
 }
 
-// Slopes of the four primitives; codes packed 2 bits per variable.  A
-// difference is negligible below kTieTol times the centre cell's density,
-// pressure, or sound speed (velocities: d^2 rho <= kTieTol^2 gamma p).
+// Slopes of the four primitives (and, if CODES, their cases packed 2 bits
+// per variable).  A difference is negligible below kTieTol times the centre
+// cell's density, pressure, or sound speed (velocities: d^2 <= kTieTol^2
+// gamma p / rho).
+template <bool CODES>
 RT_DEV W4 mc4(const Params& P, const W4& m, const W4& c, const W4& p, int& codes) {
-  const double tr = kTieTol * c.r, tp = kTieTol * c.p, tv2 = kTieTol * kTieTol * P.gamma * c.p;
-  int k0, k1, k2, k3;
+  const double tr = kTieTol * c.r, tp = kTieTol * c.p, tv2 = kTieTol * kTieTol * P.gamma * c.p * c.ri;
   W4 s;
   const double ar = c.r - m.r, br = p.r - c.r;
   const double au = c.u - m.u, bu = p.u - c.u;
   const double av = c.v - m.v, bv = p.v - c.v;
   const double ap = c.p - m.p, bp = p.p - c.p;
-  s.r = mc(ar, br, fabs(ar) <= tr, fabs(br) <= tr, k0);
-  s.u = mc(au, bu, au * au * c.r <= tv2, bu * bu * c.r <= tv2, k1);
-  s.v = mc(av, bv, av * av * c.r <= tv2, bv * bv * c.r <= tv2, k2);
-  s.p = mc(ap, bp, fabs(ap) <= tp, fabs(bp) <= tp, k3);
-  codes = k0 | (k1 << 2) | (k2 << 4) | (k3 << 6);
+  const bool sar = fabs(ar) <= tr, sbr = fabs(br) <= tr;
+  const bool sau = au * au <= tv2, sbu = bu * bu <= tv2;
+  const bool sav = av * av <= tv2, sbv = bv * bv <= tv2;
+  const bool sap = fabs(ap) <= tp, sbp = fabs(bp) <= tp;
+  s.r = mc_value(ar, br, sar, sbr);
+  s.u = mc_value(au, bu, sau, sbu);
+  s.v = mc_value(av, bv, sav, sbv);
+  s.p = mc_value(ap, bp, sap, sbp);
+  s.ri = 0.0;
+  if (CODES)
+    codes = mc_code(ar, br, sar, sbr) | (mc_code(au, bu, sau, sbu) << 2) | (mc_code(av, bv, sav, sbv) << 4) |
+            (mc_code(ap, bp, sap, sbp) << 6);
   return s;
 }
 
@@ -114,28 +170,29 @@ RT_DEV W4 mc4(const Params& P, const W4& m, const W4& c, const W4& p, int& codes
 // normal velocity negated and the pressure extrapolated hydrostatically
 // (dp/dy = rho g_y) over the distance between the two cell centres.
 RT_DEV W4 ghost_bottom(const Params& P, const W4& w) {
-  return W4{w.r, w.u, -w.v, w.p - P.g_y * w.r * P.dy};
+  return W4{w.r, w.u, -w.v, w.p - P.g_y * w.r * P.dy, w.ri};
 }
 RT_DEV W4 ghost_top(const Params& P, const W4& w) {
-  return W4{w.r, w.u, -w.v, w.p + P.g_y * w.r * P.dy};
+  return W4{w.r, w.u, -w.v, w.p + P.g_y * w.r * P.dy, w.ri};
 }
 
 // MUSCL-Hancock half step: q = W - hx A_x(W) sx - hy A_y(W) sy + (dt/2) g.
 RT_DEV W4 predict(const Params& P, const W4& w, const W4& sx, const W4& sy, double hx, double hy,
                   double half_dt_g) {
-  const double ri = 1.0 / w.r;
+  const double ri = w.ri;
   W4 q;
   q.r = w.r - hx * (w.u * sx.r + w.r * sx.u) - hy * (w.v * sy.r + w.r * sy.v);
   q.u = w.u - hx * (w.u * sx.u + sx.p * ri) - hy * (w.v * sy.u);
   q.v = w.v - hx * (w.u * sx.v) - hy * (w.v * sy.v + sy.p * ri) + half_dt_g;
   q.p = w.p - hx * (P.gamma * w.p * sx.u + w.u * sx.p) - hy * (P.gamma * w.p * sy.v + w.v * sy.p);
+  q.ri = 0.0;
   return q;
 }
 
 // Adjoint of predict: q-bar -> (W-bar, sx-bar, sy-bar), accumulated.
 RT_DEV void predict_adj(const Params& P, const W4& w, const W4& sx, const W4& sy, double hx, double hy,
                         const W4& qb, W4& wb, W4& sxb, W4& syb) {
-  const double ri = 1.0 / w.r;
+  const double ri = w.ri;
   const double g = P.gamma;
   wb.r += qb.r - hx * qb.r * sx.u - hy * qb.r * sy.v + (hx * qb.u * sx.p + hy * qb.v * sy.p) * ri * ri;
   wb.u += qb.u - hx * (qb.r * sx.r + qb.u * sx.u + qb.v * sx.v + qb.p * sx.p);
@@ -156,142 +213,158 @@ RT_DEV void predict_adj(const Params& P, const W4& w, const W4& sx, const W4& sy
 // Flux in face-normal order: mass, normal momentum, tangential momentum,
 // energy.  F = F_K + sigma (U*_K - U_K) with K = left if S* >= 0 else right,
 // sigma = min(S_L, 0) on the left, max(S_R, 0) on the right: the four cases
-// S_L >= 0 / S* >= 0 / S_R > 0 / else in one formula.
+// S_L >= 0 / S* >= 0 / S_R > 0 / else in one formula.  With d = S_K - n_K,
+// m = rho_K d and k = 1/(S_K - S*), the star state is
+//   U*_K = (m k, m k S*, m k t, k (d E_K + (S* - n_K)(m S* + p_K))),
+// the textbook star state with E/rho and p/m multiplied out.
 struct FS {
   double r, n, t, p;
 };
 
-RT_DEV void hllc(const Params& P, const FS& L, const FS& R, double F[4]) {
+// Intermediates of one HLLC evaluation, shared by the flux and its adjoint.
+struct HllcCore {
+  double cL, cR, rcL, rcR, riL, riR;  // sound speeds, their reciprocals, 1/rho
+  bool selL, selR, left, act;
+  double SL, SR, dL, dR, mL, mR, rdn, SS;
+  // selected side K
+  double r, n, t, p, S, d, m, sig, E, m0, k, f, A, B2, G;
+};
+
+RT_DEV HllcCore hllc_core(const Params& P, const FS& L, const FS& R) {
+  HllcCore h;
   const double g = P.gamma;
-  const double cL = sqrt(g * L.p / L.r), cR = sqrt(g * R.p / R.r);
-  const double tie = kTieTol * (cL + cR);  // near-ties resolve to the left state
-  const double aL = L.n - cL, bL = R.n - cR, aR = L.n + cL, bR = R.n + cR;
-  const double SL = aL <= bL + tie ? aL : bL;
-  const double SR = aR >= bR - tie ? aR : bR;
-  const double mL = L.r * (SL - L.n), mR = R.r * (SR - R.n);
-  const double SS = (R.p - L.p + mL * L.n - mR * R.n) / (mL - mR);
-  const bool left = SS >= -tie;
-  const double r = left ? L.r : R.r, n = left ? L.n : R.n, t = left ? L.t : R.t, p = left ? L.p : R.p;
-  const double S = left ? SL : SR, m = left ? mL : mR;
-  const double sig = left ? (SL < 0.0 ? SL : 0.0) : (SR > 0.0 ? SR : 0.0);
-  const double E = p * P.inv_gm1 + 0.5 * r * (n * n + t * t);
-  const double m0 = r * n;
-  const double den = sig != 0.0 ? (S - SS) : 1.0;
-  const double f = sig != 0.0 ? m / den : 0.0;
-  const double H = E / r + (SS - n) * (SS + p / m);
-  F[0] = m0 + sig * (f - r);
-  F[1] = m0 * n + p + sig * (f * SS - m0);
-  F[2] = m0 * t + sig * (f * t - r * t);
-  F[3] = n * (E + p) + sig * (f * H - E);
+  h.riL = rcp(L.r);
+  h.riR = rcp(R.r);
+  sqrt_rsqrt(g * L.p * h.riL, h.cL, h.rcL);
+  sqrt_rsqrt(g * R.p * h.riR, h.cR, h.rcR);
+  const double tie = kTieTol * (h.cL + h.cR);  // near-ties resolve to the left state
+  const double aL = L.n - h.cL, bL = R.n - h.cR, aR = L.n + h.cL, bR = R.n + h.cR;
+  h.selL = aL <= bL + tie;
+  h.selR = aR >= bR - tie;
+  h.SL = h.selL ? aL : bL;
+  h.SR = h.selR ? aR : bR;
+  h.dL = h.SL - L.n;
+  h.dR = h.SR - R.n;
+  h.mL = L.r * h.dL;
+  h.mR = R.r * h.dR;
+  const double num = R.p - L.p + h.mL * L.n - h.mR * R.n;
+  h.rdn = rcp(h.mL - h.mR);
+  h.SS = num * h.rdn;
+  h.left = h.SS >= -tie;
+  h.r = h.left ? L.r : R.r;
+  h.n = h.left ? L.n : R.n;
+  h.t = h.left ? L.t : R.t;
+  h.p = h.left ? L.p : R.p;
+  h.S = h.left ? h.SL : h.SR;
+  h.d = h.left ? h.dL : h.dR;
+  h.m = h.left ? h.mL : h.mR;
+  h.act = h.left ? (h.SL < 0.0) : (h.SR > 0.0);
+  h.sig = h.act ? h.S : 0.0;
+  h.E = h.p * P.inv_gm1 + 0.5 * h.r * (h.n * h.n + h.t * h.t);
+  h.m0 = h.r * h.n;
+  h.k = h.act ? rcp(h.S - h.SS) : 0.0;
+  h.f = h.m * h.k;
+  h.A = h.SS - h.n;
+  h.B2 = h.m * h.SS + h.p;
+  h.G = h.d * h.E + h.A * h.B2;
+  return h;
 }
 
-// Adjoint of hllc: given F-bar, accumulate L-bar and R-bar.
+RT_DEV void hllc(const Params& P, const FS& L, const FS& R, double F[4]) {
+  const HllcCore h = hllc_core(P, L, R);
+  const double fH = h.k * h.G;
+  F[0] = h.m0 + h.sig * (h.f - h.r);
+  F[1] = h.m0 * h.n + h.p + h.sig * (h.f * h.SS - h.m0);
+  F[2] = h.m0 * h.t + h.sig * (h.f * h.t - h.r * h.t);
+  F[3] = h.n * (h.E + h.p) + h.sig * (fH - h.E);
+}
+
+// Adjoint of hllc: given F-bar, accumulate L-bar and R-bar (reverse of the
+// computational graph of hllc_core + hllc).
 RT_DEV void hllc_adj(const Params& P, const FS& L, const FS& R, const double Fb[4], FS& Lb, FS& Rb) {
+  const HllcCore h = hllc_core(P, L, R);
   const double g = P.gamma;
-  // ---- forward recompute
-  const double cL = sqrt(g * L.p / L.r), cR = sqrt(g * R.p / R.r);
-  const double tie = kTieTol * (cL + cR);
-  const double aL = L.n - cL, bL = R.n - cR, aR = L.n + cL, bR = R.n + cR;
-  const bool selL = aL <= bL + tie, selR = aR >= bR - tie;
-  const double SL = selL ? aL : bL;
-  const double SR = selR ? aR : bR;
-  const double dL = SL - L.n, dR = SR - R.n;
-  const double mL = L.r * dL, mR = R.r * dR;
-  const double num = R.p - L.p + mL * L.n - mR * R.n;
-  const double dn = mL - mR;
-  const double SS = num / dn;
-  const bool left = SS >= -tie;
-  const double r = left ? L.r : R.r, n = left ? L.n : R.n, t = left ? L.t : R.t, p = left ? L.p : R.p;
-  const double S = left ? SL : SR, m = left ? mL : mR;
-  const bool act = left ? (SL < 0.0) : (SR > 0.0);
-  const double sig = act ? S : 0.0;
-  const double E = p * P.inv_gm1 + 0.5 * r * (n * n + t * t);
-  const double m0 = r * n;
-  const double den = act ? (S - SS) : 1.0;
-  const double f = act ? m / den : 0.0;
-  const double A = SS - n, Bq = SS + p / m;
-  const double H = E / r + A * Bq;
-  // ---- reverse
-  // F = FK + sig (Us - Uk), FK = (m0, m0 n + p, m0 t, n (E + p)),
-  // Us = (f, f SS, f t, f H), Uk = (r, m0, r t, E).
-  const double sigb = act ? (Fb[0] * (f - r) + Fb[1] * (f * SS - m0) + Fb[2] * (f * t - r * t) + Fb[3] * (f * H - E))
-                          : 0.0;
-  const double us0 = sig * Fb[0], us1 = sig * Fb[1], us2 = sig * Fb[2], us3 = sig * Fb[3];
-  double rb = 0.0, nb = 0.0, tb = 0.0, pb = 0.0, Eb = 0.0, SSb = 0.0, mb = 0.0, Sb = 0.0;
-  // Us
-  const double fb = us0 + us1 * SS + us2 * t + us3 * H;
-  SSb += us1 * f;
-  tb += us2 * f;
-  const double Hb = us3 * f;
-  // H = E/r + A*Bq
-  Eb += Hb / r;
-  rb -= Hb * E / (r * r);
-  const double Ab = Hb * Bq, Bqb = Hb * A;
-  SSb += Ab + Bqb;
+  const double fH = h.k * h.G;
+  const double sig = h.sig;
+  // F0 = m0 + sig (f - r); F1 = m0 n + p + sig (f SS - m0);
+  // F2 = m0 t + sig (f t - r t); F3 = n (E + p) + sig (fH - E)
+  const double sigb =
+      h.act ? (Fb[0] * (h.f - h.r) + Fb[1] * (h.f * h.SS - h.m0) + Fb[2] * (h.f * h.t - h.r * h.t) + Fb[3] * (fH - h.E))
+            : 0.0;
+  const double fb = sig * (Fb[0] + Fb[1] * h.SS + Fb[2] * h.t);
+  const double fHb = sig * Fb[3];
+  double SSb = sig * Fb[1] * h.f;
+  double tb = Fb[2] * (h.m0 + sig * (h.f - h.r));
+  double rb = -sig * (Fb[0] + Fb[2] * h.t);
+  const double m0b = Fb[0] + Fb[1] * h.n + Fb[2] * h.t - sig * Fb[1];
+  double nb = Fb[1] * h.m0 + Fb[3] * (h.E + h.p);
+  double pb = Fb[1] + Fb[3] * h.n;
+  double Eb = Fb[3] * (h.n - sig);
+  // fH = k G, G = d E + A B2, A = SS - n, B2 = m SS + p
+  double kb = fHb * h.G;
+  const double Gb = fHb * h.k;
+  const double db = Gb * h.E;
+  Eb += Gb * h.d;
+  const double Ab = Gb * h.B2, B2b = Gb * h.A;
+  double mb = B2b * h.SS;
+  SSb += B2b * h.m + Ab;
+  pb += B2b;
   nb -= Ab;
-  pb += Bqb / m;
-  mb -= Bqb * p / (m * m);
-  // f = m / (S - SS)
-  if (act) {
-    mb += fb / den;
-    Sb -= fb * f / den;
-    SSb += fb * f / den;
+  // f = m k
+  mb += fb * h.k;
+  kb += fb * h.m;
+  // k = 1/(S - SS) when active
+  double Sb = 0.0;
+  if (h.act) {
+    const double kk = kb * h.k * h.k;
+    Sb -= kk;
+    SSb += kk;
   }
-  // -Uk part (sig * (-Uk)): Uk = (r, m0, r t, E)
-  const double ukb0 = -us0, ukb1 = -us1, ukb2 = -us2, ukb3 = -us3;
-  rb += ukb0 + ukb2 * t;
-  tb += ukb2 * r;
-  double m0b = ukb1;
-  Eb += ukb3;
-  // FK
-  m0b += Fb[0] + Fb[1] * n + Fb[2] * t;
-  nb += Fb[1] * m0 + Fb[3] * (E + p);
-  pb += Fb[1] + Fb[3] * n;
-  tb += Fb[2] * m0;
-  Eb += Fb[3] * n;
   // m0 = r n
-  rb += m0b * n;
-  nb += m0b * r;
+  rb += m0b * h.n;
+  nb += m0b * h.r;
   // E = p/(g-1) + r (n^2 + t^2)/2
   pb += Eb * P.inv_gm1;
-  rb += Eb * 0.5 * (n * n + t * t);
-  nb += Eb * r * n;
-  tb += Eb * r * t;
+  rb += Eb * 0.5 * (h.n * h.n + h.t * h.t);
+  nb += Eb * h.r * h.n;
+  tb += Eb * h.r * h.t;
   // sigma = S when active
   Sb += sigb;
   // scatter the side-K quantities to L or R
   double rLb = 0, nLb = 0, tLb = 0, pLb = 0, rRb = 0, nRb = 0, tRb = 0, pRb = 0;
-  double SLb = 0, SRb = 0, mLb = 0, mRb = 0;
-  if (left) {
-    rLb += rb; nLb += nb; tLb += tb; pLb += pb; SLb += Sb; mLb += mb;
+  double SLb = 0, SRb = 0, mLb = 0, mRb = 0, dLb = 0, dRb = 0;
+  if (h.left) {
+    rLb += rb; nLb += nb; tLb += tb; pLb += pb; SLb += Sb; mLb += mb; dLb += db;
   } else {
-    rRb += rb; nRb += nb; tRb += tb; pRb += pb; SRb += Sb; mRb += mb;
+    rRb += rb; nRb += nb; tRb += tb; pRb += pb; SRb += Sb; mRb += mb; dRb += db;
   }
-  // SS = num / dn
-  const double numb = SSb / dn;
-  const double dnb = -SSb * SS / dn;
+  // SS = num / dn, dn = mL - mR, num = pR - pL + mL nL - mR nR
+  const double numb = SSb * h.rdn;
+  const double dnb = -SSb * h.SS * h.rdn;
   pRb += numb;
   pLb -= numb;
   mLb += numb * L.n + dnb;
-  nLb += numb * mL;
+  nLb += numb * h.mL;
   mRb -= numb * R.n + dnb;
-  nRb -= numb * mR;
-  // m_K = r_K (S_K - n_K)
-  rLb += mLb * dL;
-  SLb += mLb * L.r;
-  nLb -= mLb * L.r;
-  rRb += mRb * dR;
-  SRb += mRb * R.r;
-  nRb -= mRb * R.r;
+  nRb -= numb * h.mR;
+  // m_K = r_K d_K, d_K = S_K - n_K
+  rLb += mLb * h.dL;
+  dLb += mLb * L.r;
+  rRb += mRb * h.dR;
+  dRb += mRb * R.r;
+  SLb += dLb;
+  nLb -= dLb;
+  SRb += dRb;
+  nRb -= dRb;
   // Davis speeds
   double cLb = 0.0, cRb = 0.0;
-  if (selL) { nLb += SLb; cLb -= SLb; } else { nRb += SLb; cRb -= SLb; }
-  if (selR) { nLb += SRb; cLb += SRb; } else { nRb += SRb; cRb += SRb; }
-  // c = sqrt(g p / r)
-  pLb += cLb * g / (2.0 * cL * L.r);
-  rLb -= cLb * cL / (2.0 * L.r);
-  pRb += cRb * g / (2.0 * cR * R.r);
-  rRb -= cRb * cR / (2.0 * R.r);
+  if (h.selL) { nLb += SLb; cLb -= SLb; } else { nRb += SLb; cRb -= SLb; }
+  if (h.selR) { nLb += SRb; cLb += SRb; } else { nRb += SRb; cRb += SRb; }
+  // c = sqrt(g p / r): dc/dp = g/(2 c r), dc/dr = -c/(2 r)
+  pLb += cLb * 0.5 * g * h.rcL * h.riL;
+  rLb -= cLb * 0.5 * h.cL * h.riL;
+  pRb += cRb * 0.5 * g * h.rcR * h.riR;
+  rRb -= cRb * 0.5 * h.cR * h.riR;
   Lb.r += rLb; Lb.n += nLb; Lb.t += tLb; Lb.p += pLb;
   Rb.r += rRb; Rb.n += nRb; Rb.t += tRb; Rb.p += pRb;
 }
@@ -300,13 +373,15 @@ RT_DEV void hllc_adj(const Params& P, const FS& L, const FS& R, const double Fb[
 // face-normal problem) p* = p + r n (|n| + c + n); bottom wall (interior
 // above, on the right) p* = p - r n (|n| + c - n).
 RT_DEV double wall_pressure(const Params& P, const FS& w, bool top) {
-  const double c = sqrt(P.gamma * w.p / w.r);
+  const double c = sqrt_fast(P.gamma * w.p * rcp(w.r));
   const double an = w.n < -kTieTol * c ? -w.n : w.n;  // |n|; near-zero n counts as >= 0
   return top ? w.p + w.r * w.n * (an + c + w.n) : w.p - w.r * w.n * (an + c - w.n);
 }
 
 RT_DEV void wall_pressure_adj(const Params& P, const FS& w, bool top, double psb, FS& wb) {
-  const double c = sqrt(P.gamma * w.p / w.r);
+  const double ri = rcp(w.r);
+  double c, rc;
+  sqrt_rsqrt(P.gamma * w.p * ri, c, rc);
   const bool neg = w.n < -kTieTol * c;
   const double sg = neg ? -1.0 : 1.0;
   const double an = neg ? -w.n : w.n;
@@ -327,14 +402,14 @@ RT_DEV void wall_pressure_adj(const Params& P, const FS& w, bool top, double psb
   wb.n += nb;
   wb.p += psb;
   // c = sqrt(gamma p / r)
-  wb.p += qb * P.gamma / (2.0 * c * w.r);
-  wb.r -= qb * c / (2.0 * w.r);
+  wb.p += qb * 0.5 * P.gamma * rc * ri;
+  wb.r -= qb * 0.5 * c * ri;
 }
 
 // Largest signal speed of a state, for the CFL step.
 RT_DEV double signal_speed(const Params& P, double r, double mx, double my, double E) {
   const W4 w = cons_to_prim(P, r, mx, my, E);
-  const double c = sqrt(P.gamma * w.p / w.r);
+  const double c = sqrt_fast(P.gamma * w.p * w.ri);
   const double sx = (fabs(w.u) + c) * P.inv_dx, sy = (fabs(w.v) + c) * P.inv_dy;
   return sx > sy ? sx : sy;
 }

@@ -28,9 +28,12 @@ namespace rtk {
 
 namespace {
 
+// Periodic column index (the tile halo reaches at most TX + 2 columns past
+// the domain, so a few conditional adds replace an integer division).
 __device__ __forceinline__ int wrapx(int i, int nx) {
-  i %= nx;
-  return i < 0 ? i + nx : i;
+  while (i < 0) i += nx;
+  while (i >= nx) i -= nx;
+  return i;
 }
 
 __device__ __forceinline__ double wave_max(double v) {
@@ -93,11 +96,14 @@ template <int TX, int TY, int NT, class LDS>
 __device__ int tile_prims(const Params& P, const double* U, size_t N, int x0, int y0, LDS& S) {
   constexpr int AX = TX + 4, AY = TY + 4;
   int bad = 0;
-  for (int k = threadIdx.x; k < AX * AY; k += NT) {
+#pragma unroll
+  for (int it = 0; it < (AX * AY + NT - 1) / NT; ++it) {
+    const int k = (int)threadIdx.x + it * NT;
+    if (k >= AX * AY) break;
     const int lx = k % AX, ly = k / AX;
     const int gx = wrapx(x0 - 2 + lx, P.nx);
     const int gy = y0 - 2 + ly;
-    W4 w{1.0, 0.0, 0.0, 1.0};
+    W4 w{1.0, 0.0, 0.0, 1.0, 1.0};
     if (gy >= -1 && gy <= P.ny) {
       const int sy = gy < 0 ? 0 : (gy >= P.ny ? P.ny - 1 : gy);
       const size_t c = (size_t)sy * P.nx + gx;
@@ -110,17 +116,18 @@ __device__ int tile_prims(const Params& P, const double* U, size_t N, int x0, in
     S.W[1][ly][lx] = w.u;
     S.W[2][ly][lx] = w.v;
     S.W[3][ly][lx] = w.p;
+    S.W[4][ly][lx] = w.ri;
   }
   return bad;
 }
 
 template <class LDS>
 __device__ __forceinline__ W4 ldW(const LDS& S, int x, int y) {
-  return W4{S.W[0][y][x], S.W[1][y][x], S.W[2][y][x], S.W[3][y][x]};
+  return W4{S.W[0][y][x], S.W[1][y][x], S.W[2][y][x], S.W[3][y][x], S.W[4][y][x]};
 }
 template <class LDS>
 __device__ __forceinline__ W4 ldQ(const LDS& S, int k, int x, int y) {
-  return W4{S.Q[4 * k + 0][y][x], S.Q[4 * k + 1][y][x], S.Q[4 * k + 2][y][x], S.Q[4 * k + 3][y][x]};
+  return W4{S.Q[4 * k + 0][y][x], S.Q[4 * k + 1][y][x], S.Q[4 * k + 2][y][x], S.Q[4 * k + 3][y][x], 0.0};
 }
 
 // Phase B: slopes and predictor on the cross-shaped halo-1 region.  If
@@ -137,8 +144,8 @@ __device__ int tile_predict(const Params& P, double dt, int x0, int y0, LDS& S, 
     if (gy < 0 || gy >= P.ny) continue;
     const W4 wc = ldW(S, lx + 1, ly + 1);
     int cx, cy;
-    const W4 sx = mc4(P, ldW(S, lx, ly + 1), wc, ldW(S, lx + 2, ly + 1), cx);
-    const W4 sy = mc4(P, ldW(S, lx + 1, ly), wc, ldW(S, lx + 1, ly + 2), cy);
+    const W4 sx = mc4<true>(P, ldW(S, lx, ly + 1), wc, ldW(S, lx + 2, ly + 1), cx);
+    const W4 sy = mc4<true>(P, ldW(S, lx + 1, ly), wc, ldW(S, lx + 1, ly + 2), cy);
     const W4 q = predict(P, wc, sx, sy, hx, hy, hg);
     S.Q[0][ly][lx] = q.r;
     S.Q[1][ly][lx] = q.u;
@@ -193,7 +200,7 @@ struct StepLDS {
   static constexpr int AX = TX + 4, AY = TY + 4;
   static constexpr int QX = TX + 2, QY = TY + 2;
   union {
-    double W[4][AY][AX];
+    double W[5][AY][AX];  // rho, u, v, p, 1/rho
     struct {
       double F[4][TY][TX + 1];
       double G[4][TY + 1][TX];
@@ -257,31 +264,8 @@ __global__ __launch_bounds__(NT) void k_step(Params P, StepArgs a) {
   }
 
   // phase A: primitives of the tile + halo 2
-  constexpr int AX = StepLDS<TX, TY>::AX, AY = StepLDS<TX, TY>::AY;
   constexpr int QX = StepLDS<TX, TY>::QX, QY = StepLDS<TX, TY>::QY;
-  int bad = 0;
-#pragma unroll
-  for (int it = 0; it < (AX * AY + NT - 1) / NT; ++it) {
-    const int k = tid + it * NT;
-    if (k < AX * AY) {
-      const int lx = k % AX, ly = k / AX;
-      const int hx = wrapx(x0 - 2 + lx, nx);
-      const int hy = y0 - 2 + ly;
-      W4 w{1.0, 0.0, 0.0, 1.0};
-      if (hy >= -1 && hy <= ny) {
-        const int sy = hy < 0 ? 0 : (hy >= ny ? ny - 1 : hy);
-        const size_t h = (size_t)sy * nx + hx;
-        w = cons_to_prim(P, U[h], U[N + h], U[2 * N + h], U[3 * N + h]);
-        if (hy >= 0 && hy < ny) bad |= unphysical(w);
-        if (hy < 0) w = ghost_bottom(P, w);
-        else if (hy >= ny) w = ghost_top(P, w);
-      }
-      S.W[0][ly][lx] = w.r;
-      S.W[1][ly][lx] = w.u;
-      S.W[2][ly][lx] = w.v;
-      S.W[3][ly][lx] = w.p;
-    }
-  }
+  int bad = tile_prims<TX, TY, NT>(P, U, N, x0, y0, S);
   __syncthreads();
 
   // phase B: slopes and predictor on the cross-shaped halo-1 region
@@ -292,14 +276,10 @@ __global__ __launch_bounds__(NT) void k_step(Params P, StepArgs a) {
       if ((lx == 0 || lx == QX - 1) && (ly == 0 || ly == QY - 1)) continue;
       const int qy = y0 - 1 + ly;
       if (qy < 0 || qy >= ny) continue;
-      const W4 wc{S.W[0][ly + 1][lx + 1], S.W[1][ly + 1][lx + 1], S.W[2][ly + 1][lx + 1], S.W[3][ly + 1][lx + 1]};
-      const W4 wl{S.W[0][ly + 1][lx], S.W[1][ly + 1][lx], S.W[2][ly + 1][lx], S.W[3][ly + 1][lx]};
-      const W4 wr{S.W[0][ly + 1][lx + 2], S.W[1][ly + 1][lx + 2], S.W[2][ly + 1][lx + 2], S.W[3][ly + 1][lx + 2]};
-      const W4 wd{S.W[0][ly][lx + 1], S.W[1][ly][lx + 1], S.W[2][ly][lx + 1], S.W[3][ly][lx + 1]};
-      const W4 wu{S.W[0][ly + 2][lx + 1], S.W[1][ly + 2][lx + 1], S.W[2][ly + 2][lx + 1], S.W[3][ly + 2][lx + 1]};
-      int cx, cy;
-      const W4 sx = mc4(P, wl, wc, wr, cx);
-      const W4 sy = mc4(P, wd, wc, wu, cy);
+      const W4 wc = ldW(S, lx + 1, ly + 1);
+      int unused;
+      const W4 sx = mc4<false>(P, ldW(S, lx, ly + 1), wc, ldW(S, lx + 2, ly + 1), unused);
+      const W4 sy = mc4<false>(P, ldW(S, lx + 1, ly), wc, ldW(S, lx + 1, ly + 2), unused);
       const W4 q = predict(P, wc, sx, sy, hx, hy, hg);
       S.Q[0][ly][lx] = q.r;
       S.Q[1][ly][lx] = q.u;
@@ -403,7 +383,7 @@ __global__ __launch_bounds__(NT) void k_step(Params P, StepArgs a) {
     if (need_speed) {
       const W4 w = cons_to_prim(P, n0, n1, n2, n3);
       bad |= unphysical(w);
-      const double cs = sqrt(P.gamma * w.p / w.r);
+      const double cs = sqrt_fast(P.gamma * w.p * w.ri);
       const double sx = (fabs(w.u) + cs) * P.inv_dx, sy = (fabs(w.v) + cs) * P.inv_dy;
       smax = sx > sy ? sx : sy;
     }
@@ -448,7 +428,7 @@ struct AdjLDS {
   static constexpr int AX = TX + 4, AY = TY + 4;
   static constexpr int QX = TX + 2, QY = TY + 2;
   union {
-    double W[4][AY][AX];
+    double W[5][AY][AX];  // rho, u, v, p, 1/rho
     struct {
       double XL[4][TY][TX + 1];  // x faces: cotangent of the left state (r, u, v, p)
       double XR[4][TY][TX + 1];  // x faces: cotangent of the right state

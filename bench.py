@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--kernel-launches", type=int, default=300)
+    ap.add_argument("--workload", default="grad_256x512",
+                    help="grad_256x512 (default, the JSON line) or a name from paper_2608_04085_amd.workloads")
     return ap.parse_args()
 
 
@@ -110,6 +112,12 @@ def main():
         sys.exit(2)
     import torch
 
+    if args.workload != "grad_256x512":
+        from paper_2608_04085_amd import workloads
+
+        print(json.dumps(workloads.WORKLOADS[args.workload]()), flush=True)
+        return
+
     from paper_2608_04085_amd import inputs
     from paper_2608_04085_amd.config import CKPT_UNIFORM, NORM_L2, SET_SPHERE, RTConfig
     from paper_2608_04085_amd.rtcnop import Context, Policy
@@ -126,6 +134,8 @@ def main():
     u = torch.from_numpy(inputs.seed_batch(cfg, [0], rms=1e-3)).cuda()
     delta = float(math.sqrt(float((u * u).sum()) * cfg.dx * cfg.dy))
     U0 = ctx.init_state(u)
+    if args.tile is None:
+        ctx.autotune(U0, reps=20)
     _, _, n, log = ctx.integrate(U0, T, log_cap=16384)
     nt = int(n.item())
     pol = Policy(CKPT_UNIFORM, args.interval)
@@ -165,13 +175,31 @@ def main():
     t_fwd = time.perf_counter() - tf0
     fwd_rate = int(nf.item()) * cells / t_fwd
 
-    # per-kernel durations with HIP events on the library's stream
+    # finite-difference gradient for comparison: n_dof + 1 forward marches
+    # (one-sided differences), run as batches of 8 members; one batch timed
+    fd_b = 8
+    ctx_fd = Context(cfg.with_(batch=fd_b), max_steps=16384)
+    Ufd = ctx_fd.init_state(np.repeat(inputs.seed_batch(cfg, [0], rms=1e-3), fd_b, axis=0))
+    ctx_fd.autotune(Ufd, reps=10)
+    ctx_fd.integrate(Ufd, T)
+    torch.cuda.synchronize()
+    tb0 = time.perf_counter()
+    ctx_fd.integrate(Ufd, T)
+    torch.cuda.synchronize()
+    t_fd_batch = time.perf_counter() - tb0
+    del ctx_fd, Ufd
+    n_dof = 2 * cells
+    fd_iter_s = t_fd_batch * (n_dof + 1) / fd_b
+
+    # per-kernel durations with HIP events on the library's stream, one
+    # library call (one kernel) per event pair, outputs preallocated
     Uk = ctx.integrate(U0, 0.5)[0]
     dtk = ctx.cfl_dt(Uk)
     Un = torch.empty_like(Uk)
     lam = torch.randn_like(Uk) * 1e-3
-    t_step, t_step_med = time_kernel(lambda: ctx.step(Uk, dtk), args.kernel_launches, stream)
-    t_adj, t_adj_med = time_kernel(lambda: ctx.step_adjoint(Uk, dtk, lam), args.kernel_launches, stream)
+    lam_out = torch.empty_like(Uk)
+    t_step, t_step_med = time_kernel(lambda: ctx.step(Uk, dtk, out=Un), args.kernel_launches, stream)
+    t_adj, t_adj_med = time_kernel(lambda: ctx.step_adjoint(Uk, dtk, lam, out=lam_out), args.kernel_launches, stream)
     # forward launches per iteration ~ nt (march) + nt*(interval-1)/interval
     # (re-computation); adjoint launches (pairs) nt
     fw_share = t_step * nt_mean * (2 - 1.0 / args.interval)
@@ -181,20 +209,24 @@ def main():
     else:
         dom = {"kernel": "fused forward step (k_step)", "bytes_per_cell": FWD_BYTES_PER_CELL, "t": t_step}
     achieved = dom["bytes_per_cell"] * cells / dom["t"] / 1e9
+    from paper_2608_04085_amd import profiling
+
+    traffic = profiling.traffic_for(f"grad_{cfg.nx}x{cfg.ny}", "adjoint" if "adjoint" in dom["kernel"] else "step")
     roofline = {
         "bound": "hbm",
         "achieved": round(achieved, 2),
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 5),
-        "traffic": None,
+        "traffic": None if traffic is None else round(traffic, 1),
+        "algorithmic_bytes_per_launch": dom["bytes_per_cell"] * cells,
         "kernel": dom["kernel"],
         "launch_us": round(dom["t"] * 1e6, 3),
         "fwd_step_us": round(t_step * 1e6, 3),
         "adj_step_us": round(t_adj * 1e6, 3),
+        "fwd_share_of_iteration": round(fw_share / per_iter, 3),
+        "adj_share_of_iteration": round(adj_share / per_iter, 3),
     }
-    n_dof = 2 * cells
-    fd_iter_s = (n_dof + 1) * nt_mean * cells / fwd_rate  # one-sided differences, batched forwards
     out = {
         "metric": METRIC,
         "value": value,
@@ -216,6 +248,8 @@ def main():
         "grad_iters_per_s": 1.0 / per_iter,
         "fwd_cell_updates_per_s": fwd_rate,
         "fd_grad_iters_per_s_extrapolated": 1.0 / fd_iter_s,
+        "fd_batch8_forward_seconds": t_fd_batch,
+        "adjoint_vs_fd_speedup": fd_iter_s / per_iter,
         "R": float(R.item()),
         "roofline": roofline,
     }

@@ -222,13 +222,20 @@ class Context:
         _check(load().rt_cfl_dt(self._h, _ptr(U), _ptr(dt)), "rt_cfl_dt")
         return dt
 
-    def step(self, U, dt=None, want_next: bool = False):
+    def _dt(self, dt) -> torch.Tensor:
+        """Per-member step sizes as a device [B] tensor (passed through when it already is one)."""
+        if (isinstance(dt, torch.Tensor) and dt.is_cuda and dt.dtype == torch.float64 and dt.is_contiguous()
+                and dt.numel() == self.cfg.batch):
+            return dt
+        return self.as_dev(torch.as_tensor(dt, dtype=torch.float64).expand(self.cfg.batch).clone())
+
+    def step(self, U, dt=None, want_next: bool = False, out: torch.Tensor | None = None):
         self._sync_stream()
         U = self.as_dev(U)
-        Un = torch.empty_like(U)
+        Un = torch.empty_like(U) if out is None else out
         dtp = None
         if dt is not None:
-            dtp = self.as_dev(torch.as_tensor(dt, dtype=torch.float64).expand(self.cfg.batch).clone())
+            dtp = self._dt(dt)
         nxt = self._f64((self.cfg.batch,)) if want_next else None
         _check(load().rt_step(self._h, _ptr(U), _ptr(Un), _ptr(dtp), _ptr(nxt)), "rt_step")
         return (Un, nxt) if want_next else Un
@@ -251,12 +258,12 @@ class Context:
         _check(load().rt_kinetic_energy(self._h, _ptr(U), _ptr(ke)), "rt_kinetic_energy")
         return ke
 
-    def step_adjoint(self, U, dt, lam_next) -> torch.Tensor:
+    def step_adjoint(self, U, dt, lam_next, out: torch.Tensor | None = None) -> torch.Tensor:
         self._sync_stream()
         U = self.as_dev(U)
         lam_next = self.as_dev(lam_next)
-        dtp = self.as_dev(torch.as_tensor(dt, dtype=torch.float64).expand(self.cfg.batch).clone())
-        lam = torch.empty_like(lam_next)
+        dtp = self._dt(dt)
+        lam = torch.empty_like(lam_next) if out is None else out
         _check(load().rt_step_adjoint(self._h, _ptr(U), _ptr(dtp), _ptr(lam_next), _ptr(lam)), "rt_step_adjoint")
         return lam
 

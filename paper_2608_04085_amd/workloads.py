@@ -1,0 +1,162 @@
+"""The benchmark workloads, each returning a dict of measured results.
+
+    fwd_64x128            forward march to T = 2 of one RMS-1e-3 Gaussian seed; R and cell-updates/s
+    grad_256x512          forward + adjoint gradient, snapshot every 32 steps, T = 2 (bench.py's step)
+    ensemble_64x128x256   64 members (32 Gaussian seeds, 32 single Fourier modes kx = 1..16, two
+                          phases), velocity L2 norm 1e-3, T = 2, all members in one launch per step
+    cnop_8x512x1024       SPG CNOP search, 8 restarts, T = 1 or 4, binomial checkpointing <= 16 GB
+    grad_1024x2048        forward + adjoint, T = 3, binomial checkpointing <= 64 GB; top-5 horizontal
+                          mode energy of the sphere-projected gradient; adjoint/forward time ratio
+    fd_64x128             finite-difference gradient (one-sided, n_dof + 1 batched forwards) vs the adjoint
+
+All inputs are seeded synthetic fields (see inputs.py); the paper uses no dataset.
+Run: python -m paper_2608_04085_amd.workloads <name> [--iters K] [--T T]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import time
+
+import numpy as np
+import torch
+
+from . import cnop, inputs
+from .config import CKPT_REVOLVE, CKPT_UNIFORM, NORM_L2, SET_SPHERE, RTConfig
+from .rtcnop import Context, Policy
+
+
+def _sync():
+    torch.cuda.synchronize()
+
+
+def _timed(fn):
+    _sync()
+    t0 = time.perf_counter()
+    out = fn()
+    _sync()
+    return out, time.perf_counter() - t0
+
+
+def fwd_64x128(T: float = 2.0, reps: int = 5) -> dict:
+    cfg = RTConfig(nx=64, ny=128)
+    rt = Context(cfg, max_steps=8192)
+    U0 = rt.init_state(inputs.seed_batch(cfg, [0], rms=1e-3))
+    rt.autotune(U0)
+    rt.integrate(U0, T)
+    times = []
+    for _ in range(reps):
+        (UT, t, n, _), el = _timed(lambda: rt.integrate(U0, T))
+        times.append(el)
+    ke = rt.kinetic_energy(UT) / rt.kinetic_energy(U0)
+    el = float(np.median(times))
+    return {"workload": "fwd_64x128", "T": T, "nsteps": int(n.item()), "R": float(ke.item()),
+            "cell_updates_per_s": cfg.cells * int(n.item()) / el, "seconds": el, "tiles": rt.tile}
+
+
+def ensemble_64x128x256(T: float = 2.0, reps: int = 2) -> dict:
+    cfg = RTConfig(nx=128, ny=256, batch=64)
+    rt = Context(cfg, max_steps=8192)
+    uv = inputs.ensemble_batch(cfg, 1e-3)
+    U0 = rt.init_state(uv)
+    rt.autotune(U0)
+    times = []
+    for _ in range(reps):
+        (UT, t, n, _), el = _timed(lambda: rt.integrate(U0, T))
+        times.append(el)
+    R = (rt.kinetic_energy(UT) / rt.kinetic_energy(U0)).cpu().numpy()
+    el = float(np.median(times))
+    ns = n.cpu().numpy()
+    return {"workload": "ensemble_64x128x256", "T": T, "batch": 64, "nsteps_min": int(ns.min()),
+            "nsteps_max": int(ns.max()), "R_gaussian": R[:32].tolist(), "R_fourier_kx_phase": R[32:].tolist(),
+            "aggregate_cell_updates_per_s": float(cfg.nx * cfg.ny * ns.sum() / el), "seconds": el,
+            "tiles": rt.tile}
+
+
+def _revolve_pool(rt: Context, budget_bytes: int) -> torch.Tensor:
+    state = 8 * 4 * rt.cfg.cells * rt.cfg.batch
+    slots = max(2, budget_bytes // state)
+    return torch.empty(slots * state + 256, dtype=torch.uint8, device=rt.device)
+
+
+def grad_1024x2048(T: float = 3.0, budget_gb: float = 64.0) -> dict:
+    cfg = RTConfig(nx=1024, ny=2048)
+    rt = Context(cfg, max_steps=65536)
+    uv = inputs.seed_batch(cfg, [0], rms=1e-3)
+    U0 = rt.init_state(uv)
+    rt.autotune(U0, reps=5)
+    (UT, t, n, _), t_fwd = _timed(lambda: rt.integrate(U0, T))
+    pool = _revolve_pool(rt, int(budget_gb * 2**30))
+    (R, g, ng), t_grad = _timed(lambda: rt.grad_u0(uv, T, Policy(CKPT_REVOLVE, 1), pool=pool))
+    gp, _ = rt.project_to_constraint(g, math.sqrt(float((torch.as_tensor(uv) ** 2).sum()) * cfg.dx * cfg.dy),
+                                     NORM_L2, SET_SPHERE)
+    v = gp[0, 1].cpu().numpy()
+    row = cnop.peak_row(v)
+    return {"workload": "grad_1024x2048", "T": T, "nsteps": int(n.item()), "R": float(R.item()),
+            "forward_seconds": t_fwd, "gradient_seconds": t_grad, "adjoint_over_forward": t_grad / t_fwd,
+            "pool_slots": int(pool.numel() // (8 * 4 * cfg.cells)), "peak_row": row,
+            "top5_kx_energy_fraction": cnop.spectrum_top5(v[row]), "tiles": rt.tile}
+
+
+def cnop_8x512x1024(T: float = 1.0, iters: int = 50, budget_gb: float = 16.0) -> dict:
+    cfg = RTConfig(nx=512, ny=1024, batch=8)
+    rt = Context(cfg, max_steps=65536)
+    delta = 1e-3
+    uv = inputs.seed_batch(cfg, range(8), l2=delta)
+    rt.autotune(rt.init_state(uv), reps=5)
+    pool = _revolve_pool(rt, int(budget_gb * 2**30))
+    (u, R, g, log), el = _timed(lambda: cnop.spg(rt, uv, T, delta, iters, Policy(CKPT_REVOLVE, 1), pool=pool))
+    R0 = log.R[0] if log.R else None
+    return {"workload": "cnop_8x512x1024", "T": T, "iters": iters, "seconds": el, "iters_per_s": iters / el,
+            "R_first": R0, "R_final": [float(x) for x in R.tolist()], "best_R": float(max(R.tolist())),
+            "chi_final": log.chi[-1] if log.chi else None, "forward_evals": log.evals, "gradient_evals": log.grads,
+            "tiles": rt.tile}
+
+
+def fd_64x128(T: float = 2.0, batch: int = 64) -> dict:
+    """One-sided finite-difference gradient (n_dof + 1 forward runs, batched)
+    against the adjoint gradient at 64x128.  The FD time is measured on one
+    batch of `batch` perturbed members and scaled to n_dof + 1 runs."""
+    cfg = RTConfig(nx=64, ny=128)
+    n_dof = 2 * cfg.cells
+    uv = inputs.seed_batch(cfg, [0], rms=1e-3)
+    rt1 = Context(cfg, max_steps=8192)
+    rt1.integrate(rt1.init_state(uv), T)
+    (R, g, n), t_adj = _timed(lambda: rt1.grad_u0(uv, T, Policy(CKPT_UNIFORM, 32)))
+    (R, g, n), t_adj = _timed(lambda: rt1.grad_u0(uv, T, Policy(CKPT_UNIFORM, 32)))
+    cfgb = cfg.with_(batch=batch)
+    rtb = Context(cfgb, max_steps=8192)
+    h = 1e-6 * float(np.abs(uv).max())
+    pert = np.repeat(uv, batch, axis=0)
+    idx = np.arange(batch)
+    pert[idx, (idx % 2), idx // 2 % cfg.ny, idx % cfg.nx] += h
+    Ub = rtb.init_state(pert)
+    rtb.autotune(Ub, reps=5)
+    rtb.integrate(Ub, T)
+    (_, _, nb, _), t_batch = _timed(lambda: rtb.integrate(Ub, T))
+    t_fd = t_batch * (n_dof + 1) / batch
+    return {"workload": "fd_64x128", "T": T, "n_dof": n_dof, "adjoint_gradient_seconds": t_adj,
+            "fd_gradient_seconds_extrapolated": t_fd, "fd_batch_seconds_measured": t_batch, "fd_batch": batch,
+            "adjoint_speedup": t_fd / t_adj}
+
+
+WORKLOADS = {f.__name__: f for f in (fwd_64x128, ensemble_64x128x256, grad_1024x2048, cnop_8x512x1024, fd_64x128)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("name", choices=sorted(WORKLOADS))
+    ap.add_argument("--iters", type=int, default=None)
+    ap.add_argument("--T", type=float, default=None)
+    a = ap.parse_args()
+    kw = {}
+    if a.iters is not None:
+        kw["iters"] = a.iters
+    if a.T is not None:
+        kw["T"] = a.T
+    print(json.dumps(WORKLOADS[a.name](**kw)), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -54,22 +54,6 @@ def parse():
     return ap.parse_args()
 
 
-def time_kernel(fn, n, stream):
-    """Average duration of fn() (one library call) over n calls, HIP events
-    recorded on the stream the library launches on."""
-    import torch
-
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(n)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(n)]
-    for k in range(n):
-        starts[k].record(stream)
-        fn()
-        ends[k].record(stream)
-    torch.cuda.synchronize()
-    ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
-    return float(np.mean(ms)) * 1e-3, float(np.median(ms)) * 1e-3
-
-
 def cpu_baseline(cfg, T, seconds):
     """The oracle as it stands (single-threaded C++), timed on a bounded
     sample of the same workload: forward steps and reverse-mode adjoint steps
@@ -127,7 +111,6 @@ def main():
     cfg = RTConfig(nx=args.nx, ny=args.ny)
     T = args.T
     ctx = Context(cfg, max_steps=16384, tile=args.tile)
-    stream = torch.cuda.current_stream()
     cells = cfg.nx * cfg.ny
 
     # seed and step count
@@ -191,27 +174,28 @@ def main():
     n_dof = 2 * cells
     fd_iter_s = t_fd_batch * (n_dof + 1) / fd_b
 
-    # per-kernel durations with HIP events on the library's stream, one
-    # library call (one kernel) per event pair, outputs preallocated
+    # per-launch durations of the kernels as the iteration launches them,
+    # from HIP events on the library's stream around back-to-back launches
     Uk = ctx.integrate(U0, 0.5)[0]
-    dtk = ctx.cfl_dt(Uk)
-    Un = torch.empty_like(Uk)
-    lam = torch.randn_like(Uk) * 1e-3
-    lam_out = torch.empty_like(Uk)
-    t_step, t_step_med = time_kernel(lambda: ctx.step(Uk, dtk, out=Un), args.kernel_launches, stream)
-    t_adj, t_adj_med = time_kernel(lambda: ctx.step_adjoint(Uk, dtk, lam, out=lam_out), args.kernel_launches, stream)
-    # forward launches per iteration ~ nt (march) + nt*(interval-1)/interval
-    # (re-computation); adjoint launches (pairs) nt
-    fw_share = t_step * nt_mean * (2 - 1.0 / args.interval)
+    kt = ctx.kernel_times(Uk, reps=args.kernel_launches)
+    t_given, t_march, t_adj = (kt["step_given_us"] * 1e-6, kt["step_march_us"] * 1e-6,
+                               kt["adjoint_sweep_us"] * 1e-6)
+    # per iteration: nt march steps, nt (interval-1)/interval re-computed
+    # steps, nt adjoint steps (one kernel each)
+    fw_share = nt_mean * (t_march + t_given * (1 - 1.0 / args.interval))
     adj_share = t_adj * nt_mean
     if adj_share >= fw_share:
-        dom = {"kernel": "adjoint step (k_adj_a + k_adj_b)", "bytes_per_cell": ADJ_BYTES_PER_CELL, "t": t_adj}
+        dom = {"kernel": ("adjoint step (k_adj_a with the folded limiter gather)" if ctx.fold
+                          else "adjoint step (k_adj_a + k_adj_b)"),
+               "bytes_per_cell": ADJ_BYTES_PER_CELL, "t": t_adj,
+               "traffic_key": "adjoint_folded" if ctx.fold else "adjoint"}
     else:
-        dom = {"kernel": "fused forward step (k_step)", "bytes_per_cell": FWD_BYTES_PER_CELL, "t": t_step}
+        dom = {"kernel": "fused forward step (k_step, march)", "bytes_per_cell": FWD_BYTES_PER_CELL, "t": t_march,
+               "traffic_key": "step"}
     achieved = dom["bytes_per_cell"] * cells / dom["t"] / 1e9
     from paper_2608_04085_amd import profiling
 
-    traffic = profiling.traffic_for(f"grad_{cfg.nx}x{cfg.ny}", "adjoint" if "adjoint" in dom["kernel"] else "step")
+    traffic = profiling.traffic_for(f"grad_{cfg.nx}x{cfg.ny}", dom["traffic_key"])
     roofline = {
         "bound": "hbm",
         "achieved": round(achieved, 2),
@@ -222,8 +206,7 @@ def main():
         "algorithmic_bytes_per_launch": dom["bytes_per_cell"] * cells,
         "kernel": dom["kernel"],
         "launch_us": round(dom["t"] * 1e6, 3),
-        "fwd_step_us": round(t_step * 1e6, 3),
-        "adj_step_us": round(t_adj * 1e6, 3),
+        "kernel_times_us": {k: round(v, 3) for k, v in kt.items()},
         "fwd_share_of_iteration": round(fw_share / per_iter, 3),
         "adj_share_of_iteration": round(adj_share / per_iter, 3),
     }
@@ -244,6 +227,7 @@ def main():
             "workload": f"grad_{cfg.nx}x{cfg.ny}: forward + discrete-adjoint gradient of KE(T)/KE(0), T={T}, "
                         f"snapshot every {args.interval} steps, one projected-gradient iteration per step",
             "nx": cfg.nx, "ny": cfg.ny, "batch": 1, "T": T, "nsteps": nt_mean, "tile": ctx.tile,
+            "adjoint_folded": ctx.fold,
         },
         "grad_iters_per_s": 1.0 / per_iter,
         "fwd_cell_updates_per_s": fwd_rate,

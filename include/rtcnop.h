@@ -148,7 +148,9 @@ int rt_grad_u0(rt_ctx* ctx, const double* uv0, double T, const rt_ckpt_policy* p
                double* grad, int32_t* nsteps);
 
 /* Bytes of checkpoint pool that `kind`/`interval` needs for marches of
- * nsteps_max steps (RT_CKPT_REVOLVE: the minimum, two snapshots). */
+ * nsteps_max steps (RT_CKPT_UNIFORM: ceil(nsteps_max / interval) snapshots
+ * plus two segment buffers of interval - 1 states, one fewer buffer being
+ * the minimum; RT_CKPT_REVOLVE: the minimum, two snapshots). */
 int rt_pool_bytes(const rt_ctx* ctx, int32_t kind, int32_t interval, int32_t nsteps_max, size_t* bytes);
 
 /* Eq. 11: scale each member of uv ([B][2][ny][nx], in place) onto the
@@ -172,19 +174,50 @@ int rt_max_abs(rt_ctx* ctx, const double* a, double* out);
 int rt_axpy(rt_ctx* ctx, const double* x, const double* alpha, const double* y, double* out);
 
 /* Kernel variants.  The fused step and adjoint kernels come in tile shapes
- * 16x16, 32x8, 64x4 (256 threads) and 16x16, 32x8 (576 threads, one pass
- * per phase); ids 0..4 in that order.  Every variant gives bitwise-identical
+ * 16x16, 32x8, 64x4 (256 threads), 16x16, 32x8 (576 threads, one pass per
+ * phase), 16x8 (128), 8x8 (64), 16x8 (320, one pass) and 8x8 (192, one
+ * pass); ids 0..8 in that order.  Every variant gives bitwise-identical
  * results.  rt_set_tile selects one variant for both kernels;
  * rt_autotune times every variant on the state U (device) with `reps`
- * launches each on the context's stream, keeps the fastest step and
- * adjoint variants (returned in step_tile / adj_tile, may be NULL) and
+ * launches each on the context's stream (steps at a given dt and with the
+ * CFL reduction; adjoint steps folded and as two kernels), keeps the
+ * fastest step variant and the fastest adjoint variant and mode (see
+ * rt_set_fold; variants returned in step_tile / adj_tile, may be NULL) and
  * synchronises the stream.  The workspace buffers serve as scratch. */
 int rt_set_tile(rt_ctx* ctx, int32_t tile);
+/* Select the step and adjoint variants separately. */
+int rt_set_tiles(rt_ctx* ctx, int32_t step_tile, int32_t adj_tile);
 /* The adaptive march replays captured HIP graphs of 48 steps (on = 1, the
  * default) or launches step by step (on = 0); results are identical. */
 int rt_set_graphs(rt_ctx* ctx, int32_t on);
+/* The reverse sweep of RT_CKPT_UNIFORM re-computes segment k-1 on a second
+ * stream of the context (default priority, created on first use on the
+ * current device) while the adjoint of segment k runs on the context's
+ * stream, if the pool holds two segment buffers beside the snapshots (the
+ * size rt_pool_bytes returns) and on = 1 (the default); on = 0, or a pool
+ * with room for one segment buffer, runs the sweep on one stream.  Results
+ * are identical. */
+int rt_set_overlap(rt_ctx* ctx, int32_t on);
 int rt_get_tiles(const rt_ctx* ctx, int32_t* step_tile, int32_t* adj_tile);
 int rt_autotune(rt_ctx* ctx, const double* U, int32_t reps, int32_t* step_tile, int32_t* adj_tile);
+/* The reverse sweep of RT_CKPT_STORE_ALL / RT_CKPT_UNIFORM runs one kernel
+ * per adjoint step, which also completes the previous step's limiter gather
+ * (on = 1), or the two kernels of rt_step_adjoint per step (on = 0); results
+ * are identical.  rt_autotune picks the faster; before it, small grids
+ * (fewer than 2^20 cells in all) fold.  Binomial checkpointing always runs
+ * two kernels per step. */
+int rt_set_fold(rt_ctx* ctx, int32_t on);
+int rt_get_fold(const rt_ctx* ctx, int32_t* on);
+/* Measurement hook: per-launch times in microseconds of the selected
+ * variants, from HIP events on the context's stream around `reps`
+ * back-to-back launches each, with U (device) as every step's state:
+ * out[0] a step at a given dt (as re-computed in the reverse sweep), out[1]
+ * a step with the CFL reduction (as in the march), out[2] one folded
+ * adjoint step (one kernel that also completes the previous step's limiter
+ * gather), out[3] one rt_step_adjoint (two kernels), out[4] the adjoint step
+ * in the sweep's current mode (out[2] or out[3]).  out holds 5 doubles.
+ * Synchronises the stream; the workspace serves as scratch. */
+int rt_kernel_times(rt_ctx* ctx, const double* U, int32_t reps, double* out);
 
 /* Synchronise the stream and report a device-side error flag (RT_EUNPHYS)
  * raised by earlier asynchronous calls; clears the flag. */

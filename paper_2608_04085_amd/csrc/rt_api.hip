@@ -54,10 +54,10 @@ struct rt_ctx {
   char* ws = nullptr;
   size_t ws_bytes = 0;
   int32_t max_steps = 0;
-  double *S0 = nullptr, *S1 = nullptr, *L0 = nullptr, *L1 = nullptr, *Z = nullptr;
-  int32_t* codes = nullptr;
+  double *S0 = nullptr, *S1 = nullptr, *L0 = nullptr, *L1 = nullptr, *Z = nullptr, *Z2 = nullptr;
+  int32_t *codes = nullptr, *codes2 = nullptr;
   double* partial = nullptr;
-  uint64_t* acc = nullptr;  // [3][B] signal-speed accumulators of the march
+  uint64_t* acc = nullptr;  // [3][B][kAccRow] signal-speed slots of the march, then [B] for rt_step
   Ctl* ctl = nullptr;       // [2][B] march control, double buffered
   long last_launch = 0;     // launches of the last march (final ctl in ctl[last_launch & 1])
   // Graph of a chunk of kGraphChunk march steps (captured once per set of
@@ -67,9 +67,20 @@ struct rt_ctx {
   hipGraphExec_t chunk_exec = nullptr;
   const double* chunk_pool = nullptr;
   int chunk_interval = 0, chunk_slots = 0, chunk_tile = -1;
+  // Second stream of the reverse sweep: re-computes the next segment's
+  // states while the adjoint of the current one runs (default priority).
+  hipStream_t aux_stream = nullptr;
+  hipEvent_t seg_ready[2] = {nullptr, nullptr}, seg_free[2] = {nullptr, nullptr}, aux_done = nullptr;
+  bool overlap = true;
+  // Reverse sweep with the limiter gather folded into the next step's kernel
+  // (one kernel per step) or as its own kernel (two per step).
+  bool fold = true;
   ~rt_ctx() {
     if (chunk_exec) (void)hipGraphExecDestroy(chunk_exec);
     if (capture_stream) (void)hipStreamDestroy(capture_stream);
+    for (hipEvent_t e : {seg_ready[0], seg_ready[1], seg_free[0], seg_free[1], aux_done})
+      if (e) (void)hipEventDestroy(e);
+    if (aux_stream) (void)hipStreamDestroy(aux_stream);
   }
   Flags* flags = nullptr;
   double* dt_log = nullptr;
@@ -83,7 +94,7 @@ struct rt_ctx {
 namespace {
 
 struct Layout {
-  size_t S0, S1, L0, L1, Z, codes, partial, acc, ctl, flags, dt_log, nsteps, scal, total;
+  size_t S0, S1, L0, L1, Z, Z2, codes, codes2, partial, acc, ctl, flags, dt_log, nsteps, scal, total;
 };
 
 Layout layout(const rt_ctx* c, int32_t max_steps) {
@@ -102,9 +113,11 @@ Layout layout(const rt_ctx* c, int32_t max_steps) {
   L.L0 = take(se);
   L.L1 = take(se);
   L.Z = take(3 * se);
+  L.Z2 = take(3 * se);
   L.codes = take(c->cells() * c->P.nb * sizeof(int32_t));
+  L.codes2 = take(c->cells() * c->P.nb * sizeof(int32_t));
   L.partial = take((size_t)maxblk * c->P.nb * sizeof(double));
-  L.acc = take((size_t)4 * c->P.nb * sizeof(uint64_t));
+  L.acc = take(((size_t)3 * rtk::kAccRow + 1) * c->P.nb * sizeof(uint64_t));
   L.ctl = take((size_t)2 * c->P.nb * sizeof(Ctl));
   L.flags = take(sizeof(Flags));
   L.dt_log = take((size_t)c->P.nb * std::max<int32_t>(max_steps, 1) * sizeof(double));
@@ -290,6 +303,7 @@ int rt_create(const rt_grid* grid, const rt_phys* phys, void* stream, rt_ctx** o
   const bool small = (size_t)P.nx * P.ny * P.nb < ((size_t)1 << 20);
   c->tile = small ? rtk::TILE_16x16W : rtk::TILE_32x8;
   c->tile_adj = small ? rtk::TILE_16x16W : rtk::TILE_32x8;
+  c->fold = small;
   const size_t n = c->cells();
   c->red_blocks = (int)std::min<size_t>(256, std::max<size_t>(1, n / 2048));
   *out = c;
@@ -315,6 +329,14 @@ int rt_set_tile(rt_ctx* c, int32_t tile) {
   return 0;
 }
 
+int rt_set_tiles(rt_ctx* c, int32_t step_tile, int32_t adj_tile) {
+  if (!c || step_tile < 0 || step_tile >= rtk::TILE_COUNT || adj_tile < 0 || adj_tile >= rtk::TILE_COUNT)
+    return fail(RT_EINVAL, "bad tile id");
+  c->tile = step_tile;
+  c->tile_adj = adj_tile;
+  return 0;
+}
+
 int rt_get_tile(const rt_ctx* c, int32_t* tile) {
   if (!c || !tile) return fail(RT_EINVAL, "null argument");
   *tile = c->tile;
@@ -328,6 +350,24 @@ int rt_set_graphs(rt_ctx* c, int32_t on) {
   return 0;
 }
 
+int rt_set_overlap(rt_ctx* c, int32_t on) {
+  if (!c) return fail(RT_EINVAL, "null context");
+  c->overlap = on != 0;
+  return 0;
+}
+
+int rt_set_fold(rt_ctx* c, int32_t on) {
+  if (!c) return fail(RT_EINVAL, "null context");
+  c->fold = on != 0;
+  return 0;
+}
+
+int rt_get_fold(const rt_ctx* c, int32_t* on) {
+  if (!c || !on) return fail(RT_EINVAL, "null argument");
+  *on = c->fold ? 1 : 0;
+  return 0;
+}
+
 int rt_get_tiles(const rt_ctx* c, int32_t* step_tile, int32_t* adj_tile) {
   if (!c || !step_tile || !adj_tile) return fail(RT_EINVAL, "null argument");
   *step_tile = c->tile;
@@ -335,61 +375,106 @@ int rt_get_tiles(const rt_ctx* c, int32_t* step_tile, int32_t* adj_tile) {
   return 0;
 }
 
-// Autotuner: times every tile variant of the step and adjoint kernels on
-// the caller's state U (device, [B][4][ny][nx]) with HIP events on the
-// context's stream and keeps the fastest of each.  All variants give
-// bitwise-identical results, so this changes speed only.  Uses the
-// workspace buffers as scratch.  Synchronises the stream.
+namespace {
+
+// Per-launch times (ms) of the kernels as the library launches them: [0] the
+// given-dt step (re-computation), [1] the adaptive step with its CFL
+// epilogue (march; never reaches its end time here), [2] one adjoint step
+// of the folded sweep (kernel A forming lambda^{n+1} from the previous
+// step's outputs), [3] the unfolded adjoint step (kernels A + B).  The
+// state U serves as every step's state; the workspace buffers are scratch.
+int time_kernels(rt_ctx* c, const double* U, int step_tile, int adj_tile, int reps, hipEvent_t e0, hipEvent_t e1,
+                 float out[4]) {
+  hipStream_t s = c->stream;
+  const size_t se = c->state_elems();
+  const Params& P = c->P;
+  rtk::StepArgs a{};
+  a.U = U;
+  a.Un = c->S1;
+  a.dt = c->sc(3);
+  a.dt_stride = 1;
+  a.flags = c->flags;
+  rtk::AdjArgs j{};
+  j.U = U;
+  j.lam_next = c->L0;
+  j.lam = c->L1;
+  j.Z = c->Z;
+  j.codes = c->codes;
+  j.dt = c->sc(3);
+  j.dt_stride = 1;
+  j.flags = c->flags;
+  auto timed = [&](auto&& body, float* ms) -> hipError_t {
+    hipError_t e = hipEventRecord(e0, s);
+    for (int k = 0; k < reps && e == hipSuccess; ++k) e = body(k);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
+    if (e == hipSuccess) *ms /= (float)reps;
+    return e;
+  };
+  hipError_t e = rtk::launch_step(P, step_tile, a, s);
+  if (e == hipSuccess) e = rtk::launch_adjoint(P, adj_tile, j, s);  // fills Z, codes for the fold
+  if (e == hipSuccess) e = timed([&](int) { return rtk::launch_step(P, step_tile, a, s); }, &out[0]);
+  if (e == hipSuccess) e = rtk::launch_copy(U, c->S0, se, s);
+  if (e == hipSuccess) e = rtk::launch_reduce(P, 0, c->S0, nullptr, c->partial, c->red_blocks, c->sc(0), s);
+  if (e == hipSuccess) e = rtk::launch_march_begin(P, c->sc(0), 1e300, c->ctl, c->acc, c->flags, s);
+  if (e == hipSuccess)
+    e = timed(
+        [&](int k) {
+          rtk::StepArgs m = adaptive_args(c, (k & 1) ? c->S1 : c->S0, (k & 1) ? c->S0 : c->S1, k, nullptr, 1, 0);
+          m.dt_log = nullptr;
+          return rtk::launch_step(P, step_tile, m, s);
+        },
+        &out[1]);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->Z2, c->Z, 3 * se * sizeof(double), hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->codes2, c->codes, c->cells() * P.nb * sizeof(int32_t), hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess)
+    e = timed(
+        [&](int k) {
+          rtk::AdjArgs f = j;
+          f.Z = (k & 1) ? c->Z : c->Z2;
+          f.codes = (k & 1) ? c->codes : c->codes2;
+          f.fold.Z = (k & 1) ? c->Z2 : c->Z;
+          f.fold.codes = (k & 1) ? c->codes2 : c->codes;
+          f.fold.U = U;
+          f.fold.lam_next = c->L0;
+          f.fold.lam_out = c->L1;
+          f.fold.dt_index = 0;
+          return rtk::launch_adjoint(P, adj_tile, f, s, false);
+        },
+        &out[2]);
+  if (e == hipSuccess) e = timed([&](int) { return rtk::launch_adjoint(P, adj_tile, j, s); }, &out[3]);
+  return e == hipSuccess ? 0 : fail(RT_EHIP, "kernel timing: %s", hipGetErrorString(e));
+}
+
+}  // namespace
+
+// Autotuner: times every tile variant of the step kernel (given-dt plus
+// adaptive launches) and of the folded adjoint step on the caller's state U
+// (device, [B][4][ny][nx]) with HIP events on the context's stream and keeps
+// the fastest of each.  All variants give bitwise-identical results, so this
+// changes speed only.  Uses the workspace buffers as scratch.  Synchronises
+// the stream.
 int rt_autotune(rt_ctx* c, const double* U, int32_t reps, int32_t* step_tile, int32_t* adj_tile) {
   if (int rc = need_ws(c)) return rc;
   if (!U || reps < 1) return fail(RT_EINVAL, "bad argument");
-  hipStream_t s = c->stream;
-  const size_t se = c->state_elems();
   if (int rc = rt_cfl_dt(c, U, c->sc(3))) return rc;
-  RT_HIP(rtk::launch_copy(U, c->L0, se, s));  // any finite cotangent will do
+  RT_HIP(rtk::launch_copy(U, c->L0, c->state_elems(), c->stream));  // any finite cotangent will do
   hipEvent_t e0, e1;
   RT_HIP(hipEventCreate(&e0));
   RT_HIP(hipEventCreate(&e1));
   float best_s = 1e30f, best_a = 1e30f;
   int bs = c->tile, ba = c->tile_adj;
+  bool bf = c->fold;
   int rc = 0;
   for (int t = 0; t < rtk::TILE_COUNT && rc == 0; ++t) {
-    rtk::StepArgs a{};
-    a.U = U;
-    a.Un = c->S1;
-    a.dt = c->sc(3);
-    a.dt_stride = 1;
-    a.flags = c->flags;
-    rtk::AdjArgs j{};
-    j.U = U;
-    j.lam_next = c->L0;
-    j.lam = c->L1;
-    j.Z = c->Z;
-    j.codes = c->codes;
-    j.dt = c->sc(3);
-    j.dt_stride = 1;
-    j.flags = c->flags;
-    float ms_s = 0.f, ms_a = 0.f;
-    if (rtk::launch_step(c->P, t, a, s) != hipSuccess || rtk::launch_adjoint(c->P, t, j, s) != hipSuccess) {
-      rc = fail(RT_EHIP, "autotune launch failed");
-      break;
-    }
-    hipError_t e = hipEventRecord(e0, s);
-    for (int k = 0; k < reps && e == hipSuccess; ++k) e = rtk::launch_step(c->P, t, a, s);
-    if (e == hipSuccess) e = hipEventRecord(e1, s);
-    if (e == hipSuccess) e = hipEventSynchronize(e1);
-    if (e == hipSuccess) e = hipEventElapsedTime(&ms_s, e0, e1);
-    if (e == hipSuccess) e = hipEventRecord(e0, s);
-    for (int k = 0; k < reps && e == hipSuccess; ++k) e = rtk::launch_adjoint(c->P, t, j, s);
-    if (e == hipSuccess) e = hipEventRecord(e1, s);
-    if (e == hipSuccess) e = hipEventSynchronize(e1);
-    if (e == hipSuccess) e = hipEventElapsedTime(&ms_a, e0, e1);
-    if (e != hipSuccess) {
-      rc = fail(RT_EHIP, "autotune: %s", hipGetErrorString(e));
-      break;
-    }
-    if (ms_s < best_s) { best_s = ms_s; bs = t; }
-    if (ms_a < best_a) { best_a = ms_a; ba = t; }
+    float ms[4];
+    rc = time_kernels(c, U, t, t, reps, e0, e1, ms);
+    if (rc) break;
+    if (ms[0] + ms[1] < best_s) { best_s = ms[0] + ms[1]; bs = t; }
+    if (ms[2] < best_a) { best_a = ms[2]; ba = t; bf = true; }
+    if (ms[3] < best_a) { best_a = ms[3]; ba = t; bf = false; }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -397,8 +482,32 @@ int rt_autotune(rt_ctx* c, const double* U, int32_t reps, int32_t* step_tile, in
   RT_HIP(hipGetLastError());
   c->tile = bs;
   c->tile_adj = ba;
+  c->fold = bf;
   if (step_tile) *step_tile = bs;
   if (adj_tile) *adj_tile = ba;
+  Flags f{};
+  return read_flags(c, &f, true);
+}
+
+// Per-launch times (microseconds) of the current variants, as in
+// time_kernels: out[0] given-dt step, [1] adaptive step, [2] folded adjoint
+// step (one kernel), [3] unfolded adjoint step (two kernels), [4] the
+// adjoint step of the reverse sweep's current mode.
+int rt_kernel_times(rt_ctx* c, const double* U, int32_t reps, double* out) {
+  if (int rc = need_ws(c)) return rc;
+  if (!U || reps < 1 || !out) return fail(RT_EINVAL, "bad argument");
+  if (int rc = rt_cfl_dt(c, U, c->sc(3))) return rc;
+  RT_HIP(rtk::launch_copy(U, c->L0, c->state_elems(), c->stream));
+  hipEvent_t e0, e1;
+  RT_HIP(hipEventCreate(&e0));
+  RT_HIP(hipEventCreate(&e1));
+  float ms[4] = {0, 0, 0, 0};
+  const int rc = time_kernels(c, U, c->tile, c->tile_adj, reps, e0, e1, ms);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  for (int k = 0; k < 4; ++k) out[k] = 1e3 * ms[k];
+  out[4] = c->fold ? out[2] : out[3];
   Flags f{};
   return read_flags(c, &f, true);
 }
@@ -427,7 +536,9 @@ int rt_set_workspace(rt_ctx* c, void* dev, size_t bytes, int32_t max_steps) {
   c->L0 = reinterpret_cast<double*>(w + L.L0);
   c->L1 = reinterpret_cast<double*>(w + L.L1);
   c->Z = reinterpret_cast<double*>(w + L.Z);
+  c->Z2 = reinterpret_cast<double*>(w + L.Z2);
   c->codes = reinterpret_cast<int32_t*>(w + L.codes);
+  c->codes2 = reinterpret_cast<int32_t*>(w + L.codes2);
   c->partial = reinterpret_cast<double*>(w + L.partial);
   c->acc = reinterpret_cast<uint64_t*>(w + L.acc);
   c->ctl = reinterpret_cast<Ctl*>(w + L.ctl);
@@ -435,7 +546,8 @@ int rt_set_workspace(rt_ctx* c, void* dev, size_t bytes, int32_t max_steps) {
   c->dt_log = reinterpret_cast<double*>(w + L.dt_log);
   c->nsteps = reinterpret_cast<int32_t*>(w + L.nsteps);
   c->scal = reinterpret_cast<double*>(w + L.scal);
-  RT_HIP(rtk::launch_fill_i32(reinterpret_cast<int32_t*>(c->acc), 0, 8 * c->P.nb, c->stream));
+  RT_HIP(rtk::launch_fill_i32(reinterpret_cast<int32_t*>(c->acc), 0, 2 * ((size_t)3 * rtk::kAccRow + 1) * c->P.nb,
+                              c->stream));
   RT_HIP(rtk::launch_fill_i32(reinterpret_cast<int32_t*>(c->flags), 0, sizeof(Flags) / 4, c->stream));
   return 0;
 }
@@ -468,7 +580,7 @@ int rt_step(rt_ctx* c, const double* U_in, double* U_out, const double* dt, doub
   a.dt_stride = 1;
   a.dt_index = 0;
   a.flags = c->flags;
-  uint64_t* acc_out = c->acc + 3 * (size_t)c->P.nb;  // the fourth accumulator row
+  uint64_t* acc_out = c->acc + 3 * (size_t)rtk::kAccRow * c->P.nb;  // after the march's rows
   if (dt_next) {
     RT_HIP(rtk::launch_fill_i32(reinterpret_cast<int32_t*>(acc_out), 0, 2 * c->P.nb, c->stream));
     a.acc_out = acc_out;
@@ -529,7 +641,7 @@ int rt_pool_bytes(const rt_ctx* c, int32_t kind, int32_t interval, int32_t nstep
     *bytes = se * (size_t)nsteps_max;
   } else if (kind == RT_CKPT_UNIFORM) {
     if (interval < 1) return fail(RT_EINVAL, "interval must be >= 1");
-    *bytes = se * ((size_t)(nsteps_max + interval - 1) / interval + (interval - 1));
+    *bytes = se * ((size_t)(nsteps_max + interval - 1) / interval + 2 * (size_t)(interval - 1));
   } else if (kind == RT_CKPT_REVOLVE) {
     *bytes = se * 2;
   } else {
@@ -537,6 +649,18 @@ int rt_pool_bytes(const rt_ctx* c, int32_t kind, int32_t interval, int32_t nstep
   }
   return 0;
 }
+
+namespace {
+// The second stream and its events, created on first use on the current
+// device.
+int ensure_aux(rt_ctx* c) {
+  if (c->aux_stream) return 0;
+  RT_HIP(hipStreamCreateWithFlags(&c->aux_stream, hipStreamNonBlocking));
+  for (hipEvent_t* e : {&c->seg_ready[0], &c->seg_ready[1], &c->seg_free[0], &c->seg_free[1], &c->aux_done})
+    RT_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
+  return 0;
+}
+}  // namespace
 
 int rt_grad_u0(rt_ctx* c, const double* uv0, double T, const rt_ckpt_policy* pol, double* R, double* grad,
                int32_t* nsteps_out) {
@@ -595,7 +719,7 @@ int rt_grad_u0(rt_ctx* c, const double* uv0, double T, const rt_ckpt_policy* pol
   double* lam = c->L0;
   double* lam_other = c->L1;
 
-  auto step_given = [&](const double* src, double* dst, int n) -> int {
+  auto step_given = [&](const double* src, double* dst, int n, hipStream_t ss) -> int {
     rtk::StepArgs a{};
     a.U = src;
     a.Un = dst;
@@ -604,7 +728,7 @@ int rt_grad_u0(rt_ctx* c, const double* uv0, double T, const rt_ckpt_policy* pol
     a.dt_index = n;
     a.nsteps_limit = c->nsteps;
     a.flags = c->flags;
-    RT_HIP(rtk::launch_step(P, c->tile, a, s));
+    RT_HIP(rtk::launch_step(P, c->tile, a, ss));
     return 0;
   };
   auto adjoint = [&](const double* Un, int n) -> int {
@@ -623,16 +747,114 @@ int rt_grad_u0(rt_ctx* c, const double* uv0, double T, const rt_ckpt_policy* pol
     std::swap(lam, lam_other);
     return 0;
   };
+  // Folded sweep: kernel A of step n also forms lambda^{n+1} from step
+  // n+1's Z (the gather kernel is not launched), so one kernel per step.
+  // Needs U^{n+1} to stay where the previous call found it, which holds for
+  // the snapshot/segment sweep; kernel A of step n writes Z and codes into
+  // the buffer pair that step n+1 does not read.
+  struct Pending {
+    int n = -1;
+    const double* U = nullptr;
+    int buf = 0;
+  } pend;
+  double* Zb[2] = {c->Z, c->Z2};
+  int32_t* Cb[2] = {c->codes, c->codes2};
+  auto adjoint_folded = [&](const double* Un, int n) -> int {
+    rtk::AdjArgs a{};
+    const int buf = pend.n < 0 ? 0 : pend.buf ^ 1;
+    a.U = Un;
+    a.Z = Zb[buf];
+    a.codes = Cb[buf];
+    a.dt = c->dt_log;
+    a.dt_stride = c->max_steps;
+    a.dt_index = n;
+    a.nsteps_limit = c->nsteps;
+    a.flags = c->flags;
+    if (pend.n < 0) {
+      a.lam_next = lam;  // lambda^{n+1} as it is
+    } else {
+      a.fold.Z = Zb[pend.buf];
+      a.fold.codes = Cb[pend.buf];
+      a.fold.U = pend.U;
+      a.fold.lam_next = lam;
+      a.fold.lam_out = lam_other;
+      a.fold.dt_index = pend.n;
+      std::swap(lam, lam_other);
+    }
+    RT_HIP(rtk::launch_adjoint(P, c->tile_adj, a, s, false));
+    pend.n = n;
+    pend.U = Un;
+    pend.buf = buf;
+    return 0;
+  };
+  auto finish_folded = [&]() -> int {
+    if (pend.n < 0) return 0;
+    rtk::AdjArgs a{};
+    a.U = pend.U;
+    a.lam_next = lam;
+    a.lam = lam_other;
+    a.Z = Zb[pend.buf];
+    a.codes = Cb[pend.buf];
+    a.dt = c->dt_log;
+    a.dt_stride = c->max_steps;
+    a.dt_index = pend.n;
+    a.nsteps_limit = c->nsteps;
+    a.flags = c->flags;
+    RT_HIP(rtk::launch_adj_gather(P, a, s));
+    std::swap(lam, lam_other);
+    pend.n = -1;
+    return 0;
+  };
 
   if (pol->kind != RT_CKPT_REVOLVE) {
     const int K = (nmax + interval - 1) / interval;
+    // Two segment buffers if the pool has room: segment k-1 is re-computed
+    // on the second stream while the adjoint of segment k runs, which fills
+    // the GPU better when one kernel alone cannot.  The kernels and their
+    // order per buffer are those of the one-stream sweep, so the result is
+    // the same to the bit.
+    const bool two = c->overlap && interval > 1 && K > 1 && slots_total >= (size_t)K + 2 * (size_t)(interval - 1);
+    double* segs[2] = {seg, two ? state_slot((size_t)K + interval - 1) : seg};
+    if (two) {
+      if (int rc = ensure_aux(c)) return rc;
+      RT_HIP(hipEventRecord(c->seg_free[0], s));
+      RT_HIP(hipEventRecord(c->seg_free[1], s));
+    }
+    auto st = [&](int k, int n) -> double* {
+      const int base = k * interval;
+      return n == base ? state_slot(k) : segs[two ? (k & 1) : 0] + (size_t)(n - base - 1) * se;
+    };
+    auto recompute = [&](int k, hipStream_t rs) -> int {
+      const int base = k * interval, hi = std::min(base + interval, nmax);
+      for (int n = base; n < hi - 1; ++n)
+        if (int rc = step_given(st(k, n), st(k, n + 1), n, rs)) return rc;
+      return 0;
+    };
+    if (two) {
+      RT_HIP(hipStreamWaitEvent(c->aux_stream, c->seg_free[(K - 1) & 1], 0));
+      if (int rc = recompute(K - 1, c->aux_stream)) return rc;
+      RT_HIP(hipEventRecord(c->seg_ready[(K - 1) & 1], c->aux_stream));
+    }
     for (int k = K - 1; k >= 0; --k) {
       const int base = k * interval, hi = std::min(base + interval, nmax);
-      auto st = [&](int n) -> double* { return n == base ? state_slot(k) : seg + (size_t)(n - base - 1) * se; };
-      for (int n = base; n < hi - 1; ++n)
-        if (int rc = step_given(st(n), st(n + 1), n)) return rc;
+      if (two) {
+        if (k > 0) {
+          RT_HIP(hipStreamWaitEvent(c->aux_stream, c->seg_free[(k - 1) & 1], 0));
+          if (int rc = recompute(k - 1, c->aux_stream)) return rc;
+          RT_HIP(hipEventRecord(c->seg_ready[(k - 1) & 1], c->aux_stream));
+        }
+        RT_HIP(hipStreamWaitEvent(s, c->seg_ready[k & 1], 0));
+      } else if (int rc = recompute(k, s)) {
+        return rc;
+      }
       for (int n = hi - 1; n >= base; --n)
-        if (int rc = adjoint(st(n), n)) return rc;
+        if (int rc = c->fold ? adjoint_folded(st(k, n), n) : adjoint(st(k, n), n)) return rc;
+      if (two) RT_HIP(hipEventRecord(c->seg_free[k & 1], s));
+    }
+    if (int rc = finish_folded()) return rc;
+    if (two) {
+      RT_HIP(hipEventRecord(c->aux_done, c->aux_stream));
+      RT_HIP(hipStreamWaitEvent(s, c->aux_done, 0));
     }
   } else {
     // Binomial checkpointing over slots [0, slots_total): slot 0 holds U^0.
@@ -656,7 +878,7 @@ int rt_grad_u0(rt_ctx* c, const double* uv0, double T, const rt_ckpt_policy* pol
         case rtrev::Action::ADVANCE:
           for (int n = cur_step; n < act.to; ++n) {
             double* dst = (cur == c->S0) ? c->S1 : c->S0;
-            if (int rc = step_given(cur, dst, n)) return rc;
+            if (int rc = step_given(cur, dst, n, s)) return rc;
             cur = dst;
           }
           cur_step = act.to;

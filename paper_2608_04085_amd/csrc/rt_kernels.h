@@ -30,17 +30,23 @@ struct Flags {
 };
 
 // Arguments of the fused step kernel.
+constexpr int kAccSlots = 32;   // atomic-max slots per member and row
+constexpr int kAccStride = 16;  // uint64 per slot: one 128-byte line each
+constexpr int kAccRow = kAccSlots * kAccStride;
+
 struct StepArgs {
   const double* U;     // U^n       [B][4][ny][nx]
   double* Un;          // U^{n+1}
   // Adaptive mode (ctl != nullptr).  The largest signal speed of each
   // member's state is kept as the bit pattern of a non-negative double
-  // (ordered like the unsigned integer) in acc[3][B]: launch L reads
-  // acc[L % 3] (speeds of U^n) to form its CFL step, folds the speeds of
-  // U^{n+1} into acc[(L + 1) % 3] with one atomic max per block, and clears
-  // acc[(L + 2) % 3] for the next launch.
+  // (ordered like the unsigned integer) in acc[3][B][kAccSlots] (one slot
+  // per 128-byte line): launch L reads acc[L % 3] (speeds of U^n, the max
+  // over the slots) to form its CFL step, folds the speeds of U^{n+1} into
+  // acc[(L + 1) % 3] with one atomic max per block on the block's slot, and
+  // clears acc[(L + 2) % 3] for the next launch.  Spreading the blocks'
+  // atomics over the slots keeps them from queueing on one address.
   Ctl* ctl;                     // [2][B]
-  uint64_t* acc;                // [3][B]
+  uint64_t* acc;                // [3][B][kAccSlots * kAccStride]
   int32_t launch;
   double* dt_log;               // step log [B][dt_log_cap]
   int32_t dt_log_cap;
@@ -68,18 +74,46 @@ struct AdjArgs {
   int32_t dt_stride, dt_index;
   const int32_t* nsteps_limit;  // members with dt_index >= limit[b] pass lambda through
   Flags* flags;
+  // Folded gather (fold.Z != nullptr): lambda^{n+1} is not read from
+  // lam_next but formed on the tile + halo 1 from the previous adjoint
+  // kernel's outputs for step n+1 (its Z, codes, state U^{n+1} and
+  // lambda^{n+2}); the tile's own cells of lambda^{n+1} go to fold.lam_out.
+  struct Fold {
+    const double* Z;
+    const int32_t* codes;
+    const double* U;         // U^{n+1}
+    const double* lam_next;  // lambda^{n+2}
+    double* lam_out;         // lambda^{n+1}
+    int32_t dt_index;        // n + 1
+  } fold;
 };
 
 // Tile shapes of the fused step / adjoint kernels: TX x TY cells with 256
 // threads, or with 576 threads ("W" variants: one pass per phase).  All
 // variants produce bitwise-identical results.
-enum TileId { TILE_16x16 = 0, TILE_32x8 = 1, TILE_64x4 = 2, TILE_16x16W = 3, TILE_32x8W = 4, TILE_COUNT = 5 };
+enum TileId {
+  TILE_16x16 = 0,
+  TILE_32x8 = 1,
+  TILE_64x4 = 2,
+  TILE_16x16W = 3,
+  TILE_32x8W = 4,
+  TILE_16x8 = 5,
+  TILE_8x8 = 6,
+  TILE_16x8W = 7,
+  TILE_8x8W = 8,
+  TILE_COUNT = 9
+};
 void tile_dims(int tile, int* tx, int* ty, int* nt);
 int step_blocks(const Params& P, int tile);  // blocks per member
 
 hipError_t launch_init_state(const Params& P, const double* uv0, double* U, hipStream_t s);
 hipError_t launch_step(const Params& P, int tile, const StepArgs& a, hipStream_t s);
-hipError_t launch_adjoint(const Params& P, int tile, const AdjArgs& a, hipStream_t s);
+// Adjoint of one step: kernel A (face and predictor adjoints -> Z, codes),
+// then kernel B (limiter gather -> lambda^n), or kernel A alone
+// (gather = false) when the next kernel A folds the gather in.
+hipError_t launch_adjoint(const Params& P, int tile, const AdjArgs& a, hipStream_t s, bool gather = true);
+// Kernel B alone: lambda^n from Z, codes, U^n and lambda^{n+1} of step n.
+hipError_t launch_adj_gather(const Params& P, const AdjArgs& a, hipStream_t s);
 // Per-member reductions: kind 0 = max signal speed, 1 = kinetic energy,
 // 2.. = weighted |uv|^2 for the projection (norm id = kind - 2), 5 = dot,
 // 6 = max |x| of a velocity field.

@@ -223,28 +223,28 @@ __global__ __launch_bounds__(NT) void k_step(Params P, StepArgs a) {
   const double* U = a.U + (size_t)b * 4 * N;
   const bool first_block = blockIdx.x == 0 && blockIdx.y == 0;
 
-  // time step of this member
-  double dt;
+  // time step of this member.  In the march the control record and the
+  // signal-speed slots are loaded here but used only after phase A, which
+  // does not depend on them, so their latency overlaps it.
+  double dt = 0.0;
   int nstep = 0;
   bool last = false;
   const Ctl* cin = nullptr;
   Ctl* cout = nullptr;
+  int done = 0;
+  double t_in = 0.0, T_in = 0.0, ms_lane = 0.0;
   if (a.ctl) {
     const int L = a.launch;
     cin = a.ctl + (size_t)(L & 1) * P.nb + b;
     cout = a.ctl + (size_t)((L + 1) & 1) * P.nb + b;
-    if (cin->done) {
-      if (first_block && tid == 0) *cout = *cin;
-      return;
-    }
-    const double ms = __longlong_as_double((long long)a.acc[(size_t)(L % 3) * P.nb + b]);
-    const double t = cin->t, rem = cin->T - t;
-    dt = P.cfl / ms;
-    if (dt >= rem) {
-      dt = rem;
-      last = true;
-    }
+    done = cin->done;
+    t_in = cin->t;
+    T_in = cin->T;
     nstep = cin->nsteps;
+    // one slot per lane; the max across the wave is taken after phase A
+    const uint64_t* row = a.acc + ((size_t)(L % 3) * P.nb + b) * kAccRow;
+    const int lane = tid & 63;
+    ms_lane = lane < kAccSlots ? __longlong_as_double((long long)row[lane * kAccStride]) : 0.0;
   } else {
     if (a.nsteps_limit && a.dt_index >= a.nsteps_limit[b]) return;
     dt = a.dt[(size_t)b * a.dt_stride + a.dt_index];
@@ -266,6 +266,20 @@ __global__ __launch_bounds__(NT) void k_step(Params P, StepArgs a) {
   // phase A: primitives of the tile + halo 2
   constexpr int QX = StepLDS<TX, TY>::QX, QY = StepLDS<TX, TY>::QY;
   int bad = tile_prims<TX, TY, NT>(P, U, N, x0, y0, S);
+  if (a.ctl) {
+    // the same member for the whole block, so the return is uniform
+    if (done) {
+      if (first_block && tid == 0) *cout = *cin;
+      return;
+    }
+    const double ms = wave_max(ms_lane);
+    const double rem = T_in - t_in;
+    dt = P.cfl / ms;
+    if (dt >= rem) {
+      dt = rem;
+      last = true;
+    }
+  }
   __syncthreads();
 
   // phase B: slopes and predictor on the cross-shaped halo-1 region
@@ -401,22 +415,117 @@ __global__ __launch_bounds__(NT) void k_step(Params P, StepArgs a) {
     return;
   }
   const int L = a.launch;
-  atomicMax((unsigned long long*)(a.acc + (size_t)((L + 1) % 3) * P.nb + b),
+  const int slot = (int)((blockIdx.x + (size_t)gridDim.x * blockIdx.y) % kAccSlots);
+  atomicMax((unsigned long long*)(a.acc + ((size_t)((L + 1) % 3) * P.nb + b) * kAccRow + slot * kAccStride),
             (unsigned long long)__double_as_longlong(bm));
   if (!first_block) return;
-  a.acc[(size_t)((L + 2) % 3) * P.nb + b] = 0ull;
+  {
+    uint64_t* clr = a.acc + ((size_t)((L + 2) % 3) * P.nb + b) * kAccRow;
+#pragma unroll 4
+    for (int k = 0; k < kAccSlots; ++k) clr[k * kAccStride] = 0ull;
+  }
   if (a.dt_log) {
     if (nstep < a.dt_log_cap) a.dt_log[(size_t)b * a.dt_log_cap + nstep] = dt;
     else atomicOr(&a.flags->err_overflow, 1);
   }
   Ctl o;
-  o.T = cin->T;
-  o.t = last ? cin->T : cin->t + dt;
+  o.T = T_in;
+  o.t = last ? T_in : t_in + dt;
   o.dt_last = dt;
   o.nsteps = nstep + 1;
   o.done = last ? 1 : 0;
   *cout = o;
   if (last) atomicSub(&a.flags->n_active, 1);
+}
+
+// ----------------------------------------------------------------- limiter gather
+__device__ __forceinline__ void add_slope_terms(double sb[4], int code, double scale_a, double scale_b, double out[4]) {
+  // out += (scale_a * wa + scale_b * wb) * sb, per variable with its own case
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    double wa, wb;
+    mc_weights((code >> (2 * v)) & 3, wa, wb);
+    out[v] += (scale_a * wa + scale_b * wb) * sb[v];
+  }
+}
+
+// Outputs of kernel A for one step n of one member, read by the gather.
+struct GatherSrc {
+  const double* Z;        // [12][ny][nx]
+  const int32_t* codes;   // [ny][nx]
+  const double* U;        // U^n, [4][ny][nx]
+  const double* lam_next; // lambda^{n+1}, [4][ny][nx]
+  double dt;
+  bool pass;              // member finished before step n: lambda^n = lambda^{n+1}
+};
+
+// lambda^n at cell (i, j): the limiter gather of the slope cotangents of
+// the cell and its four neighbours through the MC cases, the wall ghost
+// terms, the adjoint of the primitive map at U^n, plus the identity and
+// gravity-source terms of the update.
+__device__ __forceinline__ void lambda_at(const Params& P, const GatherSrc& g, int i, int j, double out[4]) {
+  const int nx = P.nx, ny = P.ny;
+  const size_t N = (size_t)nx * ny;
+  const size_t idx = (size_t)j * nx + i;
+  const double* Lm = g.lam_next;
+  if (g.pass) {
+    out[0] = Lm[idx];
+    out[1] = Lm[N + idx];
+    out[2] = Lm[2 * N + idx];
+    out[3] = Lm[3 * N + idx];
+    return;
+  }
+  const double* Z = g.Z;
+  const int32_t* codes = g.codes;
+  const double* U = g.U;
+  double wb[4] = {Z[idx], Z[N + idx], Z[2 * N + idx], Z[3 * N + idx]};
+  // x slopes at d = c-1, c, c+1
+  {
+    const size_t cm = (size_t)j * nx + (i == 0 ? nx - 1 : i - 1);
+    const size_t cp = (size_t)j * nx + (i == nx - 1 ? 0 : i + 1);
+    double sm[4] = {Z[4 * N + cm], Z[5 * N + cm], Z[6 * N + cm], Z[7 * N + cm]};
+    double s0[4] = {Z[4 * N + idx], Z[5 * N + idx], Z[6 * N + idx], Z[7 * N + idx]};
+    double sp[4] = {Z[4 * N + cp], Z[5 * N + cp], Z[6 * N + cp], Z[7 * N + cp]};
+    add_slope_terms(sm, codes[cm] & 0xff, 0.0, 1.0, wb);    // c is d+1: +wb
+    add_slope_terms(s0, codes[idx] & 0xff, 1.0, -1.0, wb);  // c is d: wa - wb
+    add_slope_terms(sp, codes[cp] & 0xff, -1.0, 0.0, wb);   // c is d-1: -wa
+  }
+  // y slopes
+  {
+    const int c0 = codes[idx] >> 8;
+    double s0[4] = {Z[8 * N + idx], Z[9 * N + idx], Z[10 * N + idx], Z[11 * N + idx]};
+    add_slope_terms(s0, c0, 1.0, -1.0, wb);
+    if (j > 0) {
+      const size_t cm = idx - nx;
+      double sm[4] = {Z[8 * N + cm], Z[9 * N + cm], Z[10 * N + cm], Z[11 * N + cm]};
+      add_slope_terms(sm, codes[cm] >> 8, 0.0, 1.0, wb);
+    }
+    if (j < ny - 1) {
+      const size_t cp = idx + nx;
+      double sp[4] = {Z[8 * N + cp], Z[9 * N + cp], Z[10 * N + cp], Z[11 * N + cp]};
+      add_slope_terms(sp, codes[cp] >> 8, -1.0, 0.0, wb);
+    }
+    // the wall ghost cell is a function of this cell
+    if (j == 0 || j == ny - 1) {
+      double gb[4] = {0.0, 0.0, 0.0, 0.0};
+      if (j == 0) add_slope_terms(s0, c0, -1.0, 0.0, gb);       // ghost below: a = W - Wg
+      if (j == ny - 1) add_slope_terms(s0, c0, 0.0, 1.0, gb);   // ghost above: b = Wg - W
+      // (for ny == 1 both apply; ny >= 2 is required)
+      const double sgn = j == 0 ? -1.0 : 1.0;
+      wb[0] += gb[0] + sgn * P.g_y * P.dy * gb[3];
+      wb[1] += gb[1];
+      wb[2] -= gb[2];
+      wb[3] += gb[3];
+    }
+  }
+  const W4 w = cons_to_prim(P, U[idx], U[N + idx], U[2 * N + idx], U[3 * N + idx]);
+  double ub[4];
+  prim_adj(P, w, W4{wb[0], wb[1], wb[2], wb[3]}, ub);
+  const double l0 = Lm[idx], l1 = Lm[N + idx], l2 = Lm[2 * N + idx], l3 = Lm[3 * N + idx];
+  out[0] = ub[0] + l0 + g.dt * P.g_y * l2;
+  out[1] = ub[1] + l1;
+  out[2] = ub[2] + l2;
+  out[3] = ub[3] + l3;
 }
 
 // ----------------------------------------------------------------- adjoint A
@@ -452,11 +561,27 @@ __global__ __launch_bounds__(NT) void k_adj_a(Params P, AdjArgs a) {
   double(&sYT)[4][TY + 1][TX] = S.f.YT;
 
   const int b = blockIdx.z;
-  if (a.nsteps_limit && a.dt_index >= a.nsteps_limit[b]) return;
   const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
   const int tid = threadIdx.x;
   const int nx = P.nx, ny = P.ny;
   const size_t N = (size_t)nx * ny;
+  if (a.nsteps_limit && a.dt_index >= a.nsteps_limit[b]) {
+    // the member finished before step n; a folded step n+1 >= n has
+    // finished too, so lambda^{n+1} = lambda^{n+2} on the tile
+    if (a.fold.Z != nullptr && tid < TX * TY) {
+      const int gx = x0 + tid % TX, gy = y0 + tid / TX;
+      if (gx < nx && gy < ny) {
+        const size_t c = (size_t)gy * nx + gx;
+        const double* Ln = a.fold.lam_next + (size_t)b * 4 * N;
+        double* Lo = a.fold.lam_out + (size_t)b * 4 * N;
+        Lo[c] = Ln[c];
+        Lo[N + c] = Ln[N + c];
+        Lo[2 * N + c] = Ln[2 * N + c];
+        Lo[3 * N + c] = Ln[3 * N + c];
+      }
+    }
+    return;
+  }
   const double* U = a.U + (size_t)b * 4 * N;
   const double* Lm = a.lam_next + (size_t)b * 4 * N;
   const double dt = a.dt[(size_t)b * a.dt_stride + a.dt_index];
@@ -474,21 +599,47 @@ __global__ __launch_bounds__(NT) void k_adj_a(Params P, AdjArgs a) {
   }
 
   int bad = tile_prims<TX, TY, NT>(P, U, N, x0, y0, S);
+  // lambda^{n+1} on the halo-1 region (corners unused): read, or formed by
+  // the folded gather of step n+1
+  GatherSrc g{};
+  const bool fold = a.fold.Z != nullptr;
+  double* lam_out = nullptr;
+  if (fold) {
+    g.Z = a.fold.Z + (size_t)b * 12 * N;
+    g.codes = a.fold.codes + (size_t)b * N;
+    g.U = a.fold.U + (size_t)b * 4 * N;
+    g.lam_next = a.fold.lam_next + (size_t)b * 4 * N;
+    g.pass = a.nsteps_limit && a.fold.dt_index >= a.nsteps_limit[b];
+    g.dt = g.pass ? 0.0 : a.dt[(size_t)b * a.dt_stride + a.fold.dt_index];
+    lam_out = a.fold.lam_out + (size_t)b * 4 * N;
+  }
   for (int k = tid; k < QX * QY; k += NT) {
     const int lx = k % QX, ly = k / QX;
     const int gy = y0 - 1 + ly;
-    double l0 = 0.0, l1 = 0.0, l2 = 0.0, l3 = 0.0;
-    if (gy >= 0 && gy < ny) {
-      const size_t c = (size_t)gy * nx + wrapx(x0 - 1 + lx, nx);
-      l0 = Lm[c];
-      l1 = Lm[N + c];
-      l2 = Lm[2 * N + c];
-      l3 = Lm[3 * N + c];
+    double l[4] = {0.0, 0.0, 0.0, 0.0};
+    const bool corner = (lx == 0 || lx == QX - 1) && (ly == 0 || ly == QY - 1);
+    if (gy >= 0 && gy < ny && !corner) {
+      const int ux = x0 - 1 + lx, gx = wrapx(ux, nx);
+      const size_t c = (size_t)gy * nx + gx;
+      if (fold) {
+        lambda_at(P, g, gx, gy, l);
+        if (lx >= 1 && lx <= TX && ly >= 1 && ly <= TY && ux < nx) {
+          lam_out[c] = l[0];
+          lam_out[N + c] = l[1];
+          lam_out[2 * N + c] = l[2];
+          lam_out[3 * N + c] = l[3];
+        }
+      } else {
+        l[0] = Lm[c];
+        l[1] = Lm[N + c];
+        l[2] = Lm[2 * N + c];
+        l[3] = Lm[3 * N + c];
+      }
     }
-    sL[0][ly][lx] = l0 + hdtg * l2;
-    sL[1][ly][lx] = l1;
-    sL[2][ly][lx] = l2;
-    sL[3][ly][lx] = l3;
+    sL[0][ly][lx] = l[0] + hdtg * l[2];
+    sL[1][ly][lx] = l[1];
+    sL[2][ly][lx] = l[2];
+    sL[3][ly][lx] = l[3];
   }
   __syncthreads();
   bad |= tile_predict<TX, TY, NT>(P, dt, x0, y0, S, a.codes + (size_t)b * N);
@@ -577,85 +728,26 @@ __global__ __launch_bounds__(NT) void k_adj_a(Params P, AdjArgs a) {
 }
 
 // ----------------------------------------------------------------- adjoint B
-__device__ __forceinline__ void add_slope_terms(double sb[4], int code, double scale_a, double scale_b, double out[4]) {
-  // out += (scale_a * wa + scale_b * wb) * sb, per variable with its own case
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    double wa, wb;
-    mc_weights((code >> (2 * v)) & 3, wa, wb);
-    out[v] += (scale_a * wa + scale_b * wb) * sb[v];
-  }
-}
-
 __global__ __launch_bounds__(256) void k_adj_b(Params P, AdjArgs a) {
-  const int nx = P.nx, ny = P.ny;
-  const size_t N = (size_t)nx * ny;
+  const int nx = P.nx;
+  const size_t N = (size_t)nx * P.ny;
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int b = blockIdx.y;
   if (idx >= N) return;
-  const double* Lm = a.lam_next + (size_t)b * 4 * N;
+  GatherSrc g;
+  g.Z = a.Z + (size_t)b * 12 * N;
+  g.codes = a.codes + (size_t)b * N;
+  g.U = a.U + (size_t)b * 4 * N;
+  g.lam_next = a.lam_next + (size_t)b * 4 * N;
+  g.pass = a.nsteps_limit && a.dt_index >= a.nsteps_limit[b];
+  g.dt = g.pass ? 0.0 : a.dt[(size_t)b * a.dt_stride + a.dt_index];
+  double l[4];
+  lambda_at(P, g, (int)(idx % nx), (int)(idx / nx), l);
   double* Lo = a.lam + (size_t)b * 4 * N;
-  if (a.nsteps_limit && a.dt_index >= a.nsteps_limit[b]) {
-    Lo[idx] = Lm[idx];
-    Lo[N + idx] = Lm[N + idx];
-    Lo[2 * N + idx] = Lm[2 * N + idx];
-    Lo[3 * N + idx] = Lm[3 * N + idx];
-    return;
-  }
-  const int i = (int)(idx % nx), j = (int)(idx / nx);
-  const double dt = a.dt[(size_t)b * a.dt_stride + a.dt_index];
-  const double* Z = a.Z + (size_t)b * 12 * N;
-  const int32_t* codes = a.codes + (size_t)b * N;
-  const double* U = a.U + (size_t)b * 4 * N;
-
-  double wb[4] = {Z[idx], Z[N + idx], Z[2 * N + idx], Z[3 * N + idx]};
-  // x slopes at d = c-1, c, c+1
-  {
-    const size_t cm = (size_t)j * nx + (i == 0 ? nx - 1 : i - 1);
-    const size_t cp = (size_t)j * nx + (i == nx - 1 ? 0 : i + 1);
-    double sm[4] = {Z[4 * N + cm], Z[5 * N + cm], Z[6 * N + cm], Z[7 * N + cm]};
-    double s0[4] = {Z[4 * N + idx], Z[5 * N + idx], Z[6 * N + idx], Z[7 * N + idx]};
-    double sp[4] = {Z[4 * N + cp], Z[5 * N + cp], Z[6 * N + cp], Z[7 * N + cp]};
-    add_slope_terms(sm, codes[cm] & 0xff, 0.0, 1.0, wb);    // c is d+1: +wb
-    add_slope_terms(s0, codes[idx] & 0xff, 1.0, -1.0, wb);  // c is d: wa - wb
-    add_slope_terms(sp, codes[cp] & 0xff, -1.0, 0.0, wb);   // c is d-1: -wa
-  }
-  // y slopes
-  {
-    const int c0 = codes[idx] >> 8;
-    double s0[4] = {Z[8 * N + idx], Z[9 * N + idx], Z[10 * N + idx], Z[11 * N + idx]};
-    add_slope_terms(s0, c0, 1.0, -1.0, wb);
-    if (j > 0) {
-      const size_t cm = idx - nx;
-      double sm[4] = {Z[8 * N + cm], Z[9 * N + cm], Z[10 * N + cm], Z[11 * N + cm]};
-      add_slope_terms(sm, codes[cm] >> 8, 0.0, 1.0, wb);
-    }
-    if (j < ny - 1) {
-      const size_t cp = idx + nx;
-      double sp[4] = {Z[8 * N + cp], Z[9 * N + cp], Z[10 * N + cp], Z[11 * N + cp]};
-      add_slope_terms(sp, codes[cp] >> 8, -1.0, 0.0, wb);
-    }
-    // the wall ghost cell is a function of this cell
-    if (j == 0 || j == ny - 1) {
-      double gb[4] = {0.0, 0.0, 0.0, 0.0};
-      if (j == 0) add_slope_terms(s0, c0, -1.0, 0.0, gb);       // ghost below: a = W - Wg
-      if (j == ny - 1) add_slope_terms(s0, c0, 0.0, 1.0, gb);   // ghost above: b = Wg - W
-      // (for ny == 1 both apply; ny >= 2 is required)
-      const double sgn = j == 0 ? -1.0 : 1.0;
-      wb[0] += gb[0] + sgn * P.g_y * P.dy * gb[3];
-      wb[1] += gb[1];
-      wb[2] -= gb[2];
-      wb[3] += gb[3];
-    }
-  }
-  const W4 w = cons_to_prim(P, U[idx], U[N + idx], U[2 * N + idx], U[3 * N + idx]);
-  double ub[4];
-  prim_adj(P, w, W4{wb[0], wb[1], wb[2], wb[3]}, ub);
-  const double l0 = Lm[idx], l1 = Lm[N + idx], l2 = Lm[2 * N + idx], l3 = Lm[3 * N + idx];
-  Lo[idx] = ub[0] + l0 + dt * P.g_y * l2;
-  Lo[N + idx] = ub[1] + l1;
-  Lo[2 * N + idx] = ub[2] + l2;
-  Lo[3 * N + idx] = ub[3] + l3;
+  Lo[idx] = l[0];
+  Lo[N + idx] = l[1];
+  Lo[2 * N + idx] = l[2];
+  Lo[3 * N + idx] = l[3];
 }
 
 // ----------------------------------------------------------------- small kernels
@@ -757,9 +849,10 @@ __global__ void k_march_begin(Params P, const double* ms, double T, Ctl* ctl, ui
   c.nsteps = 0;
   c.done = 0;
   ctl[b] = c;
-  acc[b] = (uint64_t)__double_as_longlong(ms[b]);
-  acc[P.nb + b] = 0ull;
-  acc[2 * P.nb + b] = 0ull;
+  for (int r = 0; r < 3; ++r)
+    for (int k = 0; k < kAccSlots; ++k)
+      acc[((size_t)r * P.nb + b) * kAccRow + k * kAccStride] =
+          (r == 0 && k == 0) ? (uint64_t)__double_as_longlong(ms[b]) : 0ull;
 }
 
 __global__ void k_cfl_from_bits(Params P, const uint64_t* acc, double* dt) {
@@ -884,6 +977,10 @@ void tile_dims(int tile, int* tx, int* ty, int* nt) {
     case TILE_64x4: a = 64; b = 4; break;
     case TILE_16x16W: t = 576; break;
     case TILE_32x8W: a = 32; b = 8; t = 576; break;
+    case TILE_16x8: b = 8; t = 128; break;
+    case TILE_8x8: a = 8; b = 8; t = 64; break;
+    case TILE_16x8W: b = 8; t = 320; break;
+    case TILE_8x8W: a = 8; b = 8; t = 192; break;
     default: break;
   }
   *tx = a;
@@ -910,6 +1007,10 @@ hipError_t launch_step(const Params& P, int tile, const StepArgs& a, hipStream_t
     case TILE_64x4: return launch_step_t<64, 4, 256>(P, a, s);
     case TILE_16x16W: return launch_step_t<16, 16, 576>(P, a, s);
     case TILE_32x8W: return launch_step_t<32, 8, 576>(P, a, s);
+    case TILE_16x8: return launch_step_t<16, 8, 128>(P, a, s);
+    case TILE_8x8: return launch_step_t<8, 8, 64>(P, a, s);
+    case TILE_16x8W: return launch_step_t<16, 8, 320>(P, a, s);
+    case TILE_8x8W: return launch_step_t<8, 8, 192>(P, a, s);
     default: return launch_step_t<16, 16, 256>(P, a, s);
   }
 }
@@ -918,21 +1019,32 @@ template <int TX, int TY, int NT>
 static hipError_t launch_adj_t(const Params& P, const AdjArgs& a, hipStream_t s) {
   dim3 grid((P.nx + TX - 1) / TX, (P.ny + TY - 1) / TY, P.nb);
   hipLaunchKernelGGL((k_adj_a<TX, TY, NT>), grid, dim3(NT), 0, s, P, a);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const size_t N = (size_t)P.nx * P.ny;
-  hipLaunchKernelGGL(k_adj_b, cells_grid(P, N), dim3(256), 0, s, P, a);
   return hipGetLastError();
 }
 
-hipError_t launch_adjoint(const Params& P, int tile, const AdjArgs& a, hipStream_t s) {
+hipError_t launch_adj_gather(const Params& P, const AdjArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_adj_b, cells_grid(P, (size_t)P.nx * P.ny), dim3(256), 0, s, P, a);
+  return hipGetLastError();
+}
+
+static hipError_t launch_adj_a(const Params& P, int tile, const AdjArgs& a, hipStream_t s) {
   switch (tile) {
     case TILE_32x8: return launch_adj_t<32, 8, 256>(P, a, s);
     case TILE_64x4: return launch_adj_t<64, 4, 256>(P, a, s);
     case TILE_16x16W: return launch_adj_t<16, 16, 576>(P, a, s);
     case TILE_32x8W: return launch_adj_t<32, 8, 576>(P, a, s);
+    case TILE_16x8: return launch_adj_t<16, 8, 128>(P, a, s);
+    case TILE_8x8: return launch_adj_t<8, 8, 64>(P, a, s);
+    case TILE_16x8W: return launch_adj_t<16, 8, 320>(P, a, s);
+    case TILE_8x8W: return launch_adj_t<8, 8, 192>(P, a, s);
     default: return launch_adj_t<16, 16, 256>(P, a, s);
   }
+}
+
+hipError_t launch_adjoint(const Params& P, int tile, const AdjArgs& a, hipStream_t s, bool gather) {
+  hipError_t e = launch_adj_a(P, tile, a, s);
+  if (e != hipSuccess || !gather) return e;
+  return launch_adj_gather(P, a, s);
 }
 
 hipError_t launch_init_state(const Params& P, const double* uv0, double* U, hipStream_t s) {

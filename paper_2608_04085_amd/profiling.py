@@ -1,17 +1,19 @@
 """Counter runs of the hot-path kernels and their summaries.
 
     python -m paper_2608_04085_amd.profiling drive NX NY B K STEP_TILE ADJ_TILE
-        K launches of the step kernel and K of the adjoint step at one grid,
-        then K copies of a 2 GiB buffer (a plain copy of known size whose
-        FETCH_SIZE / WRITE_SIZE calibrate the counters).  Run it under
-        rocprofv3 (kernel trace, then --pmc FETCH_SIZE, then --pmc WRITE_SIZE).
+        The library's kernel-timing hook (K launches each of the step at a
+        given dt, the march step, the folded adjoint step and the two-kernel
+        adjoint step on one grid), then K copies of a 2 GiB buffer: a plain
+        copy of known size whose FETCH_SIZE / WRITE_SIZE calibrate the
+        counters.  Run it under rocprofv3: --kernel-trace, then --pmc
+        FETCH_SIZE, then --pmc WRITE_SIZE, then --pmc TCC_EA0_RDREQ_32B_sum
+        TCC_EA0_RDREQ_64B_sum TCC_EA0_RDREQ_128B_sum TCC_EA0_RDREQ_sum.
     python -m paper_2608_04085_amd.profiling summarize WORKLOAD TRACE FETCH WRITE REQ OUT_MD
-        Turns the rocprofv3 CSV directories (kernel trace; --pmc FETCH_SIZE;
-        --pmc WRITE_SIZE; --pmc TCC_EA0_RDREQ_32B_sum TCC_EA0_RDREQ_64B_sum
-        TCC_EA0_RDREQ_128B_sum TCC_EA0_RDREQ_sum) into a short Markdown summary
+        Turns the four rocprofv3 CSV directories into a short Markdown summary
         and records per-launch HBM bytes in profiles/traffic.json, keyed by the
         hash of the kernel sources (bench.py reports the traffic only while the
-        kernels are unchanged).
+        kernels are unchanged).  The command lines go in via the environment
+        variable RT_PROFILE_COMMAND.
 
 FETCH_SIZE and WRITE_SIZE are scaled by what they read for the plain copy
 (bytes moved / counted bytes).  On gfx950 the derived FETCH_SIZE counts a
@@ -33,6 +35,7 @@ ROOT = os.path.dirname(HERE)
 KERNEL_SOURCES = ["csrc/rt_kernels.hip", "csrc/rt_device.h", "csrc/rt_kernels.h"]
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic.json")
 COPY_BYTES = 2 * 1024**3
+CATEGORIES = ["step_given", "step_march", "adj_a_folded", "adj_a", "adj_b", "copy"]
 
 
 def kernel_source_hash() -> str:
@@ -51,17 +54,10 @@ def drive(nx: int, ny: int, B: int, K: int, step_tile: str, adj_tile: str):
     from .rtcnop import Context
 
     cfg = RTConfig(nx=nx, ny=ny, batch=B)
-    rt = Context(cfg, max_steps=64, tile=step_tile)
+    rt = Context(cfg, max_steps=64)
+    rt.set_tiles(step_tile, adj_tile)
     U = rt.init_state(inputs.seed_batch(cfg, range(B), rms=1e-3))
-    dt = rt.cfl_dt(U)
-    Un = torch.empty_like(U)
-    for _ in range(K):
-        rt.step(U, dt, out=Un)
-    rt.set_tile(adj_tile)
-    lam = torch.empty_like(U).fill_(1e-3)
-    lo = torch.empty_like(U)
-    for _ in range(K):
-        rt.step_adjoint(U, dt, lam, out=lo)
+    times = rt.kernel_times(U, reps=K)
     n = COPY_BYTES // 8
     a = torch.empty(n, dtype=torch.float64, device="cuda").fill_(1.0)
     flush = torch.empty(n, dtype=torch.float64, device="cuda").fill_(2.0)  # evicts a from the last-level cache
@@ -70,7 +66,7 @@ def drive(nx: int, ny: int, B: int, K: int, step_tile: str, adj_tile: str):
         b.copy_(a)
         flush.fill_(3.0)
     torch.cuda.synchronize()
-    print(f"drive done {nx}x{ny}x{B} K={K} step={step_tile} adj={adj_tile}", flush=True)
+    print(f"drive done {nx}x{ny}x{B} K={K} tiles={rt.tile} {json.dumps(times)}", flush=True)
 
 
 def _rows(d: str, name: str):
@@ -81,37 +77,52 @@ def _rows(d: str, name: str):
         return list(csv.DictReader(f))
 
 
-def _kind(name: str) -> str | None:
-    if "k_step" in name:
-        return "step"
-    if "k_adj_a" in name:
-        return "adj_a"
-    if "k_adj_b" in name:
-        return "adj_b"
-    if "copy" in name.lower() and "rtk" not in name:
-        return "copy"
-    return None
-
-
-def _counter_avgs(dirs):
-    counters: dict = {}
-    for d in dirs:
-        if d is None:
-            continue
-        for r in _rows(d, "*counter_collection.csv"):
-            k = _kind(r["Kernel_Name"])
-            if k:
-                counters.setdefault(k, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
-    return counters
+def _classify(rows):
+    """Category of each dispatch, in dispatch order: steps after the march
+    set-up kernel are march steps; an adjoint kernel A followed by kernel B
+    is the two-kernel form, otherwise the folded one."""
+    disp = {}
+    for r in rows:
+        disp.setdefault(int(r["Dispatch_Id"]), r["Kernel_Name"])
+    order = sorted(disp)
+    cat = {}
+    march = False
+    for i, d in enumerate(order):
+        n = disp[d]
+        if "k_march_begin" in n:
+            march = True
+        if "k_step" in n:
+            cat[d] = "step_march" if march else "step_given"
+        elif "k_adj_a" in n:
+            nxt = disp[order[i + 1]] if i + 1 < len(order) else ""
+            cat[d] = "adj_a" if "k_adj_b" in nxt else "adj_a_folded"
+        elif "k_adj_b" in n:
+            cat[d] = "adj_b"
+        elif "copyBuffer" in n:
+            cat[d] = "copy"
+    return cat
 
 
 def summarize(workload: str, trace: str, fetch: str, write: str, req: str | None, out_md: str, command: str = ""):
-    stats = {}
-    for r in _rows(trace, "*kernel_stats.csv"):
-        k = _kind(r["Name"])
-        if k and k != "copy":
-            stats[k] = (int(r["Calls"]), float(r["AverageNs"]) / 1e3, r["Name"])
-    counters = _counter_avgs([fetch, write, req])
+    trows = _rows(trace, "*kernel_trace.csv")
+    tcat = _classify(trows)
+    dur: dict = {}
+    meta: dict = {}
+    for r in trows:
+        c = tcat.get(int(r["Dispatch_Id"]))
+        if c:
+            dur.setdefault(c, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3)
+            meta[c] = (r["Kernel_Name"], r["LDS_Block_Size"], r["VGPR_Count"], r["Workgroup_Size_X"])
+    counters: dict = {}
+    for d in (fetch, write, req):
+        if not d:
+            continue
+        crows = _rows(d, "*counter_collection.csv")
+        ccat = _classify(crows)
+        for r in crows:
+            c = ccat.get(int(r["Dispatch_Id"]))
+            if c:
+                counters.setdefault(c, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
     avg = {k: {c: sum(v) / len(v) for c, v in d.items()} for k, d in counters.items()}
     cp = avg.get("copy", {})
     kib = COPY_BYTES / 1024
@@ -126,31 +137,39 @@ def summarize(workload: str, trace: str, fetch: str, write: str, req: str | None
     lines = [f"# HBM traffic and kernel times: {workload}", "", "Commands (repository root):", "", "```"]
     lines += command.strip().split("\n") if command else []
     lines += ["```", "",
-              "| kernel | launches | avg us | FETCH_SIZE KiB | WRITE_SIZE KiB | read KiB from request sizes "
-              "(32/64/128 B requests) |", "|---|---|---|---|---|---|"]
-    for k in ("step", "adj_a", "adj_b", "copy"):
+              "| kernel (launch form) | name | threads | LDS B | VGPR | launches | avg us | FETCH_SIZE KiB | "
+              "WRITE_SIZE KiB | read KiB from request sizes (n32/n64/n128) |",
+              "|---|---|---|---|---|---|---|---|---|---|"]
+    for k in CATEGORIES:
+        if k not in dur and k not in avg:
+            continue
         c = avg.get(k, {})
-        name, calls, us = (stats[k][2][:58], stats[k][0], f"{stats[k][1]:.3f}") if k in stats else (k, "", "")
+        name, lds, vgpr, wg = meta.get(k, ("", "", "", ""))
+        name = name.replace("rtk::(anonymous namespace)::", "").split("(")[0]
+        ds = dur.get(k, [])
+        us = f"{sum(ds) / len(ds):.3f}" if ds else ""
         rb = req_bytes(c)
         rq = "" if rb is None else (f"{rb / 1024:.1f} ({c['TCC_EA0_RDREQ_32B_sum']:.0f}/"
                                     f"{c['TCC_EA0_RDREQ_64B_sum']:.0f}/{c['TCC_EA0_RDREQ_128B_sum']:.0f})")
-        lines.append(f"| `{name}` | {calls} | {us} | {c.get('FETCH_SIZE', float('nan')):.1f} | "
-                     f"{c.get('WRITE_SIZE', float('nan')):.1f} | {rq} |")
+        lines.append(f"| {k} | `{name}` | {wg} | {lds} | {vgpr} | {len(ds)} | {us} | "
+                     f"{c.get('FETCH_SIZE', float('nan')):.1f} | {c.get('WRITE_SIZE', float('nan')):.1f} | {rq} |")
     lines += ["", f"Calibration: a plain copy of {COPY_BYTES} B (reads {COPY_BYTES} B, writes {COPY_BYTES} B, "
               f"source evicted from the last-level cache before each copy) reads FETCH_SIZE "
-              f"{cp.get('FETCH_SIZE', float('nan')):.1f} KiB and WRITE_SIZE {cp.get('WRITE_SIZE', float('nan')):.1f} KiB "
-              f"per dispatch: scale factors fetch {f_scale}, write {w_scale}."]
+              f"{cp.get('FETCH_SIZE', float('nan')):.1f} KiB and WRITE_SIZE {cp.get('WRITE_SIZE', float('nan')):.1f} "
+              f"KiB per dispatch: scale factors fetch {f_scale}, write {w_scale}.", ""]
     entry = {}
-    for name, parts in (("step", ["step"]), ("adjoint", ["adj_a", "adj_b"])):
+    for name, parts in (("step", ["step_given"]), ("step_march", ["step_march"]), ("adjoint", ["adj_a", "adj_b"]),
+                        ("adjoint_folded", ["adj_a_folded"])):
         if all(p in avg for p in parts):
             fb = sum(avg[p].get("FETCH_SIZE", 0.0) for p in parts) * 1024 * (f_scale or 1.0)
             wb = sum(avg[p].get("WRITE_SIZE", 0.0) for p in parts) * 1024 * (w_scale or 1.0)
             rbs = [req_bytes(avg[p]) for p in parts]
             rb = None if any(x is None for x in rbs) else sum(rbs)
+            us = sum(sum(dur[p]) / len(dur[p]) for p in parts if p in dur)
             entry[name] = {"fetch_bytes_scaled": fb, "write_bytes_scaled": wb, "bytes_per_launch": fb + wb,
-                           "read_bytes_request_sizes": rb}
-            lines.append(f"Per launch, {name}: scaled fetch {fb / 2**20:.2f} MiB + write {wb / 2**20:.2f} MiB = "
-                         f"{(fb + wb) / 2**20:.2f} MiB"
+                           "read_bytes_request_sizes": rb, "avg_us": us}
+            lines.append(f"Per launch, {name}: {us:.3f} us; scaled fetch {fb / 2**20:.2f} MiB + write "
+                         f"{wb / 2**20:.2f} MiB = {(fb + wb) / 2**20:.2f} MiB"
                          + ("" if rb is None else f"; read bytes from request sizes {rb / 2**20:.2f} MiB"))
     with open(out_md, "w") as f:
         f.write("\n".join(lines) + "\n")
@@ -159,8 +178,7 @@ def summarize(workload: str, trace: str, fetch: str, write: str, req: str | None
         with open(TRAFFIC_JSON) as f:
             data = json.load(f)
     data[workload] = {"source_hash": kernel_source_hash(), "kernels": entry, "fetch_scale": f_scale,
-                      "write_scale": w_scale,
-                      "kernel_names": {k: v[2] for k, v in stats.items()}}
+                      "write_scale": w_scale, "kernel_names": {k: v[0] for k, v in meta.items()}}
     with open(TRAFFIC_JSON, "w") as f:
         json.dump(data, f, indent=1)
     print("\n".join(lines))

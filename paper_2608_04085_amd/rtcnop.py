@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librtcnop.so")
 
 STATUS = {0: "RT_OK", -1: "RT_EINVAL", -2: "RT_EHIP", -3: "RT_ENOMEM", -4: "RT_EUNPHYS", -5: "RT_ESTATE"}
-TILES = {"16x16": 0, "32x8": 1, "64x4": 2, "16x16w": 3, "32x8w": 4}
+TILES = {"16x16": 0, "32x8": 1, "64x4": 2, "16x16w": 3, "32x8w": 4, "16x8": 5, "8x8": 6, "16x8w": 7, "8x8w": 8}
 
 
 class RTError(RuntimeError):
@@ -80,6 +80,11 @@ def load():
         "rt_dot": [_vp, _vp, _vp, _vp],
         "rt_max_abs": [_vp, _vp, _vp],
         "rt_set_graphs": [_vp, _i32],
+        "rt_set_overlap": [_vp, _i32],
+        "rt_kernel_times": [_vp, _vp, _i32, ctypes.POINTER(ctypes.c_double)],
+        "rt_set_fold": [_vp, _i32],
+        "rt_set_tiles": [_vp, _i32, _i32],
+        "rt_get_fold": [_vp, ctypes.POINTER(_i32)],
         "rt_axpy": [_vp, _vp, _vp, _vp, _vp],
         "rt_check_error": [_vp],
         "rt_revolve_stats": [_i32, _i32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
@@ -97,7 +102,9 @@ def load():
 EXPORTED = ["rt_create", "rt_destroy", "rt_set_stream", "rt_workspace_bytes", "rt_set_workspace",
             "rt_init_state", "rt_cfl_dt", "rt_step", "rt_integrate", "rt_kinetic_energy", "rt_step_adjoint",
             "rt_grad_u0", "rt_pool_bytes", "rt_project_to_constraint", "rt_dot", "rt_axpy", "rt_check_error",
-            "rt_last_error", "rt_set_tile", "rt_get_tiles", "rt_autotune", "rt_max_abs", "rt_set_graphs"]
+            "rt_last_error", "rt_set_tile", "rt_get_tiles", "rt_autotune", "rt_max_abs", "rt_set_graphs",
+            "rt_set_overlap", "rt_kernel_times", "rt_set_fold", "rt_get_fold",
+            "rt_set_tiles"]
 
 
 def _check(rc: int, call: str):
@@ -196,8 +203,36 @@ class Context:
     def set_tile(self, name: str):
         _check(load().rt_set_tile(self._h, TILES[name]), "rt_set_tile")
 
+    def set_tiles(self, step: str, adjoint: str):
+        _check(load().rt_set_tiles(self._h, TILES[step], TILES[adjoint]), "rt_set_tiles")
+
     def set_graphs(self, on: bool):
         _check(load().rt_set_graphs(self._h, 1 if on else 0), "rt_set_graphs")
+
+    def kernel_times(self, U, reps: int = 100) -> dict:
+        """Per-launch microseconds of the selected variants (HIP events on the
+        context's stream): given-dt step, march step, folded adjoint step
+        (the reverse sweep's kernel), rt_step_adjoint (two kernels)."""
+        self._sync_stream()
+        U = self.as_dev(U)
+        out = (ctypes.c_double * 5)()
+        _check(load().rt_kernel_times(self._h, _ptr(U), int(reps), out), "rt_kernel_times")
+        return {"step_given_us": out[0], "step_march_us": out[1], "adjoint_folded_us": out[2],
+                "adjoint_two_kernel_us": out[3], "adjoint_sweep_us": out[4]}
+
+    @property
+    def fold(self) -> bool:
+        """Reverse sweep with the limiter gather folded into the next adjoint kernel."""
+        v = ctypes.c_int32()
+        _check(load().rt_get_fold(self._h, ctypes.byref(v)), "rt_get_fold")
+        return bool(v.value)
+
+    def set_fold(self, on: bool):
+        _check(load().rt_set_fold(self._h, 1 if on else 0), "rt_set_fold")
+
+    def set_overlap(self, on: bool):
+        """Two-stream reverse sweep of the UNIFORM policy (default on); results are identical."""
+        _check(load().rt_set_overlap(self._h, 1 if on else 0), "rt_set_overlap")
 
     def autotune(self, U, reps: int = 20) -> str:
         """Time every kernel variant on U and keep the fastest (bitwise-identical results)."""

@@ -59,7 +59,7 @@ def test_init_and_cfl_match_oracle(cfg):
     np.testing.assert_allclose(ke, o.kinetic_energy(Uo), rtol=1e-13)
 
 
-TILE_NAMES = ["16x16", "32x8", "64x4", "16x16w", "32x8w"]
+TILE_NAMES = ["16x16", "32x8", "64x4", "16x16w", "32x8w", "16x8", "8x8", "16x8w", "8x8w"]
 
 
 @pytest.mark.parametrize("tile", TILE_NAMES)
@@ -156,7 +156,7 @@ def test_step_adjoint_matches_oracle(cfg):
     dt = o.cfl_dt(Uo)
     lam_next = np.random.default_rng(7).standard_normal(Uo.shape)
     ref = o.step_vjp(Uo, dt, lam_next)
-    for tile in ["16x16", "64x4", "32x8w"]:
+    for tile in ["16x16", "64x4", "32x8w", "8x8", "16x8w"]:
         r = rt().Context(cfg, max_steps=64, tile=tile)
         lam = r.step_adjoint(torch.from_numpy(Uo), torch.from_numpy(dt), torch.from_numpy(lam_next))
         assert normwise(host(lam), ref) <= 1e-12
@@ -181,6 +181,33 @@ def test_gradient_matches_oracle_and_policies_agree_bitwise(cfg, T):
     for Rk, gk, nk in results[1:]:
         np.testing.assert_array_equal(gk, g)
         np.testing.assert_array_equal(Rk, R)
+
+
+def test_two_stream_and_folded_sweeps_match_bitwise():
+    # members with different step counts, several segments, a ragged last one
+    cfg = RTConfig(nx=40, ny=72, batch=2)
+    uv = inputs.seed_batch(cfg, [3, 4], rms=1e-3)
+    uv[1] *= 40.0
+    r = rt().Context(cfg, max_steps=2048)
+    out = {}
+    for on, fold in ((True, True), (False, True), (True, False), (False, False)):
+        r.set_overlap(on)
+        r.set_fold(fold)
+        R, g, n = r.grad_u0(uv, 0.2, rt().Policy(CKPT_UNIFORM, 5))
+        out[on, fold] = (host(R), host(g), host(n))
+    r.set_overlap(True)
+    r.set_fold(True)
+    assert out[True, True][2][0] != out[True, True][2][1]
+    for key in out:
+        np.testing.assert_array_equal(out[key][0], out[True, True][0])
+        np.testing.assert_array_equal(out[key][1], out[True, True][1])
+    out = {True: out[True, True]}
+    Rs, gs, _ = r.grad_u0(uv, 0.2, rt().Policy(CKPT_STORE_ALL, 1))
+    np.testing.assert_array_equal(host(gs), out[True][1])
+    # binomial checkpointing runs the unfolded two-kernel adjoint
+    Rr, gr, _ = r.grad_u0(uv, 0.2, rt().Policy(CKPT_REVOLVE, 1, pool_bytes=4 * 8 * 4 * cfg.cells * cfg.batch))
+    np.testing.assert_array_equal(host(gr), out[True][1])
+    np.testing.assert_array_equal(host(Rr), out[True][0])
 
 
 def test_gradient_matches_finite_differences_on_gpu():

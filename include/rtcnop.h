@@ -203,9 +203,11 @@ int rt_autotune(rt_ctx* ctx, const double* U, int32_t reps, int32_t* step_tile, 
 /* The reverse sweep of RT_CKPT_STORE_ALL / RT_CKPT_UNIFORM runs one kernel
  * per adjoint step, which also completes the previous step's limiter gather
  * (on = 1), or the two kernels of rt_step_adjoint per step (on = 0); results
- * are identical.  rt_autotune picks the faster; before it, small grids
- * (fewer than 2^20 cells in all) fold.  Binomial checkpointing always runs
- * two kernels per step. */
+ * are identical.  rt_autotune folds when the folded step is more than 10%
+ * faster than the two-kernel step on their own (the folded kernel shares
+ * the CUs less well with the concurrent re-computation); before it, small
+ * grids (fewer than 2^20 cells in all) fold.  Binomial checkpointing always
+ * runs two kernels per step. */
 int rt_set_fold(rt_ctx* ctx, int32_t on);
 int rt_get_fold(const rt_ctx* ctx, int32_t* on);
 /* Measurement hook: per-launch times in microseconds of the selected

@@ -376,6 +376,18 @@ int rt_get_tiles(const rt_ctx* c, int32_t* step_tile, int32_t* adj_tile) {
 }
 
 namespace {
+// The second stream and its events, created on first use on the current
+// device.
+int ensure_aux(rt_ctx* c) {
+  if (c->aux_stream) return 0;
+  RT_HIP(hipStreamCreateWithFlags(&c->aux_stream, hipStreamNonBlocking));
+  for (hipEvent_t* e : {&c->seg_ready[0], &c->seg_ready[1], &c->seg_free[0], &c->seg_free[1], &c->aux_done})
+    RT_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
+  return 0;
+}
+}  // namespace
+
+namespace {
 
 // Per-launch times (ms) of the kernels as the library launches them: [0] the
 // given-dt step (re-computation), [1] the adaptive step with its CFL
@@ -451,9 +463,10 @@ int time_kernels(rt_ctx* c, const double* U, int step_tile, int adj_tile, int re
 }  // namespace
 
 // Autotuner: times every tile variant of the step kernel (given-dt plus
-// adaptive launches) and of the folded adjoint step on the caller's state U
-// (device, [B][4][ny][nx]) with HIP events on the context's stream and keeps
-// the fastest of each.  All variants give bitwise-identical results, so this
+// adaptive launches) and of the adjoint step (folded and two-kernel) on the
+// caller's state U (device, [B][4][ny][nx]) with HIP events on the context's
+// stream and keeps the fastest step variant and the fastest adjoint variant
+// of the chosen form.  All variants give bitwise-identical results, so this
 // changes speed only.  Uses the workspace buffers as scratch.  Synchronises
 // the stream.
 int rt_autotune(rt_ctx* c, const double* U, int32_t reps, int32_t* step_tile, int32_t* adj_tile) {
@@ -464,25 +477,31 @@ int rt_autotune(rt_ctx* c, const double* U, int32_t reps, int32_t* step_tile, in
   hipEvent_t e0, e1;
   RT_HIP(hipEventCreate(&e0));
   RT_HIP(hipEventCreate(&e1));
-  float best_s = 1e30f, best_a = 1e30f;
-  int bs = c->tile, ba = c->tile_adj;
-  bool bf = c->fold;
+  float best_s = 1e30f, best_f = 1e30f, best_u = 1e30f;
+  int bs = c->tile, bfold = c->tile_adj, bunf = c->tile_adj;
   int rc = 0;
   for (int t = 0; t < rtk::TILE_COUNT && rc == 0; ++t) {
     float ms[4];
     rc = time_kernels(c, U, t, t, reps, e0, e1, ms);
     if (rc) break;
     if (ms[0] + ms[1] < best_s) { best_s = ms[0] + ms[1]; bs = t; }
-    if (ms[2] < best_a) { best_a = ms[2]; ba = t; bf = true; }
-    if (ms[3] < best_a) { best_a = ms[3]; ba = t; bf = false; }
+    if (ms[2] < best_f) { best_f = ms[2]; bfold = t; }
+    if (ms[3] < best_u) { best_u = ms[3]; bunf = t; }
   }
+  // Folded or two-kernel adjoint.  In the two-stream sweep the folded
+  // kernel (more LDS, no LDS-free gather kernel between adjoint launches)
+  // leaves less room on the CUs for the concurrent re-computation, which
+  // costs it about 10% there relative to its time alone; so it is taken
+  // only when it is more than 10% faster alone.
+  const bool fold = best_f < 0.9f * best_u;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc) return rc;
   RT_HIP(hipGetLastError());
+  const int ba = fold ? bfold : bunf;
   c->tile = bs;
   c->tile_adj = ba;
-  c->fold = bf;
+  c->fold = fold;
   if (step_tile) *step_tile = bs;
   if (adj_tile) *adj_tile = ba;
   Flags f{};
@@ -650,17 +669,6 @@ int rt_pool_bytes(const rt_ctx* c, int32_t kind, int32_t interval, int32_t nstep
   return 0;
 }
 
-namespace {
-// The second stream and its events, created on first use on the current
-// device.
-int ensure_aux(rt_ctx* c) {
-  if (c->aux_stream) return 0;
-  RT_HIP(hipStreamCreateWithFlags(&c->aux_stream, hipStreamNonBlocking));
-  for (hipEvent_t* e : {&c->seg_ready[0], &c->seg_ready[1], &c->seg_free[0], &c->seg_free[1], &c->aux_done})
-    RT_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
-  return 0;
-}
-}  // namespace
 
 int rt_grad_u0(rt_ctx* c, const double* uv0, double T, const rt_ckpt_policy* pol, double* R, double* grad,
                int32_t* nsteps_out) {
@@ -680,13 +688,11 @@ int rt_grad_u0(rt_ctx* c, const double* uv0, double T, const rt_ckpt_policy* pol
 
   int interval = 1;
   size_t snap_slots = 0;
-  double* seg = nullptr;
   if (pol->kind == RT_CKPT_STORE_ALL || pol->kind == RT_CKPT_UNIFORM) {
     interval = pol->kind == RT_CKPT_STORE_ALL ? 1 : pol->interval;
     if (interval < 1) return fail(RT_EINVAL, "interval must be >= 1");
     if (slots_total < (size_t)interval) return fail(RT_ENOMEM, "pool holds %zu states, need > %d", slots_total, interval - 1);
     snap_slots = slots_total - (interval - 1);
-    seg = state_slot(snap_slots);
     if (int rc = march(c, T, pool, interval, (int)std::min<size_t>(snap_slots, 1u << 30))) return rc;
   } else if (pol->kind == RT_CKPT_REVOLVE) {
     if (slots_total < 2) return fail(RT_ENOMEM, "revolve needs a pool of at least 2 states");
@@ -813,8 +819,10 @@ int rt_grad_u0(rt_ctx* c, const double* uv0, double T, const rt_ckpt_policy* pol
     // the GPU better when one kernel alone cannot.  The kernels and their
     // order per buffer are those of the one-stream sweep, so the result is
     // the same to the bit.
+    // Segment buffers right after the K snapshots the march wrote (the march
+    // leaves room for one: K <= slots_total - (interval - 1)).
     const bool two = c->overlap && interval > 1 && K > 1 && slots_total >= (size_t)K + 2 * (size_t)(interval - 1);
-    double* segs[2] = {seg, two ? state_slot((size_t)K + interval - 1) : seg};
+    double* segs[2] = {state_slot((size_t)K), state_slot((size_t)K + (two ? interval - 1 : 0))};
     if (two) {
       if (int rc = ensure_aux(c)) return rc;
       RT_HIP(hipEventRecord(c->seg_free[0], s));

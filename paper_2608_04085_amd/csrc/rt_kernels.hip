@@ -529,11 +529,15 @@ __device__ __forceinline__ void lambda_at(const Params& P, const GatherSrc& g, i
 }
 
 // ----------------------------------------------------------------- adjoint A
-// LDS of adjoint kernel A: the face cotangents reuse the primitive tile,
+// LDS of adjoint kernel A.  The face cotangents reuse the primitive tile,
 // which is dead once the predictor has run (the tile cell's own primitives
-// are recomputed from registers for the predictor adjoint).
+// are recomputed from registers for the predictor adjoint); x faces and
+// y faces take turns in that space.  lambda^{n+1} on the halo-1 region is
+// staged in LDS only when the kernel forms it by the folded gather;
+// otherwise the face loops read it from global memory (L2), which keeps the
+// footprint small enough for more resident blocks per CU.
 template <int TX, int TY>
-struct AdjLDS {
+struct AdjCore {
   static constexpr int AX = TX + 4, AY = TY + 4;
   static constexpr int QX = TX + 2, QY = TY + 2;
   union {
@@ -541,24 +545,26 @@ struct AdjLDS {
     struct {
       double XL[4][TY][TX + 1];  // x faces: cotangent of the left state (r, u, v, p)
       double XR[4][TY][TX + 1];  // x faces: cotangent of the right state
+    } fx;
+    struct {
       double YB[4][TY + 1][TX];  // y faces: cotangent of the state below
       double YT[4][TY + 1][TX];  // y faces: cotangent of the state above
-    } f;
+    } fy;
   };
   double Q[12][QY][QX];
-  double L[4][QY][QX];  // lambda-tilde on the halo-1 region
+};
+template <int TX, int TY, bool FOLD>
+struct AdjLDS : AdjCore<TX, TY> {};
+template <int TX, int TY>
+struct AdjLDS<TX, TY, true> : AdjCore<TX, TY> {
+  double L[4][AdjCore<TX, TY>::QY][AdjCore<TX, TY>::QX];  // lambda-tilde on the halo-1 region
 };
 
-template <int TX, int TY, int NT>
+template <int TX, int TY, int NT, bool FOLD>
 __global__ __launch_bounds__(NT) void k_adj_a(Params P, AdjArgs a) {
   static_assert(NT >= TX * TY && NT % 64 == 0, "one thread per tile cell at least");
-  constexpr int QX = AdjLDS<TX, TY>::QX, QY = AdjLDS<TX, TY>::QY;
-  __shared__ AdjLDS<TX, TY> S;
-  double(&sL)[4][QY][QX] = S.L;
-  double(&sXL)[4][TY][TX + 1] = S.f.XL;
-  double(&sXR)[4][TY][TX + 1] = S.f.XR;
-  double(&sYB)[4][TY + 1][TX] = S.f.YB;
-  double(&sYT)[4][TY + 1][TX] = S.f.YT;
+  constexpr int QX = AdjCore<TX, TY>::QX, QY = AdjCore<TX, TY>::QY;
+  __shared__ AdjLDS<TX, TY, FOLD> S;
 
   const int b = blockIdx.z;
   const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
@@ -568,7 +574,7 @@ __global__ __launch_bounds__(NT) void k_adj_a(Params P, AdjArgs a) {
   if (a.nsteps_limit && a.dt_index >= a.nsteps_limit[b]) {
     // the member finished before step n; a folded step n+1 >= n has
     // finished too, so lambda^{n+1} = lambda^{n+2} on the tile
-    if (a.fold.Z != nullptr && tid < TX * TY) {
+    if (FOLD && tid < TX * TY) {
       const int gx = x0 + tid % TX, gy = y0 + tid / TX;
       if (gx < nx && gy < ny) {
         const size_t c = (size_t)gy * nx + gx;
@@ -599,112 +605,136 @@ __global__ __launch_bounds__(NT) void k_adj_a(Params P, AdjArgs a) {
   }
 
   int bad = tile_prims<TX, TY, NT>(P, U, N, x0, y0, S);
-  // lambda^{n+1} on the halo-1 region (corners unused): read, or formed by
-  // the folded gather of step n+1
-  GatherSrc g{};
-  const bool fold = a.fold.Z != nullptr;
-  double* lam_out = nullptr;
-  if (fold) {
+  if constexpr (FOLD) {
+    // lambda^{n+1} on the halo-1 region (corners unused), formed by the
+    // folded gather of step n+1; the tile's own cells go to lam_out
+    GatherSrc g{};
     g.Z = a.fold.Z + (size_t)b * 12 * N;
     g.codes = a.fold.codes + (size_t)b * N;
     g.U = a.fold.U + (size_t)b * 4 * N;
     g.lam_next = a.fold.lam_next + (size_t)b * 4 * N;
     g.pass = a.nsteps_limit && a.fold.dt_index >= a.nsteps_limit[b];
     g.dt = g.pass ? 0.0 : a.dt[(size_t)b * a.dt_stride + a.fold.dt_index];
-    lam_out = a.fold.lam_out + (size_t)b * 4 * N;
-  }
-  for (int k = tid; k < QX * QY; k += NT) {
-    const int lx = k % QX, ly = k / QX;
-    const int gy = y0 - 1 + ly;
-    double l[4] = {0.0, 0.0, 0.0, 0.0};
-    const bool corner = (lx == 0 || lx == QX - 1) && (ly == 0 || ly == QY - 1);
-    if (gy >= 0 && gy < ny && !corner) {
-      const int ux = x0 - 1 + lx, gx = wrapx(ux, nx);
-      const size_t c = (size_t)gy * nx + gx;
-      if (fold) {
-        lambda_at(P, g, gx, gy, l);
+    double* lam_out = a.fold.lam_out + (size_t)b * 4 * N;
+    for (int k = tid; k < QX * QY; k += NT) {
+      const int lx = k % QX, ly = k / QX;
+      const int qy = y0 - 1 + ly;
+      double l[4] = {0.0, 0.0, 0.0, 0.0};
+      const bool corner = (lx == 0 || lx == QX - 1) && (ly == 0 || ly == QY - 1);
+      if (qy >= 0 && qy < ny && !corner) {
+        const int ux = x0 - 1 + lx, qx = wrapx(ux, nx);
+        lambda_at(P, g, qx, qy, l);
         if (lx >= 1 && lx <= TX && ly >= 1 && ly <= TY && ux < nx) {
-          lam_out[c] = l[0];
-          lam_out[N + c] = l[1];
-          lam_out[2 * N + c] = l[2];
-          lam_out[3 * N + c] = l[3];
+          const size_t cc = (size_t)qy * nx + qx;
+          lam_out[cc] = l[0];
+          lam_out[N + cc] = l[1];
+          lam_out[2 * N + cc] = l[2];
+          lam_out[3 * N + cc] = l[3];
         }
-      } else {
-        l[0] = Lm[c];
-        l[1] = Lm[N + c];
-        l[2] = Lm[2 * N + c];
-        l[3] = Lm[3 * N + c];
       }
+      S.L[0][ly][lx] = l[0] + hdtg * l[2];
+      S.L[1][ly][lx] = l[1];
+      S.L[2][ly][lx] = l[2];
+      S.L[3][ly][lx] = l[3];
     }
-    sL[0][ly][lx] = l[0] + hdtg * l[2];
-    sL[1][ly][lx] = l[1];
-    sL[2][ly][lx] = l[2];
-    sL[3][ly][lx] = l[3];
   }
   __syncthreads();
   bad |= tile_predict<TX, TY, NT>(P, dt, x0, y0, S, a.codes + (size_t)b * N);
   __syncthreads();
 
+  // lambda-tilde (rho entry shifted by the momentum source) at halo-1
+  // position (lx, ly) of the tile; rows outside the domain are never asked
+  auto lam = [&](int lx, int ly, double l[4]) {
+    if constexpr (FOLD) {
+      l[0] = S.L[0][ly][lx];
+      l[1] = S.L[1][ly][lx];
+      l[2] = S.L[2][ly][lx];
+      l[3] = S.L[3][ly][lx];
+    } else {
+      const size_t cc = (size_t)(y0 - 1 + ly) * nx + wrapx(x0 - 1 + lx, nx);
+      const double l2 = Lm[2 * N + cc];
+      l[0] = Lm[cc] + hdtg * l2;
+      l[1] = Lm[N + cc];
+      l[2] = l2;
+      l[3] = Lm[3 * N + cc];
+    }
+  };
+
   const double ax = dt * P.inv_dx, ay = dt * P.inv_dy;
+  // x faces
   for (int k = tid; k < (TX + 1) * TY; k += NT) {
     const int fx = k % (TX + 1), fy = k / (TX + 1);
     FS Lb{0, 0, 0, 0}, Rb{0, 0, 0, 0};
     if (y0 + fy < ny) {
       // face between halo-1 cells (fx, fy+1) [left] and (fx+1, fy+1) [right]
-      const double Fb[4] = {ax * (sL[0][fy + 1][fx + 1] - sL[0][fy + 1][fx]),
-                            ax * (sL[1][fy + 1][fx + 1] - sL[1][fy + 1][fx]),
-                            ax * (sL[2][fy + 1][fx + 1] - sL[2][fy + 1][fx]),
-                            ax * (sL[3][fy + 1][fx + 1] - sL[3][fy + 1][fx])};
+      double lL[4], lR[4];
+      lam(fx, fy + 1, lL);
+      lam(fx + 1, fy + 1, lR);
+      const double Fb[4] = {ax * (lR[0] - lL[0]), ax * (lR[1] - lL[1]), ax * (lR[2] - lL[2]), ax * (lR[3] - lL[3])};
       hllc_adj(P, xface_right_of(S, fx, fy + 1), xface_left_of(S, fx + 1, fy + 1), Fb, Lb, Rb);
     }
     // x-frame (r, n = u, t = v, p) is the primitive order
-    sXL[0][fy][fx] = Lb.r;
-    sXL[1][fy][fx] = Lb.n;
-    sXL[2][fy][fx] = Lb.t;
-    sXL[3][fy][fx] = Lb.p;
-    sXR[0][fy][fx] = Rb.r;
-    sXR[1][fy][fx] = Rb.n;
-    sXR[2][fy][fx] = Rb.t;
-    sXR[3][fy][fx] = Rb.p;
+    S.fx.XL[0][fy][fx] = Lb.r;
+    S.fx.XL[1][fy][fx] = Lb.n;
+    S.fx.XL[2][fy][fx] = Lb.t;
+    S.fx.XL[3][fy][fx] = Lb.p;
+    S.fx.XR[0][fy][fx] = Rb.r;
+    S.fx.XR[1][fy][fx] = Rb.n;
+    S.fx.XR[2][fy][fx] = Rb.t;
+    S.fx.XR[3][fy][fx] = Rb.p;
   }
+  __syncthreads();
+  // the tile cell's x contributions: q-bar from both x faces, sx-bar
+  W4 qx{0, 0, 0, 0, 0}, sxb{0, 0, 0, 0, 0};
+  if (own) {
+    const W4 xl{S.fx.XR[0][ty][tx], S.fx.XR[1][ty][tx], S.fx.XR[2][ty][tx], S.fx.XR[3][ty][tx]};
+    const W4 xr{S.fx.XL[0][ty][tx + 1], S.fx.XL[1][ty][tx + 1], S.fx.XL[2][ty][tx + 1], S.fx.XL[3][ty][tx + 1]};
+    qx = W4{xl.r + xr.r, xl.u + xr.u, xl.v + xr.v, xl.p + xr.p};
+    sxb = W4{0.5 * (xr.r - xl.r), 0.5 * (xr.u - xl.u), 0.5 * (xr.v - xl.v), 0.5 * (xr.p - xl.p)};
+  }
+  __syncthreads();
+  // y faces
   for (int k = tid; k < TX * (TY + 1); k += NT) {
     const int fx = k % TX, fy = k / TX;
     const int j = y0 + fy;
     FS Bb{0, 0, 0, 0}, Tb{0, 0, 0, 0};
     // below = halo-1 cell (fx+1, fy), above = (fx+1, fy+1)
     if (j == 0) {
-      wall_pressure_adj(P, yface_bottom_of(S, fx + 1, fy + 1), false, ay * sL[2][fy + 1][fx + 1], Tb);
+      double lT[4];
+      lam(fx + 1, fy + 1, lT);
+      wall_pressure_adj(P, yface_bottom_of(S, fx + 1, fy + 1), false, ay * lT[2], Tb);
     } else if (j == ny) {
-      wall_pressure_adj(P, yface_top_of(S, fx + 1, fy), true, -ay * sL[2][fy][fx + 1], Bb);
+      double lB[4];
+      lam(fx + 1, fy, lB);
+      wall_pressure_adj(P, yface_top_of(S, fx + 1, fy), true, -ay * lB[2], Bb);
     } else if (j < ny) {
-      const double g0 = ay * (sL[0][fy + 1][fx + 1] - sL[0][fy][fx + 1]) + hdtg * (sL[3][fy + 1][fx + 1] + sL[3][fy][fx + 1]);
-      const double g1 = ay * (sL[1][fy + 1][fx + 1] - sL[1][fy][fx + 1]);
-      const double g2 = ay * (sL[2][fy + 1][fx + 1] - sL[2][fy][fx + 1]);
-      const double g3 = ay * (sL[3][fy + 1][fx + 1] - sL[3][fy][fx + 1]);
+      double lB[4], lT[4];
+      lam(fx + 1, fy, lB);
+      lam(fx + 1, fy + 1, lT);
+      const double g0 = ay * (lT[0] - lB[0]) + hdtg * (lT[3] + lB[3]);
+      const double g1 = ay * (lT[1] - lB[1]);
+      const double g2 = ay * (lT[2] - lB[2]);
+      const double g3 = ay * (lT[3] - lB[3]);
       const double Fb[4] = {g0, g2, g1, g3};  // y frame: normal momentum is m_y
       hllc_adj(P, yface_top_of(S, fx + 1, fy), yface_bottom_of(S, fx + 1, fy + 1), Fb, Bb, Tb);
     }
     // y-frame (r, n = v, t = u, p) -> primitive order (r, u, v, p)
-    sYB[0][fy][fx] = Bb.r;
-    sYB[1][fy][fx] = Bb.t;
-    sYB[2][fy][fx] = Bb.n;
-    sYB[3][fy][fx] = Bb.p;
-    sYT[0][fy][fx] = Tb.r;
-    sYT[1][fy][fx] = Tb.t;
-    sYT[2][fy][fx] = Tb.n;
-    sYT[3][fy][fx] = Tb.p;
+    S.fy.YB[0][fy][fx] = Bb.r;
+    S.fy.YB[1][fy][fx] = Bb.t;
+    S.fy.YB[2][fy][fx] = Bb.n;
+    S.fy.YB[3][fy][fx] = Bb.p;
+    S.fy.YT[0][fy][fx] = Tb.r;
+    S.fy.YT[1][fy][fx] = Tb.t;
+    S.fy.YT[2][fy][fx] = Tb.n;
+    S.fy.YT[3][fy][fx] = Tb.p;
   }
   __syncthreads();
 
   if (own) {
     const int lx = tx + 1, ly = ty + 1;
-    const W4 xl{sXR[0][ty][tx], sXR[1][ty][tx], sXR[2][ty][tx], sXR[3][ty][tx]};
-    const W4 xr{sXL[0][ty][tx + 1], sXL[1][ty][tx + 1], sXL[2][ty][tx + 1], sXL[3][ty][tx + 1]};
-    const W4 yb{sYT[0][ty][tx], sYT[1][ty][tx], sYT[2][ty][tx], sYT[3][ty][tx]};
-    const W4 yt{sYB[0][ty + 1][tx], sYB[1][ty + 1][tx], sYB[2][ty + 1][tx], sYB[3][ty + 1][tx]};
-    const W4 qb{xl.r + xr.r + yb.r + yt.r, xl.u + xr.u + yb.u + yt.u, xl.v + xr.v + yb.v + yt.v,
-                xl.p + xr.p + yb.p + yt.p};
-    W4 sxb{0.5 * (xr.r - xl.r), 0.5 * (xr.u - xl.u), 0.5 * (xr.v - xl.v), 0.5 * (xr.p - xl.p)};
+    const W4 yb{S.fy.YT[0][ty][tx], S.fy.YT[1][ty][tx], S.fy.YT[2][ty][tx], S.fy.YT[3][ty][tx]};
+    const W4 yt{S.fy.YB[0][ty + 1][tx], S.fy.YB[1][ty + 1][tx], S.fy.YB[2][ty + 1][tx], S.fy.YB[3][ty + 1][tx]};
+    const W4 qb{qx.r + yb.r + yt.r, qx.u + yb.u + yt.u, qx.v + yb.v + yt.v, qx.p + yb.p + yt.p};
     W4 syb{0.5 * (yt.r - yb.r), 0.5 * (yt.u - yb.u), 0.5 * (yt.v - yb.v), 0.5 * (yt.p - yb.p)};
     W4 wb{0.0, 0.0, 0.0, 0.0};
     const W4 w = cons_to_prim(P, u0, u1, u2, u3);
@@ -1018,7 +1048,10 @@ hipError_t launch_step(const Params& P, int tile, const StepArgs& a, hipStream_t
 template <int TX, int TY, int NT>
 static hipError_t launch_adj_t(const Params& P, const AdjArgs& a, hipStream_t s) {
   dim3 grid((P.nx + TX - 1) / TX, (P.ny + TY - 1) / TY, P.nb);
-  hipLaunchKernelGGL((k_adj_a<TX, TY, NT>), grid, dim3(NT), 0, s, P, a);
+  if (a.fold.Z != nullptr)
+    hipLaunchKernelGGL((k_adj_a<TX, TY, NT, true>), grid, dim3(NT), 0, s, P, a);
+  else
+    hipLaunchKernelGGL((k_adj_a<TX, TY, NT, false>), grid, dim3(NT), 0, s, P, a);
   return hipGetLastError();
 }
 

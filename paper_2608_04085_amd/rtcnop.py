@@ -142,7 +142,12 @@ class Context:
 
     def __init__(self, cfg: RTConfig, max_steps: int = 65536, device: str | int = "cuda", tile: str | None = None):
         self.cfg = cfg
-        self.device = torch.device(device)
+        dev = torch.device(device) if not isinstance(device, int) else torch.device("cuda", device)
+        if dev.type != "cuda":
+            raise ValueError(f"the library runs on a HIP device, not {dev}")
+        if dev.index is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
         self.max_steps = int(max_steps)
         L = load()
         grid = RtGrid(cfg.nx, cfg.ny, cfg.batch, 0, cfg.lx, cfg.ly)
@@ -315,9 +320,13 @@ class Context:
         if pool is None:
             nbytes = policy.pool_bytes or self.pool_bytes(policy.kind, policy.interval, self.max_steps)
             pool = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        if pool.device != self.device or not pool.is_contiguous():
+            raise ValueError("the checkpoint pool must be a contiguous tensor on the context's device")
         off = (-pool.data_ptr()) % 256
-        pol = RtCkptPolicy(policy.kind, policy.interval, ctypes.c_void_p(pool.data_ptr() + off),
-                           pool.numel() - off)
+        nbytes = pool.numel() * pool.element_size() - off
+        if nbytes <= 0:
+            raise ValueError("checkpoint pool too small")
+        pol = RtCkptPolicy(policy.kind, policy.interval, ctypes.c_void_p(pool.data_ptr() + off), nbytes)
         R = self._f64((self.cfg.batch,))
         g = self._f64(self.shape_uv)
         n = torch.empty((self.cfg.batch,), dtype=torch.int32, device=self.device)

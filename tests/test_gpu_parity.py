@@ -210,6 +210,31 @@ def test_two_stream_and_folded_sweeps_match_bitwise():
     np.testing.assert_array_equal(host(Rr), out[True][0])
 
 
+@pytest.mark.parametrize("slack", [0, 1, 7, 64])
+def test_two_stream_sweep_with_pool_sized_to_the_run(slack):
+    # pools sized from the actual step count (plus some slack) put both
+    # segment buffers next to the snapshots; the result must not depend on
+    # the stream overlap or on the pool size
+    cfg = RTConfig(nx=48, ny=80)
+    uv = inputs.seed_batch(cfg, [5], rms=1e-3)
+    r = rt().Context(cfg, max_steps=4096)
+    interval = 6
+    _, _, n, _ = r.integrate(r.init_state(uv), 0.25)
+    nsteps = int(host(n)[0])
+    pb = r.pool_bytes(CKPT_UNIFORM, interval, nsteps + slack)
+    out = []
+    for ov in (True, False, True):
+        r.set_overlap(ov)
+        pool = torch.full(((pb + 256) // 8,), float("nan"), dtype=torch.float64, device=r.device)
+        R, g, _ = r.grad_u0(uv, 0.25, rt().Policy(CKPT_UNIFORM, interval), pool=pool)
+        out.append((host(R), host(g)))
+    r.set_overlap(True)
+    Rs, gs, _ = r.grad_u0(uv, 0.25, rt().Policy(CKPT_STORE_ALL, 1))
+    for R, g in out:
+        np.testing.assert_array_equal(R, host(Rs))
+        np.testing.assert_array_equal(g, host(gs))
+
+
 def test_gradient_matches_finite_differences_on_gpu():
     # central differences of the frozen-schedule march, GPU only
     cfg = RTConfig(nx=64, ny=128)

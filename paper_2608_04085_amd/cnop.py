@@ -55,8 +55,9 @@ def ke_ratio(rt: Context, uv: torch.Tensor, T: float) -> torch.Tensor:
 
 def spg(rt: Context, uv0, T: float, delta: float, iters: int, policy: Policy | None = None,
         pool: torch.Tensor | None = None, memory: int = 10, c_armijo: float = 1e-4, max_backtracks: int = 8,
-        log: SPGLog | None = None):
+        log: SPGLog | None = None, on_iter=None):
     """Run `iters` SPG iterations from uv0 (projected onto ||u|| = delta).
+    on_iter(k, R, log), if given, is called after iteration k.
     Returns (u, R, g, log)."""
     log = log or SPGLog()
     B = rt.cfg.batch
@@ -67,7 +68,7 @@ def spg(rt: Context, uv0, T: float, delta: float, iters: int, policy: Policy | N
     hist = [Rh.copy()]
     gn = _l2dv(rt, g)
     alpha = 0.1 * delta / np.maximum(gn, 1e-300)
-    for _ in range(iters):
+    for it in range(iters):
         lam = np.ones(B)
         accepted = np.zeros(B, dtype=bool)
         u_new = torch.empty_like(u)
@@ -110,6 +111,8 @@ def spg(rt: Context, uv0, T: float, delta: float, iters: int, policy: Policy | N
         log.grad_norm.append(gn.tolist())
         log.chi.append(chi.tolist())
         log.backtracks.append(nback.tolist())
+        if on_iter is not None:
+            on_iter(it, Rh, log)
     return u, torch.as_tensor(Rh), g, log
 
 

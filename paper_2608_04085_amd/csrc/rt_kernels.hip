@@ -313,10 +313,14 @@ __global__ __launch_bounds__(NT) void k_step(Params P, StepArgs a) {
   }
   __syncthreads();
 
-  // phase C: every face of the tile once (x faces, then y faces)
+  // phase C: every face of the tile once (x faces, then y faces).  The x
+  // faces are padded to whole wavefronts so that no wavefront runs both the
+  // x and the y branch (which would put two flux evaluations in series).
   constexpr int NXF = (TX + 1) * TY, NYF = TX * (TY + 1);
-  for (int k = tid; k < NXF + NYF; k += NT) {
-    if (k < NXF) {
+  constexpr int NXP = (NXF + 63) / 64 * 64;
+  for (int k = tid; k < NXP + NYF; k += NT) {
+    if (k < NXP) {
+      if (k >= NXF) continue;
       const int fx = k % (TX + 1), fy = k / (TX + 1);
       if (y0 + fy >= ny) continue;
       const int l = fx, r = fx + 1, y = fy + 1;
@@ -331,7 +335,7 @@ __global__ __launch_bounds__(NT) void k_step(Params P, StepArgs a) {
       S.fg.F[2][fy][fx] = F[2];
       S.fg.F[3][fy][fx] = F[3];
     } else {
-      const int kk = k - NXF;
+      const int kk = k - NXP;
       const int fx = kk % TX, fy = kk / TX;
       const int j = y0 + fy;
       if (j > ny) continue;
@@ -693,8 +697,9 @@ __global__ __launch_bounds__(NT) void k_adj_a(Params P, AdjArgs a) {
     sxb = W4{0.5 * (xr.r - xl.r), 0.5 * (xr.u - xl.u), 0.5 * (xr.v - xl.v), 0.5 * (xr.p - xl.p)};
   }
   __syncthreads();
-  // y faces
-  for (int k = tid; k < TX * (TY + 1); k += NT) {
+  // y faces, the thread index rotated by one wavefront so that a second
+  // pass of this loop and of the x-face loop fall on different wavefronts
+  for (int k = (tid + NT - 64) % NT; k < TX * (TY + 1); k += NT) {
     const int fx = k % TX, fy = k / TX;
     const int j = y0 + fy;
     FS Bb{0, 0, 0, 0}, Tb{0, 0, 0, 0};

@@ -147,6 +147,25 @@ int rt_step_adjoint(rt_ctx* ctx, const double* U, const double* dt, const double
 int rt_grad_u0(rt_ctx* ctx, const double* uv0, double T, const rt_ckpt_policy* policy, double* R,
                double* grad, int32_t* nsteps);
 
+/* Kinetic-energy density of Eq. 7, e_k = |m|^2 / (2 rho), of every cell:
+ * U [B][4][ny][nx] -> ek [B][ny][nx] (device). */
+int rt_ek_field(rt_ctx* ctx, const double* U, double* ek);
+
+/* Objective of Eq. 8 on the grid: J[B] = sum over cells of
+ * (e_k(U) - ek_base)^2 dx dy, with ek_base [B][ny][nx] the e_k field of the
+ * unperturbed run at the same time (device arrays). */
+int rt_ek_anomaly(rt_ctx* ctx, const double* U, const double* ek_base, double* J);
+
+/* J[B] of Eq. 8 for the perturbation uv0 marched to time T, and its
+ * gradient dJ/d(u0, v0) ([B][2][ny][nx]) by the discrete adjoint with the
+ * forward run's time steps held fixed (Sec. 3.4), under the same checkpoint
+ * policies and with the same kernels as rt_grad_u0.  ek_base is the
+ * baseline field (rt_ek_field of the unperturbed march to T).  A zero
+ * perturbation is allowed (J and the gradient are then those at the
+ * baseline).  Synchronises the stream; errors as rt_grad_u0. */
+int rt_grad_ek_anomaly(rt_ctx* ctx, const double* uv0, double T, const rt_ckpt_policy* policy,
+                       const double* ek_base, double* J, double* grad, int32_t* nsteps);
+
 /* Bytes of checkpoint pool that `kind`/`interval` needs for marches of
  * nsteps_max steps (RT_CKPT_UNIFORM: ceil(nsteps_max / interval) snapshots
  * plus two segment buffers of interval - 1 states, one fewer buffer being

@@ -15,6 +15,10 @@
 //                      the initial velocity field, by reverse-mode AD through
 //                      the whole discrete march with the time steps of the
 //                      forward run held fixed (Sec. 3.4)
+//   rto_ek_field       kinetic-energy density field of Eq. 7
+//   rto_ek_anomaly_frozen  objective J of Eq. 8 after a march with given steps
+//   rto_grad_ek_anomaly    J and its exact gradient (same reverse sweep as
+//                      rto_grad_u0, terminal adjoint dJ/dU^N)
 //   rto_project_to_constraint  scaling onto the constraint set (Eq. 11)
 //   rto_hllc, rto_wall_pressure  single-face fluxes for unit tests
 #include <cmath>
@@ -254,6 +258,98 @@ int rto_ke_ratio_frozen(const Problem* P, const double* uv0, const double* dt_lo
       U.swap(Un);
     }
     R[b] = rto::kinetic_energy<double>(Q, U.data()) / ke0;
+  }
+  return 0;
+}
+
+// Kinetic-energy density e_k = |m|^2/(2 rho) of each cell (Eq. 7),
+// layout [nb][ny][nx].
+int rto_ek_field(const Problem* P, const double* U, double* ek) {
+  if (!valid(P) || !U || !ek) return kEInval;
+  const size_t N = cells(P);
+  for (int b = 0; b < P->nb; ++b) rto::ek_field<double>(*P, U + 4 * N * b, ek + N * b);
+  return 0;
+}
+
+// J = sum over cells of (e_k(U^N) - ek_base)^2 dx dy (Eq. 8) after the march
+// with the given steps dt_log[nb][cap] (nsteps[b] of them); ek_base is
+// [nb][ny][nx].
+int rto_ek_anomaly_frozen(const Problem* P, const double* uv0, const double* dt_log, const int32_t* nsteps,
+                          int32_t cap, const double* ek_base, double* J) {
+  if (!valid(P) || !uv0 || !dt_log || !nsteps || !ek_base || !J) return kEInval;
+  const size_t N = cells(P), n4 = 4 * N;
+  std::vector<double> U(n4), Un(n4);
+  for (int b = 0; b < P->nb; ++b) {
+    Problem Q = *P;
+    Q.nb = 1;
+    rto::init_member<double>(Q, uv0 + 2 * N * b, U.data());
+    for (int32_t s = 0; s < nsteps[b]; ++s) {
+      if (rto::step_member<double>(Q, U.data(), Un.data(), dt_log[static_cast<size_t>(b) * cap + s]))
+        return kEUnphys;
+      U.swap(Un);
+    }
+    J[b] = rto::ek_anomaly<double>(Q, U.data(), ek_base + N * b);
+  }
+  return 0;
+}
+
+// J of Eq. 8 for each member and dJ/d(u0, v0) ([2][ny][nx]), by reverse-mode
+// AD through the march with the forward run's steps held fixed (as in
+// rto_grad_u0): terminal adjoint dJ/dU^N, the stored-state reverse sweep,
+// then the adjoint of U^0(uv0).
+int rto_grad_ek_anomaly(const Problem* P, const double* uv0, double T, const double* ek_base, double* J,
+                        double* grad, int32_t* nsteps, double* dt_log, int32_t cap) {
+  if (!valid(P) || !uv0 || !ek_base || !J || !grad || !(T > 0)) return kEInval;
+  const size_t N = cells(P), n4 = 4 * N;
+  rto::Tape& tp = rto::tape();
+  for (int b = 0; b < P->nb; ++b) {
+    Problem Q = *P;
+    Q.nb = 1;
+    const double* uv = uv0 + 2 * N * b;
+    const double* ekb = ek_base + N * b;
+    std::vector<double> U(n4);
+    rto::init_member<double>(Q, uv, U.data());
+    std::vector<double> dts;
+    std::vector<std::vector<double>> states;
+    int32_t n = 0;
+    const int rc = integrate_member(Q, U.data(), T, nullptr, &n, &dts, &states);
+    if (rc) return rc;
+    if (nsteps) nsteps[b] = n;
+    if (dt_log) {
+      if (n > cap) return kENomem;
+      for (int32_t k = 0; k < n; ++k) dt_log[static_cast<size_t>(b) * cap + k] = dts[k];
+    }
+    J[b] = rto::ek_anomaly<double>(Q, U.data(), ekb);
+
+    std::vector<double> lam(n4), lam_prev(n4);
+    {
+      tp.clear();
+      std::vector<Rev> x(n4);
+      for (size_t k = 0; k < n4; ++k) x[k] = Rev::leaf(U[k]);
+      const Rev r = rto::ek_anomaly<Rev>(Q, x.data(), ekb);
+      tp.adj.assign(tp.nodes.size(), 0.0);
+      tp.adj[r.i] = 1.0;
+      tp.sweep();
+      for (size_t k = 0; k < n4; ++k) lam[k] = tp.adj[x[k].i];
+      tp.clear();
+    }
+    for (int32_t s = n - 1; s >= 0; --s) {
+      if (vjp_member(Q, states[s].data(), dts[s], lam.data(), lam_prev.data())) return kEUnphys;
+      lam.swap(lam_prev);
+    }
+    {
+      tp.clear();
+      std::vector<Rev> q(2 * N), U0(n4);
+      for (size_t k = 0; k < 2 * N; ++k) q[k] = Rev::leaf(uv[k]);
+      rto::init_member<Rev>(Q, q.data(), U0.data());
+      Rev f(0.0);
+      for (size_t k = 0; k < n4; ++k) f = f + lam[k] * U0[k];
+      tp.adj.assign(tp.nodes.size(), 0.0);
+      tp.adj[f.i] = 1.0;
+      tp.sweep();
+      for (size_t k = 0; k < 2 * N; ++k) grad[2 * N * b + k] = tp.adj[q[k].i];
+      tp.clear();
+    }
   }
   return 0;
 }

@@ -62,6 +62,9 @@ def lib():
             "rto_grad_u0": [P, _dp, ctypes.c_double, _dp, _dp, _ip, _dp, ctypes.c_int32],
             "rto_ke_ratio_frozen": [P, _dp, _dp, _ip, ctypes.c_int32, _dp],
             "rto_project_to_constraint": [P, _dp, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, _dp],
+            "rto_ek_field": [P, _dp, _dp],
+            "rto_ek_anomaly_frozen": [P, _dp, _dp, _ip, ctypes.c_int32, _dp, _dp],
+            "rto_grad_ek_anomaly": [P, _dp, ctypes.c_double, _dp, _dp, _dp, _ip, _dp, ctypes.c_int32],
             "rto_hllc": [ctypes.c_double, _dp, _dp, _dp],
             "rto_background": [P, _dp, _dp],
         }
@@ -185,6 +188,48 @@ class Oracle:
                                        int(dt_log.shape[1]), _p(R))
         _check(rc, "ke_ratio_frozen")
         return R
+
+    def ek_field(self, U):
+        """Kinetic-energy density e_k = |m|^2/(2 rho) of every cell, [nb][ny][nx] (Eq. 7)."""
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        ek = np.empty((self.prob.nb, self.prob.ny, self.prob.nx))
+        _check(lib().rto_ek_field(ctypes.byref(self.prob), _p(U), _p(ek)), "ek_field")
+        return ek
+
+    def _ekb(self, ek_base):
+        return np.ascontiguousarray(np.broadcast_to(np.asarray(ek_base, dtype=np.float64),
+                                                    (self.prob.nb, self.prob.ny, self.prob.nx)))
+
+    def grad_ek_anomaly(self, uv0, T, ek_base, cap: int = 0):
+        """(J, grad, nsteps, dt_log): objective of Eq. 8 against the baseline
+        field ek_base and its exact frozen-schedule gradient."""
+        uv0 = np.ascontiguousarray(uv0, dtype=np.float64).reshape(self.shape_uv)
+        ekb = self._ekb(ek_base)
+        J = np.empty(self.prob.nb)
+        g = np.empty(self.shape_uv)
+        n = np.empty(self.prob.nb, dtype=np.int32)
+        log = np.zeros((self.prob.nb, max(cap, 1)))
+        rc = lib().rto_grad_ek_anomaly(ctypes.byref(self.prob), _p(uv0), float(T), _p(ekb), _p(J), _p(g), _ipt(n),
+                                       _p(log) if cap > 0 else None, int(cap))
+        _check(rc, "grad_ek_anomaly")
+        return J, g, n, (log if cap > 0 else None)
+
+    def ek_anomaly_frozen(self, uv0, dt_log, nsteps, ek_base):
+        uv0 = np.ascontiguousarray(uv0, dtype=np.float64).reshape(self.shape_uv)
+        dt_log = np.ascontiguousarray(dt_log, dtype=np.float64)
+        nsteps = np.ascontiguousarray(nsteps, dtype=np.int32)
+        ekb = self._ekb(ek_base)
+        J = np.empty(self.prob.nb)
+        rc = lib().rto_ek_anomaly_frozen(ctypes.byref(self.prob), _p(uv0), _p(dt_log), _ipt(nsteps),
+                                         int(dt_log.shape[1]), _p(ekb), _p(J))
+        _check(rc, "ek_anomaly_frozen")
+        return J
+
+    def baseline_ek(self, T):
+        """e_k of the unperturbed run at time T (the reference field of Eq. 8)."""
+        U0 = self.init_state(np.zeros(self.shape_uv))
+        UT, _, _, _ = self.integrate(U0, T)
+        return self.ek_field(UT)
 
     def project_to_constraint(self, uv, delta, norm: int = 0, kind: int = 0):
         uv = np.array(uv, dtype=np.float64, copy=True, order="C").reshape(self.shape_uv)

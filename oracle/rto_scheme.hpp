@@ -316,6 +316,30 @@ T kinetic_energy(const Problem& P, const T* U) {
   return s * dV;
 }
 
+// Kinetic-energy density field of Eq. 7, e_k = rho |u|^2 / 2 = |m|^2 / (2 rho),
+// cell by cell.
+template <class T>
+void ek_field(const Problem& P, const T* U, T* ek) {
+  const int N = P.nx * P.ny;
+  for (int c = 0; c < N; ++c) ek[c] = 0.5 * (U[N + c] * U[N + c] + U[2 * N + c] * U[2 * N + c]) / U[c];
+}
+
+// Objective of Eq. 8 on the grid: the volume integral of the squared
+// departure of e_k(U) from the baseline field ek_base.
+template <class T>
+T ek_anomaly(const Problem& P, const T* U, const double* ek_base) {
+  const int N = P.nx * P.ny;
+  const double dV = dx_of(P) * dy_of(P);
+  std::vector<T> ek(N);
+  ek_field<T>(P, U, ek.data());
+  T s(0.0);
+  for (int c = 0; c < N; ++c) {
+    const T d = ek[c] - ek_base[c];
+    s = s + d * d;
+  }
+  return s * dV;
+}
+
 // Initial state of one member from the velocity perturbation (u0, v0) laid
 // out [2][ny][nx]: the hydrostatic two-layer background (Sec. 2.2) plus the
 // perturbation velocity, evaluated at cell centres.  Components switched off

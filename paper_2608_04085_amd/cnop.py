@@ -27,7 +27,8 @@ from dataclasses import dataclass, field
 import numpy as np
 import torch
 
-from .config import NORM_L2, SET_SPHERE
+from . import optim
+from .config import NORM_L2, NORM_RHO_KE, SET_BALL, SET_SPHERE
 from .rtcnop import Context, Policy
 
 
@@ -114,6 +115,56 @@ def spg(rt: Context, uv0, T: float, delta: float, iters: int, policy: Policy | N
         if on_iter is not None:
             on_iter(it, Rh, log)
     return u, torch.as_tensor(Rh), g, log
+
+
+class LibraryBackend:
+    """Field operations of the projected L-BFGS search on the HIP library,
+    for the paper's problem (Sec. 3.1): maximise J of Eq. 8 against the
+    baseline field ek_base at time T over the ball C <= eps of Eq. 9, with
+    the projection of Eq. 11."""
+
+    def __init__(self, rt: Context, T: float, ek_base, eps: float, policy: Policy | None = None,
+                 pool: torch.Tensor | None = None):
+        self.rt, self.T, self.eps, self.policy, self.pool = rt, float(T), float(eps), policy, pool
+        self.ek_base = rt.as_dev(ek_base).expand(rt.cfg.batch, rt.cfg.ny, rt.cfg.nx).contiguous()
+
+    def dot(self, a, b):
+        return self.rt.dot(a, b).cpu().numpy()
+
+    def axpy(self, x, alpha, y):
+        return self.rt.axpy(x, alpha, y)
+
+    def project(self, x):
+        return self.rt.project_to_constraint(x, self.eps, NORM_RHO_KE, SET_BALL)[0]
+
+    def max_abs(self, x):
+        return self.rt.max_abs(x).cpu().numpy()
+
+    def where(self, mask, a, b):
+        m = torch.as_tensor(np.asarray(mask), device=a.device).view(-1, 1, 1, 1)
+        return torch.where(m, a, b)
+
+    def value(self, x):
+        U0 = self.rt.init_state(x)
+        UT, _, _, _ = self.rt.integrate(U0, self.T)
+        return self.rt.ek_anomaly(UT, self.ek_base).cpu().numpy()
+
+    def value_and_grad(self, x):
+        J, g, _ = self.rt.grad_ek_anomaly(x, self.T, self.ek_base, self.policy, pool=self.pool)
+        return J.cpu().numpy(), g
+
+
+def paper_cnop(rt: Context, uv0, T: float, eps: float, iters: int, policy: Policy | None = None,
+               pool: torch.Tensor | None = None, memory: int = 10, on_iter=None):
+    """The paper's search (Sec. 3): maximise J of Eq. 8 over C <= eps with
+    projected L-BFGS (m = memory) and a non-monotone Armijo line search, from
+    initial guesses uv0 scaled to C = eps.  Every member is an independent
+    restart.  Returns (u, J, g, log, ek_base)."""
+    ek_base = rt.baseline_ek(T)
+    u0, _ = rt.project_to_constraint(rt.as_dev(uv0), eps, NORM_RHO_KE, SET_SPHERE)
+    be = LibraryBackend(rt, T, ek_base, eps, policy, pool)
+    u, J, g, log = optim.lbfgs_max(be, u0, iters, memory=memory, on_iter=on_iter)
+    return u, J, g, log, ek_base
 
 
 def spectrum_top5(v_row: np.ndarray) -> float:

@@ -670,8 +670,12 @@ int rt_pool_bytes(const rt_ctx* c, int32_t kind, int32_t interval, int32_t nstep
 }
 
 
-int rt_grad_u0(rt_ctx* c, const double* uv0, double T, const rt_ckpt_policy* pol, double* R, double* grad,
-               int32_t* nsteps_out) {
+namespace {
+// Forward march with checkpoints, then the reverse sweep, for the objective
+// R = KE(T)/KE(0) (ek_base == nullptr) or J of Eq. 8 against the baseline
+// field ek_base; the objective value goes to val[B].
+int grad_objective(rt_ctx* c, const double* uv0, double T, const rt_ckpt_policy* pol, const double* ek_base,
+                   double* R, double* grad, int32_t* nsteps_out) {
   if (int rc = need_ws(c)) return rc;
   if (!uv0 || !pol || !R || !grad || !(T > 0) || !std::isfinite(T)) return fail(RT_EINVAL, "bad argument");
   if (!pol->pool) return fail(RT_EINVAL, "checkpoint pool is null");
@@ -715,13 +719,19 @@ int rt_grad_u0(rt_ctx* c, const double* uv0, double T, const rt_ckpt_policy* pol
   RT_HIP(hipMemcpyAsync(hn.data(), c->nsteps, sizeof(int32_t) * P.nb, hipMemcpyDeviceToHost, s));
   RT_HIP(hipMemcpyAsync(hke0.data(), c->sc(1), sizeof(double) * P.nb, hipMemcpyDeviceToHost, s));
   RT_HIP(hipStreamSynchronize(s));
-  for (double k : hke0)
-    if (!(k > 0.0)) return fail(RT_EINVAL, "KE(0) = %g: the perturbation is zero", k);
+  if (!ek_base)
+    for (double k : hke0)
+      if (!(k > 0.0)) return fail(RT_EINVAL, "KE(0) = %g: the perturbation is zero", k);
   const int nmax = *std::max_element(hn.begin(), hn.end());
 
   // terminal adjoint lambda^N into L0 (from U^N in L1)
-  RT_HIP(rtk::launch_reduce(P, 1, c->L1, nullptr, c->partial, c->red_blocks, c->sc(2), s));
-  RT_HIP(rtk::launch_terminal_adjoint(P, c->L1, c->sc(1), c->L0, s));
+  if (ek_base) {
+    RT_HIP(rtk::launch_reduce(P, 7, c->L1, ek_base, c->partial, c->red_blocks, R, s));
+    RT_HIP(rtk::launch_terminal_adjoint_ek(P, c->L1, ek_base, c->L0, s));
+  } else {
+    RT_HIP(rtk::launch_reduce(P, 1, c->L1, nullptr, c->partial, c->red_blocks, c->sc(2), s));
+    RT_HIP(rtk::launch_terminal_adjoint(P, c->L1, c->sc(1), c->L0, s));
+  }
   double* lam = c->L0;
   double* lam_other = c->L1;
 
@@ -899,9 +909,38 @@ int rt_grad_u0(rt_ctx* c, const double* uv0, double T, const rt_ckpt_policy* pol
   }
 
   // initial adjoint -> R, gradient
-  RT_HIP(rtk::launch_initial_adjoint(P, uv0, lam, c->sc(1), c->sc(2), R, grad, s));
+  if (ek_base)
+    RT_HIP(rtk::launch_initial_adjoint_plain(P, uv0, lam, grad, s));
+  else
+    RT_HIP(rtk::launch_initial_adjoint(P, uv0, lam, c->sc(1), c->sc(2), R, grad, s));
   if (int rc = read_flags(c, &f, true)) return rc;
   return flags_status(f);
+}
+}  // namespace
+
+int rt_grad_u0(rt_ctx* c, const double* uv0, double T, const rt_ckpt_policy* pol, double* R, double* grad,
+               int32_t* nsteps_out) {
+  return grad_objective(c, uv0, T, pol, nullptr, R, grad, nsteps_out);
+}
+
+int rt_grad_ek_anomaly(rt_ctx* c, const double* uv0, double T, const rt_ckpt_policy* pol, const double* ek_base,
+                       double* J, double* grad, int32_t* nsteps) {
+  if (!ek_base) return fail(RT_EINVAL, "null baseline field");
+  return grad_objective(c, uv0, T, pol, ek_base, J, grad, nsteps);
+}
+
+int rt_ek_field(rt_ctx* c, const double* U, double* ek) {
+  if (int rc = need_ws(c)) return rc;
+  if (!U || !ek) return fail(RT_EINVAL, "null argument");
+  RT_HIP(rtk::launch_ek_field(c->P, U, ek, c->stream));
+  return 0;
+}
+
+int rt_ek_anomaly(rt_ctx* c, const double* U, const double* ek_base, double* J) {
+  if (int rc = need_ws(c)) return rc;
+  if (!U || !ek_base || !J) return fail(RT_EINVAL, "null argument");
+  RT_HIP(rtk::launch_reduce(c->P, 7, U, ek_base, c->partial, c->red_blocks, J, c->stream));
+  return 0;
 }
 
 int rt_project_to_constraint(rt_ctx* c, double* uv, double delta, int32_t norm, int32_t set, double* norm_out) {

@@ -116,7 +116,8 @@ hipError_t launch_adjoint(const Params& P, int tile, const AdjArgs& a, hipStream
 hipError_t launch_adj_gather(const Params& P, const AdjArgs& a, hipStream_t s);
 // Per-member reductions: kind 0 = max signal speed, 1 = kinetic energy,
 // 2.. = weighted |uv|^2 for the projection (norm id = kind - 2), 5 = dot,
-// 6 = max |x| of a velocity field.
+// 6 = max |x| of a velocity field, 7 = objective of Eq. 8 (a = U,
+// b = baseline e_k field [B][ny][nx]).
 hipError_t launch_reduce(const Params& P, int kind, const double* a, const double* b, double* partial,
                          int nblk, double* out, hipStream_t s);
 hipError_t launch_march_begin(const Params& P, const double* maxspeed, double T, Ctl* ctl, uint64_t* acc,
@@ -132,6 +133,11 @@ hipError_t launch_terminal_adjoint(const Params& P, const double* U, const doubl
                                    hipStream_t s);
 hipError_t launch_initial_adjoint(const Params& P, const double* uv0, const double* lam0, const double* ke0,
                                   const double* keN, double* R, double* grad, hipStream_t s);
+hipError_t launch_terminal_adjoint_ek(const Params& P, const double* U, const double* ek_base, double* lam,
+                                      hipStream_t s);
+hipError_t launch_initial_adjoint_plain(const Params& P, const double* uv0, const double* lam0, double* grad,
+                                       hipStream_t s);
+hipError_t launch_ek_field(const Params& P, const double* U, double* ek, hipStream_t s);
 hipError_t launch_scale_project(const Params& P, double* uv, const double* m, double delta, int norm,
                                 int set, hipStream_t s);
 hipError_t launch_axpy(const Params& P, const double* x, const double* alpha, const double* y, double* out,

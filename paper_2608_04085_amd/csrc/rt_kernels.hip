@@ -834,6 +834,15 @@ __global__ __launch_bounds__(256) void k_reduce_partial(Params P, int kind, cons
       if (kind == 4) w = 0.5 * rho0_at(P, ((int)(c / P.nx) + 0.5) * P.dy);
       acc += w * (u * u + v * v);
     }
+  } else if (kind == 7) {
+    // (e_k(U) - e_k,base)^2 summed over the cells (objective of Eq. 8)
+    const double* U = A + (size_t)b * 4 * N;
+    const double* ekb = Bv + (size_t)b * N;
+    for (size_t c = (size_t)blockIdx.x * 256 + threadIdx.x; c < N; c += (size_t)nblk * 256) {
+      const double mx = U[N + c], my = U[2 * N + c];
+      const double d = 0.5 * (mx * mx + my * my) / U[c] - ekb[c];
+      acc += d * d;
+    }
   } else if (kind == 5) {
     const double* x = A + (size_t)b * 2 * N;
     const double* y = Bv + (size_t)b * 2 * N;
@@ -869,6 +878,7 @@ __global__ __launch_bounds__(256) void k_reduce_final(Params P, int kind, const 
     case 2: out[b] = sqrt(r * dV); break;  // velocity L2 norm
     case 3: out[b] = sqrt(r / N); break;   // RMS
     case 4: out[b] = r * dV; break;        // energy C of Eq. 9
+    case 7: out[b] = r * dV; break;        // objective of Eq. 8
     default: out[b] = r; break;            // dot product
   }
 }
@@ -949,6 +959,57 @@ __global__ void k_terminal_adjoint(Params P, const double* U, const double* ke0,
   l[N + idx] = vx * s;
   l[2 * N + idx] = vy * s;
   l[3 * N + idx] = 0.0;
+}
+
+// Terminal adjoint of J (Eq. 8): 2 (e_k - e_k,base) dV times de_k/dU =
+// (-(u^2 + v^2)/2, u, v, 0).
+__global__ void k_terminal_adjoint_ek(Params P, const double* U, const double* ek_base, double* lam) {
+  const size_t N = (size_t)P.nx * P.ny;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y;
+  if (idx >= N) return;
+  const double* u = U + (size_t)b * 4 * N;
+  double* l = lam + (size_t)b * 4 * N;
+  const double mx = u[N + idx], my = u[2 * N + idx];
+  const double ri = 1.0 / u[idx];
+  const double vx = mx * ri, vy = my * ri;
+  // e_k exactly as the field and the objective compute it, so that the
+  // unperturbed run gives a zero terminal adjoint
+  const double ek = 0.5 * (mx * mx + my * my) / u[idx];
+  const double w = 2.0 * (ek - ek_base[(size_t)b * N + idx]) * (P.dx * P.dy);
+  l[idx] = -0.5 * (vx * vx + vy * vy) * w;
+  l[N + idx] = vx * w;
+  l[2 * N + idx] = vy * w;
+  l[3 * N + idx] = 0.0;
+}
+
+// Gradient of an objective that depends on uv0 only through U^0:
+// grad_u = rho0 (lam_mx + u0 lam_E) (and v), masked components zero.
+__global__ void k_initial_adjoint_plain(Params P, const double* uv0, const double* lam0, double* grad) {
+  const size_t N = (size_t)P.nx * P.ny;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y;
+  if (idx >= N) return;
+  const int j = (int)(idx / P.nx);
+  const double r0 = rho0_at(P, (j + 0.5) * P.dy);
+  const double* q = uv0 + (size_t)b * 2 * N;
+  const double* l = lam0 + (size_t)b * 4 * N;
+  double* g = grad + (size_t)b * 2 * N;
+  const double u = (P.comp_mask & 1) ? q[idx] : 0.0;
+  const double v = (P.comp_mask & 2) ? q[N + idx] : 0.0;
+  g[idx] = (P.comp_mask & 1) ? r0 * (l[N + idx] + u * l[3 * N + idx]) : 0.0;
+  g[N + idx] = (P.comp_mask & 2) ? r0 * (l[2 * N + idx] + v * l[3 * N + idx]) : 0.0;
+}
+
+// e_k = |m|^2 / (2 rho) of every cell, [B][ny][nx].
+__global__ void k_ek_field(Params P, const double* U, double* ek) {
+  const size_t N = (size_t)P.nx * P.ny;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y;
+  if (idx >= N) return;
+  const double* u = U + (size_t)b * 4 * N;
+  const double mx = u[N + idx], my = u[2 * N + idx];
+  ek[(size_t)b * N + idx] = 0.5 * (mx * mx + my * my) / u[idx];
 }
 
 // grad_u = rho0 (lam_mx + u0 lam_E) - (R/KE0) rho0 u0 dV (and v), R = KE_N/KE0.
@@ -1149,6 +1210,25 @@ hipError_t launch_initial_adjoint(const Params& P, const double* uv0, const doub
                                   const double* keN, double* R, double* grad, hipStream_t s) {
   hipLaunchKernelGGL(k_initial_adjoint, cells_grid(P, (size_t)P.nx * P.ny), dim3(256), 0, s, P, uv0, lam0, ke0,
                      keN, R, grad);
+  return hipGetLastError();
+}
+
+hipError_t launch_terminal_adjoint_ek(const Params& P, const double* U, const double* ek_base, double* lam,
+                                      hipStream_t s) {
+  hipLaunchKernelGGL(k_terminal_adjoint_ek, cells_grid(P, (size_t)P.nx * P.ny), dim3(256), 0, s, P, U, ek_base,
+                     lam);
+  return hipGetLastError();
+}
+
+hipError_t launch_initial_adjoint_plain(const Params& P, const double* uv0, const double* lam0, double* grad,
+                                       hipStream_t s) {
+  hipLaunchKernelGGL(k_initial_adjoint_plain, cells_grid(P, (size_t)P.nx * P.ny), dim3(256), 0, s, P, uv0, lam0,
+                     grad);
+  return hipGetLastError();
+}
+
+hipError_t launch_ek_field(const Params& P, const double* U, double* ek, hipStream_t s) {
+  hipLaunchKernelGGL(k_ek_field, cells_grid(P, (size_t)P.nx * P.ny), dim3(256), 0, s, P, U, ek);
   return hipGetLastError();
 }
 

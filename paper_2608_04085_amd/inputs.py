@@ -36,10 +36,10 @@ def envelope(cfg: RTConfig, width: float = ENVELOPE_WIDTH) -> np.ndarray:
     return np.exp(-(((y - cfg.y0) / width) ** 2))
 
 
-def gaussian_seed(cfg: RTConfig, seed: int) -> np.ndarray:
+def gaussian_seed(cfg: RTConfig, seed: int, width: float = ENVELOPE_WIDTH) -> np.ndarray:
     """(2, ny, nx) envelope-masked i.i.d. Gaussian field, unscaled."""
     xi = np.random.default_rng(seed).standard_normal((2, cfg.ny, cfg.nx))
-    return xi * envelope(cfg)[None, :, None]
+    return xi * envelope(cfg, width)[None, :, None]
 
 
 def fourier_seed(cfg: RTConfig, kx: int, phase: float) -> np.ndarray:
@@ -105,3 +105,12 @@ def direction_batch(cfg: RTConfig, seeds, delta: float) -> np.ndarray:
     """Envelope-masked Gaussian directions at L2 norm delta (for finite
     differences of the objective along random directions)."""
     return seed_batch(cfg, seeds, rms=None, l2=delta)
+
+
+def paper_seed_batch(cfg: RTConfig, seeds, width_frac: float = 0.1) -> np.ndarray:
+    """[B][2][ny][nx] initial guesses of the paper's search (Sec. 3.4): a
+    Gaussian field localised near the interface with envelope width
+    width_frac * Ly, in the components of cfg.comp_mask (v only for the
+    paper's setup), unscaled; the caller scales it onto the constraint."""
+    return np.ascontiguousarray(np.stack([mask_components(gaussian_seed(cfg, int(s), width_frac * cfg.ly),
+                                                          cfg.comp_mask) for s in seeds]))

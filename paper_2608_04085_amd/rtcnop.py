@@ -84,6 +84,9 @@ def load():
         "rt_kernel_times": [_vp, _vp, _i32, ctypes.POINTER(ctypes.c_double)],
         "rt_set_fold": [_vp, _i32],
         "rt_set_tiles": [_vp, _i32, _i32],
+        "rt_ek_field": [_vp, _vp, _vp],
+        "rt_ek_anomaly": [_vp, _vp, _vp, _vp],
+        "rt_grad_ek_anomaly": [_vp, _vp, ctypes.c_double, _vp, _vp, _vp, _vp, _vp],
         "rt_get_fold": [_vp, ctypes.POINTER(_i32)],
         "rt_axpy": [_vp, _vp, _vp, _vp, _vp],
         "rt_check_error": [_vp],
@@ -104,7 +107,7 @@ EXPORTED = ["rt_create", "rt_destroy", "rt_set_stream", "rt_workspace_bytes", "r
             "rt_grad_u0", "rt_pool_bytes", "rt_project_to_constraint", "rt_dot", "rt_axpy", "rt_check_error",
             "rt_last_error", "rt_set_tile", "rt_get_tiles", "rt_autotune", "rt_max_abs", "rt_set_graphs",
             "rt_set_overlap", "rt_kernel_times", "rt_set_fold", "rt_get_fold",
-            "rt_set_tiles"]
+            "rt_set_tiles", "rt_ek_field", "rt_ek_anomaly", "rt_grad_ek_anomaly"]
 
 
 def _check(rc: int, call: str):
@@ -317,6 +320,15 @@ class Context:
         self._sync_stream()
         policy = policy or Policy()
         uv0 = self.as_dev(uv0).reshape(self.shape_uv)
+        pool, pol = self._pool(policy, pool)
+        R = self._f64((self.cfg.batch,))
+        g = self._f64(self.shape_uv)
+        n = torch.empty((self.cfg.batch,), dtype=torch.int32, device=self.device)
+        _check(load().rt_grad_u0(self._h, _ptr(uv0), float(T), ctypes.byref(pol), _ptr(R), _ptr(g), _ptr(n)),
+               "rt_grad_u0")
+        return R, g, n
+
+    def _pool(self, policy, pool):
         if pool is None:
             nbytes = policy.pool_bytes or self.pool_bytes(policy.kind, policy.interval, self.max_steps)
             pool = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
@@ -326,13 +338,45 @@ class Context:
         nbytes = pool.numel() * pool.element_size() - off
         if nbytes <= 0:
             raise ValueError("checkpoint pool too small")
-        pol = RtCkptPolicy(policy.kind, policy.interval, ctypes.c_void_p(pool.data_ptr() + off), nbytes)
-        R = self._f64((self.cfg.batch,))
+        return pool, RtCkptPolicy(policy.kind, policy.interval, ctypes.c_void_p(pool.data_ptr() + off), nbytes)
+
+    def ek_field(self, U) -> torch.Tensor:
+        """Kinetic-energy density e_k = |m|^2/(2 rho) of every cell, [B][ny][nx] (Eq. 7)."""
+        self._sync_stream()
+        U = self.as_dev(U)
+        ek = self._f64((self.cfg.batch, self.cfg.ny, self.cfg.nx))
+        _check(load().rt_ek_field(self._h, _ptr(U), _ptr(ek)), "rt_ek_field")
+        return ek
+
+    def baseline_ek(self, T: float) -> torch.Tensor:
+        """e_k field of the unperturbed run at time T: the reference of Eq. 8."""
+        U0 = self.init_state(torch.zeros(self.shape_uv, dtype=torch.float64, device=self.device))
+        UT, _, _, _ = self.integrate(U0, T)
+        return self.ek_field(UT)
+
+    def ek_anomaly(self, U, ek_base) -> torch.Tensor:
+        """J[B] of Eq. 8 for the state U against the baseline field."""
+        self._sync_stream()
+        U = self.as_dev(U)
+        ekb = self.as_dev(ek_base).expand(self.cfg.batch, self.cfg.ny, self.cfg.nx).contiguous()
+        J = self._f64((self.cfg.batch,))
+        _check(load().rt_ek_anomaly(self._h, _ptr(U), _ptr(ekb), _ptr(J)), "rt_ek_anomaly")
+        return J
+
+    def grad_ek_anomaly(self, uv0, T: float, ek_base, policy: Policy | None = None,
+                        pool: torch.Tensor | None = None):
+        """(J[B], grad[B][2][ny][nx], nsteps[B]) of Eq. 8 on the device."""
+        self._sync_stream()
+        policy = policy or Policy()
+        uv0 = self.as_dev(uv0).reshape(self.shape_uv)
+        ekb = self.as_dev(ek_base).expand(self.cfg.batch, self.cfg.ny, self.cfg.nx).contiguous()
+        pool, pol = self._pool(policy, pool)
+        J = self._f64((self.cfg.batch,))
         g = self._f64(self.shape_uv)
         n = torch.empty((self.cfg.batch,), dtype=torch.int32, device=self.device)
-        _check(load().rt_grad_u0(self._h, _ptr(uv0), float(T), ctypes.byref(pol), _ptr(R), _ptr(g), _ptr(n)),
-               "rt_grad_u0")
-        return R, g, n
+        _check(load().rt_grad_ek_anomaly(self._h, _ptr(uv0), float(T), ctypes.byref(pol), _ptr(ekb), _ptr(J),
+                                         _ptr(g), _ptr(n)), "rt_grad_ek_anomaly")
+        return J, g, n
 
     def project_to_constraint(self, uv, delta: float, norm: int = NORM_L2, kind: int = SET_SPHERE):
         """In-place on a copy: returns (projected uv, norm before scaling)."""

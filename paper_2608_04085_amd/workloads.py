@@ -8,6 +8,8 @@
     grad_1024x2048        forward + adjoint, T = 3, binomial checkpointing <= 64 GB; top-5 horizontal
                           mode energy of the sphere-projected gradient; adjoint/forward time ratio
     fd_64x128             finite-difference gradient (one-sided, n_dof + 1 batched forwards) vs the adjoint
+    paper_cnop_128        the paper's own search on its physics: J of Eq. 8 over C <= 1e-6, projected L-BFGS
+                          (m = 10) against the memory-free driver (SPG) at equal gradient budget
 
 All inputs are seeded synthetic fields (see inputs.py); the paper uses no dataset.
 Run: python -m paper_2608_04085_amd.workloads <name> [--iters K] [--T T]
@@ -23,8 +25,8 @@ import time
 import numpy as np
 import torch
 
-from . import cnop, inputs
-from .config import CKPT_REVOLVE, CKPT_UNIFORM, NORM_L2, SET_SPHERE, RTConfig
+from . import cnop, inputs, optim
+from .config import CKPT_REVOLVE, CKPT_UNIFORM, NORM_L2, NORM_RHO_KE, SET_SPHERE, RTConfig, paper_preset
 from .rtcnop import Context, Policy
 
 
@@ -156,7 +158,40 @@ def fd_64x128(T: float = 2.0, batch: int = 64) -> dict:
             "adjoint_speedup": t_fd / t_adj}
 
 
-WORKLOADS = {f.__name__: f for f in (fwd_64x128, ensemble_64x128x256, grad_1024x2048, cnop_8x512x1024, fd_64x128)}
+def paper_cnop_128(T: float = 2.0, iters: int = 20, restarts: int = 4) -> dict:
+    """The paper's own search (Sec. 3; run T2_N128 of its run table): J of
+    Eq. 8 over C <= 1e-6 (Eq. 9, ball projection of Eq. 11), u_y-only seeds
+    localised at the interface (width 0.1 L), paper physics on 128 x 128,
+    projected L-BFGS with m = 10 against the same driver without memory (the
+    spectral projected gradient method) at equal gradient budget; restarts
+    are batch members.  UNIFORM(32) checkpoints."""
+    cfg = paper_preset(128, batch=restarts)
+    rt = Context(cfg, max_steps=16384)
+    uv = inputs.paper_seed_batch(cfg, range(restarts))
+    rt.autotune(rt.init_state(uv), reps=10)
+    pol = Policy(CKPT_UNIFORM, 32)
+    out = {"workload": "paper_cnop_128", "T": T, "eps": 1e-6, "restarts": restarts, "iters": iters,
+           "tiles": rt.tile}
+    for name, mem in (("lbfgs_m10", 10), ("spg_m0", 0)):
+        t0 = time.perf_counter()
+
+        def progress(k, f, lg, name=name, t0=t0):
+            print(f"{name} iter {k + 1}/{iters} {time.perf_counter() - t0:.1f}s max J {float(np.max(f)):.4g}",
+                  file=sys.stderr, flush=True)
+
+        ekb = rt.baseline_ek(T)
+        u0, _ = rt.project_to_constraint(rt.as_dev(uv), 1e-6, NORM_RHO_KE, SET_SPHERE)
+        be = cnop.LibraryBackend(rt, T, ekb, 1e-6, pol)
+        (u, J, g, log), el = _timed(lambda: optim.lbfgs_max(be, u0, iters, memory=mem, on_iter=progress))
+        out[name] = {"seconds": el, "iters_per_s": iters / el, "gradient_evals": log.grads,
+                     "forward_evals": log.evals, "J_first": log.f[0], "J_final": [float(x) for x in J],
+                     "J_history_max": [float(np.max(x)) for x in log.f], "chi_final": log.chi[-1],
+                     "resets": int(np.sum(log.resets))}
+    return out
+
+
+WORKLOADS = {f.__name__: f for f in (fwd_64x128, ensemble_64x128x256, grad_1024x2048, cnop_8x512x1024, fd_64x128,
+                                     paper_cnop_128)}
 
 
 def main():

@@ -12,7 +12,7 @@ import torch
 from oracle.rto import Oracle
 from paper_2608_04085_amd import inputs
 from paper_2608_04085_amd.config import (CKPT_REVOLVE, CKPT_STORE_ALL, CKPT_UNIFORM, NORM_L2, NORM_RHO_KE,
-                                         NORM_RMS, SET_BALL, SET_SPHERE, RTConfig)
+                                         NORM_RMS, SET_BALL, SET_SPHERE, RTConfig, paper_preset)
 
 pytestmark = pytest.mark.gpu
 
@@ -366,3 +366,68 @@ def test_spg_search_keeps_the_constraint_and_ascends():
     assert np.all(np.diff(np.minimum.accumulate(Rs, axis=0), axis=0) >= -1e-15)
     assert np.all(Rs[-1] >= Rs[0]), Rs
     assert np.all(np.isfinite(np.array(log.chi)))
+
+
+# ------------------------------------------------------------ objective of Eq. 8
+def test_ek_field_matches_oracle():
+    cfg = RTConfig(nx=40, ny=24, batch=2)
+    o = Oracle.from_config(cfg)
+    U = o.integrate(o.init_state(inputs.seed_batch(cfg, [0, 1], rms=1e-2)), 0.05)[0]
+    r = rt().Context(cfg, max_steps=64)
+    np.testing.assert_array_equal(host(r.ek_field(torch.from_numpy(U))), o.ek_field(U))
+
+
+@pytest.mark.parametrize("cfg,T", [(paper_preset(32), 0.2), (RTConfig(nx=24, ny=30, batch=2), 0.08)],
+                         ids=["paper32", "24x30x2"])
+def test_ek_anomaly_gradient_matches_oracle_and_policies_agree_bitwise(cfg, T):
+    o = Oracle.from_config(cfg)
+    uv = inputs.seed_batch(cfg, range(cfg.batch), rms=1e-2)
+    r = rt().Context(cfg, max_steps=1024)
+    # the two baselines agree to round-off; parity of J is taken against the
+    # oracle's baseline on both sides
+    ekb = o.baseline_ek(T)
+    ekb_gpu = host(r.baseline_ek(T))
+    assert np.max(np.abs(ekb_gpu - ekb)) <= 1e-8 * max(np.max(np.abs(ekb)), 1e-300) + 1e-30
+    Jo, go, no, _ = o.grad_ek_anomaly(uv, T, ekb)
+    results = []
+    for pol in [rt().Policy(CKPT_STORE_ALL, 1), rt().Policy(CKPT_UNIFORM, 7),
+                rt().Policy(CKPT_REVOLVE, 1, pool_bytes=3 * 8 * 4 * cfg.cells * cfg.batch)]:
+        J, g, n = r.grad_ek_anomaly(uv, T, torch.from_numpy(ekb), pol)
+        results.append((host(J), host(g), host(n)))
+    J, g, n = results[0]
+    np.testing.assert_array_equal(n, no)
+    np.testing.assert_allclose(J, Jo, rtol=1e-9)
+    assert normwise(g, go) <= 1e-9
+    for Jk, gk, _ in results[1:]:
+        np.testing.assert_array_equal(gk, g)
+        np.testing.assert_array_equal(Jk, J)
+    # value-only call on the final state agrees with the gradient call
+    UT = r.integrate(r.init_state(uv), T)[0]
+    np.testing.assert_array_equal(host(r.ek_anomaly(UT, torch.from_numpy(ekb))), J)
+
+
+def test_ek_anomaly_is_zero_at_the_gpu_baseline():
+    cfg = paper_preset(32)
+    r = rt().Context(cfg, max_steps=1024)
+    T = 0.2
+    ekb = r.baseline_ek(T)
+    J, g, n = r.grad_ek_anomaly(torch.zeros(r.shape_uv, dtype=torch.float64), T, ekb)
+    assert host(J)[0] == 0.0 and host(n)[0] > 0
+    assert not torch.any(g != 0)
+
+
+def test_paper_search_improves_J_and_stays_feasible():
+    # projected L-BFGS on J of Eq. 8 over C <= eps (Eq. 9, ball of Eq. 11),
+    # u_y-only seeds: J rises, every iterate is feasible, u_x stays zero
+    from paper_2608_04085_amd import cnop
+    cfg = paper_preset(32, batch=2)
+    r = rt().Context(cfg, max_steps=2048)
+    eps = 1e-6
+    uv = inputs.paper_seed_batch(cfg, [0, 1])
+    u, J, g, log, ekb = cnop.paper_cnop(r, uv, 0.5, eps, iters=4)
+    J0 = np.array(log.f[0])
+    assert np.all(J >= J0) and np.all(np.array(log.f[-1]) > 0)
+    _, C = r.project_to_constraint(u, eps, NORM_RHO_KE, SET_BALL)
+    assert np.all(host(C) <= eps * (1 + 1e-12))
+    assert not torch.any(u[:, 0] != 0)
+    assert log.grads == 5

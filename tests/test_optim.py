@@ -1,0 +1,170 @@
+"""The projected L-BFGS driver on problems with known answers (CPU).
+
+The driver runs on numpy fields through the same backend interface the HIP
+library implements.  What the method computes (Sec. 3.4 with the projection
+of Eq. 11, which rescales along the ray from the origin):
+
+* with the maximiser inside the constraint set it is a plain L-BFGS ascent
+  and must find the maximiser, faster than the gradient method it reduces to
+  without memory;
+* on the sphere of an unweighted norm the maximiser of x^T A x is the top
+  eigenvector of A, scaled onto the sphere;
+* with a weighted constraint energy the fixed points of the projected
+  iteration are the boundary points where the gradient is parallel to x
+  (chi of Appendix A = 0), i.e. eigenvectors of A for x^T A x; the search
+  can also stop where no projected step ascends.
+"""
+import numpy as np
+import pytest
+
+from paper_2608_04085_amd import optim
+
+
+class QuadBall:
+    """B independent problems x^T A_b x on sum w x^2 / 2 <= eps (x of shape [B][n])."""
+
+    def __init__(self, A, w, eps):
+        self.A, self.w, self.eps = A, w, eps
+
+    def dot(self, a, b):
+        return np.einsum("bi,bi->b", a, b)
+
+    def axpy(self, x, alpha, y):
+        return x + np.asarray(alpha, dtype=float).reshape(-1, 1) * y
+
+    def project(self, x):
+        C = 0.5 * np.einsum("i,bi->b", self.w, x * x)
+        s = np.where(C > self.eps, np.sqrt(self.eps / np.maximum(C, 1e-300)), 1.0)
+        return x * s[:, None]
+
+    def max_abs(self, x):
+        return np.max(np.abs(x), axis=1)
+
+    def where(self, mask, a, b):
+        return np.where(np.asarray(mask)[:, None], a, b)
+
+    def value(self, x):
+        return np.einsum("bi,bij,bj->b", x, self.A, x)
+
+    def value_and_grad(self, x):
+        return self.value(x), 2.0 * np.einsum("bij,bj->bi", self.A, x)
+
+
+class Interior(QuadBall):
+    """-(x - c)^T A (x - c) with A positive definite and c inside the ball."""
+
+    def __init__(self, A, c, eps):
+        super().__init__(A, np.ones(A.shape[1]), eps)
+        self.c = c
+
+    def value(self, x):
+        d = x - self.c
+        return -np.einsum("bi,bij,bj->b", d, self.A, d)
+
+    def value_and_grad(self, x):
+        return self.value(x), -2.0 * np.einsum("bij,bj->bi", self.A, x - self.c)
+
+
+def _symmetric(B, n, seed):
+    rng = np.random.default_rng(seed)
+    M = rng.standard_normal((B, n, n))
+    return 0.5 * (M + M.transpose(0, 2, 1)) + 2.0 * np.eye(n)
+
+
+def test_interior_maximiser_found_and_memory_pays():
+    rng = np.random.default_rng(4)
+    B, n = 2, 40
+    M = rng.standard_normal((B, n, n))
+    A = np.einsum("bij,bkj->bik", M, M) / n + np.diag(np.logspace(-2, 1, n))[None]
+    c = 0.1 * rng.standard_normal((B, n))
+
+    def run(memory):
+        hits = []
+        x, f, _, _ = optim.lbfgs_max(Interior(A, c, 100.0), np.zeros((B, n)), iters=400, memory=memory,
+                                     on_iter=lambda k, f, lg: hits.append(k) if np.all(f >= -1e-20) else None)
+        return x, (hits[0] if hits else 10**9)
+
+    x10, k10 = run(10)
+    x0, k0 = run(0)
+    assert np.max(np.abs(x10 - c)) <= 1e-12
+    assert k10 < k0 and k10 <= 150, (k10, k0)
+
+
+@pytest.mark.parametrize("n,seed", [(12, 0), (40, 1)])
+def test_unweighted_sphere_gives_the_top_eigenvector(n, seed):
+    B, eps, w = 3, 1e-6, 1.7
+    A = _symmetric(B, n, seed)
+    be = QuadBall(A, np.full(n, w), eps)
+    x0 = be.project(np.random.default_rng(seed + 10).standard_normal((B, n)) * 1e3)
+    x, f, _, log = optim.lbfgs_max(be, x0, iters=800)
+    for b in range(B):
+        lam, V = np.linalg.eigh(A[b])
+        fmax = lam[-1] * 2.0 * eps / w
+        assert abs(f[b] - fmax) <= 1e-6 * fmax, (b, f[b] / fmax)
+        v = V[:, -1] * np.sqrt(2.0 * eps / w)
+        err = min(np.max(np.abs(x[b] - v)), np.max(np.abs(x[b] + v))) / np.max(np.abs(v))
+        assert err <= 1e-3, (b, err)
+    assert np.all(np.array(log.chi[-1]) <= 1e-6 * np.max(np.abs(x), axis=1))
+
+
+def test_weighted_ball_stays_feasible_and_improves():
+    # With a weighted energy the projection of Eq. 11 (scaling along the
+    # ray) is not the orthogonal one: a gradient step followed by it need
+    # not ascend on the boundary, so the search may stop short of the
+    # constrained maximiser.  What holds: every iterate is feasible and on
+    # the boundary, the objective ends above its start, and a member that
+    # reaches chi = 0 sits at a point where the gradient is parallel to x
+    # (an eigenvector of A).
+    B, n, eps = 3, 12, 1e-6
+    A = _symmetric(B, n, 0)
+    w = 1.0 + np.random.default_rng(1).random(n)
+    be = QuadBall(A, w, eps)
+    x0 = be.project(np.random.default_rng(10).standard_normal((B, n)) * 1e3)
+    f0 = be.value(x0)
+    x, f, _, log = optim.lbfgs_max(be, x0, iters=400)
+    assert np.all(f >= 1.2 * f0)
+    chi = np.array(log.chi[-1])
+    for b in range(B):
+        assert abs(0.5 * np.sum(w * x[b] ** 2) - eps) <= 1e-12 * eps
+        if chi[b] <= 1e-12 * np.max(np.abs(x[b])):
+            ray = A[b] @ x[b] - (x[b] @ A[b] @ x[b]) / (x[b] @ x[b]) * x[b]
+            assert np.max(np.abs(ray)) <= 1e-8 * np.max(np.abs(A[b] @ x[b])), b
+    assert np.any(chi <= 1e-12 * np.max(np.abs(x), axis=1))
+
+
+def test_members_are_independent():
+    B, n, eps = 2, 16, 2.0
+    A = _symmetric(B, n, 7)
+    w = np.ones(n)
+    x0 = QuadBall(A, w, eps).project(np.random.default_rng(3).standard_normal((B, n)) * 5)
+    xb, fb, _, _ = optim.lbfgs_max(QuadBall(A, w, eps), x0, iters=25)
+    for b in range(B):
+        xs, fs, _, _ = optim.lbfgs_max(QuadBall(A[b:b + 1], w, eps), x0[b:b + 1], iters=25)
+        np.testing.assert_allclose(xs[0], xb[b], rtol=1e-10, atol=1e-14)
+        np.testing.assert_allclose(fs[0], fb[b], rtol=1e-10)
+
+
+class Scripted(QuadBall):
+    """Objective values from a script: value_and_grad returns the value of
+    the accepted point, value() the trial values in order."""
+
+    def __init__(self, trials, accepted):
+        super().__init__(np.eye(2)[None], np.ones(2), 10.0)
+        self.trials, self.accepted = iter(trials), iter(accepted)
+
+    def value(self, x):
+        return np.array([next(self.trials)])
+
+    def value_and_grad(self, x):
+        return np.array([next(self.accepted)]), np.array([[1e-3, 0.0]])
+
+
+@pytest.mark.parametrize("M,expect_backtrack", [(5, False), (1, True)])
+def test_nonmonotone_acceptance(M, expect_backtrack):
+    # iterate values 4 -> 5, then a trial at 4.5: below the current value
+    # but above the minimum 4 of the last M = 5 values (accepted at once);
+    # the monotone test (M = 1) backtracks
+    be = Scripted(trials=[5.0, 4.5, 6.0, 6.0], accepted=[4.0, 5.0, 4.5, 6.0])
+    _, _, _, log = optim.lbfgs_max(be, np.array([[0.1, 0.0]]), iters=2, nonmonotone=M, c_armijo=0.0)
+    assert log.backtracks[0][0] == 0
+    assert (log.backtracks[1][0] > 0) == expect_backtrack

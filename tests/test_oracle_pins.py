@@ -405,6 +405,98 @@ def test_gradient_v_only_mask_zeroes_u():
     assert np.all(g[0, 0] == 0) and np.any(g[0, 1] != 0)
 
 
+# ------------------------------------------------------------ objective of Eq. 8
+def test_ek_field_is_half_rho_speed_squared():
+    # Eq. 7 from primitive fields built independently of the conserved state
+    cfg = RTConfig(nx=8, ny=16)
+    o = Oracle.from_config(cfg)
+    rng = np.random.default_rng(11)
+    rho = 1.0 + rng.random((cfg.ny, cfg.nx))
+    u, v = rng.standard_normal((2, cfg.ny, cfg.nx))
+    U = _state(cfg, rho, u, v, 1.0 + rng.random((cfg.ny, cfg.nx)))
+    np.testing.assert_allclose(o.ek_field(U)[0], 0.5 * rho * (u * u + v * v), rtol=1e-14)
+
+
+def test_ek_anomaly_vanishes_at_the_baseline_with_zero_gradient():
+    # the unperturbed run reproduces the baseline field: J = 0, and J is
+    # quadratic in the anomaly, so its gradient there is exactly zero
+    cfg = paper_preset(16, batch=1).with_(nx=8, ny=16)
+    o = Oracle.from_config(cfg)
+    T = 0.2
+    ekb = o.baseline_ek(T)
+    J, g, n, _ = o.grad_ek_anomaly(np.zeros(o.shape_uv), T, ekb)
+    assert J[0] == 0.0 and n[0] > 0
+    assert np.all(g == 0.0)
+
+
+def test_ek_anomaly_one_tiny_step_approaches_closed_form():
+    # After one step of length tau -> 0, U(tau) -> U(0), so J -> sum over
+    # cells of (rho0 |u0|^2 / 2 - e_k,base)^2 dV with e_k,base -> 0; the
+    # difference is O(tau).
+    cfg = RTConfig(nx=8, ny=16)
+    o = Oracle.from_config(cfg)
+    uv = inputs.seed_batch(cfg, [2], rms=1e-1)
+    rho0 = o.background()[0][:, None]
+    closed = np.sum((0.5 * rho0 * (uv[0, 0] ** 2 + uv[0, 1] ** 2)) ** 2) * cfg.dx * cfg.dy
+    errs = []
+    for tau in (1e-6, 1e-8):
+        J, _, n, _ = o.grad_ek_anomaly(uv, tau, o.baseline_ek(tau))
+        assert n[0] == 1
+        errs.append(abs(J[0] - closed) / closed)
+    assert errs[1] <= 1e-6 and errs[1] < errs[0]
+
+
+@pytest.mark.parametrize("nx,ny,T", [(8, 16, 0.3), (16, 16, 0.15)])
+def test_ek_anomaly_gradient_matches_central_differences(nx, ny, T):
+    cfg = paper_preset(16).with_(nx=nx, ny=ny)
+    o = Oracle.from_config(cfg)
+    uv = inputs.seed_batch(cfg, [0], rms=1e-2)
+    assert np.all(uv[0, 0] == 0)  # u_y-only perturbation of the paper
+    ekb = o.baseline_ek(T)
+    J, g, n, log = o.grad_ek_anomaly(uv, T, ekb, cap=4096)
+    assert np.all(g[0, 0] == 0)
+    delta = np.sqrt(np.sum(uv * uv) * cfg.dx * cfg.dy)
+    for s in range(1000, 1004):
+        d = inputs.direction_batch(cfg, [s], delta)
+        an = np.sum(g * d)
+        errs = []
+        for h in (1e-5, 1e-6):
+            fp = o.ek_anomaly_frozen(uv + h * d, log, n, ekb)[0]
+            fm = o.ek_anomaly_frozen(uv - h * d, log, n, ekb)[0]
+            errs.append(abs((fp - fm) / (2 * h) - an) / abs(an))
+        assert min(errs) <= 1e-6, (s, errs)
+    assert o.ek_anomaly_frozen(uv, log, n, ekb)[0] == J[0]
+
+
+def test_ek_anomaly_terminal_adjoint_closed_form():
+    # one clipped step: dJ/dU^N = 2 (e_k - e_k,base) (-|m|^2/(2 rho^2), m_x/rho,
+    # m_y/rho, 0) dV, then the step adjoint and the initial chain
+    # rho0 (lam_m + u0 lam_E)
+    cfg = RTConfig(nx=8, ny=16)
+    o = Oracle.from_config(cfg)
+    uv = inputs.seed_batch(cfg, [4], rms=1e-2)
+    U0 = o.init_state(uv)
+    T = 0.5 * o.cfl_dt(U0)[0]
+    rng = np.random.default_rng(3)
+    ekb = 1e-6 * rng.random((1, cfg.ny, cfg.nx))
+    J, g, n, _ = o.grad_ek_anomaly(uv, T, ekb, cap=8)
+    assert n[0] == 1
+    U1 = o.step(U0, T)
+    dV = cfg.dx * cfg.dy
+    r, mx, my = U1[0, 0], U1[0, 1], U1[0, 2]
+    ek = 0.5 * (mx * mx + my * my) / r
+    np.testing.assert_allclose(J[0], np.sum((ek - ekb[0]) ** 2) * dV, rtol=1e-12)
+    w = 2 * (ek - ekb[0]) * dV
+    lamN = np.stack([-w * (mx * mx + my * my) / (2 * r * r), w * mx / r, w * my / r, 0 * r])[None]
+    lam0 = o.step_vjp(U0, T, lamN)
+    rho0 = U0[0, 0]
+    gu = rho0 * (lam0[0, 1] + uv[0, 0] * lam0[0, 3])
+    gv = rho0 * (lam0[0, 2] + uv[0, 1] * lam0[0, 3])
+    scale = np.max(np.abs(g))
+    assert np.max(np.abs(gu - g[0, 0])) <= 1e-12 * scale
+    assert np.max(np.abs(gv - g[0, 1])) <= 1e-12 * scale
+
+
 # ------------------------------------------------------------ projection
 def test_projection_sphere_ball_and_energy_norm():
     cfg = RTConfig(nx=16, ny=32, batch=2)

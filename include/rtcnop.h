@@ -224,9 +224,10 @@ int rt_autotune(rt_ctx* ctx, const double* U, int32_t reps, int32_t* step_tile, 
  * (on = 1), or the two kernels of rt_step_adjoint per step (on = 0); results
  * are identical.  rt_autotune folds when the folded step is more than 10%
  * faster than the two-kernel step on their own (the folded kernel shares
- * the CUs less well with the concurrent re-computation); before it, small
- * grids (fewer than 2^20 cells in all) fold.  Binomial checkpointing always
- * runs two kernels per step. */
+ * the CUs less well with the concurrent re-computation); before it, grids
+ * of fewer than 2^16 cells in all fold (and use 8x8 single-pass tiles),
+ * larger ones use 32x8 tiles and two kernels.  Binomial checkpointing
+ * always runs two kernels per step. */
 int rt_set_fold(rt_ctx* ctx, int32_t on);
 int rt_get_fold(const rt_ctx* ctx, int32_t* on);
 /* Measurement hook: per-launch times in microseconds of the selected

@@ -297,13 +297,16 @@ int rt_create(const rt_grid* grid, const rt_phys* phys, void* stream, rt_ctx** o
   P.h = phys->h;
   P.p_int = phys->p_int;
   c->stream = reinterpret_cast<hipStream_t>(stream);
-  // Small grids fill the chip with one round of blocks, so the single-pass
-  // 576-thread tiles (shorter critical path) win; large grids are throughput
-  // bound and prefer 256-thread tiles.  rt_autotune measures instead.
-  const bool small = (size_t)P.nx * P.ny * P.nb < ((size_t)1 << 20);
-  c->tile = small ? rtk::TILE_16x16W : rtk::TILE_32x8;
-  c->tile_adj = small ? rtk::TILE_16x16W : rtk::TILE_32x8;
-  c->fold = small;
+  // Defaults from measurements on MI355X.  Tiny grids (one partial round of
+  // blocks) are bound by one block's critical path: single-pass 8x8 tiles
+  // and the folded adjoint (one kernel per step) win.  From 2^16 cells on,
+  // 32x8 tiles of 256 threads and the two-kernel adjoint win, in the
+  // two-stream reverse sweep too, where their LDS footprints let the
+  // re-computation share the CUs.  rt_autotune measures instead.
+  const bool tiny = (size_t)P.nx * P.ny * P.nb < ((size_t)1 << 16);
+  c->tile = tiny ? rtk::TILE_8x8W : rtk::TILE_32x8;
+  c->tile_adj = tiny ? rtk::TILE_8x8W : rtk::TILE_32x8;
+  c->fold = tiny;
   const size_t n = c->cells();
   c->red_blocks = (int)std::min<size_t>(256, std::max<size_t>(1, n / 2048));
   *out = c;

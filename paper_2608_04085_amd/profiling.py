@@ -1,6 +1,7 @@
 """Counter runs of the hot-path kernels and their summaries.
 
     python -m paper_2608_04085_amd.profiling drive NX NY B K STEP_TILE ADJ_TILE
+        (STEP_TILE "auto": the autotuner's choice, as bench.py makes it.)
         The library's kernel-timing hook (K launches each of the step at a
         given dt, the march step, the folded adjoint step and the two-kernel
         adjoint step on one grid), then K copies of a 2 GiB buffer: a plain
@@ -14,6 +15,10 @@
         hash of the kernel sources (bench.py reports the traffic only while the
         kernels are unchanged).  The command lines go in via the environment
         variable RT_PROFILE_COMMAND.
+    python -m paper_2608_04085_amd.profiling stats TITLE TRACE OUT_MD
+        Kernel times of a --kernel-trace run as Markdown, per kernel and grid.
+    python -m paper_2608_04085_amd.profiling counters TITLE DIR... OUT_MD
+        Per-dispatch averages of the counters of --pmc runs, per kernel class.
 
 FETCH_SIZE and WRITE_SIZE are scaled by what they read for the plain copy
 (bytes moved / counted bytes).  On gfx950 the derived FETCH_SIZE counts a
@@ -55,9 +60,14 @@ def drive(nx: int, ny: int, B: int, K: int, step_tile: str, adj_tile: str):
 
     cfg = RTConfig(nx=nx, ny=ny, batch=B)
     rt = Context(cfg, max_steps=64)
-    rt.set_tiles(step_tile, adj_tile)
     U = rt.init_state(inputs.seed_batch(cfg, range(B), rms=1e-3))
+    if step_tile == "auto":
+        rt.autotune(U, reps=20)
+    else:
+        rt.set_tiles(step_tile, adj_tile)
     times = rt.kernel_times(U, reps=K)
+    with open(os.path.join(ROOT, "gpurun_out", f"drive_tiles_{nx}x{ny}x{B}.json"), "w") as f:
+        json.dump({"tiles": rt.tile, "fold": rt.fold, "times_us": times}, f)
     n = COPY_BYTES // 8
     a = torch.empty(n, dtype=torch.float64, device="cuda").fill_(1.0)
     flush = torch.empty(n, dtype=torch.float64, device="cuda").fill_(2.0)  # evicts a from the last-level cache
@@ -80,11 +90,13 @@ def _rows(d: str, name: str):
 def _classify(rows):
     """Category of each dispatch, in dispatch order: steps after the march
     set-up kernel are march steps; an adjoint kernel A followed by kernel B
-    is the two-kernel form, otherwise the folded one."""
+    is the two-kernel form, otherwise the folded one; copies after the last
+    library kernel are the calibration copies."""
     disp = {}
     for r in rows:
         disp.setdefault(int(r["Dispatch_Id"]), r["Kernel_Name"])
     order = sorted(disp)
+    last_lib = max([d for d in order if "rtk::" in disp[d]], default=-1)
     cat = {}
     march = False
     for i, d in enumerate(order):
@@ -98,18 +110,22 @@ def _classify(rows):
             cat[d] = "adj_a" if "k_adj_b" in nxt else "adj_a_folded"
         elif "k_adj_b" in n:
             cat[d] = "adj_b"
-        elif "copyBuffer" in n:
-            cat[d] = "copy"
+        elif "copyBuffer" in n and d > last_lib:
+            cat[d] = "copy"  # the calibration copies come after every library kernel
     return cat
 
 
-def summarize(workload: str, trace: str, fetch: str, write: str, req: str | None, out_md: str, command: str = ""):
+def summarize(workload: str, trace: str, fetch: str, write: str, req: str | None, out_md: str, command: str = "",
+              tiles: str = ""):
     trows = _rows(trace, "*kernel_trace.csv")
     tcat = _classify(trows)
     dur: dict = {}
     meta: dict = {}
+    tbig = max((int(r["Grid_Size_X"]) for r in trows if tcat.get(int(r["Dispatch_Id"])) == "copy"), default=0)
     for r in trows:
         c = tcat.get(int(r["Dispatch_Id"]))
+        if c == "copy" and int(r["Grid_Size_X"]) < tbig:
+            continue
         if c:
             dur.setdefault(c, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3)
             meta[c] = (r["Kernel_Name"], r["LDS_Block_Size"], r["VGPR_Count"], r["Workgroup_Size_X"])
@@ -119,8 +135,12 @@ def summarize(workload: str, trace: str, fetch: str, write: str, req: str | None
             continue
         crows = _rows(d, "*counter_collection.csv")
         ccat = _classify(crows)
+        # calibration copies: the largest copy dispatches only
+        big = max((int(r["Grid_Size"]) for r in crows if ccat.get(int(r["Dispatch_Id"])) == "copy"), default=0)
         for r in crows:
             c = ccat.get(int(r["Dispatch_Id"]))
+            if c == "copy" and int(r["Grid_Size"]) < big:
+                continue
             if c:
                 counters.setdefault(c, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
     avg = {k: {c: sum(v) / len(v) for c, v in d.items()} for k, d in counters.items()}
@@ -177,16 +197,17 @@ def summarize(workload: str, trace: str, fetch: str, write: str, req: str | None
     if os.path.exists(TRAFFIC_JSON):
         with open(TRAFFIC_JSON) as f:
             data = json.load(f)
-    data[workload] = {"source_hash": kernel_source_hash(), "kernels": entry, "fetch_scale": f_scale,
+    data[workload] = {"source_hash": kernel_source_hash(), "tiles": tiles, "kernels": entry, "fetch_scale": f_scale,
                       "write_scale": w_scale, "kernel_names": {k: v[0] for k, v in meta.items()}}
     with open(TRAFFIC_JSON, "w") as f:
         json.dump(data, f, indent=1)
     print("\n".join(lines))
 
 
-def traffic_for(workload: str, kernel: str) -> float | None:
+def traffic_for(workload: str, kernel: str, tiles: str | None = None) -> float | None:
     """Per-launch HBM bytes of `kernel` from the committed counters, or None
-    if there are none or the kernel sources changed since they were taken."""
+    if there are none, the kernel sources changed since they were taken, or
+    they were taken with other tile variants than `tiles`."""
     try:
         with open(TRAFFIC_JSON) as f:
             d = json.load(f)[workload]
@@ -194,8 +215,65 @@ def traffic_for(workload: str, kernel: str) -> float | None:
         return None
     if d.get("source_hash") != kernel_source_hash():
         return None
+    if tiles is not None and d.get("tiles") and d["tiles"] != tiles:
+        return None
     k = d.get("kernels", {}).get(kernel)
     return None if k is None else float(k["bytes_per_launch"])
+
+
+def stats_md(title: str, trace: str, out_md: str, command: str = "", top: int = 14):
+    """Kernel statistics of a --kernel-trace run as Markdown, one row per
+    kernel and launch grid (so that launches over different batch sizes are
+    not averaged together)."""
+    rows = _rows(trace, "*kernel_trace.csv")
+    groups: dict = {}
+    total = 0.0
+    for r in rows:
+        key = (r["Kernel_Name"], f"{r['Grid_Size_X']}x{r['Grid_Size_Y']}x{r['Grid_Size_Z']}", r["Workgroup_Size_X"])
+        d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3
+        groups.setdefault(key, []).append(d)
+        total += d
+    order = sorted(groups, key=lambda k: -sum(groups[k]))
+    lines = [f"# Kernel time: {title}", "", "Command (repository root):", "", "```"]
+    lines += command.strip().split("\n") if command else []
+    lines += ["```", "", "One row per kernel and launch grid (threads: grid size in threads x, y, z).", "",
+              "| kernel | grid (threads) | block | calls | total ms | avg us | min us | max us | share % |",
+              "|---|---|---|---|---|---|---|---|---|"]
+    for k in order[:top]:
+        v = groups[k]
+        name = k[0].replace("rtk::(anonymous namespace)::", "").split("(")[0]
+        lines.append(f"| `{name[:60]}` | {k[1]} | {k[2]} | {len(v)} | {sum(v) * 1e-3:.3f} | {sum(v) / len(v):.3f} | "
+                     f"{min(v):.3f} | {max(v):.3f} | {100 * sum(v) / total:.2f} |")
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def counters_md(title: str, dirs: list, out_md: str, command: str = ""):
+    """Per-dispatch averages of every collected counter, per kernel class."""
+    per: dict = {}
+    for d in dirs:
+        rows = _rows(d, "*counter_collection.csv")
+        cat = _classify(rows)
+        for r in rows:
+            c = cat.get(int(r["Dispatch_Id"]))
+            if c and c != "copy":
+                per.setdefault(c, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    names = sorted({n for v in per.values() for n in v})
+    lines = [f"# Counters: {title}", "", "Commands (repository root):", "", "```"]
+    lines += command.strip().split("\n") if command else []
+    lines += ["```", "", "Per-dispatch averages.", "", "| counter | " + " | ".join(k for k in CATEGORIES if k in per) + " |",
+              "|---|" + "---|" * len([k for k in CATEGORIES if k in per])]
+    for n in names:
+        vals = []
+        for k in CATEGORIES:
+            if k in per:
+                v = per[k].get(n)
+                vals.append("" if not v else f"{sum(v) / len(v):.4g}")
+        lines.append(f"| {n} | " + " | ".join(vals) + " |")
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
 
 
 if __name__ == "__main__":
@@ -204,6 +282,11 @@ if __name__ == "__main__":
         drive(nx, ny, B, K, sys.argv[6], sys.argv[7])
     elif sys.argv[1] == "summarize":
         cmd = os.environ.get("RT_PROFILE_COMMAND", "")
-        summarize(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], sys.argv[6] or None, sys.argv[7], cmd)
+        tiles = sys.argv[8] if len(sys.argv) > 8 else ""
+        summarize(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], sys.argv[6] or None, sys.argv[7], cmd, tiles)
+    elif sys.argv[1] == "stats":
+        stats_md(sys.argv[2], sys.argv[3], sys.argv[4], os.environ.get("RT_PROFILE_COMMAND", ""))
+    elif sys.argv[1] == "counters":
+        counters_md(sys.argv[2], sys.argv[3:-1], sys.argv[-1], os.environ.get("RT_PROFILE_COMMAND", ""))
     else:
         raise SystemExit(__doc__)

@@ -89,6 +89,30 @@ __device__ __forceinline__ double p0_at(const Params& P, double y) {
   return P.p_int + P.g_y * (0.5 * (P.rho_h + P.rho_l) * (y - P.y0) + 0.5 * (P.rho_h - P.rho_l) * P.h * lc);
 }
 
+// ----------------------------------------------------------------- tile of a workgroup
+// Workgroups are dispatched round-robin over the 8 XCDs of the chip (linear
+// id mod 8), and each XCD has its own L2.  With tiles in raster order,
+// horizontally adjacent tiles would sit on different XCDs and each L2 would
+// fetch the halo cache lines they share.  Instead, the workgroups of XCD k
+// take the k-th contiguous band of tiles (in raster order within the band):
+// horizontal neighbours share an L2, and vertical neighbours follow one
+// tile row later in the same L2.  A bijection of [0, T) for any T.
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ int xcd_band(int L, int T) {
+  const int per = (T + kXcds - 1) / kXcds;  // items of each of the first `tall` XCDs
+  const int tall = T - (per - 1) * kXcds;   // 1..8 XCDs with `per` items, the rest per - 1
+  const int xcd = L % kXcds, local = L / kXcds;
+  return xcd < tall ? xcd * per + local : tall * per + (xcd - tall) * (per - 1) + local;
+}
+
+__device__ __forceinline__ void tile_of_block(int& bx, int& by) {
+  const int nbx = (int)gridDim.x;
+  const int t = xcd_band((int)blockIdx.x + nbx * (int)blockIdx.y, nbx * (int)gridDim.y);
+  bx = t % nbx;
+  by = t / nbx;
+}
+
 // ----------------------------------------------------------------- LDS tile helpers
 // Phase A: primitives of the tile + halo 2.  Returns nonzero on an
 // unphysical interior state.
@@ -216,7 +240,9 @@ __global__ __launch_bounds__(NT) void k_step(Params P, StepArgs a) {
   __shared__ double sRed[NT / 64];
 
   const int b = blockIdx.z;
-  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+  int tbx, tby;
+  tile_of_block(tbx, tby);
+  const int x0 = tbx * TX, y0 = tby * TY;
   const int tid = threadIdx.x;
   const int nx = P.nx, ny = P.ny;
   const size_t N = (size_t)nx * ny;
@@ -571,7 +597,9 @@ __global__ __launch_bounds__(NT) void k_adj_a(Params P, AdjArgs a) {
   __shared__ AdjLDS<TX, TY, FOLD> S;
 
   const int b = blockIdx.z;
-  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+  int tbx, tby;
+  tile_of_block(tbx, tby);
+  const int x0 = tbx * TX, y0 = tby * TY;
   const int tid = threadIdx.x;
   const int nx = P.nx, ny = P.ny;
   const size_t N = (size_t)nx * ny;
@@ -766,7 +794,8 @@ __global__ __launch_bounds__(NT) void k_adj_a(Params P, AdjArgs a) {
 __global__ __launch_bounds__(256) void k_adj_b(Params P, AdjArgs a) {
   const int nx = P.nx;
   const size_t N = (size_t)nx * P.ny;
-  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // rows in XCD bands, so that the rows above and below are in the same L2
+  const size_t idx = (size_t)xcd_band((int)blockIdx.x, (int)gridDim.x) * blockDim.x + threadIdx.x;
   const int b = blockIdx.y;
   if (idx >= N) return;
   GatherSrc g;

@@ -267,10 +267,12 @@ __global__ __launch_bounds__(NT) void k_step(Params P, StepArgs a) {
     t_in = cin->t;
     T_in = cin->T;
     nstep = cin->nsteps;
-    // one slot per lane; the max across the wave is taken after phase A
+    // a few slots per lane; the max across the wave is taken after phase A
     const uint64_t* row = a.acc + ((size_t)(L % 3) * P.nb + b) * kAccRow;
     const int lane = tid & 63;
-    ms_lane = lane < kAccSlots ? __longlong_as_double((long long)row[lane * kAccStride]) : 0.0;
+#pragma unroll
+    for (int k = lane; k < kAccSlots; k += 64)
+      ms_lane = fmax(ms_lane, __longlong_as_double((long long)row[k * kAccStride]));
   } else {
     if (a.nsteps_limit && a.dt_index >= a.nsteps_limit[b]) return;
     dt = a.dt[(size_t)b * a.dt_stride + a.dt_index];
@@ -439,21 +441,21 @@ __global__ __launch_bounds__(NT) void k_step(Params P, StepArgs a) {
   // epilogue: fold the block's largest signal speed of U^{n+1} into the
   // member's accumulator (non-negative doubles order like their bits)
   const double bm = block_max<NT>(smax, sRed);
-  if (tid != 0) return;
   if (a.ctl == nullptr) {
-    atomicMax((unsigned long long*)(a.acc_out + b), (unsigned long long)__double_as_longlong(bm));
+    if (tid == 0) atomicMax((unsigned long long*)(a.acc_out + b), (unsigned long long)__double_as_longlong(bm));
     return;
   }
   const int L = a.launch;
+  if (first_block) {
+    // clear the slots of launch L + 1's target, one per thread
+    uint64_t* clr = a.acc + ((size_t)((L + 2) % 3) * P.nb + b) * kAccRow;
+    for (int k = tid; k < kAccSlots; k += NT) clr[k * kAccStride] = 0ull;
+  }
+  if (tid != 0) return;
   const int slot = (int)((blockIdx.x + (size_t)gridDim.x * blockIdx.y) % kAccSlots);
   atomicMax((unsigned long long*)(a.acc + ((size_t)((L + 1) % 3) * P.nb + b) * kAccRow + slot * kAccStride),
             (unsigned long long)__double_as_longlong(bm));
   if (!first_block) return;
-  {
-    uint64_t* clr = a.acc + ((size_t)((L + 2) % 3) * P.nb + b) * kAccRow;
-#pragma unroll 4
-    for (int k = 0; k < kAccSlots; ++k) clr[k * kAccStride] = 0ull;
-  }
   if (a.dt_log) {
     if (nstep < a.dt_log_cap) a.dt_log[(size_t)b * a.dt_log_cap + nstep] = dt;
     else atomicOr(&a.flags->err_overflow, 1);

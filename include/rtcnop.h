@@ -94,8 +94,8 @@ enum { RT_NORM_L2 = 0, RT_NORM_RMS = 1, RT_NORM_RHO_KE = 2 };
 enum { RT_SET_SPHERE = 0, RT_SET_BALL = 1 };
 
 /* Create a context for one grid / physics / stream.  Validates the numbers
- * (nx >= 3, ny >= 2, batch >= 1, positive lengths, gamma > 1, h > 0,
- * cfl > 0).  No device work. */
+ * (nx >= 3, ny >= 2, nx * ny < 2^28, batch >= 1, positive lengths,
+ * gamma > 1, h > 0, cfl > 0).  No device work. */
 int rt_create(const rt_grid* grid, const rt_phys* phys, void* stream, rt_ctx** out);
 int rt_destroy(rt_ctx* ctx);
 int rt_set_stream(rt_ctx* ctx, void* stream);

@@ -271,7 +271,8 @@ const char* rt_last_error(void) { return g_err.c_str(); }
 int rt_create(const rt_grid* grid, const rt_phys* phys, void* stream, rt_ctx** out) {
   if (!grid || !phys || !out) return fail(RT_EINVAL, "null argument");
   if (grid->nx < 3 || grid->ny < 2 || grid->batch < 1) return fail(RT_EINVAL, "grid must be at least 3 x 2 with batch >= 1");
-  if ((size_t)grid->nx * grid->ny > (size_t)1 << 30) return fail(RT_EINVAL, "grid too large");
+  // the kernels address a plane of a state with 32-bit byte offsets
+  if ((size_t)grid->nx * grid->ny >= (size_t)1 << 28) return fail(RT_EINVAL, "grid too large (nx * ny >= 2^28)");
   if (!(grid->lx > 0) || !(grid->ly > 0)) return fail(RT_EINVAL, "domain lengths must be positive");
   if (!(phys->gamma > 1.0) || !(phys->h > 0) || !(phys->cfl > 0) || !(phys->rho_h > 0) || !(phys->rho_l > 0))
     return fail(RT_EINVAL, "need gamma > 1, h > 0, cfl > 0, positive densities");

@@ -28,12 +28,33 @@ namespace rtk {
 
 namespace {
 
-// Periodic column index (the tile halo reaches at most TX + 2 columns past
-// the domain, so a few conditional adds replace an integer division).
+// Periodic column index.  The tile halos reach at most TX + 2 columns past
+// the domain, so for every grid wider than that one conditional add or
+// subtract does; narrower grids take the loop.
 __device__ __forceinline__ int wrapx(int i, int nx) {
-  while (i < 0) i += nx;
-  while (i >= nx) i -= nx;
+  i = i < 0 ? i + nx : (i >= nx ? i - nx : i);
+  if ((unsigned)i >= (unsigned)nx) {
+    while (i < 0) i += nx;
+    while (i >= nx) i -= nx;
+  }
   return i;
+}
+
+// Element i of an array of doubles (or int32) addressed as a uniform base
+// plus a 32-bit byte offset, which maps onto the scalar-base / 32-bit
+// vector-offset form of the global memory instructions.  Every plane of a
+// state holds fewer than 2^28 cells (checked when a context is created).
+__device__ __forceinline__ double ldg(const double* base, uint32_t i) {
+  return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(base) + i * 8u);
+}
+__device__ __forceinline__ void stg(double* base, uint32_t i, double v) {
+  *reinterpret_cast<double*>(reinterpret_cast<char*>(base) + i * 8u) = v;
+}
+__device__ __forceinline__ int32_t ldg(const int32_t* base, uint32_t i) {
+  return *reinterpret_cast<const int32_t*>(reinterpret_cast<const char*>(base) + i * 4u);
+}
+__device__ __forceinline__ void stg(int32_t* base, uint32_t i, int32_t v) {
+  *reinterpret_cast<int32_t*>(reinterpret_cast<char*>(base) + i * 4u) = v;
 }
 
 __device__ __forceinline__ double wave_max(double v) {
@@ -130,8 +151,8 @@ __device__ int tile_prims(const Params& P, const double* U, size_t N, int x0, in
     W4 w{1.0, 0.0, 0.0, 1.0, 1.0};
     if (gy >= -1 && gy <= P.ny) {
       const int sy = gy < 0 ? 0 : (gy >= P.ny ? P.ny - 1 : gy);
-      const size_t c = (size_t)sy * P.nx + gx;
-      w = cons_to_prim(P, U[c], U[N + c], U[2 * N + c], U[3 * N + c]);
+      const uint32_t c = (uint32_t)(sy * P.nx + gx);
+      w = cons_to_prim(P, ldg(U, c), ldg(U + N, c), ldg(U + 2 * N, c), ldg(U + 3 * N, c));
       if (gy >= 0 && gy < P.ny) bad |= unphysical(w);
       if (gy < 0) w = ghost_bottom(P, w);
       else if (gy >= P.ny) w = ghost_top(P, w);
@@ -187,7 +208,7 @@ __device__ int tile_predict(const Params& P, double dt, int x0, int y0, LDS& S, 
     bad |= !(q.r - hr > 0.0) || !(q.p - hp > 0.0) || !(q.r - vr > 0.0) || !(q.p - vp > 0.0);
     if (codes_out && lx >= 1 && lx <= TX && ly >= 1 && ly <= TY) {
       const int gx = x0 - 1 + lx;
-      if (gx < P.nx) codes_out[(size_t)gy * P.nx + gx] = cx | (cy << 8);
+      if (gx < P.nx) stg(codes_out, (uint32_t)(gy * P.nx + gx), cx | (cy << 8));
     }
   }
   return bad;
@@ -282,13 +303,13 @@ __global__ __launch_bounds__(NT) void k_step(Params P, StepArgs a) {
   const int tx = tid % TX, ty = tid / TX;
   const int gx = x0 + tx, gy = y0 + ty;
   const bool own = tid < TX * TY && gx < nx && gy < ny;
-  const size_t c = own ? (size_t)gy * nx + gx : 0;
+  const uint32_t c = own ? (uint32_t)(gy * nx + gx) : 0u;
   double u0 = 0.0, u1 = 0.0, u2 = 0.0, u3 = 0.0;
   if (own) {
-    u0 = U[c];
-    u1 = U[N + c];
-    u2 = U[2 * N + c];
-    u3 = U[3 * N + c];
+    u0 = ldg(U, c);
+    u1 = ldg(U + N, c);
+    u2 = ldg(U + 2 * N, c);
+    u3 = ldg(U + 3 * N, c);
   }
 
   // phase A: primitives of the tile + halo 2
@@ -410,18 +431,18 @@ __global__ __launch_bounds__(NT) void k_step(Params P, StepArgs a) {
     n2 = n2 + dtg * 0.5 * (u0 + n0);
     n3 = n3 + dtg * 0.5 * (S.fg.G[0][ty][tx] + S.fg.G[0][ty + 1][tx]);
     double* Un = a.Un + (size_t)b * 4 * N;
-    Un[c] = n0;
-    Un[N + c] = n1;
-    Un[2 * N + c] = n2;
-    Un[3 * N + c] = n3;
+    stg(Un, c, n0);
+    stg(Un + N, c, n1);
+    stg(Un + 2 * N, c, n2);
+    stg(Un + 3 * N, c, n3);
     if (a.pool && (nstep % a.snap_interval) == 0) {
       const int slot = nstep / a.snap_interval;
       if (slot < a.snap_slots) {
         double* sp = a.pool + ((size_t)slot * P.nb + b) * 4 * N;
-        sp[c] = u0;
-        sp[N + c] = u1;
-        sp[2 * N + c] = u2;
-        sp[3 * N + c] = u3;
+        stg(sp, c, u0);
+        stg(sp + N, c, u1);
+        stg(sp + 2 * N, c, u2);
+        stg(sp + 3 * N, c, u3);
       } else {
         bad |= 2;  // overflow, reported below
       }
@@ -498,44 +519,44 @@ struct GatherSrc {
 __device__ __forceinline__ void lambda_at(const Params& P, const GatherSrc& g, int i, int j, double out[4]) {
   const int nx = P.nx, ny = P.ny;
   const size_t N = (size_t)nx * ny;
-  const size_t idx = (size_t)j * nx + i;
+  const uint32_t idx = (uint32_t)(j * nx + i);
   const double* Lm = g.lam_next;
   if (g.pass) {
-    out[0] = Lm[idx];
-    out[1] = Lm[N + idx];
-    out[2] = Lm[2 * N + idx];
-    out[3] = Lm[3 * N + idx];
+    out[0] = ldg(Lm, idx);
+    out[1] = ldg(Lm + N, idx);
+    out[2] = ldg(Lm + 2 * N, idx);
+    out[3] = ldg(Lm + 3 * N, idx);
     return;
   }
   const double* Z = g.Z;
   const int32_t* codes = g.codes;
   const double* U = g.U;
-  double wb[4] = {Z[idx], Z[N + idx], Z[2 * N + idx], Z[3 * N + idx]};
+  double wb[4] = {ldg(Z, idx), ldg(Z + N, idx), ldg(Z + 2 * N, idx), ldg(Z + 3 * N, idx)};
   // x slopes at d = c-1, c, c+1
   {
-    const size_t cm = (size_t)j * nx + (i == 0 ? nx - 1 : i - 1);
-    const size_t cp = (size_t)j * nx + (i == nx - 1 ? 0 : i + 1);
-    double sm[4] = {Z[4 * N + cm], Z[5 * N + cm], Z[6 * N + cm], Z[7 * N + cm]};
-    double s0[4] = {Z[4 * N + idx], Z[5 * N + idx], Z[6 * N + idx], Z[7 * N + idx]};
-    double sp[4] = {Z[4 * N + cp], Z[5 * N + cp], Z[6 * N + cp], Z[7 * N + cp]};
-    add_slope_terms(sm, codes[cm] & 0xff, 0.0, 1.0, wb);    // c is d+1: +wb
-    add_slope_terms(s0, codes[idx] & 0xff, 1.0, -1.0, wb);  // c is d: wa - wb
-    add_slope_terms(sp, codes[cp] & 0xff, -1.0, 0.0, wb);   // c is d-1: -wa
+    const uint32_t cm = (uint32_t)(j * nx + (i == 0 ? nx - 1 : i - 1));
+    const uint32_t cp = (uint32_t)(j * nx + (i == nx - 1 ? 0 : i + 1));
+    double sm[4] = {ldg(Z + 4 * N, cm), ldg(Z + 5 * N, cm), ldg(Z + 6 * N, cm), ldg(Z + 7 * N, cm)};
+    double s0[4] = {ldg(Z + 4 * N, idx), ldg(Z + 5 * N, idx), ldg(Z + 6 * N, idx), ldg(Z + 7 * N, idx)};
+    double sp[4] = {ldg(Z + 4 * N, cp), ldg(Z + 5 * N, cp), ldg(Z + 6 * N, cp), ldg(Z + 7 * N, cp)};
+    add_slope_terms(sm, ldg(codes, cm) & 0xff, 0.0, 1.0, wb);    // c is d+1: +wb
+    add_slope_terms(s0, ldg(codes, idx) & 0xff, 1.0, -1.0, wb);  // c is d: wa - wb
+    add_slope_terms(sp, ldg(codes, cp) & 0xff, -1.0, 0.0, wb);   // c is d-1: -wa
   }
   // y slopes
   {
-    const int c0 = codes[idx] >> 8;
-    double s0[4] = {Z[8 * N + idx], Z[9 * N + idx], Z[10 * N + idx], Z[11 * N + idx]};
+    const int c0 = ldg(codes, idx) >> 8;
+    double s0[4] = {ldg(Z + 8 * N, idx), ldg(Z + 9 * N, idx), ldg(Z + 10 * N, idx), ldg(Z + 11 * N, idx)};
     add_slope_terms(s0, c0, 1.0, -1.0, wb);
     if (j > 0) {
-      const size_t cm = idx - nx;
-      double sm[4] = {Z[8 * N + cm], Z[9 * N + cm], Z[10 * N + cm], Z[11 * N + cm]};
-      add_slope_terms(sm, codes[cm] >> 8, 0.0, 1.0, wb);
+      const uint32_t cm = idx - (uint32_t)nx;
+      double sm[4] = {ldg(Z + 8 * N, cm), ldg(Z + 9 * N, cm), ldg(Z + 10 * N, cm), ldg(Z + 11 * N, cm)};
+      add_slope_terms(sm, ldg(codes, cm) >> 8, 0.0, 1.0, wb);
     }
     if (j < ny - 1) {
-      const size_t cp = idx + nx;
-      double sp[4] = {Z[8 * N + cp], Z[9 * N + cp], Z[10 * N + cp], Z[11 * N + cp]};
-      add_slope_terms(sp, codes[cp] >> 8, -1.0, 0.0, wb);
+      const uint32_t cp = idx + (uint32_t)nx;
+      double sp[4] = {ldg(Z + 8 * N, cp), ldg(Z + 9 * N, cp), ldg(Z + 10 * N, cp), ldg(Z + 11 * N, cp)};
+      add_slope_terms(sp, ldg(codes, cp) >> 8, -1.0, 0.0, wb);
     }
     // the wall ghost cell is a function of this cell
     if (j == 0 || j == ny - 1) {
@@ -550,10 +571,10 @@ __device__ __forceinline__ void lambda_at(const Params& P, const GatherSrc& g, i
       wb[3] += gb[3];
     }
   }
-  const W4 w = cons_to_prim(P, U[idx], U[N + idx], U[2 * N + idx], U[3 * N + idx]);
+  const W4 w = cons_to_prim(P, ldg(U, idx), ldg(U + N, idx), ldg(U + 2 * N, idx), ldg(U + 3 * N, idx));
   double ub[4];
   prim_adj(P, w, W4{wb[0], wb[1], wb[2], wb[3]}, ub);
-  const double l0 = Lm[idx], l1 = Lm[N + idx], l2 = Lm[2 * N + idx], l3 = Lm[3 * N + idx];
+  const double l0 = ldg(Lm, idx), l1 = ldg(Lm + N, idx), l2 = ldg(Lm + 2 * N, idx), l3 = ldg(Lm + 3 * N, idx);
   out[0] = ub[0] + l0 + g.dt * P.g_y * l2;
   out[1] = ub[1] + l1;
   out[2] = ub[2] + l2;
@@ -611,13 +632,13 @@ __global__ __launch_bounds__(NT) void k_adj_a(Params P, AdjArgs a) {
     if (FOLD && tid < TX * TY) {
       const int gx = x0 + tid % TX, gy = y0 + tid / TX;
       if (gx < nx && gy < ny) {
-        const size_t c = (size_t)gy * nx + gx;
+        const uint32_t c = (uint32_t)(gy * nx + gx);
         const double* Ln = a.fold.lam_next + (size_t)b * 4 * N;
         double* Lo = a.fold.lam_out + (size_t)b * 4 * N;
-        Lo[c] = Ln[c];
-        Lo[N + c] = Ln[N + c];
-        Lo[2 * N + c] = Ln[2 * N + c];
-        Lo[3 * N + c] = Ln[3 * N + c];
+        stg(Lo, c, ldg(Ln, c));
+        stg(Lo + N, c, ldg(Ln + N, c));
+        stg(Lo + 2 * N, c, ldg(Ln + 2 * N, c));
+        stg(Lo + 3 * N, c, ldg(Ln + 3 * N, c));
       }
     }
     return;
@@ -629,13 +650,13 @@ __global__ __launch_bounds__(NT) void k_adj_a(Params P, AdjArgs a) {
   const int tx = tid % TX, ty = tid / TX;
   const int gx = x0 + tx, gy = y0 + ty;
   const bool own = tid < TX * TY && gx < nx && gy < ny;
-  const size_t c = own ? (size_t)gy * nx + gx : 0;
+  const uint32_t c = own ? (uint32_t)(gy * nx + gx) : 0u;
   double u0 = 1.0, u1 = 0.0, u2 = 0.0, u3 = 1.0;
   if (own) {
-    u0 = U[c];
-    u1 = U[N + c];
-    u2 = U[2 * N + c];
-    u3 = U[3 * N + c];
+    u0 = ldg(U, c);
+    u1 = ldg(U + N, c);
+    u2 = ldg(U + 2 * N, c);
+    u3 = ldg(U + 3 * N, c);
   }
 
   int bad = tile_prims<TX, TY, NT>(P, U, N, x0, y0, S);
@@ -659,11 +680,11 @@ __global__ __launch_bounds__(NT) void k_adj_a(Params P, AdjArgs a) {
         const int ux = x0 - 1 + lx, qx = wrapx(ux, nx);
         lambda_at(P, g, qx, qy, l);
         if (lx >= 1 && lx <= TX && ly >= 1 && ly <= TY && ux < nx) {
-          const size_t cc = (size_t)qy * nx + qx;
-          lam_out[cc] = l[0];
-          lam_out[N + cc] = l[1];
-          lam_out[2 * N + cc] = l[2];
-          lam_out[3 * N + cc] = l[3];
+          const uint32_t cc = (uint32_t)(qy * nx + qx);
+          stg(lam_out, cc, l[0]);
+          stg(lam_out + N, cc, l[1]);
+          stg(lam_out + 2 * N, cc, l[2]);
+          stg(lam_out + 3 * N, cc, l[3]);
         }
       }
       S.L[0][ly][lx] = l[0] + hdtg * l[2];
@@ -685,12 +706,12 @@ __global__ __launch_bounds__(NT) void k_adj_a(Params P, AdjArgs a) {
       l[2] = S.L[2][ly][lx];
       l[3] = S.L[3][ly][lx];
     } else {
-      const size_t cc = (size_t)(y0 - 1 + ly) * nx + wrapx(x0 - 1 + lx, nx);
-      const double l2 = Lm[2 * N + cc];
-      l[0] = Lm[cc] + hdtg * l2;
-      l[1] = Lm[N + cc];
+      const uint32_t cc = (uint32_t)((y0 - 1 + ly) * nx + wrapx(x0 - 1 + lx, nx));
+      const double l2 = ldg(Lm + 2 * N, cc);
+      l[0] = ldg(Lm, cc) + hdtg * l2;
+      l[1] = ldg(Lm + N, cc);
       l[2] = l2;
-      l[3] = Lm[3 * N + cc];
+      l[3] = ldg(Lm + 3 * N, cc);
     }
   };
 
@@ -776,18 +797,18 @@ __global__ __launch_bounds__(NT) void k_adj_a(Params P, AdjArgs a) {
     const W4 sx = ldQ(S, 1, lx, ly), sy = ldQ(S, 2, lx, ly);
     predict_adj(P, w, sx, sy, 0.5 * dt * P.inv_dx, 0.5 * dt * P.inv_dy, qb, wb, sxb, syb);
     double* Z = a.Z + (size_t)b * 12 * N;
-    Z[c] = wb.r;
-    Z[N + c] = wb.u;
-    Z[2 * N + c] = wb.v;
-    Z[3 * N + c] = wb.p;
-    Z[4 * N + c] = sxb.r;
-    Z[5 * N + c] = sxb.u;
-    Z[6 * N + c] = sxb.v;
-    Z[7 * N + c] = sxb.p;
-    Z[8 * N + c] = syb.r;
-    Z[9 * N + c] = syb.u;
-    Z[10 * N + c] = syb.v;
-    Z[11 * N + c] = syb.p;
+    stg(Z, c, wb.r);
+    stg(Z + N, c, wb.u);
+    stg(Z + 2 * N, c, wb.v);
+    stg(Z + 3 * N, c, wb.p);
+    stg(Z + 4 * N, c, sxb.r);
+    stg(Z + 5 * N, c, sxb.u);
+    stg(Z + 6 * N, c, sxb.v);
+    stg(Z + 7 * N, c, sxb.p);
+    stg(Z + 8 * N, c, syb.r);
+    stg(Z + 9 * N, c, syb.u);
+    stg(Z + 10 * N, c, syb.v);
+    stg(Z + 11 * N, c, syb.p);
   }
   if (bad) atomicOr(&a.flags->err_unphys, 1);
 }
@@ -797,7 +818,7 @@ __global__ __launch_bounds__(256) void k_adj_b(Params P, AdjArgs a) {
   const int nx = P.nx;
   const size_t N = (size_t)nx * P.ny;
   // rows in XCD bands, so that the rows above and below are in the same L2
-  const size_t idx = (size_t)xcd_band((int)blockIdx.x, (int)gridDim.x) * blockDim.x + threadIdx.x;
+  const uint32_t idx = (uint32_t)xcd_band((int)blockIdx.x, (int)gridDim.x) * blockDim.x + threadIdx.x;
   const int b = blockIdx.y;
   if (idx >= N) return;
   GatherSrc g;
@@ -810,10 +831,10 @@ __global__ __launch_bounds__(256) void k_adj_b(Params P, AdjArgs a) {
   double l[4];
   lambda_at(P, g, (int)(idx % nx), (int)(idx / nx), l);
   double* Lo = a.lam + (size_t)b * 4 * N;
-  Lo[idx] = l[0];
-  Lo[N + idx] = l[1];
-  Lo[2 * N + idx] = l[2];
-  Lo[3 * N + idx] = l[3];
+  stg(Lo, idx, l[0]);
+  stg(Lo + N, idx, l[1]);
+  stg(Lo + 2 * N, idx, l[2]);
+  stg(Lo + 3 * N, idx, l[3]);
 }
 
 // ----------------------------------------------------------------- small kernels

@@ -151,6 +151,11 @@ int rt_grad_u0(rt_ctx* ctx, const double* uv0, double T, const rt_ckpt_policy* p
  * U [B][4][ny][nx] -> ek [B][ny][nx] (device). */
 int rt_ek_field(rt_ctx* ctx, const double* U, double* ek);
 
+/* Mixing-layer width of Eqs. 13-14 for each member: h[B] = sum over rows
+ * of 4 f (1 - f) dy, f = clip((<rho>_x - rho_l) / (rho_h - rho_l), 0, 1),
+ * <rho>_x the mean density of the row (device arrays; U [B][4][ny][nx]). */
+int rt_mix_width(rt_ctx* ctx, const double* U, double* h);
+
 /* Objective of Eq. 8 on the grid: J[B] = sum over cells of
  * (e_k(U) - ek_base)^2 dx dy, with ek_base [B][ny][nx] the e_k field of the
  * unperturbed run at the same time (device arrays). */

@@ -15,6 +15,7 @@
 //                      the initial velocity field, by reverse-mode AD through
 //                      the whole discrete march with the time steps of the
 //                      forward run held fixed (Sec. 3.4)
+//   rto_mix_width      mixing-layer width of Eqs. 13-14
 //   rto_ek_field       kinetic-energy density field of Eq. 7
 //   rto_ek_anomaly_frozen  objective J of Eq. 8 after a march with given steps
 //   rto_grad_ek_anomaly    J and its exact gradient (same reverse sweep as
@@ -258,6 +259,30 @@ int rto_ke_ratio_frozen(const Problem* P, const double* uv0, const double* dt_lo
       U.swap(Un);
     }
     R[b] = rto::kinetic_energy<double>(Q, U.data()) / ke0;
+  }
+  return 0;
+}
+
+// Mixing-layer width (Eqs. 13-14): the integral over y of 4 f (1 - f),
+// f the horizontally averaged density normalised between rho_l and rho_h
+// and clipped to [0, 1]; midpoint rule over the rows.
+int rto_mix_width(const Problem* P, const double* U, double* h) {
+  if (!valid(P) || !U || !h) return kEInval;
+  const size_t N = cells(P);
+  const double dy = P->ly / P->ny;
+  for (int b = 0; b < P->nb; ++b) {
+    const double* r = U + 4 * N * b;
+    double s = 0.0;
+    for (int j = 0; j < P->ny; ++j) {
+      double mean = 0.0;
+      for (int i = 0; i < P->nx; ++i) mean += r[static_cast<size_t>(j) * P->nx + i];
+      mean /= P->nx;
+      double f = (mean - P->rho_l) / (P->rho_h - P->rho_l);
+      if (f < 0.0) f = 0.0;
+      if (f > 1.0) f = 1.0;
+      s += 4.0 * f * (1.0 - f) * dy;
+    }
+    h[b] = s;
   }
   return 0;
 }

@@ -63,6 +63,7 @@ def lib():
             "rto_ke_ratio_frozen": [P, _dp, _dp, _ip, ctypes.c_int32, _dp],
             "rto_project_to_constraint": [P, _dp, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, _dp],
             "rto_ek_field": [P, _dp, _dp],
+            "rto_mix_width": [P, _dp, _dp],
             "rto_ek_anomaly_frozen": [P, _dp, _dp, _ip, ctypes.c_int32, _dp, _dp],
             "rto_grad_ek_anomaly": [P, _dp, ctypes.c_double, _dp, _dp, _dp, _ip, _dp, ctypes.c_int32],
             "rto_hllc": [ctypes.c_double, _dp, _dp, _dp],
@@ -188,6 +189,13 @@ class Oracle:
                                        int(dt_log.shape[1]), _p(R))
         _check(rc, "ke_ratio_frozen")
         return R
+
+    def mix_width(self, U):
+        """Mixing-layer width of Eqs. 13-14 for each member."""
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        h = np.empty(self.prob.nb)
+        _check(lib().rto_mix_width(ctypes.byref(self.prob), _p(U), _p(h)), "mix_width")
+        return h
 
     def ek_field(self, U):
         """Kinetic-energy density e_k = |m|^2/(2 rho) of every cell, [nb][ny][nx] (Eq. 7)."""

@@ -179,3 +179,76 @@ def spectrum_top5(v_row: np.ndarray) -> float:
 def peak_row(v: np.ndarray) -> int:
     """Row whose rms along x is largest (lowest index on ties)."""
     return int(np.argmax(np.sqrt(np.mean(v * v, axis=1))))
+
+
+# ---------------------------------------------------------------------------
+# Forward comparison suite (Sec. 3.3 run design, Sec. 4.3-4.4 diagnostics)
+
+def dominant_modes(v: np.ndarray, k: int = 5) -> np.ndarray:
+    """Horizontal mode numbers n >= 1 of the k largest E_n (Eq. 12) at the
+    peak row of v ([ny][nx])."""
+    c = np.fft.rfft(v[peak_row(v)])
+    e = np.abs(c[1:]) ** 2
+    return 1 + np.argsort(-e, kind="stable")[:k]
+
+
+def five_mode_seed(v: np.ndarray, k: int = 5) -> np.ndarray:
+    """The 5modes perturbation: every row of v keeps only the k dominant
+    horizontal modes of the peak row, with their amplitudes and phases
+    (rfft bins n and, implicitly, -n); the rest of each row is dropped."""
+    modes = dominant_modes(v, k)
+    c = np.fft.rfft(v, axis=1)
+    keep = np.zeros(c.shape[1], dtype=bool)
+    keep[modes] = True
+    return np.fft.irfft(np.where(keep[None, :], c, 0.0), n=v.shape[1], axis=1)
+
+
+def power_reconstruction(v: np.ndarray, frac: float = 0.9) -> np.ndarray:
+    """The 2-D reconstruction of App. B: the fewest 2-D Fourier modes of v
+    that hold `frac` of its spectral energy (strongest first), inverse
+    transformed."""
+    F = np.fft.fft2(v)
+    e = np.abs(F) ** 2
+    order = np.argsort(-e, axis=None, kind="stable")
+    csum = np.cumsum(e.ravel()[order])
+    m = int(np.searchsorted(csum, frac * csum[-1]) + 1)
+    mask = np.zeros(e.size, dtype=bool)
+    mask[order[:m]] = True
+    return np.real(np.fft.ifft2(np.where(mask.reshape(e.shape), F, 0.0)))
+
+
+COMPARISON_KINDS = ("CNOP", "Random", "5modes", "2D90")
+
+
+def comparison_seeds(cfg, v_cnop: np.ndarray, random_seed: int = 1000) -> np.ndarray:
+    """[4][2][ny][nx] u_y-only perturbations of the comparison suite, unscaled:
+    the CNOP itself, a localised Gaussian field (the optimiser's initial-guess
+    construction), its 5-mode reduction and its 90%-power 2-D
+    reconstruction."""
+    from . import inputs
+
+    rnd = inputs.paper_seed_batch(cfg.with_(batch=1), [random_seed])[0, 1]
+    out = np.zeros((4, 2, cfg.ny, cfg.nx))
+    for k, v in enumerate((v_cnop, rnd, five_mode_seed(v_cnop), power_reconstruction(v_cnop))):
+        out[k, 1] = v
+    return out
+
+
+def comparison_runs(rt: Context, seeds, eps: float, T: float, n_snap: int) -> dict:
+    """March every member (one batched launch per step) from its seed scaled
+    to C = eps (Eq. 9) to T, with n_snap uniformly spaced diagnostics:
+    total kinetic energy and mixing-layer width (Eqs. 13-14).  Each interval
+    ends exactly on its snapshot time (its last CFL step clipped)."""
+    u, _ = rt.project_to_constraint(rt.as_dev(seeds), eps, NORM_RHO_KE, SET_SPHERE)
+    U = rt.init_state(u)
+    t = [0.0]
+    ke = [rt.kinetic_energy(U).cpu().numpy().tolist()]
+    hm = [rt.mix_width(U).cpu().numpy().tolist()]
+    steps = np.zeros(rt.cfg.batch, dtype=np.int64)
+    for k in range(1, n_snap + 1):
+        U, _, n, _ = rt.integrate(U, T / n_snap)
+        steps += n.cpu().numpy()
+        t.append(k * T / n_snap)
+        ke.append(rt.kinetic_energy(U).cpu().numpy().tolist())
+        hm.append(rt.mix_width(U).cpu().numpy().tolist())
+    return {"t": t, "ke": ke, "h_mix": hm, "steps": steps.tolist()}

@@ -57,6 +57,7 @@ struct rt_ctx {
   double *S0 = nullptr, *S1 = nullptr, *L0 = nullptr, *L1 = nullptr, *Z = nullptr, *Z2 = nullptr;
   int32_t *codes = nullptr, *codes2 = nullptr;
   double* partial = nullptr;
+  double* rowmean = nullptr;  // [B][ny] horizontal density means
   uint64_t* acc = nullptr;  // [3][B][kAccRow] signal-speed slots of the march, then [B] for rt_step
   Ctl* ctl = nullptr;       // [2][B] march control, double buffered
   long last_launch = 0;     // launches of the last march (final ctl in ctl[last_launch & 1])
@@ -94,7 +95,7 @@ struct rt_ctx {
 namespace {
 
 struct Layout {
-  size_t S0, S1, L0, L1, Z, Z2, codes, codes2, partial, acc, ctl, flags, dt_log, nsteps, scal, total;
+  size_t S0, S1, L0, L1, Z, Z2, codes, codes2, partial, rowmean, acc, ctl, flags, dt_log, nsteps, scal, total;
 };
 
 Layout layout(const rt_ctx* c, int32_t max_steps) {
@@ -117,6 +118,7 @@ Layout layout(const rt_ctx* c, int32_t max_steps) {
   L.codes = take(c->cells() * c->P.nb * sizeof(int32_t));
   L.codes2 = take(c->cells() * c->P.nb * sizeof(int32_t));
   L.partial = take((size_t)maxblk * c->P.nb * sizeof(double));
+  L.rowmean = take((size_t)c->P.ny * c->P.nb * sizeof(double));
   L.acc = take(((size_t)3 * rtk::kAccRow + 1) * c->P.nb * sizeof(uint64_t));
   L.ctl = take((size_t)2 * c->P.nb * sizeof(Ctl));
   L.flags = take(sizeof(Flags));
@@ -563,6 +565,7 @@ int rt_set_workspace(rt_ctx* c, void* dev, size_t bytes, int32_t max_steps) {
   c->codes = reinterpret_cast<int32_t*>(w + L.codes);
   c->codes2 = reinterpret_cast<int32_t*>(w + L.codes2);
   c->partial = reinterpret_cast<double*>(w + L.partial);
+  c->rowmean = reinterpret_cast<double*>(w + L.rowmean);
   c->acc = reinterpret_cast<uint64_t*>(w + L.acc);
   c->ctl = reinterpret_cast<Ctl*>(w + L.ctl);
   c->flags = reinterpret_cast<Flags*>(w + L.flags);
@@ -937,6 +940,13 @@ int rt_ek_field(rt_ctx* c, const double* U, double* ek) {
   if (int rc = need_ws(c)) return rc;
   if (!U || !ek) return fail(RT_EINVAL, "null argument");
   RT_HIP(rtk::launch_ek_field(c->P, U, ek, c->stream));
+  return 0;
+}
+
+int rt_mix_width(rt_ctx* c, const double* U, double* h) {
+  if (int rc = need_ws(c)) return rc;
+  if (!U || !h) return fail(RT_EINVAL, "null argument");
+  RT_HIP(rtk::launch_mix_width(c->P, U, c->rowmean, h, c->stream));
   return 0;
 }
 

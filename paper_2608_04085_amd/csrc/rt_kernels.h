@@ -138,6 +138,8 @@ hipError_t launch_terminal_adjoint_ek(const Params& P, const double* U, const do
 hipError_t launch_initial_adjoint_plain(const Params& P, const double* uv0, const double* lam0, double* grad,
                                        hipStream_t s);
 hipError_t launch_ek_field(const Params& P, const double* U, double* ek, hipStream_t s);
+// Mixing width of Eqs. 13-14 (rowmean: scratch [B][ny]).
+hipError_t launch_mix_width(const Params& P, const double* U, double* rowmean, double* h, hipStream_t s);
 hipError_t launch_scale_project(const Params& P, double* uv, const double* m, double delta, int norm,
                                 int set, hipStream_t s);
 hipError_t launch_axpy(const Params& P, const double* x, const double* alpha, const double* y, double* out,

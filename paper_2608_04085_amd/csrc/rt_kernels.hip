@@ -1053,6 +1053,35 @@ __global__ void k_initial_adjoint_plain(Params P, const double* uv0, const doubl
   g[N + idx] = (P.comp_mask & 2) ? r0 * (l[2 * N + idx] + v * l[3 * N + idx]) : 0.0;
 }
 
+// Mixing width (Eqs. 13-14), pass 1: the horizontal mean of the density of
+// every row, rowmean[B][ny]; one block per row, fixed summation order.
+__global__ __launch_bounds__(256) void k_row_mean(Params P, const double* U, double* rowmean) {
+  __shared__ double red[4];
+  const int j = blockIdx.x, b = blockIdx.y;
+  const size_t N = (size_t)P.nx * P.ny;
+  const double* r = U + (size_t)b * 4 * N + (size_t)j * P.nx;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < P.nx; i += 256) s += r[i];
+  s = block_sum<256>(s, red);
+  if (threadIdx.x == 0) rowmean[(size_t)b * P.ny + j] = s / P.nx;
+}
+
+// Pass 2: h_mix = sum over rows of 4 f (1 - f) dy with
+// f = clip((<rho>_x - rho_l)/(rho_h - rho_l), 0, 1); one block per member.
+__global__ __launch_bounds__(256) void k_mix_width(Params P, const double* rowmean, double* h) {
+  __shared__ double red[4];
+  const int b = blockIdx.x;
+  const double inv = 1.0 / (P.rho_h - P.rho_l);
+  double s = 0.0;
+  for (int j = threadIdx.x; j < P.ny; j += 256) {
+    double f = (rowmean[(size_t)b * P.ny + j] - P.rho_l) * inv;
+    f = f < 0.0 ? 0.0 : (f > 1.0 ? 1.0 : f);
+    s += 4.0 * f * (1.0 - f);
+  }
+  s = block_sum<256>(s, red);
+  if (threadIdx.x == 0) h[b] = s * P.dy;
+}
+
 // e_k = |m|^2 / (2 rho) of every cell, [B][ny][nx].
 __global__ void k_ek_field(Params P, const double* U, double* ek) {
   const size_t N = (size_t)P.nx * P.ny;
@@ -1276,6 +1305,14 @@ hipError_t launch_initial_adjoint_plain(const Params& P, const double* uv0, cons
                                        hipStream_t s) {
   hipLaunchKernelGGL(k_initial_adjoint_plain, cells_grid(P, (size_t)P.nx * P.ny), dim3(256), 0, s, P, uv0, lam0,
                      grad);
+  return hipGetLastError();
+}
+
+hipError_t launch_mix_width(const Params& P, const double* U, double* rowmean, double* h, hipStream_t s) {
+  hipLaunchKernelGGL(k_row_mean, dim3((unsigned)P.ny, (unsigned)P.nb), dim3(256), 0, s, P, U, rowmean);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_mix_width, dim3((unsigned)P.nb), dim3(256), 0, s, P, rowmean, h);
   return hipGetLastError();
 }
 

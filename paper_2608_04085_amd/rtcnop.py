@@ -85,6 +85,7 @@ def load():
         "rt_set_fold": [_vp, _i32],
         "rt_set_tiles": [_vp, _i32, _i32],
         "rt_ek_field": [_vp, _vp, _vp],
+        "rt_mix_width": [_vp, _vp, _vp],
         "rt_ek_anomaly": [_vp, _vp, _vp, _vp],
         "rt_grad_ek_anomaly": [_vp, _vp, ctypes.c_double, _vp, _vp, _vp, _vp, _vp],
         "rt_get_fold": [_vp, ctypes.POINTER(_i32)],
@@ -107,7 +108,8 @@ EXPORTED = ["rt_create", "rt_destroy", "rt_set_stream", "rt_workspace_bytes", "r
             "rt_grad_u0", "rt_pool_bytes", "rt_project_to_constraint", "rt_dot", "rt_axpy", "rt_check_error",
             "rt_last_error", "rt_set_tile", "rt_get_tiles", "rt_autotune", "rt_max_abs", "rt_set_graphs",
             "rt_set_overlap", "rt_kernel_times", "rt_set_fold", "rt_get_fold",
-            "rt_set_tiles", "rt_ek_field", "rt_ek_anomaly", "rt_grad_ek_anomaly"]
+            "rt_set_tiles", "rt_ek_field", "rt_ek_anomaly", "rt_grad_ek_anomaly",
+            "rt_mix_width"]
 
 
 def _check(rc: int, call: str):
@@ -347,6 +349,14 @@ class Context:
         ek = self._f64((self.cfg.batch, self.cfg.ny, self.cfg.nx))
         _check(load().rt_ek_field(self._h, _ptr(U), _ptr(ek)), "rt_ek_field")
         return ek
+
+    def mix_width(self, U) -> torch.Tensor:
+        """Mixing-layer width h_mix[B] of Eqs. 13-14."""
+        self._sync_stream()
+        U = self.as_dev(U)
+        h = self._f64((self.cfg.batch,))
+        _check(load().rt_mix_width(self._h, _ptr(U), _ptr(h)), "rt_mix_width")
+        return h
 
     def baseline_ek(self, T: float) -> torch.Tensor:
         """e_k field of the unperturbed run at time T: the reference of Eq. 8."""

@@ -10,6 +10,8 @@
     fd_64x128             finite-difference gradient (one-sided, n_dof + 1 batched forwards) vs the adjoint
     paper_cnop_128        the paper's own search on its physics: J of Eq. 8 over C <= 1e-6, projected L-BFGS
                           (m = 10) against the memory-free driver (SPG) at equal gradient budget
+    paper_compare_128     the paper's forward comparison suite: CNOP, Random, 5modes and 2-D 90% reconstructions
+                          marched together, KE(t) and mixing width h_mix(t)
 
 All inputs are seeded synthetic fields (see inputs.py); the paper uses no dataset.
 Run: python -m paper_2608_04085_amd.workloads <name> [--iters K] [--T T]
@@ -190,8 +192,38 @@ def paper_cnop_128(T: float = 2.0, iters: int = 20, restarts: int = 4) -> dict:
     return out
 
 
+def paper_compare_128(T: float = 2.0, iters: int = 20, n_snap: int = 20) -> dict:
+    """The forward comparison suite of the paper (run design of Sec. 3.3,
+    diagnostics of Sec. 4.3-4.4) on its physics at 128 x 128: a CNOP from
+    `iters` projected-gradient iterations on J (Eq. 8, C <= 1e-6), then the
+    CNOP, a localised random seed, the CNOP's 5-mode reduction and its
+    90%-power 2-D reconstruction, all at C = 1e-6, marched together to T
+    with n_snap uniformly spaced KE and mixing-width diagnostics."""
+    cfg = paper_preset(128, batch=1)
+    rt = Context(cfg, max_steps=16384)
+    uv = inputs.paper_seed_batch(cfg, [0])
+    pol = Policy(CKPT_UNIFORM, 32)
+    t0 = time.perf_counter()
+    ekb = rt.baseline_ek(T)
+    u0, _ = rt.project_to_constraint(rt.as_dev(uv), 1e-6, NORM_RHO_KE, SET_SPHERE)
+    be = cnop.LibraryBackend(rt, T, ekb, 1e-6, pol)
+    u, J, g, log = optim.lbfgs_max(be, u0, iters, memory=0)
+    t_search = time.perf_counter() - t0
+    seeds = cnop.comparison_seeds(cfg, u[0, 1].cpu().numpy())
+    rc = Context(cfg.with_(batch=4), max_steps=16384)
+    (res, el) = _timed(lambda: cnop.comparison_runs(rc, seeds, 1e-6, T, n_snap))
+    ke = np.array(res["ke"])
+    hm = np.array(res["h_mix"])
+    return {"workload": "paper_compare_128", "T": T, "search_iters": iters, "search_seconds": t_search,
+            "J_cnop": float(J[0]), "kinds": list(cnop.COMPARISON_KINDS),
+            "dominant_modes": cnop.dominant_modes(u[0, 1].cpu().numpy()).tolist(),
+            "ke_ratio_T": (ke[-1] / ke[0]).tolist(), "h_mix_0": hm[0].tolist(), "h_mix_T": hm[-1].tolist(),
+            "ke_series": res["ke"], "h_mix_series": res["h_mix"], "t": res["t"], "steps": res["steps"],
+            "suite_seconds": el}
+
+
 WORKLOADS = {f.__name__: f for f in (fwd_64x128, ensemble_64x128x256, grad_1024x2048, cnop_8x512x1024, fd_64x128,
-                                     paper_cnop_128)}
+                                     paper_cnop_128, paper_compare_128)}
 
 
 def main():

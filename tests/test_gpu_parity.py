@@ -454,6 +454,14 @@ def test_ek_anomaly_gradient_matches_oracle_and_policies_agree_bitwise(cfg, T):
     np.testing.assert_array_equal(host(r.ek_anomaly(UT, torch.from_numpy(ekb))), J)
 
 
+def test_mix_width_matches_oracle():
+    cfg = RTConfig(nx=48, ny=300, batch=2)
+    o = Oracle.from_config(cfg)
+    U = o.integrate(o.init_state(inputs.seed_batch(cfg, [0, 1], rms=5e-2)), 0.3)[0]
+    r = rt().Context(cfg, max_steps=64)
+    np.testing.assert_allclose(host(r.mix_width(torch.from_numpy(U))), o.mix_width(U), rtol=1e-13)
+
+
 def test_ek_anomaly_is_zero_at_the_gpu_baseline():
     cfg = paper_preset(32)
     r = rt().Context(cfg, max_steps=1024)
@@ -479,3 +487,21 @@ def test_paper_search_improves_J_and_stays_feasible():
     assert np.all(host(C) <= eps * (1 + 1e-12))
     assert not torch.any(u[:, 0] != 0)
     assert log.grads == 5
+
+
+def test_comparison_suite_runs_all_kinds_at_the_energy_budget():
+    from paper_2608_04085_amd import cnop
+    cfg = paper_preset(32, batch=1)
+    v = inputs.paper_seed_batch(cfg, [3])[0, 1]
+    seeds = cnop.comparison_seeds(cfg, v)
+    r = rt().Context(cfg.with_(batch=4), max_steps=2048)
+    res = cnop.comparison_runs(r, seeds, 1e-6, 0.3, 3)
+    assert len(res["t"]) == 4 and abs(res["t"][-1] - 0.3) < 1e-15
+    u, C = r.project_to_constraint(torch.from_numpy(seeds), 1e-6, NORM_RHO_KE, SET_SPHERE)
+    _, C2 = r.project_to_constraint(u, 1e-6, NORM_RHO_KE, SET_BALL)
+    np.testing.assert_allclose(host(C2), 1e-6, rtol=1e-12)
+    # the same member marched alone gives the same diagnostics (batch independence)
+    r1 = rt().Context(cfg, max_steps=2048)
+    res1 = cnop.comparison_runs(r1, seeds[:1], 1e-6, 0.3, 3)
+    np.testing.assert_array_equal(np.array(res1["ke"])[:, 0], np.array(res["ke"])[:, 0])
+    np.testing.assert_array_equal(np.array(res1["h_mix"])[:, 0], np.array(res["h_mix"])[:, 0])

@@ -168,3 +168,24 @@ def test_nonmonotone_acceptance(M, expect_backtrack):
     _, _, _, log = optim.lbfgs_max(be, np.array([[0.1, 0.0]]), iters=2, nonmonotone=M, c_armijo=0.0)
     assert log.backtracks[0][0] == 0
     assert (log.backtracks[1][0] > 0) == expect_backtrack
+
+
+# ------------------------------------------------------------ comparison seeds
+def test_five_mode_and_power_reconstructions():
+    from paper_2608_04085_amd import cnop
+    ny, nx = 24, 64
+    x = np.arange(nx) / nx
+    env = np.exp(-((np.arange(ny) - 11.5) / 4.0) ** 2)[:, None]
+    modes = {3: 1.0, 7: 0.8, 9: 0.6, 12: 0.5, 15: 0.4, 20: 0.05, 25: 0.02}
+    v = sum(a * np.cos(2 * np.pi * n * x + 0.3 * n) for n, a in modes.items()) * env
+    assert sorted(cnop.dominant_modes(v).tolist()) == [3, 7, 9, 12, 15]
+    v5 = cnop.five_mode_seed(v)
+    expect = sum(a * np.cos(2 * np.pi * n * x + 0.3 * n) for n, a in modes.items() if n <= 15) * env
+    np.testing.assert_allclose(v5, expect, atol=1e-12)
+    # the 2-D reconstruction keeps at least 90% of the energy (Parseval), and
+    # at 100% it drops only modes below the round-off of the energy sum
+    r = cnop.power_reconstruction(v, 0.9)
+    assert np.sum(r * r) >= 0.9 * np.sum(v * v) * (1 - 1e-12)
+    assert np.sum(r * r) < np.sum(v * v)
+    d = cnop.power_reconstruction(v, 1.0) - v
+    assert np.sum(d * d) <= 1e-14 * np.sum(v * v)

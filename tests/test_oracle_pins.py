@@ -497,6 +497,38 @@ def test_ek_anomaly_terminal_adjoint_closed_form():
     assert np.max(np.abs(gv - g[0, 1])) <= 1e-12 * scale
 
 
+# ------------------------------------------------------------ mixing width (Eqs. 13-14)
+def test_mix_width_special_profiles():
+    cfg = RTConfig(nx=6, ny=40)
+    o = Oracle.from_config(cfg)
+    one = np.ones((cfg.ny, cfg.nx))
+    mid = 0.5 * (cfg.rho_h + cfg.rho_l)
+    # fully mixed: f = 1/2 everywhere, 4 f (1 - f) = 1, width = Ly
+    assert abs(o.mix_width(_state(cfg, mid * one, 0 * one, 0 * one, one))[0] - cfg.ly) <= 1e-14
+    # sharp two-layer state and densities outside [rho_l, rho_h]: no mixed layer
+    y = (np.arange(cfg.ny) + 0.5) * cfg.dy
+    sharp = np.where(y[:, None] > cfg.y0, cfg.rho_h, cfg.rho_l) * one
+    assert o.mix_width(_state(cfg, sharp, 0 * one, 0 * one, one))[0] == 0.0
+    out = np.where(y[:, None] > cfg.y0, 3.0, 0.5) * one
+    assert o.mix_width(_state(cfg, out, 0 * one, 0 * one, one))[0] == 0.0
+    # only row means matter: shuffling cells within rows changes nothing
+    rng = np.random.default_rng(0)
+    r = cfg.rho_l + (cfg.rho_h - cfg.rho_l) * rng.random((cfg.ny, cfg.nx))
+    a = o.mix_width(_state(cfg, r, 0 * one, 0 * one, one))[0]
+    b = o.mix_width(_state(cfg, rng.permuted(r, axis=1), 0 * one, 0 * one, one))[0]
+    assert abs(a - b) <= 1e-14 * a
+
+
+def test_mix_width_of_the_tanh_background():
+    # f = (1 + tanh z)/2, 4 f (1 - f) = sech^2 z: the width is
+    # h (tanh((Ly - y0)/h) + tanh(y0/h)), close to 2h, up to the midpoint rule
+    cfg = RTConfig(nx=4, ny=4096)
+    o = Oracle.from_config(cfg)
+    U = o.init_state(np.zeros(o.shape_uv))
+    exact = cfg.h * (math.tanh((cfg.ly - cfg.y0) / cfg.h) + math.tanh(cfg.y0 / cfg.h))
+    assert abs(o.mix_width(U)[0] - exact) <= 1e-6 * exact
+
+
 # ------------------------------------------------------------ projection
 def test_projection_sphere_ball_and_energy_norm():
     cfg = RTConfig(nx=16, ny=32, batch=2)

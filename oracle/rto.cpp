@@ -20,6 +20,12 @@
 //   rto_ek_anomaly_frozen  objective J of Eq. 8 after a march with given steps
 //   rto_grad_ek_anomaly    J and its exact gradient (same reverse sweep as
 //                      rto_grad_u0, terminal adjoint dJ/dU^N)
+//   rto_objective_adaptive  R or J after the adaptive march (the map whose
+//                      full derivative rto_grad_adaptive gives)
+//   rto_grad_adaptive  R or J and its exact gradient through the adaptive
+//                      march, the dependence of every CFL step on the state
+//                      and of the clipped last step on the earlier ones
+//                      included
 //   rto_project_to_constraint  scaling onto the constraint set (Eq. 11)
 //   rto_hllc, rto_wall_pressure  single-face fluxes for unit tests
 #include <cmath>
@@ -97,6 +103,13 @@ int integrate_member(const Problem& P, double* U, double T, double* t_out, int32
   if (t_out) *t_out = t;
   if (n_out) *n_out = n;
   return bad ? kEUnphys : 0;
+}
+
+// Objective of one member at its final state: J of Eq. 8 when ek_base is
+// given, else KE(U^N)/ke0.
+double objective_value(const Problem& P, const double* U, const double* ek_base, double ke0) {
+  if (ek_base) return rto::ek_anomaly<double>(P, U, ek_base);
+  return rto::kinetic_energy<double>(P, U) / ke0;
 }
 }  // namespace
 
@@ -368,6 +381,120 @@ int rto_grad_ek_anomaly(const Problem* P, const double* uv0, double T, const dou
       for (size_t k = 0; k < 2 * N; ++k) q[k] = Rev::leaf(uv[k]);
       rto::init_member<Rev>(Q, q.data(), U0.data());
       Rev f(0.0);
+      for (size_t k = 0; k < n4; ++k) f = f + lam[k] * U0[k];
+      tp.adj.assign(tp.nodes.size(), 0.0);
+      tp.adj[f.i] = 1.0;
+      tp.sweep();
+      for (size_t k = 0; k < 2 * N; ++k) grad[2 * N * b + k] = tp.adj[q[k].i];
+      tp.clear();
+    }
+  }
+  return 0;
+}
+
+// R = KE(T)/KE(0) (ek_base null) or J of Eq. 8 (ek_base [nb][ny][nx]) after
+// the adaptive march to T, and nsteps[b] (may be null).
+int rto_objective_adaptive(const Problem* P, const double* uv0, double T, const double* ek_base, double* val,
+                           int32_t* nsteps) {
+  if (!valid(P) || !uv0 || !val || !(T > 0)) return kEInval;
+  const size_t N = cells(P), n4 = 4 * N;
+  for (int b = 0; b < P->nb; ++b) {
+    Problem Q = *P;
+    Q.nb = 1;
+    std::vector<double> U(n4);
+    rto::init_member<double>(Q, uv0 + 2 * N * b, U.data());
+    const double ke0 = rto::kinetic_energy<double>(Q, U.data());
+    if (!ek_base && !(ke0 > 0.0)) return kEInval;
+    int32_t n = 0;
+    if (int rc = integrate_member(Q, U.data(), T, nullptr, &n, nullptr, nullptr)) return rc;
+    if (nsteps) nsteps[b] = n;
+    val[b] = objective_value(Q, U.data(), ek_base ? ek_base + N * b : nullptr, ke0);
+  }
+  return 0;
+}
+
+// R or J (as rto_objective_adaptive) and its gradient with respect to
+// (u0, v0) ([nb][2][ny][nx]) through the adaptive march itself: the march
+// carries (U, t), and each step is
+//     dt = cfl / S(U),  clipped to T - t on the last step,
+//     U <- step(U, dt),  t <- t + dt  (t = T after the last step),
+// with S the largest signal speed.  Reverse mode runs on that whole map,
+// one step's tape at a time, with adjoints of both U and t; which step is
+// the last, and which cell holds the largest speed, are taken from the
+// primal values (the number of steps is locally constant).
+int rto_grad_adaptive(const Problem* P, const double* uv0, double T, const double* ek_base, double* val,
+                      double* grad, int32_t* nsteps) {
+  if (!valid(P) || !uv0 || !val || !grad || !(T > 0)) return kEInval;
+  const size_t N = cells(P), n4 = 4 * N;
+  rto::Tape& tp = rto::tape();
+  for (int b = 0; b < P->nb; ++b) {
+    Problem Q = *P;
+    Q.nb = 1;
+    const double* uv = uv0 + 2 * N * b;
+    const double* ekb = ek_base ? ek_base + N * b : nullptr;
+    std::vector<double> U(n4);
+    rto::init_member<double>(Q, uv, U.data());
+    const double ke0 = rto::kinetic_energy<double>(Q, U.data());
+    if (!ekb && !(ke0 > 0.0)) return kEInval;
+    std::vector<double> dts;
+    std::vector<std::vector<double>> states;
+    int32_t n = 0;
+    if (int rc = integrate_member(Q, U.data(), T, nullptr, &n, &dts, &states)) return rc;
+    if (nsteps) nsteps[b] = n;
+    const double keN = rto::kinetic_energy<double>(Q, U.data());
+    val[b] = objective_value(Q, U.data(), ekb, ke0);
+    // times t^k at the start of each step, summed as the march sums them
+    std::vector<double> times(n);
+    double t = 0.0;
+    for (int32_t k = 0; k < n; ++k) {
+      times[k] = t;
+      t = t + dts[k];
+    }
+
+    // terminal adjoint of U^N (KE(0) held fixed for R); the adjoint of t^N
+    // is zero: the objective does not read the time
+    std::vector<double> lam(n4);
+    double lam_t = 0.0;
+    {
+      tp.clear();
+      std::vector<Rev> x(n4);
+      for (size_t k = 0; k < n4; ++k) x[k] = Rev::leaf(U[k]);
+      const Rev r = ekb ? rto::ek_anomaly<Rev>(Q, x.data(), ekb) : rto::kinetic_energy<Rev>(Q, x.data()) / ke0;
+      tp.adj.assign(tp.nodes.size(), 0.0);
+      tp.adj[r.i] = 1.0;
+      tp.sweep();
+      for (size_t k = 0; k < n4; ++k) lam[k] = tp.adj[x[k].i];
+      tp.clear();
+    }
+    for (int32_t s = n - 1; s >= 0; --s) {
+      tp.clear();
+      std::vector<Rev> x(n4), y(n4);
+      for (size_t k = 0; k < n4; ++k) x[k] = Rev::leaf(states[s][k]);
+      const Rev ts = Rev::leaf(times[s]);
+      Rev dt = Q.cfl / rto::max_signal_speed<Rev>(Q, x.data());
+      const Rev rem = Rev(T) - ts;
+      const bool last = rto::val(dt) >= rto::val(rem);
+      if (last != (s == n - 1)) return kEInval;  // must retrace the primal march
+      if (last) dt = rem;
+      if (rto::val(dt) != dts[s]) return kEInval;
+      if (rto::step_member<Rev, Rev>(Q, x.data(), y.data(), dt)) return kEUnphys;
+      const Rev tn = last ? Rev(T) : ts + dt;
+      tp.adj.assign(tp.nodes.size(), 0.0);
+      for (size_t k = 0; k < n4; ++k)
+        if (y[k].i >= 0) tp.adj[y[k].i] += lam[k];
+      if (tn.i >= 0) tp.adj[tn.i] += lam_t;
+      tp.sweep();
+      for (size_t k = 0; k < n4; ++k) lam[k] = tp.adj[x[k].i];
+      lam_t = tp.adj[ts.i];
+      tp.clear();
+    }
+    // initial adjoint: through U^0(uv0), and for R through KE(0) too
+    {
+      tp.clear();
+      std::vector<Rev> q(2 * N), U0(n4);
+      for (size_t k = 0; k < 2 * N; ++k) q[k] = Rev::leaf(uv[k]);
+      rto::init_member<Rev>(Q, q.data(), U0.data());
+      Rev f = ekb ? Rev(0.0) : keN / rto::kinetic_energy<Rev>(Q, U0.data());
       for (size_t k = 0; k < n4; ++k) f = f + lam[k] * U0[k];
       tp.adj.assign(tp.nodes.size(), 0.0);
       tp.adj[f.i] = 1.0;

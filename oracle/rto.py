@@ -66,6 +66,8 @@ def lib():
             "rto_mix_width": [P, _dp, _dp],
             "rto_ek_anomaly_frozen": [P, _dp, _dp, _ip, ctypes.c_int32, _dp, _dp],
             "rto_grad_ek_anomaly": [P, _dp, ctypes.c_double, _dp, _dp, _dp, _ip, _dp, ctypes.c_int32],
+            "rto_objective_adaptive": [P, _dp, ctypes.c_double, _dp, _dp, _ip],
+            "rto_grad_adaptive": [P, _dp, ctypes.c_double, _dp, _dp, _dp, _ip],
             "rto_hllc": [ctypes.c_double, _dp, _dp, _dp],
             "rto_background": [P, _dp, _dp],
         }
@@ -232,6 +234,32 @@ class Oracle:
                                          int(dt_log.shape[1]), _p(ekb), _p(J))
         _check(rc, "ek_anomaly_frozen")
         return J
+
+    def objective_adaptive(self, uv0, T, ek_base=None):
+        """(value, nsteps): R = KE(T)/KE(0), or J of Eq. 8 when ek_base is
+        given, after the adaptive march (every step from the CFL rule)."""
+        uv0 = np.ascontiguousarray(uv0, dtype=np.float64).reshape(self.shape_uv)
+        ekb = None if ek_base is None else self._ekb(ek_base)
+        v = np.empty(self.prob.nb)
+        n = np.empty(self.prob.nb, dtype=np.int32)
+        rc = lib().rto_objective_adaptive(ctypes.byref(self.prob), _p(uv0), float(T),
+                                          None if ekb is None else _p(ekb), _p(v), _ipt(n))
+        _check(rc, "objective_adaptive")
+        return v, n
+
+    def grad_adaptive(self, uv0, T, ek_base=None):
+        """(value, grad, nsteps): R (or J) and its gradient through the
+        adaptive march, the state dependence of the CFL steps and of the
+        clipped last step included."""
+        uv0 = np.ascontiguousarray(uv0, dtype=np.float64).reshape(self.shape_uv)
+        ekb = None if ek_base is None else self._ekb(ek_base)
+        v = np.empty(self.prob.nb)
+        g = np.empty(self.shape_uv)
+        n = np.empty(self.prob.nb, dtype=np.int32)
+        rc = lib().rto_grad_adaptive(ctypes.byref(self.prob), _p(uv0), float(T),
+                                     None if ekb is None else _p(ekb), _p(v), _p(g), _ipt(n))
+        _check(rc, "grad_adaptive")
+        return v, g, n
 
     def baseline_ek(self, T):
         """e_k of the unperturbed run at time T (the reference field of Eq. 8)."""

@@ -198,9 +198,11 @@ T wall_pressure(const Problem& P, const FaceState<T>& w, bool interior_left) {
 
 // ------------------------------------------------------------------ one step
 // Advance one member from U (4*ny*nx) to Un by dt.  Returns nonzero if a cell
-// or face state is unphysical (rho <= 0, p <= 0, or not finite).
-template <class T>
-int step_member(const Problem& P, const T* U, T* Un, double dt) {
+// or face state is unphysical (rho <= 0, p <= 0, or not finite).  The step
+// dt has its own scalar type D, so that reverse mode can also follow the
+// dependence of the state on dt (a D other than double needs T == D).
+template <class T, class D = double>
+int step_member(const Problem& P, const T* U, T* Un, D dt) {
   const int nx = P.nx, ny = P.ny, N = nx * ny;
   const double dx = dx_of(P), dy = dy_of(P), g = P.g_y;
   int bad = 0;
@@ -229,7 +231,7 @@ int step_member(const Problem& P, const T* U, T* Un, double dt) {
       const Prim<T>& w = Wat(i, j);
       const Prim<T> sx = mc_slope(P, Wat((i + nx - 1) % nx, j), w, Wat((i + 1) % nx, j));
       const Prim<T> sy = mc_slope(P, Wat(i, j - 1), w, Wat(i, j + 1));
-      const double hx = 0.5 * dt / dx, hy = 0.5 * dt / dy;
+      const D hx = 0.5 * dt / dx, hy = 0.5 * dt / dy;
       Prim<T> q;
       q.r = w.r - hx * (w.u * sx.r + w.r * sx.u) - hy * (w.v * sy.r + w.r * sy.v);
       q.u = w.u - hx * (w.u * sx.u + sx.p / w.r) - hy * (w.v * sy.u);
@@ -273,7 +275,7 @@ int step_member(const Problem& P, const T* U, T* Un, double dt) {
     }
 
   // Conservative update plus the gravity source.
-  const double ax = dt / dx, ay = dt / dy;
+  const D ax = dt / dx, ay = dt / dy;
   for (int j = 0; j < ny; ++j)
     for (int i = 0; i < nx; ++i) {
       const int c = j * nx + i;
@@ -290,17 +292,21 @@ int step_member(const Problem& P, const T* U, T* Un, double dt) {
   return bad;
 }
 
-// Largest signal speed max((|u|+c)/dx, (|v|+c)/dy) over one member's cells.
-inline double max_signal_speed(const Problem& P, const double* U) {
+// Largest signal speed max((|u|+c)/dx, (|v|+c)/dy) over one member's cells;
+// the first cell in storage order wins a tie, and within a cell the y speed
+// wins a tie with the x speed.  With T = Rev the result carries the
+// derivative of the selected cell's speed (the subgradient of that choice).
+template <class T>
+T max_signal_speed(const Problem& P, const T* U) {
   const int N = P.nx * P.ny;
   const double dx = dx_of(P), dy = dy_of(P);
-  double m = 0.0;
+  T m(0.0);
   for (int c = 0; c < N; ++c) {
-    const Prim<double> w = cons_to_prim(P, U[c], U[N + c], U[2 * N + c], U[3 * N + c]);
-    const double cs = std::sqrt(P.gamma * w.p / w.r);
-    const double sx = (std::fabs(w.u) + cs) / dx, sy = (std::fabs(w.v) + cs) / dy;
-    const double s = sx > sy ? sx : sy;
-    if (s > m) m = s;
+    const Prim<T> w = cons_to_prim(P, U[c], U[N + c], U[2 * N + c], U[3 * N + c]);
+    const T cs = sqrt(P.gamma * w.p / w.r);
+    const T sx = (fabs(w.u) + cs) / dx, sy = (fabs(w.v) + cs) / dy;
+    const T s = val(sx) > val(sy) ? sx : sy;
+    if (val(s) > val(m)) m = s;
   }
   return m;
 }

@@ -497,6 +497,77 @@ def test_ek_anomaly_terminal_adjoint_closed_form():
     assert np.max(np.abs(gv - g[0, 1])) <= 1e-12 * scale
 
 
+# ------------------------------------------- gradient through the adaptive march
+def _adaptive_case(cfg, seed, amp):
+    """A white-noise velocity field (so that one cell clearly holds the
+    largest signal speed) and an end time half-way through the second-last
+    CFL step of a 0.3-long run (so that the step count does not change under
+    a small perturbation)."""
+    o = Oracle.from_config(cfg)
+    rng = np.random.default_rng(seed)
+    uv = amp * rng.standard_normal((1, 2, cfg.ny, cfg.nx))
+    uv = uv * np.array([1.0 if cfg.comp_mask & 1 else 0.0, 1.0 if cfg.comp_mask & 2 else 0.0])[None, :, None, None]
+    _, _, n, log = o.integrate(o.init_state(uv), 0.3, cap=4096)
+    dts = log[0, : n[0]]
+    T = float(np.sum(dts[:-2]) + 0.5 * dts[-2])
+    return o, uv, T, rng
+
+
+@pytest.mark.parametrize("objective", ["R", "J"])
+def test_adaptive_gradient_matches_central_differences_of_the_adaptive_map(objective):
+    # the full derivative (CFL steps depend on the state, the last step on
+    # the earlier ones) against finite differences of the adaptive march
+    # itself; the frozen-schedule gradient misses those terms and fails the
+    # same bound by orders of magnitude, so the check sees them
+    if objective == "R":
+        cfg = RTConfig(nx=8, ny=16)
+        o, uv, T, rng = _adaptive_case(cfg, 5, 0.05)
+        ekb = None
+        _, gf, _, _ = o.grad_u0(uv, T)
+    else:
+        cfg = paper_preset(16).with_(nx=8, ny=16)
+        o, uv, T, rng = _adaptive_case(cfg, 6, 0.05)
+        ekb = o.baseline_ek(T)
+        _, gf, _, _ = o.grad_ek_anomaly(uv, T, ekb)
+    v, g, n = o.grad_adaptive(uv, T, ekb)
+    v2, n2 = o.objective_adaptive(uv, T, ekb)
+    assert v2[0] == v[0] and n2[0] == n[0] > 2
+    assert np.linalg.norm(g - gf) > 1e-5 * np.linalg.norm(g)
+    for s in range(4):
+        d = np.abs(uv).mean() * rng.standard_normal(uv.shape) * (uv != 0)
+        an, anf = np.sum(g * d), np.sum(gf * d)
+        errs = []
+        for h in (1e-5, 1e-6):
+            fp = o.objective_adaptive(uv + h * d, T, ekb)[0][0]
+            fm = o.objective_adaptive(uv - h * d, T, ekb)[0][0]
+            fd = (fp - fm) / (2 * h)
+            errs.append(abs(fd - an) / abs(an))
+        assert min(errs) <= 1e-7, (s, errs)
+        assert abs(fd - anf) / abs(anf) > 1e-5
+
+
+def test_adaptive_gradient_of_a_single_clipped_step_is_the_frozen_one():
+    # one step of length T: dt does not depend on the state, so both
+    # derivatives are the same map's
+    cfg = RTConfig(nx=8, ny=16)
+    o, uv, _, _ = _adaptive_case(cfg, 7, 0.05)
+    T = 0.5 * o.cfl_dt(o.init_state(uv))[0]
+    v, g, n = o.grad_adaptive(uv, T)
+    vf, gf, nf, _ = o.grad_u0(uv, T)
+    assert n[0] == nf[0] == 1 and v[0] == vf[0]
+    np.testing.assert_allclose(g, gf, rtol=0, atol=1e-13 * np.max(np.abs(gf)))
+
+
+def test_adaptive_march_is_the_frozen_march_of_its_own_schedule():
+    # the primal of the adaptive map equals the frozen map at the logged steps
+    cfg = RTConfig(nx=8, ny=16)
+    o, uv, T, _ = _adaptive_case(cfg, 8, 0.05)
+    v, n = o.objective_adaptive(uv, T)
+    R, _, nf, log = o.grad_u0(uv, T, cap=4096)
+    assert v[0] == R[0] and n[0] == nf[0]
+    assert o.ke_ratio_frozen(uv, log, nf)[0] == v[0]
+
+
 # ------------------------------------------------------------ mixing width (Eqs. 13-14)
 def test_mix_width_special_profiles():
     cfg = RTConfig(nx=6, ny=40)

@@ -235,6 +235,23 @@ int rt_autotune(rt_ctx* ctx, const double* U, int32_t reps, int32_t* step_tile, 
  * always runs two kernels per step. */
 int rt_set_fold(rt_ctx* ctx, int32_t on);
 int rt_get_fold(const rt_ctx* ctx, int32_t* on);
+
+/* Time steps in the gradients of rt_grad_u0 and rt_grad_ek_anomaly.
+ * RT_DT_FROZEN (the default): the steps of the forward run are held fixed,
+ * so the gradient is that of the march with that schedule.
+ * RT_DT_DIFFERENTIATED: the gradient of the adaptive march itself, in which
+ * every step but the last is dt_n = cfl / S(U^n) (S the largest signal
+ * speed, Sec. 2.3) and the last one is T - t_n.  The reverse sweep then also
+ * forms mu_n = <lambda^{n+1}, dU^{n+1}/d dt_n> and, on every step before the
+ * member's last, adds (mu_n - mu_last) d dt_n / dU^n at the cell holding the
+ * largest speed (the first such cell in storage order on a tie, the y speed
+ * on a tie between x and y).  The number of steps is taken as locally
+ * constant.  This mode always runs two kernels per adjoint step plus one
+ * small kernel; it is deterministic for a given adjoint tile, and tiles
+ * differ only in the rounding of mu's sum. */
+enum { RT_DT_FROZEN = 0, RT_DT_DIFFERENTIATED = 1 };
+int rt_set_dt_mode(rt_ctx* ctx, int32_t mode);
+int rt_get_dt_mode(const rt_ctx* ctx, int32_t* mode);
 /* Measurement hook: per-launch times in microseconds of the selected
  * variants, from HIP events on the context's stream around `reps`
  * back-to-back launches each, with U (device) as every step's state:

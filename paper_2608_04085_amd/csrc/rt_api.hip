@@ -76,6 +76,12 @@ struct rt_ctx {
   // Reverse sweep with the limiter gather folded into the next step's kernel
   // (one kernel per step) or as its own kernel (two per step).
   bool fold = true;
+  // Step sizes in the gradient: held at the forward run's values
+  // (RT_DT_FROZEN) or differentiated (RT_DT_DIFFERENTIATED).
+  int dt_mode = RT_DT_FROZEN;
+  double *dtd_mu = nullptr, *dtd_smax = nullptr, *dtd_mu_last = nullptr;
+  int32_t* dtd_imax = nullptr;
+  int32_t dtd_stride = 0;
   ~rt_ctx() {
     if (chunk_exec) (void)hipGraphExecDestroy(chunk_exec);
     if (capture_stream) (void)hipStreamDestroy(capture_stream);
@@ -95,7 +101,9 @@ struct rt_ctx {
 namespace {
 
 struct Layout {
-  size_t S0, S1, L0, L1, Z, Z2, codes, codes2, partial, rowmean, acc, ctl, flags, dt_log, nsteps, scal, total;
+  size_t S0, S1, L0, L1, Z, Z2, codes, codes2, partial, rowmean, acc, ctl, flags, dt_log, nsteps, scal;
+  size_t dtd_mu, dtd_smax, dtd_imax, dtd_mu_last, total;
+  int32_t dtd_stride;
 };
 
 Layout layout(const rt_ctx* c, int32_t max_steps) {
@@ -125,6 +133,14 @@ Layout layout(const rt_ctx* c, int32_t max_steps) {
   L.dt_log = take((size_t)c->P.nb * std::max<int32_t>(max_steps, 1) * sizeof(double));
   L.nsteps = take((size_t)c->P.nb * sizeof(int32_t));
   L.scal = take((size_t)8 * c->P.nb * sizeof(double));
+  // per-block partials of the step-size derivative, for any adjoint tile
+  int adjblk = 1;
+  for (int t = 0; t < rtk::TILE_COUNT; ++t) adjblk = std::max(adjblk, rtk::step_blocks(c->P, t));
+  L.dtd_stride = adjblk;
+  L.dtd_mu = take((size_t)adjblk * c->P.nb * sizeof(double));
+  L.dtd_smax = take((size_t)adjblk * c->P.nb * sizeof(double));
+  L.dtd_imax = take((size_t)adjblk * c->P.nb * sizeof(int32_t));
+  L.dtd_mu_last = take((size_t)c->P.nb * sizeof(double));
   L.total = off;
   return L;
 }
@@ -374,6 +390,19 @@ int rt_get_fold(const rt_ctx* c, int32_t* on) {
   return 0;
 }
 
+int rt_set_dt_mode(rt_ctx* c, int32_t mode) {
+  if (!c) return fail(RT_EINVAL, "null context");
+  if (mode != RT_DT_FROZEN && mode != RT_DT_DIFFERENTIATED) return fail(RT_EINVAL, "unknown dt mode %d", mode);
+  c->dt_mode = mode;
+  return 0;
+}
+
+int rt_get_dt_mode(const rt_ctx* c, int32_t* mode) {
+  if (!c || !mode) return fail(RT_EINVAL, "null argument");
+  *mode = c->dt_mode;
+  return 0;
+}
+
 int rt_get_tiles(const rt_ctx* c, int32_t* step_tile, int32_t* adj_tile) {
   if (!c || !step_tile || !adj_tile) return fail(RT_EINVAL, "null argument");
   *step_tile = c->tile;
@@ -572,6 +601,11 @@ int rt_set_workspace(rt_ctx* c, void* dev, size_t bytes, int32_t max_steps) {
   c->dt_log = reinterpret_cast<double*>(w + L.dt_log);
   c->nsteps = reinterpret_cast<int32_t*>(w + L.nsteps);
   c->scal = reinterpret_cast<double*>(w + L.scal);
+  c->dtd_mu = reinterpret_cast<double*>(w + L.dtd_mu);
+  c->dtd_smax = reinterpret_cast<double*>(w + L.dtd_smax);
+  c->dtd_imax = reinterpret_cast<int32_t*>(w + L.dtd_imax);
+  c->dtd_mu_last = reinterpret_cast<double*>(w + L.dtd_mu_last);
+  c->dtd_stride = L.dtd_stride;
   RT_HIP(rtk::launch_fill_i32(reinterpret_cast<int32_t*>(c->acc), 0, 2 * ((size_t)3 * rtk::kAccRow + 1) * c->P.nb,
                               c->stream));
   RT_HIP(rtk::launch_fill_i32(reinterpret_cast<int32_t*>(c->flags), 0, sizeof(Flags) / 4, c->stream));
@@ -754,6 +788,7 @@ int grad_objective(rt_ctx* c, const double* uv0, double T, const rt_ckpt_policy*
     RT_HIP(rtk::launch_step(P, c->tile, a, ss));
     return 0;
   };
+  const bool dtd = c->dt_mode == RT_DT_DIFFERENTIATED;
   auto adjoint = [&](const double* Un, int n) -> int {
     rtk::AdjArgs a{};
     a.U = Un;
@@ -766,7 +801,16 @@ int grad_objective(rt_ctx* c, const double* uv0, double T, const rt_ckpt_policy*
     a.dt_index = n;
     a.nsteps_limit = c->nsteps;
     a.flags = c->flags;
+    if (dtd) {
+      a.dtd.mu = c->dtd_mu;
+      a.dtd.smax = c->dtd_smax;
+      a.dtd.imax = c->dtd_imax;
+      a.dtd.stride = c->dtd_stride;
+      a.dtd.count = rtk::step_blocks(P, c->tile_adj);
+      a.dtd.mu_last = c->dtd_mu_last;
+    }
     RT_HIP(rtk::launch_adjoint(P, c->tile_adj, a, s));
+    if (dtd) RT_HIP(rtk::launch_dt_correct(P, a, s));  // updates lambda^n (a.lam) in place
     std::swap(lam, lam_other);
     return 0;
   };
@@ -873,7 +917,7 @@ int grad_objective(rt_ctx* c, const double* uv0, double T, const rt_ckpt_policy*
         return rc;
       }
       for (int n = hi - 1; n >= base; --n)
-        if (int rc = c->fold ? adjoint_folded(st(k, n), n) : adjoint(st(k, n), n)) return rc;
+        if (int rc = (c->fold && !dtd) ? adjoint_folded(st(k, n), n) : adjoint(st(k, n), n)) return rc;
       if (two) RT_HIP(hipEventRecord(c->seg_free[k & 1], s));
     }
     if (int rc = finish_folded()) return rc;

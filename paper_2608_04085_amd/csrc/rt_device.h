@@ -280,12 +280,20 @@ RT_DEV void hllc(const Params& P, const FS& L, const FS& R, double F[4]) {
 }
 
 // Adjoint of hllc: given F-bar, accumulate L-bar and R-bar (reverse of the
-// computational graph of hllc_core + hllc).
-RT_DEV void hllc_adj(const Params& P, const FS& L, const FS& R, const double Fb[4], FS& Lb, FS& Rb) {
+// computational graph of hllc_core + hllc).  F, if not null, also receives
+// the flux itself (as hllc gives it).
+RT_DEV void hllc_adj(const Params& P, const FS& L, const FS& R, const double Fb[4], FS& Lb, FS& Rb,
+                     double* F = nullptr) {
   const HllcCore h = hllc_core(P, L, R);
   const double g = P.gamma;
   const double fH = h.k * h.G;
   const double sig = h.sig;
+  if (F) {
+    F[0] = h.m0 + h.sig * (h.f - h.r);
+    F[1] = h.m0 * h.n + h.p + h.sig * (h.f * h.SS - h.m0);
+    F[2] = h.m0 * h.t + h.sig * (h.f * h.t - h.r * h.t);
+    F[3] = h.n * (h.E + h.p) + h.sig * (fH - h.E);
+  }
   // F0 = m0 + sig (f - r); F1 = m0 n + p + sig (f SS - m0);
   // F2 = m0 t + sig (f t - r t); F3 = n (E + p) + sig (fH - E)
   const double sigb =
@@ -412,6 +420,28 @@ RT_DEV double signal_speed(const Params& P, double r, double mx, double my, doub
   const double c = sqrt_fast(P.gamma * w.p * w.ri);
   const double sx = (fabs(w.u) + c) * P.inv_dx, sy = (fabs(w.v) + c) * P.inv_dy;
   return sx > sy ? sx : sy;
+}
+
+// The same speed and its gradient with respect to (r, m_x, m_y, E), the
+// speed's branch (x or y; y on a tie) and |.| (slope +1 at 0) taken as
+// signal_speed takes them.  With c^2 = gamma p / r,
+//   dc = (c/2) (dp/p - dr/r),  dp = (gamma - 1) ((u^2+v^2)/2, -u, -v, 1),
+//   d|u| = sign(u) (-u/r, 1/r, 0, 0),  d|v| = sign(v) (-v/r, 0, 1/r, 0).
+RT_DEV double signal_speed_grad(const Params& P, double r, double mx, double my, double E, double d[4]) {
+  const W4 w = cons_to_prim(P, r, mx, my, E);
+  const double c = sqrt_fast(P.gamma * w.p * w.ri);
+  const double sx = (fabs(w.u) + c) * P.inv_dx, sy = (fabs(w.v) + c) * P.inv_dy;
+  const double hp = 0.5 * c * rcp(w.p) * P.gm1;  // (c/2) (gamma - 1) / p
+  const double dc[4] = {hp * 0.5 * (w.u * w.u + w.v * w.v) - 0.5 * c * w.ri, -hp * w.u, -hp * w.v, hp};
+  const bool xs = sx > sy;
+  const double a = xs ? w.u : w.v;
+  const double sg = (a < 0.0 ? -1.0 : 1.0) * w.ri;
+  const double inv = xs ? P.inv_dx : P.inv_dy;
+  d[0] = (dc[0] - sg * a) * inv;
+  d[1] = (dc[1] + (xs ? sg : 0.0)) * inv;
+  d[2] = (dc[2] + (xs ? 0.0 : sg)) * inv;
+  d[3] = dc[3] * inv;
+  return xs ? sx : sy;
 }
 
 }  // namespace rtk

@@ -86,6 +86,20 @@ struct AdjArgs {
     double* lam_out;         // lambda^{n+1}
     int32_t dt_index;        // n + 1
   } fold;
+  // Differentiated step size (dtd.mu != nullptr, two-kernel form only):
+  // kernel A also writes, per block (tile index ty * tiles_x + tx), its
+  // share of mu = <lambda^{n+1}, dU^{n+1}/d dt> (every face once, every own
+  // cell once) and the largest signal speed of U^n over its own cells with
+  // the smallest index of a cell that holds it; launch_dt_correct then
+  // combines them.
+  struct Dtd {
+    double* mu;       // [B][stride]
+    double* smax;     // [B][stride]
+    int32_t* imax;    // [B][stride]
+    int32_t stride;   // partials per member, >= the adjoint grid's tiles
+    int32_t count;    // tiles of the adjoint grid per member
+    double* mu_last;  // [B] mu of each member's last (clipped) step
+  } dtd;
 };
 
 // Tile shapes of the fused step / adjoint kernels: TX x TY cells with 256
@@ -114,6 +128,12 @@ hipError_t launch_step(const Params& P, int tile, const StepArgs& a, hipStream_t
 hipError_t launch_adjoint(const Params& P, int tile, const AdjArgs& a, hipStream_t s, bool gather = true);
 // Kernel B alone: lambda^n from Z, codes, U^n and lambda^{n+1} of step n.
 hipError_t launch_adj_gather(const Params& P, const AdjArgs& a, hipStream_t s);
+// Differentiated step size, after both adjoint kernels of step n (a.U = U^n,
+// a.lam = lambda^n, updated in place, a.dtd filled by kernel A): on the
+// member's last step, mu_last = mu; on every earlier step,
+// lambda^n += (mu - mu_last) d dt_n / dU^n at the cell of the largest
+// signal speed, dt_n = cfl / S(U^n).  One block per member.
+hipError_t launch_dt_correct(const Params& P, const AdjArgs& a, hipStream_t s);
 // Per-member reductions: kind 0 = max signal speed, 1 = kinetic energy,
 // 2.. = weighted |uv|^2 for the projection (norm id = kind - 2), 5 = dot,
 // 6 = max |x| of a velocity field, 7 = objective of Eq. 8 (a = U,

@@ -95,6 +95,32 @@ __device__ double block_sum(double v, double* red) {
   return s;
 }
 
+// Largest s over the block with the smallest i among equal s (a total
+// order, so the result does not depend on the order of combination).
+__device__ __forceinline__ void argmax_merge(double& s, int& i, double s2, int i2) {
+  if (s2 > s || (s2 == s && i2 < i)) {
+    s = s2;
+    i = i2;
+  }
+}
+
+template <int NT>
+__device__ void block_argmax(double& s, int& i, double* rs, int* ri) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) argmax_merge(s, i, __shfl_xor(s, o, 64), __shfl_xor(i, o, 64));
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) {
+    rs[w] = s;
+    ri[w] = i;
+  }
+  __syncthreads();
+  s = rs[0];
+  i = ri[0];
+#pragma unroll
+  for (int k = 1; k < NT / 64; ++k) argmax_merge(s, i, rs[k], ri[k]);
+}
+
 __device__ __forceinline__ double load_coherent(const double* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -613,9 +639,21 @@ struct AdjLDS<TX, TY, true> : AdjCore<TX, TY> {
   double L[4][AdjCore<TX, TY>::QY][AdjCore<TX, TY>::QX];  // lambda-tilde on the halo-1 region
 };
 
-template <int TX, int TY, int NT, bool FOLD>
+// DTD: also the step-size derivative mu and the signal-speed argmax of U^n
+// (AdjArgs::Dtd).  With lambda-tilde l (l_0 = lambda_0 + (dt g/2) lambda_2)
+// and the fluxes F of the step, mu sums
+//   x faces   (1/dx) [<l_R - l_L, F> + (dt g/2)(l_2R - l_2L) F_0]
+//   y faces   (1/dy) [<l_T - l_B, G> + (dt g/2)(l_2T - l_2B) G_0]
+//             + (g/2)(l_3B + l_3T) G_0     (walls: +-(1/dy) l_2 p*)
+//   cells     g lambda_2 rho - <q-bar, A_x(W) s_x>/(2 dx)
+//             - <q-bar, A_y(W) s_y>/(2 dy) + (g/2) q-bar_v
+// which is d<lambda^{n+1}, U^{n+1}>/d dt of the update with gravity
+// source (the flux terms once from the explicit dt, once from the dt in
+// the source's use of rho^{n+1}) and of the MUSCL-Hancock predictor.
+template <int TX, int TY, int NT, bool FOLD, bool DTD>
 __global__ __launch_bounds__(NT) void k_adj_a(Params P, AdjArgs a) {
   static_assert(NT >= TX * TY && NT % 64 == 0, "one thread per tile cell at least");
+  static_assert(!(FOLD && DTD), "the step-size derivative needs the two-kernel form");
   constexpr int QX = AdjCore<TX, TY>::QX, QY = AdjCore<TX, TY>::QY;
   __shared__ AdjLDS<TX, TY, FOLD> S;
 
@@ -716,6 +754,7 @@ __global__ __launch_bounds__(NT) void k_adj_a(Params P, AdjArgs a) {
   };
 
   const double ax = dt * P.inv_dx, ay = dt * P.inv_dy;
+  double mu = 0.0;  // DTD: this thread's share of d<lambda^{n+1}, U^{n+1}>/d dt
   // x faces
   for (int k = tid; k < (TX + 1) * TY; k += NT) {
     const int fx = k % (TX + 1), fy = k / (TX + 1);
@@ -726,7 +765,16 @@ __global__ __launch_bounds__(NT) void k_adj_a(Params P, AdjArgs a) {
       lam(fx, fy + 1, lL);
       lam(fx + 1, fy + 1, lR);
       const double Fb[4] = {ax * (lR[0] - lL[0]), ax * (lR[1] - lL[1]), ax * (lR[2] - lL[2]), ax * (lR[3] - lL[3])};
-      hllc_adj(P, xface_right_of(S, fx, fy + 1), xface_left_of(S, fx + 1, fy + 1), Fb, Lb, Rb);
+      if constexpr (DTD) {
+        double F[4];
+        hllc_adj(P, xface_right_of(S, fx, fy + 1), xface_left_of(S, fx + 1, fy + 1), Fb, Lb, Rb, F);
+        // each face once: the right faces of the tile's own cells
+        if (fx >= 1 && x0 + fx - 1 < nx)
+          mu += P.inv_dx * ((lR[0] - lL[0]) * F[0] + (lR[1] - lL[1]) * F[1] + (lR[2] - lL[2]) * F[2] +
+                            (lR[3] - lL[3]) * F[3] + hdtg * (lR[2] - lL[2]) * F[0]);
+      } else {
+        hllc_adj(P, xface_right_of(S, fx, fy + 1), xface_left_of(S, fx + 1, fy + 1), Fb, Lb, Rb);
+      }
     }
     // x-frame (r, n = u, t = v, p) is the primitive order
     S.fx.XL[0][fy][fx] = Lb.r;
@@ -755,14 +803,21 @@ __global__ __launch_bounds__(NT) void k_adj_a(Params P, AdjArgs a) {
     const int j = y0 + fy;
     FS Bb{0, 0, 0, 0}, Tb{0, 0, 0, 0};
     // below = halo-1 cell (fx+1, fy), above = (fx+1, fy+1)
+    // DTD counts each face once: the walls, and the top faces of the tile's
+    // own rows
+    const bool col = x0 + fx < nx;
     if (j == 0) {
       double lT[4];
       lam(fx + 1, fy + 1, lT);
       wall_pressure_adj(P, yface_bottom_of(S, fx + 1, fy + 1), false, ay * lT[2], Tb);
+      if constexpr (DTD)
+        if (col) mu += P.inv_dy * lT[2] * wall_pressure(P, yface_bottom_of(S, fx + 1, fy + 1), false);
     } else if (j == ny) {
       double lB[4];
       lam(fx + 1, fy, lB);
       wall_pressure_adj(P, yface_top_of(S, fx + 1, fy), true, -ay * lB[2], Bb);
+      if constexpr (DTD)
+        if (col) mu -= P.inv_dy * lB[2] * wall_pressure(P, yface_top_of(S, fx + 1, fy), true);
     } else if (j < ny) {
       double lB[4], lT[4];
       lam(fx + 1, fy, lB);
@@ -772,7 +827,16 @@ __global__ __launch_bounds__(NT) void k_adj_a(Params P, AdjArgs a) {
       const double g2 = ay * (lT[2] - lB[2]);
       const double g3 = ay * (lT[3] - lB[3]);
       const double Fb[4] = {g0, g2, g1, g3};  // y frame: normal momentum is m_y
-      hllc_adj(P, yface_top_of(S, fx + 1, fy), yface_bottom_of(S, fx + 1, fy + 1), Fb, Bb, Tb);
+      if constexpr (DTD) {
+        double F[4];  // y frame: mass, m_y, m_x, energy
+        hllc_adj(P, yface_top_of(S, fx + 1, fy), yface_bottom_of(S, fx + 1, fy + 1), Fb, Bb, Tb, F);
+        if (fy >= 1 && col)
+          mu += P.inv_dy * ((lT[0] - lB[0]) * F[0] + (lT[1] - lB[1]) * F[2] + (lT[2] - lB[2]) * F[1] +
+                            (lT[3] - lB[3]) * F[3] + hdtg * (lT[2] - lB[2]) * F[0]) +
+                0.5 * P.g_y * (lT[3] + lB[3]) * F[0];
+      } else {
+        hllc_adj(P, yface_top_of(S, fx + 1, fy), yface_bottom_of(S, fx + 1, fy + 1), Fb, Bb, Tb);
+      }
     }
     // y-frame (r, n = v, t = u, p) -> primitive order (r, u, v, p)
     S.fy.YB[0][fy][fx] = Bb.r;
@@ -796,6 +860,17 @@ __global__ __launch_bounds__(NT) void k_adj_a(Params P, AdjArgs a) {
     const W4 w = cons_to_prim(P, u0, u1, u2, u3);
     const W4 sx = ldQ(S, 1, lx, ly), sy = ldQ(S, 2, lx, ly);
     predict_adj(P, w, sx, sy, 0.5 * dt * P.inv_dx, 0.5 * dt * P.inv_dy, qb, wb, sxb, syb);
+    if constexpr (DTD) {
+      double l[4];
+      lam(lx, ly, l);
+      const double ri = w.ri;
+      const double axr = w.u * sx.r + w.r * sx.u, axu = w.u * sx.u + sx.p * ri, axv = w.u * sx.v,
+                   axp = P.gamma * w.p * sx.u + w.u * sx.p;
+      const double ayr = w.v * sy.r + w.r * sy.v, ayu = w.v * sy.u, ayv = w.v * sy.v + sy.p * ri,
+                   ayp = P.gamma * w.p * sy.v + w.v * sy.p;
+      mu += P.g_y * l[2] * u0 - 0.5 * P.inv_dx * (qb.r * axr + qb.u * axu + qb.v * axv + qb.p * axp) -
+            0.5 * P.inv_dy * (qb.r * ayr + qb.u * ayu + qb.v * ayv + qb.p * ayp) + 0.5 * P.g_y * qb.v;
+    }
     double* Z = a.Z + (size_t)b * 12 * N;
     stg(Z, c, wb.r);
     stg(Z + N, c, wb.u);
@@ -811,6 +886,24 @@ __global__ __launch_bounds__(NT) void k_adj_a(Params P, AdjArgs a) {
     stg(Z + 11 * N, c, syb.p);
   }
   if (bad) atomicOr(&a.flags->err_unphys, 1);
+  if constexpr (DTD) {
+    __shared__ double rmu[NT / 64], rsp[NT / 64];
+    __shared__ int rix[NT / 64];
+    double sp = -1.0;
+    int ix = 0x7fffffff;
+    if (own) {
+      sp = signal_speed(P, u0, u1, u2, u3);
+      ix = (int)c;
+    }
+    const double m = block_sum<NT>(mu, rmu);
+    block_argmax<NT>(sp, ix, rsp, rix);
+    if (tid == 0) {
+      const size_t o = (size_t)b * a.dtd.stride + (size_t)tby * gridDim.x + tbx;
+      a.dtd.mu[o] = m;
+      a.dtd.smax[o] = sp;
+      a.dtd.imax[o] = ix;
+    }
+  }
 }
 
 // ----------------------------------------------------------------- adjoint B
@@ -835,6 +928,45 @@ __global__ __launch_bounds__(256) void k_adj_b(Params P, AdjArgs a) {
   stg(Lo + N, idx, l[1]);
   stg(Lo + 2 * N, idx, l[2]);
   stg(Lo + 3 * N, idx, l[3]);
+}
+
+// ----------------------------------------------------------------- step-size derivative
+// The step n of member b is dt_n = cfl / S(U^n) unless it is the last one,
+// which is T - t_n and so takes -1 times every earlier step's change.  The
+// reverse sweep meets the last step first and keeps its mu; every earlier
+// step adds (mu_n - mu_last) d dt_n / dU^n = (mu_n - mu_last) (-cfl / S^2)
+// dS/dU at the one cell that holds the largest speed S.
+__global__ __launch_bounds__(256) void k_dt_correct(Params P, AdjArgs a) {
+  __shared__ double rm[4], rs[4];
+  __shared__ int ri[4];
+  const int b = blockIdx.x;
+  const int n = a.dt_index, last = a.nsteps_limit[b] - 1;
+  if (n > last) return;
+  const size_t o = (size_t)b * a.dtd.stride;
+  double m = 0.0, sp = -1.0;
+  int ix = 0x7fffffff;
+  for (int k = threadIdx.x; k < a.dtd.count; k += 256) {
+    m += a.dtd.mu[o + k];
+    argmax_merge(sp, ix, a.dtd.smax[o + k], a.dtd.imax[o + k]);
+  }
+  m = block_sum<256>(m, rm);
+  block_argmax<256>(sp, ix, rs, ri);
+  if (threadIdx.x != 0) return;
+  if (n == last) {
+    a.dtd.mu_last[b] = m;
+    return;
+  }
+  const size_t N = (size_t)P.nx * P.ny;
+  if (ix < 0 || (size_t)ix >= N) return;
+  const double* U = a.U + (size_t)b * 4 * N;
+  double d[4];
+  const double S = signal_speed_grad(P, U[ix], U[N + ix], U[2 * N + ix], U[3 * N + ix], d);
+  const double coef = (m - a.dtd.mu_last[b]) * (-P.cfl / (S * S));
+  double* L = a.lam + (size_t)b * 4 * N;
+  L[ix] += coef * d[0];
+  L[N + ix] += coef * d[1];
+  L[2 * N + ix] += coef * d[2];
+  L[3 * N + ix] += coef * d[3];
 }
 
 // ----------------------------------------------------------------- small kernels
@@ -1195,15 +1327,28 @@ hipError_t launch_step(const Params& P, int tile, const StepArgs& a, hipStream_t
 template <int TX, int TY, int NT>
 static hipError_t launch_adj_t(const Params& P, const AdjArgs& a, hipStream_t s) {
   dim3 grid((P.nx + TX - 1) / TX, (P.ny + TY - 1) / TY, P.nb);
-  if (a.fold.Z != nullptr)
-    hipLaunchKernelGGL((k_adj_a<TX, TY, NT, true>), grid, dim3(NT), 0, s, P, a);
-  else
-    hipLaunchKernelGGL((k_adj_a<TX, TY, NT, false>), grid, dim3(NT), 0, s, P, a);
+  if (a.dtd.mu != nullptr) {
+    if (a.fold.Z != nullptr || a.dtd.count != (int)(grid.x * grid.y) || a.dtd.stride < a.dtd.count)
+      return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_adj_a<TX, TY, NT, false, true>), grid, dim3(NT), 0, s, P, a);
+  } else if (a.fold.Z != nullptr) {
+    hipLaunchKernelGGL((k_adj_a<TX, TY, NT, true, false>), grid, dim3(NT), 0, s, P, a);
+  } else {
+    hipLaunchKernelGGL((k_adj_a<TX, TY, NT, false, false>), grid, dim3(NT), 0, s, P, a);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_adj_gather(const Params& P, const AdjArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_adj_b, cells_grid(P, (size_t)P.nx * P.ny), dim3(256), 0, s, P, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_dt_correct(const Params& P, const AdjArgs& a, hipStream_t s) {
+  if (!a.dtd.mu || !a.dtd.smax || !a.dtd.imax || !a.dtd.mu_last || !a.nsteps_limit || a.dtd.count < 1 ||
+      a.dtd.stride < a.dtd.count)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_dt_correct, dim3(P.nb), dim3(256), 0, s, P, a);
   return hipGetLastError();
 }
 

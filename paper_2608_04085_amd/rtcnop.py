@@ -20,6 +20,8 @@ LIB_PATH = os.path.join(_HERE, "librtcnop.so")
 
 STATUS = {0: "RT_OK", -1: "RT_EINVAL", -2: "RT_EHIP", -3: "RT_ENOMEM", -4: "RT_EUNPHYS", -5: "RT_ESTATE"}
 TILES = {"16x16": 0, "32x8": 1, "64x4": 2, "16x16w": 3, "32x8w": 4, "16x8": 5, "8x8": 6, "16x8w": 7, "8x8w": 8}
+DT_MODES = {"frozen": 0, "differentiated": 1}
+DT_MODES_BY_ID = {v: k for k, v in DT_MODES.items()}
 
 
 class RTError(RuntimeError):
@@ -89,6 +91,8 @@ def load():
         "rt_ek_anomaly": [_vp, _vp, _vp, _vp],
         "rt_grad_ek_anomaly": [_vp, _vp, ctypes.c_double, _vp, _vp, _vp, _vp, _vp],
         "rt_get_fold": [_vp, ctypes.POINTER(_i32)],
+        "rt_set_dt_mode": [_vp, _i32],
+        "rt_get_dt_mode": [_vp, ctypes.POINTER(_i32)],
         "rt_axpy": [_vp, _vp, _vp, _vp, _vp],
         "rt_check_error": [_vp],
         "rt_revolve_stats": [_i32, _i32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
@@ -109,7 +113,7 @@ EXPORTED = ["rt_create", "rt_destroy", "rt_set_stream", "rt_workspace_bytes", "r
             "rt_last_error", "rt_set_tile", "rt_get_tiles", "rt_autotune", "rt_max_abs", "rt_set_graphs",
             "rt_set_overlap", "rt_kernel_times", "rt_set_fold", "rt_get_fold",
             "rt_set_tiles", "rt_ek_field", "rt_ek_anomaly", "rt_grad_ek_anomaly",
-            "rt_mix_width"]
+            "rt_mix_width", "rt_set_dt_mode", "rt_get_dt_mode"]
 
 
 def _check(rc: int, call: str):
@@ -239,6 +243,17 @@ class Context:
 
     def set_fold(self, on: bool):
         _check(load().rt_set_fold(self._h, 1 if on else 0), "rt_set_fold")
+
+    @property
+    def dt_mode(self) -> str:
+        """"frozen" (the forward run's steps held fixed in the gradient, the
+        default) or "differentiated" (the gradient of the adaptive march)."""
+        v = ctypes.c_int32()
+        _check(load().rt_get_dt_mode(self._h, ctypes.byref(v)), "rt_get_dt_mode")
+        return DT_MODES_BY_ID[v.value]
+
+    def set_dt_mode(self, mode: str):
+        _check(load().rt_set_dt_mode(self._h, DT_MODES[mode]), "rt_set_dt_mode")
 
     def set_overlap(self, on: bool):
         """Two-stream reverse sweep of the UNIFORM policy (default on); results are identical."""

@@ -505,3 +505,107 @@ def test_comparison_suite_runs_all_kinds_at_the_energy_budget():
     res1 = cnop.comparison_runs(r1, seeds[:1], 1e-6, 0.3, 3)
     np.testing.assert_array_equal(np.array(res1["ke"])[:, 0], np.array(res["ke"])[:, 0])
     np.testing.assert_array_equal(np.array(res1["h_mix"])[:, 0], np.array(res["h_mix"])[:, 0])
+
+
+# ------------------------------------------------------ differentiated time steps
+# The gradient of the adaptive march itself (rt_set_dt_mode): parity with
+# the oracle's reverse mode through the adaptive march, and central
+# differences of the GPU's own adaptive march at the full gradient size.
+DTD_CASES = [
+    (RTConfig(nx=40, ny=24, batch=3), (0.05, 0.1, 0.03), 0.05),           # tiles + ragged tails, step counts differ
+    (RTConfig(nx=5, ny=9), (0.05,), 0.2),                                 # smaller than one tile
+    (paper_preset(16).with_(nx=40, ny=24, batch=2), (0.05, 0.02), 0.05),  # objective J, u_y only
+]
+
+
+def _white(cfg, amps, seed=21):
+    """White-noise velocity fields (one cell clearly holds the largest signal speed)."""
+    rng = np.random.default_rng(seed)
+    uv = np.stack([a * rng.standard_normal((2, cfg.ny, cfg.nx)) for a in amps])
+    if not cfg.comp_mask & 1:
+        uv[:, 0] = 0.0
+    if not cfg.comp_mask & 2:
+        uv[:, 1] = 0.0
+    return uv
+
+
+@pytest.mark.parametrize("case", range(len(DTD_CASES)), ids=["40x24x3", "5x9", "paper40x24x2-J"])
+def test_differentiated_dt_gradient_matches_oracle(case):
+    cfg, amps, T = DTD_CASES[case]
+    use_j = cfg.comp_mask == 2
+    o = Oracle.from_config(cfg)
+    uv = _white(cfg, amps)
+    ekb = o.baseline_ek(T) if use_j else None
+    vo, go, no = o.grad_adaptive(uv, T, ekb)
+    r = rt().Context(cfg, max_steps=1024)
+    r.set_dt_mode("differentiated")
+    assert r.dt_mode == "differentiated"
+
+    def grad(pol):
+        if use_j:
+            return r.grad_ek_anomaly(uv, T, torch.from_numpy(ekb), pol)
+        return r.grad_u0(uv, T, pol)
+
+    pols = [rt().Policy(CKPT_STORE_ALL, 1), rt().Policy(CKPT_UNIFORM, 5),
+            rt().Policy(CKPT_REVOLVE, 1, pool_bytes=3 * 8 * 4 * cfg.cells * cfg.batch)]
+    for tile in ("32x8", "16x16", "8x8w"):
+        r.set_tiles(tile, tile)
+        res = [tuple(host(x) for x in grad(p)) for p in pols]
+        v, g, n = res[0]
+        np.testing.assert_array_equal(n, no)
+        np.testing.assert_allclose(v, vo, rtol=1e-9 if use_j else 1e-12)
+        err = normwise(g, go)
+        print(f"differentiated dt {cfg.nx}x{cfg.ny}x{cfg.batch} tile {tile}: normwise {err:.2e}")
+        assert err <= 1e-9
+        for vk, gk, nk in res[1:]:  # deterministic across checkpoint policies
+            np.testing.assert_array_equal(gk, g)
+            np.testing.assert_array_equal(vk, v)
+    # the step-size terms are visible at this tolerance
+    r.set_dt_mode("frozen")
+    gf = host(grad(pols[0])[1])
+    assert normwise(gf, go) > 1e-6
+
+
+def test_differentiated_dt_at_full_size_against_fd_of_the_adaptive_march():
+    # 256 x 512 with the gradient workload's seed, to an end time half-way
+    # through the second-last CFL step of the T = 2 run (so that no perturbed
+    # run takes a different number of steps), snapshots every 32 steps and
+    # the two-stream sweep; 16 seeded directions, each perturbed run marching
+    # adaptively (one batch of 64 members, each with its own steps).
+    cfg = RTConfig(nx=256, ny=512)
+    r = rt().Context(cfg, max_steps=8192)
+    uv = inputs.seed_batch(cfg, [0], rms=1e-3)
+    _, _, n0, log = r.integrate(r.init_state(uv), 2.0, log_cap=8192)
+    dts = host(log)[0, : int(host(n0)[0])]
+    T = float(np.sum(dts[:-2]) + 0.5 * dts[-2])
+    r.set_dt_mode("differentiated")
+    R, g, n = r.grad_u0(uv, T, rt().Policy(CKPT_UNIFORM, 32))
+    r.set_dt_mode("frozen")
+    _, gf, _ = r.grad_u0(uv, T, rt().Policy(CKPT_UNIFORM, 32))
+    delta = float(np.sqrt(np.sum(uv * uv) * cfg.dx * cfg.dy))
+    dirs = [inputs.direction_batch(cfg, [s], delta)[0] for s in range(1000, 1016)]
+    hs = (1e-5, 1e-6)
+    members = [uv[0] + sg * h * d for d in dirs for h in hs for sg in (1.0, -1.0)]
+    cb = cfg.with_(batch=len(members))
+    rb = rt().Context(cb, max_steps=8192)
+    U0 = rb.init_state(np.stack(members))
+    UT, _, nb_, _ = rb.integrate(U0, T)
+    assert np.all(host(nb_) == int(host(n)[0]))
+    Rb = host(rb.kinetic_energy(UT) / rb.kinetic_energy(U0))
+    gh, gfh = host(g), host(gf)
+    gn = np.linalg.norm(gh)
+    nrm, nrm_f, rel = [], [], []
+    for i, d in enumerate(dirs):
+        an, anf = float(np.sum(gh * d)), float(np.sum(gfh * d))
+        errs, errs_f = [], []
+        for j, h in enumerate(hs):
+            k = 4 * i + 2 * j
+            fd = (Rb[k] - Rb[k + 1]) / (2 * h)
+            errs.append(abs(fd - an))
+            errs_f.append(abs(fd - anf))
+        rel.append(min(errs) / abs(an))
+        nrm.append(min(errs) / (gn * np.linalg.norm(d)))
+        nrm_f.append(min(errs_f) / (gn * np.linalg.norm(d)))
+    print("adaptive-map FD 256x512: differentiated normwise", max(nrm), "median relative", float(np.median(rel)),
+          "| frozen normwise", max(nrm_f), "| |g - g_frozen| / |g|", np.linalg.norm(gh - gfh) / gn)
+    assert max(nrm) <= 1e-5, nrm

@@ -46,6 +46,7 @@ def parse():
     ap.add_argument("--T", type=float, default=2.0)
     ap.add_argument("--interval", type=int, default=32)
     ap.add_argument("--tile", default=None, help="tile variant of both kernels (default: the library's choice)")
+    ap.add_argument("--tiles", default=None, help="STEP/ADJOINT tile variants (overrides --tile)")
     ap.add_argument("--autotune", action="store_true",
                     help="run the kernel autotuner, then keep the fastest of its pick and two fixed pairs on a "
                          "full gradient each (default: the library's measured defaults, so that a profile of "
@@ -115,6 +116,8 @@ def main():
     cfg = RTConfig(nx=args.nx, ny=args.ny)
     T = args.T
     ctx = Context(cfg, max_steps=16384, tile=args.tile)
+    if args.tiles:
+        ctx.set_tiles(*args.tiles.split("/"))
     cells = cfg.nx * cfg.ny
 
     # seed and step count

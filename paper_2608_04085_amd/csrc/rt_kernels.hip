@@ -57,16 +57,50 @@ __device__ __forceinline__ void stg(int32_t* base, uint32_t i, int32_t v) {
   *reinterpret_cast<int32_t*>(reinterpret_cast<char*>(base) + i * 4u) = v;
 }
 
+// Wavefront reductions with DPP lane permutations inside each row of 16
+// lanes (swap neighbours, swap pairs, mirror half-rows, mirror rows: after
+// the four steps every lane holds its row's result, the same in every lane
+// because each step combines a lane with its partner in both orders), then
+// the four rows' results read from lanes 0, 16, 32, 48 and combined in a
+// fixed order.  Called with the whole wavefront active; `id` fills lanes
+// whose source is inactive.
+template <int CTRL>
+__device__ __forceinline__ double dpp_perm(double v, double id) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned long long o = (unsigned long long)__double_as_longlong(id);
+  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)o, (int)(unsigned)b, CTRL, 0xf, 0xf, false);
+  const unsigned hi =
+      (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)(o >> 32), (int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+__device__ __forceinline__ double read_lane(double v, int lane) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), lane);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+constexpr int kDppQuadSwap1 = 0xB1;  // quad_perm [1, 0, 3, 2]
+constexpr int kDppQuadSwap2 = 0x4E;  // quad_perm [2, 3, 0, 1]
+constexpr int kDppHalfMirror = 0x141;
+constexpr int kDppMirror = 0x140;
+
 __device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
+  const double id = -__builtin_inf();
+  v = fmax(v, dpp_perm<kDppQuadSwap1>(v, id));
+  v = fmax(v, dpp_perm<kDppQuadSwap2>(v, id));
+  v = fmax(v, dpp_perm<kDppHalfMirror>(v, id));
+  v = fmax(v, dpp_perm<kDppMirror>(v, id));
+  return fmax(fmax(read_lane(v, 0), read_lane(v, 16)), fmax(read_lane(v, 32), read_lane(v, 48)));
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += dpp_perm<kDppQuadSwap1>(v, 0.0);
+  v += dpp_perm<kDppQuadSwap2>(v, 0.0);
+  v += dpp_perm<kDppHalfMirror>(v, 0.0);
+  v += dpp_perm<kDppMirror>(v, 0.0);
+  return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
 }
 
 template <int NT>

@@ -43,6 +43,13 @@ def test_create_rejects_bad_grid_without_gpu():
     assert L.rt_create(ctypes.byref(g), ctypes.byref(p), None, ctypes.byref(h)) == 0
     # calls that need a workspace refuse to run without one
     assert L.rt_kinetic_energy(h, ctypes.c_void_p(8), ctypes.c_void_p(8)) == -5
+    # the gradient's time-step mode: frozen by default, two valid values
+    mode = ctypes.c_int32(-1)
+    assert L.rt_get_dt_mode(h, ctypes.byref(mode)) == 0 and mode.value == rtcnop.DT_MODES["frozen"]
+    assert L.rt_set_dt_mode(h, 2) == -1 and b"dt mode" in L.rt_last_error()
+    assert L.rt_set_dt_mode(h, rtcnop.DT_MODES["differentiated"]) == 0
+    assert L.rt_get_dt_mode(h, ctypes.byref(mode)) == 0 and mode.value == 1
+    assert L.rt_set_dt_mode(None, 0) == -1
     n = ctypes.c_size_t()
     assert L.rt_workspace_bytes(h, 100, ctypes.byref(n)) == 0 and n.value > 8 * 8 * 4 * 8 * 4
     assert L.rt_destroy(h) == 0

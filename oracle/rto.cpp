@@ -54,7 +54,7 @@ constexpr int kEUnphys = -4;
 
 bool valid(const Problem* P) {
   return P && P->nx >= 3 && P->ny >= 2 && P->nb >= 1 && P->lx > 0 && P->ly > 0 && P->gamma > 1.0 &&
-         P->h > 0 && P->cfl > 0;
+         P->h > 0 && P->cfl > 0 && (P->recon == 0 || P->recon == 1);
 }
 size_t cells(const Problem* P) { return static_cast<size_t>(P->nx) * P->ny; }
 
@@ -578,7 +578,7 @@ int rto_background(const Problem* P, double* rho0, double* p0) {
   if (!valid(P) || !rho0 || !p0) return kEInval;
   for (int j = 0; j < P->ny; ++j) {
     rho0[j] = rto::rho0_at(*P, rto::yc(*P, j));
-    p0[j] = rto::p0_at(*P, rto::yc(*P, j));
+    p0[j] = rto::background_p(*P, j);
   }
   return 0;
 }

@@ -34,6 +34,7 @@ class Problem(ctypes.Structure):
         ("rho_h", ctypes.c_double), ("rho_l", ctypes.c_double),
         ("y0", ctypes.c_double), ("h", ctypes.c_double),
         ("p_int", ctypes.c_double), ("cfl", ctypes.c_double),
+        ("recon", ctypes.c_int32), ("pad", ctypes.c_int32),
     ]
 
 
@@ -107,7 +108,7 @@ class Oracle:
         p = Problem(
             nx=cfg.nx, ny=cfg.ny, nb=cfg.batch if nb is None else nb, comp_mask=cfg.comp_mask,
             lx=cfg.lx, ly=cfg.ly, gamma=cfg.gamma, g_y=cfg.g_y, rho_h=cfg.rho_h, rho_l=cfg.rho_l,
-            y0=cfg.y0, h=cfg.h, p_int=cfg.p_int, cfl=cfg.cfl,
+            y0=cfg.y0, h=cfg.h, p_int=cfg.p_int, cfl=cfg.cfl, recon=getattr(cfg, "recon", 0),
         )
         return cls(p)
 

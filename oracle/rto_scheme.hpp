@@ -27,6 +27,15 @@
 //   * Time step from the CFL condition on the state at the start of the step,
 //     dt = CFL / max over cells of max((|u|+c)/dx, (|v|+c)/dy), the last step
 //     clipped so that the run ends exactly at T.
+//   * Optional well-balanced variant (recon = 1; an extension, the paper
+//     instead subtracts an unperturbed run): the background pressure is
+//     built row by row so that p_{j+1} - p_j = g_y dy (rho_j + rho_{j+1})/2,
+//     and the y slope of the pressure is the local hydrostatic slope of the
+//     cell's own density plus a limited slope of the departures from it.
+//     The unperturbed state is then kept to round-off: the departures vanish
+//     or change sign (monotone density), the two face pressures agree, the
+//     HLLC flux of a stationary contact is the pressure alone, and its
+//     difference cancels the gravity source.
 //
 // Layout: a member's state is U[4][ny][nx] with variables
 // (rho, m_x = rho u, m_y = rho v, E) and x fastest; members follow each other.
@@ -47,6 +56,7 @@ struct Problem {
   double rho_h, rho_l, y0, h; // two-layer profile (Sec. 2.2, Eq. 5)
   double p_int;               // pressure at the interface height y0
   double cfl;
+  int recon, pad;             // recon 1: well-balanced variant (see above)
 };
 
 inline double dx_of(const Problem& P) { return P.lx / P.nx; }
@@ -70,6 +80,23 @@ inline double log_cosh(double z) {
 inline double p0_at(const Problem& P, double y) {
   const double rbar = 0.5 * (P.rho_h + P.rho_l), drho = 0.5 * (P.rho_h - P.rho_l);
   return P.p_int + P.g_y * (rbar * (y - P.y0) + drho * P.h * log_cosh((y - P.y0) / P.h));
+}
+
+// Well-balanced variant: the background pressure of every row, the closed
+// form at the bottom row's centre and then
+// p_{j+1} = p_j + g_y dy (rho0_j + rho0_{j+1}) / 2 upward.
+inline std::vector<double> p_background_rows(const Problem& P) {
+  const double dy = dy_of(P);
+  std::vector<double> p(P.ny);
+  p[0] = p0_at(P, yc(P, 0));
+  for (int j = 0; j + 1 < P.ny; ++j)
+    p[j + 1] = p[j] + P.g_y * dy * (0.5 * (rho0_at(P, yc(P, j)) + rho0_at(P, yc(P, j + 1))));
+  return p;
+}
+
+// Background pressure of row j in the selected variant.
+inline double background_p(const Problem& P, int j) {
+  return P.recon == 1 ? p_background_rows(P)[j] : p0_at(P, yc(P, j));
 }
 
 // ------------------------------------------------------------ primitive state
@@ -132,6 +159,19 @@ Prim<T> mc_slope(const Problem& P, const Prim<T>& wm, const Prim<T>& w, const Pr
   auto small_v = [tv2, r](double d) { return d * d * r <= tv2; };
   return Prim<T>{mc_slope(w.r - wm.r, wp.r - w.r, small_r), mc_slope(w.u - wm.u, wp.u - w.u, small_v),
                  mc_slope(w.v - wm.v, wp.v - w.v, small_v), mc_slope(w.p - wm.p, wp.p - w.p, small_p)};
+}
+
+// y slopes of the well-balanced variant: as mc_slope, except the pressure,
+// which is the cell's hydrostatic slope h = rho g_y dy plus the limited slope
+// of the departures from it, a' = (p - p_below) - h, b' = (p_above - p) - h.
+template <class T>
+Prim<T> mc_slope_y_balanced(const Problem& P, const Prim<T>& wm, const Prim<T>& w, const Prim<T>& wp) {
+  Prim<T> s = mc_slope(P, wm, w, wp);
+  const double tp = kTieTol * val(w.p);
+  auto small_p = [tp](double d) { return std::fabs(d) <= tp; };
+  const T h = w.r * (P.g_y * dy_of(P));
+  s.p = h + mc_slope((w.p - wm.p) - h, (wp.p - w.p) - h, small_p);
+  return s;
 }
 
 // Face-normal Riemann data: n is the normal velocity, t the tangential one.
@@ -230,7 +270,8 @@ int step_member(const Problem& P, const T* U, T* Un, D dt) {
     for (int i = 0; i < nx; ++i) {
       const Prim<T>& w = Wat(i, j);
       const Prim<T> sx = mc_slope(P, Wat((i + nx - 1) % nx, j), w, Wat((i + 1) % nx, j));
-      const Prim<T> sy = mc_slope(P, Wat(i, j - 1), w, Wat(i, j + 1));
+      const Prim<T> sy = P.recon == 1 ? mc_slope_y_balanced(P, Wat(i, j - 1), w, Wat(i, j + 1))
+                                      : mc_slope(P, Wat(i, j - 1), w, Wat(i, j + 1));
       const D hx = 0.5 * dt / dx, hy = 0.5 * dt / dy;
       Prim<T> q;
       q.r = w.r - hx * (w.u * sx.r + w.r * sx.u) - hy * (w.v * sy.r + w.r * sy.v);
@@ -348,15 +389,17 @@ T ek_anomaly(const Problem& P, const T* U, const double* ek_base) {
 
 // Initial state of one member from the velocity perturbation (u0, v0) laid
 // out [2][ny][nx]: the hydrostatic two-layer background (Sec. 2.2) plus the
-// perturbation velocity, evaluated at cell centres.  Components switched off
+// perturbation velocity, evaluated at cell centres (the pressure from
+// p_background_rows in the well-balanced variant).  Components switched off
 // by comp_mask are taken as zero.
 template <class T>
 void init_member(const Problem& P, const T* uv, T* U) {
   const int nx = P.nx, ny = P.ny, N = nx * ny;
   const bool use_u = (P.comp_mask & 1) != 0, use_v = (P.comp_mask & 2) != 0;
+  const std::vector<double> pb = P.recon == 1 ? p_background_rows(P) : std::vector<double>();
   for (int j = 0; j < ny; ++j) {
     const double y = yc(P, j);
-    const double r = rho0_at(P, y), p = p0_at(P, y);
+    const double r = rho0_at(P, y), p = P.recon == 1 ? pb[j] : p0_at(P, y);
     for (int i = 0; i < nx; ++i) {
       const int c = j * nx + i;
       const T u = use_u ? uv[c] : T(0.0);

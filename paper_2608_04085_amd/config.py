@@ -25,6 +25,10 @@ NORM_RHO_KE = 2  # C = sum rho0 (u^2+v^2)/2 dx dy   (Eq. 9)
 SET_SPHERE = 0
 SET_BALL = 1
 
+# Reconstructions.
+RECON_PRIMITIVE = 0
+RECON_BALANCED = 1
+
 # Checkpoint policies of the gradient.
 CKPT_STORE_ALL = 0
 CKPT_UNIFORM = 1
@@ -47,6 +51,11 @@ class RTConfig:
     p_int: float = 2.5
     cfl: float = 0.4
     comp_mask: int = COMP_UV
+    # 0: primitive MC reconstruction on the closed-form background (the
+    # workloads); 1: the well-balanced variant (row-balanced background and
+    # hydrostatic pressure slopes), which keeps the unperturbed state to
+    # round-off instead of relying on a subtracted baseline run
+    recon: int = RECON_PRIMITIVE
 
     @property
     def dx(self) -> float:

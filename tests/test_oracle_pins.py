@@ -15,8 +15,8 @@ from scipy import integrate
 from oracle import exact_riemann
 from oracle.rto import Oracle, OracleError, hllc, wall_pressure
 from paper_2608_04085_amd import inputs
-from paper_2608_04085_amd.config import (NORM_L2, NORM_RHO_KE, NORM_RMS, SET_BALL, SET_SPHERE,
-                                         RTConfig, paper_preset)
+from paper_2608_04085_amd.config import (NORM_L2, NORM_RHO_KE, NORM_RMS, RECON_BALANCED, RECON_PRIMITIVE,
+                                         SET_BALL, SET_SPHERE, RTConfig, paper_preset)
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -258,6 +258,74 @@ def test_hydrostatic_residual_shrinks_under_refinement():
         U, _, _, _ = o.integrate(o.init_state(np.zeros((1, 2, ny, nx))), 0.25)
         res.append(o.kinetic_energy(U)[0])
     assert res[1] < 0.5 * res[0], res
+
+
+# ------------------------------------------- well-balanced variant (recon = 1)
+def test_balanced_variant_keeps_the_unperturbed_state_to_round_off():
+    # the primitive reconstruction leaves a residual flow (above); the
+    # balanced one keeps the two-layer state at rest to round-off, on the
+    # workload physics and on the paper preset
+    for cfg in (RTConfig(nx=32, ny=128, recon=RECON_BALANCED), paper_preset(32).with_(recon=RECON_BALANCED)):
+        o = Oracle.from_config(cfg)
+        U0 = o.init_state(np.zeros((1, 2, cfg.ny, cfg.nx)))
+        U, _, n, _ = o.integrate(U0, 1.0)
+        assert n[0] > 100
+        assert np.max(np.abs(U[0, 1:3] / U[0, 0])) <= 1e-13
+        for k in (0, 3):  # density and energy, normwise
+            assert np.max(np.abs(U[0, k] - U0[0, k])) <= 1e-13 * np.max(np.abs(U0[0, k]))
+        Up, _, _, _ = Oracle.from_config(cfg.with_(recon=RECON_PRIMITIVE)).integrate(U0, 1.0)
+        assert np.max(np.abs(Up[0, 2] / Up[0, 0])) > 1e-8  # the primitive variant does move
+
+
+def test_balanced_background_is_row_balanced_and_converges_to_the_closed_form():
+    errs = []
+    for ny in (256, 512, 1024):  # dy below the interface width h = 0.01
+        cfg = RTConfig(nx=4, ny=ny, recon=RECON_BALANCED)
+        rho, p = Oracle.from_config(cfg).background()
+        np.testing.assert_allclose(np.diff(p), cfg.g_y * cfg.dy * 0.5 * (rho[1:] + rho[:-1]), rtol=0, atol=1e-13)
+        _, pc = Oracle.from_config(cfg.with_(recon=RECON_PRIMITIVE)).background()
+        assert p[0] == pc[0]
+        errs.append(np.max(np.abs(p - pc)))
+    # second order: the trapezoid rule's error of the hydrostatic integral
+    assert errs[1] < 0.3 * errs[0] and errs[2] < 0.3 * errs[1], errs
+
+
+def test_balanced_variant_without_gravity_is_the_primitive_scheme_bitwise():
+    cfg = RTConfig(nx=16, ny=24, g_y=0.0)
+    o0, o1 = Oracle.from_config(cfg), Oracle.from_config(cfg.with_(recon=RECON_BALANCED))
+    uv = inputs.seed_batch(cfg, [5], rms=3e-2)
+    U0 = o0.init_state(uv)
+    np.testing.assert_array_equal(o1.init_state(uv), U0)
+    np.testing.assert_array_equal(o1.integrate(U0, 0.2)[0], o0.integrate(U0, 0.2)[0])
+
+
+def test_balanced_variant_tangent_adjoint_and_gradient_pins():
+    cfg = RTConfig(nx=8, ny=16, recon=RECON_BALANCED)
+    o, U = _random_state(cfg, 14)
+    rng = np.random.default_rng(4)
+    dU = rng.standard_normal(U.shape)
+    w = rng.standard_normal(U.shape)
+    dt = o.cfl_dt(U)
+    _, jv = o.step_jvp(U, dU, dt)
+    vj = o.step_vjp(U, dt, w)
+    a, b = np.sum(jv * w), np.sum(dU * vj)
+    assert abs(a - b) <= 1e-12 * max(abs(a), abs(b))
+    # the gradient of R against central differences of the frozen-schedule
+    # march.  The limiter here acts on the small departures from balance, so
+    # its case boundaries lie closer together than in the primitive variant
+    # and the differences need smaller steps (h <= 1e-7 of the seed).
+    uv = inputs.seed_batch(cfg, [0], rms=1e-3)
+    R, g, n, log = o.grad_u0(uv, 0.3, cap=4096)
+    delta = np.sqrt(np.sum(uv * uv) * cfg.dx * cfg.dy)
+    for s in range(1000, 1004):
+        d = inputs.direction_batch(cfg, [s], delta)
+        an = np.sum(g * d)
+        errs = []
+        for h in (1e-6, 1e-7, 1e-8):
+            fp = o.ke_ratio_frozen(uv + h * d, log, n)[0]
+            fm = o.ke_ratio_frozen(uv - h * d, log, n)[0]
+            errs.append(abs((fp - fm) / (2 * h) - an) / abs(an))
+        assert min(errs) <= 2e-6, (s, errs)
 
 
 def test_periodic_shift_equivariance_bitwise():

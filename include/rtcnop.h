@@ -70,11 +70,21 @@ typedef struct rt_grid {
 /* Physics.  g_y < 0 points down.  The background is
  * rho0(y) = (rho_h + rho_l)/2 + (rho_h - rho_l)/2 tanh((y - y0)/h) (Eq. 5)
  * with p0 from dp0/dy = rho0 g_y and p0(y0) = p_int.  comp_mask: bit 0 = u
- * is perturbed, bit 1 = v (the paper perturbs v only, Sec. 3.1). */
+ * is perturbed, bit 1 = v (the paper perturbs v only, Sec. 3.1).
+ * recon: RT_RECON_PRIMITIVE (MC slopes of the primitives, the background
+ * in closed form at the cell centres: the scheme the workloads use), or
+ * RT_RECON_BALANCED, a well-balanced variant beyond the paper's method:
+ * the background pressure is built row by row, p_{j+1} = p_j + g_y dy
+ * (rho0_j + rho0_{j+1})/2 from the closed form at the bottom row, and the y
+ * slope of the pressure is rho g_y dy plus the MC slope of the departures
+ * from that hydrostatic slope.  The unperturbed state then stays at rest to
+ * round-off (the paper instead subtracts an unperturbed run, Sec. 3.2). */
 typedef struct rt_phys {
   double gamma, g_y, rho_h, rho_l, y0, h, p_int, cfl;
-  int32_t comp_mask, reserved;
+  int32_t comp_mask, recon;
 } rt_phys;
+
+enum { RT_RECON_PRIMITIVE = 0, RT_RECON_BALANCED = 1 };
 
 typedef struct rt_ctx rt_ctx;
 
@@ -231,8 +241,9 @@ int rt_autotune(rt_ctx* ctx, const double* U, int32_t reps, int32_t* step_tile, 
  * faster than the two-kernel step on their own (the folded kernel shares
  * the CUs less well with the concurrent re-computation); before it, grids
  * of fewer than 2^16 cells in all fold (and use 8x8 single-pass tiles),
- * larger ones use 32x8 tiles and two kernels.  Binomial checkpointing
- * always runs two kernels per step. */
+ * larger ones use 32x8 tiles and two kernels.  Binomial checkpointing,
+ * differentiated time steps (rt_set_dt_mode) and the well-balanced variant
+ * (RT_RECON_BALANCED) always run two kernels per step. */
 int rt_set_fold(rt_ctx* ctx, int32_t on);
 int rt_get_fold(const rt_ctx* ctx, int32_t* on);
 

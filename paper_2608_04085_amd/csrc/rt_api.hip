@@ -82,6 +82,7 @@ struct rt_ctx {
   double *dtd_mu = nullptr, *dtd_smax = nullptr, *dtd_mu_last = nullptr;
   int32_t* dtd_imax = nullptr;
   int32_t dtd_stride = 0;
+  double* bg_p = nullptr;  // [ny] background pressure rows of the well-balanced variant
   ~rt_ctx() {
     if (chunk_exec) (void)hipGraphExecDestroy(chunk_exec);
     if (capture_stream) (void)hipStreamDestroy(capture_stream);
@@ -102,7 +103,7 @@ namespace {
 
 struct Layout {
   size_t S0, S1, L0, L1, Z, Z2, codes, codes2, partial, rowmean, acc, ctl, flags, dt_log, nsteps, scal;
-  size_t dtd_mu, dtd_smax, dtd_imax, dtd_mu_last, total;
+  size_t dtd_mu, dtd_smax, dtd_imax, dtd_mu_last, bg_p, total;
   int32_t dtd_stride;
 };
 
@@ -141,8 +142,14 @@ Layout layout(const rt_ctx* c, int32_t max_steps) {
   L.dtd_smax = take((size_t)adjblk * c->P.nb * sizeof(double));
   L.dtd_imax = take((size_t)adjblk * c->P.nb * sizeof(int32_t));
   L.dtd_mu_last = take((size_t)c->P.nb * sizeof(double));
+  L.bg_p = take((size_t)c->P.ny * sizeof(double));
   L.total = off;
   return L;
+}
+
+// The row pressures of the well-balanced background, or null (closed form).
+const double* background_rows(const rt_ctx* c) {
+  return c->P.recon == RT_RECON_BALANCED ? c->bg_p : nullptr;
 }
 
 int need_ws(const rt_ctx* c) {
@@ -295,12 +302,15 @@ int rt_create(const rt_grid* grid, const rt_phys* phys, void* stream, rt_ctx** o
   if (!(phys->gamma > 1.0) || !(phys->h > 0) || !(phys->cfl > 0) || !(phys->rho_h > 0) || !(phys->rho_l > 0))
     return fail(RT_EINVAL, "need gamma > 1, h > 0, cfl > 0, positive densities");
   if (phys->comp_mask < 1 || phys->comp_mask > 3) return fail(RT_EINVAL, "comp_mask must be 1, 2 or 3");
+  if (phys->recon != RT_RECON_PRIMITIVE && phys->recon != RT_RECON_BALANCED)
+    return fail(RT_EINVAL, "recon must be RT_RECON_PRIMITIVE or RT_RECON_BALANCED");
   rt_ctx* c = new rt_ctx();
   Params& P = c->P;
   P.nx = grid->nx;
   P.ny = grid->ny;
   P.nb = grid->batch;
   P.comp_mask = phys->comp_mask;
+  P.recon = phys->recon;
   P.dx = grid->lx / grid->nx;
   P.dy = grid->ly / grid->ny;
   P.inv_dx = 1.0 / P.dx;
@@ -473,10 +483,13 @@ int time_kernels(rt_ctx* c, const double* U, int step_tile, int adj_tile, int re
           return rtk::launch_step(P, step_tile, m, s);
         },
         &out[1]);
-  if (e == hipSuccess) e = hipMemcpyAsync(c->Z2, c->Z, 3 * se * sizeof(double), hipMemcpyDeviceToDevice, s);
-  if (e == hipSuccess)
+  // the well-balanced variant has no folded form: out[2] repeats out[3]
+  const bool can_fold = P.recon == RT_RECON_PRIMITIVE;
+  if (e == hipSuccess && can_fold)
+    e = hipMemcpyAsync(c->Z2, c->Z, 3 * se * sizeof(double), hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess && can_fold)
     e = hipMemcpyAsync(c->codes2, c->codes, c->cells() * P.nb * sizeof(int32_t), hipMemcpyDeviceToDevice, s);
-  if (e == hipSuccess)
+  if (e == hipSuccess && can_fold)
     e = timed(
         [&](int k) {
           rtk::AdjArgs f = j;
@@ -492,6 +505,7 @@ int time_kernels(rt_ctx* c, const double* U, int step_tile, int adj_tile, int re
         },
         &out[2]);
   if (e == hipSuccess) e = timed([&](int) { return rtk::launch_adjoint(P, adj_tile, j, s); }, &out[3]);
+  if (!can_fold) out[2] = out[3];
   return e == hipSuccess ? 0 : fail(RT_EHIP, "kernel timing: %s", hipGetErrorString(e));
 }
 
@@ -528,7 +542,7 @@ int rt_autotune(rt_ctx* c, const double* U, int32_t reps, int32_t* step_tile, in
   // leaves less room on the CUs for the concurrent re-computation, which
   // costs it about 10% there relative to its time alone; so it is taken
   // only when it is more than 10% faster alone.
-  const bool fold = best_f < 0.9f * best_u;
+  const bool fold = c->P.recon == RT_RECON_PRIMITIVE && best_f < 0.9f * best_u;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc) return rc;
@@ -561,7 +575,7 @@ int rt_kernel_times(rt_ctx* c, const double* U, int32_t reps, double* out) {
   (void)hipEventDestroy(e1);
   if (rc) return rc;
   for (int k = 0; k < 4; ++k) out[k] = 1e3 * ms[k];
-  out[4] = c->fold ? out[2] : out[3];
+  out[4] = (c->fold && c->dt_mode == RT_DT_FROZEN && c->P.recon == RT_RECON_PRIMITIVE) ? out[2] : out[3];
   Flags f{};
   return read_flags(c, &f, true);
 }
@@ -606,6 +620,8 @@ int rt_set_workspace(rt_ctx* c, void* dev, size_t bytes, int32_t max_steps) {
   c->dtd_imax = reinterpret_cast<int32_t*>(w + L.dtd_imax);
   c->dtd_mu_last = reinterpret_cast<double*>(w + L.dtd_mu_last);
   c->dtd_stride = L.dtd_stride;
+  c->bg_p = reinterpret_cast<double*>(w + L.bg_p);
+  if (c->P.recon == RT_RECON_BALANCED) RT_HIP(rtk::launch_background_rows(c->P, c->bg_p, c->stream));
   RT_HIP(rtk::launch_fill_i32(reinterpret_cast<int32_t*>(c->acc), 0, 2 * ((size_t)3 * rtk::kAccRow + 1) * c->P.nb,
                               c->stream));
   RT_HIP(rtk::launch_fill_i32(reinterpret_cast<int32_t*>(c->flags), 0, sizeof(Flags) / 4, c->stream));
@@ -614,7 +630,7 @@ int rt_set_workspace(rt_ctx* c, void* dev, size_t bytes, int32_t max_steps) {
 
 int rt_init_state(rt_ctx* c, const double* uv0, double* U) {
   if (!c || !uv0 || !U) return fail(RT_EINVAL, "null argument");
-  RT_HIP(rtk::launch_init_state(c->P, uv0, U, c->stream));
+  RT_HIP(rtk::launch_init_state(c->P, uv0, U, background_rows(c), c->stream));
   return 0;
 }
 
@@ -728,7 +744,7 @@ int grad_objective(rt_ctx* c, const double* uv0, double T, const rt_ckpt_policy*
   auto state_slot = [&](size_t k) { return pool + k * se; };
 
   // forward: U^0, KE(U^0)
-  RT_HIP(rtk::launch_init_state(P, uv0, c->S0, s));
+  RT_HIP(rtk::launch_init_state(P, uv0, c->S0, background_rows(c), s));
   RT_HIP(rtk::launch_reduce(P, 1, c->S0, nullptr, c->partial, c->red_blocks, c->sc(1), s));
 
   int interval = 1;
@@ -789,6 +805,8 @@ int grad_objective(rt_ctx* c, const double* uv0, double T, const rt_ckpt_policy*
     return 0;
   };
   const bool dtd = c->dt_mode == RT_DT_DIFFERENTIATED;
+  // the folded sweep serves the frozen steps of the primitive variant
+  const bool use_fold = c->fold && !dtd && P.recon == RT_RECON_PRIMITIVE;
   auto adjoint = [&](const double* Un, int n) -> int {
     rtk::AdjArgs a{};
     a.U = Un;
@@ -917,7 +935,7 @@ int grad_objective(rt_ctx* c, const double* uv0, double T, const rt_ckpt_policy*
         return rc;
       }
       for (int n = hi - 1; n >= base; --n)
-        if (int rc = (c->fold && !dtd) ? adjoint_folded(st(k, n), n) : adjoint(st(k, n), n)) return rc;
+        if (int rc = use_fold ? adjoint_folded(st(k, n), n) : adjoint(st(k, n), n)) return rc;
       if (two) RT_HIP(hipEventRecord(c->seg_free[k & 1], s));
     }
     if (int rc = finish_folded()) return rc;

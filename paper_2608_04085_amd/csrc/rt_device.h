@@ -39,6 +39,7 @@ struct Params {
   double dx, dy, inv_dx, inv_dy;
   double gamma, gm1, inv_gm1, g_y, cfl;
   double rho_h, rho_l, y0, h, p_int;
+  int recon, pad;  // recon 1: well-balanced variant (mc_p_balanced, row-balanced background)
 };
 
 // Primitive state plus the reciprocal density, which later steps reuse.
@@ -164,6 +165,23 @@ RT_DEV W4 mc4(const Params& P, const W4& m, const W4& c, const W4& p, int& codes
     codes = mc_code(ar, br, sar, sbr) | (mc_code(au, bu, sau, sbu) << 2) | (mc_code(av, bv, sav, sbv) << 4) |
             (mc_code(ap, bp, sap, sbp) << 6);
   return s;
+}
+
+// y slope of the pressure in the well-balanced variant: the cell's own
+// hydrostatic slope h = rho g_y dy plus the MC slope of the departures from
+// it, a' = (p_c - p_m) - h and b' = (p_p - p_c) - h (tie tolerance as for the
+// pressure in mc4).  Replaces s.p (and, if CODES, the pressure's case in
+// codes).  For a row-balanced state with monotone density a' and b' vanish
+// or differ in sign, so the two pressures at a face agree and the pressure
+// difference across the cell cancels the gravity source.
+template <bool CODES>
+RT_DEV void mc_p_balanced(const Params& P, const W4& m, const W4& c, const W4& p, W4& s, int& codes) {
+  const double h = c.r * (P.g_y * P.dy);
+  const double tp = kTieTol * c.p;
+  const double a = (c.p - m.p) - h, b = (p.p - c.p) - h;
+  const bool sa = fabs(a) <= tp, sb = fabs(b) <= tp;
+  s.p = h + mc_value(a, b, sa, sb);
+  if (CODES) codes = (codes & ~(3 << 6)) | (mc_code(a, b, sa, sb) << 6);
 }
 
 // Ghost cells of the y walls: mirror of the adjacent interior cell with the

@@ -120,7 +120,10 @@ enum TileId {
 void tile_dims(int tile, int* tx, int* ty, int* nt);
 int step_blocks(const Params& P, int tile);  // blocks per member
 
-hipError_t launch_init_state(const Params& P, const double* uv0, double* U, hipStream_t s);
+// prow: background pressure per row (well-balanced variant) or null.
+hipError_t launch_init_state(const Params& P, const double* uv0, double* U, const double* prow, hipStream_t s);
+// Background pressure per row of the well-balanced variant into prow[ny].
+hipError_t launch_background_rows(const Params& P, double* prow, hipStream_t s);
 hipError_t launch_step(const Params& P, int tile, const StepArgs& a, hipStream_t s);
 // Adjoint of one step: kernel A (face and predictor adjoints -> Z, codes),
 // then kernel B (limiter gather -> lambda^n), or kernel A alone

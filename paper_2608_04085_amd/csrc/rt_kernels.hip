@@ -236,8 +236,9 @@ __device__ __forceinline__ W4 ldQ(const LDS& S, int k, int x, int y) {
 }
 
 // Phase B: slopes and predictor on the cross-shaped halo-1 region.  If
-// codes_out is given, the MC cases of the tile cells are stored there.
-template <int TX, int TY, int NT, class LDS>
+// codes_out is given, the MC cases of the tile cells are stored there.  BAL:
+// the well-balanced pressure slopes in y (mc_p_balanced).
+template <int TX, int TY, int NT, bool BAL, class LDS>
 __device__ int tile_predict(const Params& P, double dt, int x0, int y0, LDS& S, int32_t* codes_out) {
   constexpr int QX = TX + 2, QY = TY + 2;
   const double hx = 0.5 * dt * P.inv_dx, hy = 0.5 * dt * P.inv_dy, hg = 0.5 * dt * P.g_y;
@@ -250,7 +251,8 @@ __device__ int tile_predict(const Params& P, double dt, int x0, int y0, LDS& S, 
     const W4 wc = ldW(S, lx + 1, ly + 1);
     int cx, cy;
     const W4 sx = mc4<true>(P, ldW(S, lx, ly + 1), wc, ldW(S, lx + 2, ly + 1), cx);
-    const W4 sy = mc4<true>(P, ldW(S, lx + 1, ly), wc, ldW(S, lx + 1, ly + 2), cy);
+    W4 sy = mc4<true>(P, ldW(S, lx + 1, ly), wc, ldW(S, lx + 1, ly + 2), cy);
+    if constexpr (BAL) mc_p_balanced<true>(P, ldW(S, lx + 1, ly), wc, ldW(S, lx + 1, ly + 2), sy, cy);
     const W4 q = predict(P, wc, sx, sy, hx, hy, hg);
     S.Q[0][ly][lx] = q.r;
     S.Q[1][ly][lx] = q.u;
@@ -314,7 +316,7 @@ struct StepLDS {
   double Q[12][QY][QX];
 };
 
-template <int TX, int TY, int NT>
+template <int TX, int TY, int NT, bool BAL>
 __global__ __launch_bounds__(NT) void k_step(Params P, StepArgs a) {
   static_assert(NT >= TX * TY && NT % 64 == 0, "one thread per tile cell at least");
   __shared__ StepLDS<TX, TY> S;
@@ -402,7 +404,8 @@ __global__ __launch_bounds__(NT) void k_step(Params P, StepArgs a) {
       const W4 wc = ldW(S, lx + 1, ly + 1);
       int unused;
       const W4 sx = mc4<false>(P, ldW(S, lx, ly + 1), wc, ldW(S, lx + 2, ly + 1), unused);
-      const W4 sy = mc4<false>(P, ldW(S, lx + 1, ly), wc, ldW(S, lx + 1, ly + 2), unused);
+      W4 sy = mc4<false>(P, ldW(S, lx + 1, ly), wc, ldW(S, lx + 1, ly + 2), unused);
+      if constexpr (BAL) mc_p_balanced<false>(P, ldW(S, lx + 1, ly), wc, ldW(S, lx + 1, ly + 2), sy, unused);
       const W4 q = predict(P, wc, sx, sy, hx, hy, hg);
       S.Q[0][ly][lx] = q.r;
       S.Q[1][ly][lx] = q.u;
@@ -575,7 +578,9 @@ struct GatherSrc {
 // lambda^n at cell (i, j): the limiter gather of the slope cotangents of
 // the cell and its four neighbours through the MC cases, the wall ghost
 // terms, the adjoint of the primitive map at U^n, plus the identity and
-// gravity-source terms of the update.
+// gravity-source terms of the update.  BAL: the well-balanced pressure
+// slopes' dependence on the cell's density.
+template <bool BAL>
 __device__ __forceinline__ void lambda_at(const Params& P, const GatherSrc& g, int i, int j, double out[4]) {
   const int nx = P.nx, ny = P.ny;
   const size_t N = (size_t)nx * ny;
@@ -608,6 +613,13 @@ __device__ __forceinline__ void lambda_at(const Params& P, const GatherSrc& g, i
     const int c0 = ldg(codes, idx) >> 8;
     double s0[4] = {ldg(Z + 8 * N, idx), ldg(Z + 9 * N, idx), ldg(Z + 10 * N, idx), ldg(Z + 11 * N, idx)};
     add_slope_terms(s0, c0, 1.0, -1.0, wb);
+    if constexpr (BAL) {
+      // the balanced pressure slope h + MC(a' , b') also depends on the
+      // cell's density through h = rho g_y dy, in h and in a', b'
+      double wa, wbb;
+      mc_weights((c0 >> 6) & 3, wa, wbb);
+      wb[0] += P.g_y * P.dy * (1.0 - wa - wbb) * s0[3];
+    }
     if (j > 0) {
       const uint32_t cm = idx - (uint32_t)nx;
       double sm[4] = {ldg(Z + 8 * N, cm), ldg(Z + 9 * N, cm), ldg(Z + 10 * N, cm), ldg(Z + 11 * N, cm)};
@@ -684,10 +696,11 @@ struct AdjLDS<TX, TY, true> : AdjCore<TX, TY> {
 // which is d<lambda^{n+1}, U^{n+1}>/d dt of the update with gravity
 // source (the flux terms once from the explicit dt, once from the dt in
 // the source's use of rho^{n+1}) and of the MUSCL-Hancock predictor.
-template <int TX, int TY, int NT, bool FOLD, bool DTD>
+template <int TX, int TY, int NT, bool FOLD, bool DTD, bool BAL>
 __global__ __launch_bounds__(NT) void k_adj_a(Params P, AdjArgs a) {
   static_assert(NT >= TX * TY && NT % 64 == 0, "one thread per tile cell at least");
   static_assert(!(FOLD && DTD), "the step-size derivative needs the two-kernel form");
+  static_assert(!(FOLD && BAL), "the well-balanced variant runs the two-kernel form");
   constexpr int QX = AdjCore<TX, TY>::QX, QY = AdjCore<TX, TY>::QY;
   __shared__ AdjLDS<TX, TY, FOLD> S;
 
@@ -750,7 +763,7 @@ __global__ __launch_bounds__(NT) void k_adj_a(Params P, AdjArgs a) {
       const bool corner = (lx == 0 || lx == QX - 1) && (ly == 0 || ly == QY - 1);
       if (qy >= 0 && qy < ny && !corner) {
         const int ux = x0 - 1 + lx, qx = wrapx(ux, nx);
-        lambda_at(P, g, qx, qy, l);
+        lambda_at<false>(P, g, qx, qy, l);
         if (lx >= 1 && lx <= TX && ly >= 1 && ly <= TY && ux < nx) {
           const uint32_t cc = (uint32_t)(qy * nx + qx);
           stg(lam_out, cc, l[0]);
@@ -766,7 +779,7 @@ __global__ __launch_bounds__(NT) void k_adj_a(Params P, AdjArgs a) {
     }
   }
   __syncthreads();
-  bad |= tile_predict<TX, TY, NT>(P, dt, x0, y0, S, a.codes + (size_t)b * N);
+  bad |= tile_predict<TX, TY, NT, BAL>(P, dt, x0, y0, S, a.codes + (size_t)b * N);
   __syncthreads();
 
   // lambda-tilde (rho entry shifted by the momentum source) at halo-1
@@ -941,6 +954,7 @@ __global__ __launch_bounds__(NT) void k_adj_a(Params P, AdjArgs a) {
 }
 
 // ----------------------------------------------------------------- adjoint B
+template <bool BAL>
 __global__ __launch_bounds__(256) void k_adj_b(Params P, AdjArgs a) {
   const int nx = P.nx;
   const size_t N = (size_t)nx * P.ny;
@@ -956,7 +970,7 @@ __global__ __launch_bounds__(256) void k_adj_b(Params P, AdjArgs a) {
   g.pass = a.nsteps_limit && a.dt_index >= a.nsteps_limit[b];
   g.dt = g.pass ? 0.0 : a.dt[(size_t)b * a.dt_stride + a.dt_index];
   double l[4];
-  lambda_at(P, g, (int)(idx % nx), (int)(idx / nx), l);
+  lambda_at<BAL>(P, g, (int)(idx % nx), (int)(idx / nx), l);
   double* Lo = a.lam + (size_t)b * 4 * N;
   stg(Lo, idx, l[0]);
   stg(Lo + N, idx, l[1]);
@@ -1004,14 +1018,29 @@ __global__ __launch_bounds__(256) void k_dt_correct(Params P, AdjArgs a) {
 }
 
 // ----------------------------------------------------------------- small kernels
-__global__ void k_init_state(Params P, const double* uv0, double* U) {
+// Background pressure of the well-balanced variant, one value per row: the
+// closed form at the bottom row's centre, then
+// p_{j+1} = p_j + g_y dy (rho0_j + rho0_{j+1}) / 2 upward.  One thread.
+__global__ void k_background_rows(Params P, double* prow) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  double p = p0_at(P, 0.5 * P.dy);
+  prow[0] = p;
+  for (int j = 0; j + 1 < P.ny; ++j) {
+    p = p + P.g_y * P.dy * (0.5 * (rho0_at(P, (j + 0.5) * P.dy) + rho0_at(P, (j + 1.5) * P.dy)));
+    prow[j + 1] = p;
+  }
+}
+
+// prow: the background pressure per row (well-balanced variant), or null
+// for the closed form.
+__global__ void k_init_state(Params P, const double* uv0, double* U, const double* prow) {
   const size_t N = (size_t)P.nx * P.ny;
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int b = blockIdx.y;
   if (idx >= N) return;
   const int j = (int)(idx / P.nx);
   const double y = (j + 0.5) * P.dy;
-  const double r = rho0_at(P, y), p = p0_at(P, y);
+  const double r = rho0_at(P, y), p = prow ? prow[j] : p0_at(P, y);
   const double* q = uv0 + (size_t)b * 2 * N;
   const double u = (P.comp_mask & 1) ? q[idx] : 0.0;
   const double v = (P.comp_mask & 2) ? q[N + idx] : 0.0;
@@ -1340,7 +1369,10 @@ int step_blocks(const Params& P, int tile) {
 template <int TX, int TY, int NT>
 static hipError_t launch_step_t(const Params& P, const StepArgs& a, hipStream_t s) {
   dim3 grid((P.nx + TX - 1) / TX, (P.ny + TY - 1) / TY, P.nb);
-  hipLaunchKernelGGL((k_step<TX, TY, NT>), grid, dim3(NT), 0, s, P, a);
+  if (P.recon == 1)
+    hipLaunchKernelGGL((k_step<TX, TY, NT, true>), grid, dim3(NT), 0, s, P, a);
+  else
+    hipLaunchKernelGGL((k_step<TX, TY, NT, false>), grid, dim3(NT), 0, s, P, a);
   return hipGetLastError();
 }
 
@@ -1361,20 +1393,29 @@ hipError_t launch_step(const Params& P, int tile, const StepArgs& a, hipStream_t
 template <int TX, int TY, int NT>
 static hipError_t launch_adj_t(const Params& P, const AdjArgs& a, hipStream_t s) {
   dim3 grid((P.nx + TX - 1) / TX, (P.ny + TY - 1) / TY, P.nb);
+  const bool bal = P.recon == 1;
+  if (a.fold.Z != nullptr && (bal || a.dtd.mu != nullptr)) return hipErrorInvalidValue;
   if (a.dtd.mu != nullptr) {
-    if (a.fold.Z != nullptr || a.dtd.count != (int)(grid.x * grid.y) || a.dtd.stride < a.dtd.count)
-      return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_adj_a<TX, TY, NT, false, true>), grid, dim3(NT), 0, s, P, a);
+    if (a.dtd.count != (int)(grid.x * grid.y) || a.dtd.stride < a.dtd.count) return hipErrorInvalidValue;
+    if (bal)
+      hipLaunchKernelGGL((k_adj_a<TX, TY, NT, false, true, true>), grid, dim3(NT), 0, s, P, a);
+    else
+      hipLaunchKernelGGL((k_adj_a<TX, TY, NT, false, true, false>), grid, dim3(NT), 0, s, P, a);
   } else if (a.fold.Z != nullptr) {
-    hipLaunchKernelGGL((k_adj_a<TX, TY, NT, true, false>), grid, dim3(NT), 0, s, P, a);
+    hipLaunchKernelGGL((k_adj_a<TX, TY, NT, true, false, false>), grid, dim3(NT), 0, s, P, a);
+  } else if (bal) {
+    hipLaunchKernelGGL((k_adj_a<TX, TY, NT, false, false, true>), grid, dim3(NT), 0, s, P, a);
   } else {
-    hipLaunchKernelGGL((k_adj_a<TX, TY, NT, false, false>), grid, dim3(NT), 0, s, P, a);
+    hipLaunchKernelGGL((k_adj_a<TX, TY, NT, false, false, false>), grid, dim3(NT), 0, s, P, a);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_adj_gather(const Params& P, const AdjArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_adj_b, cells_grid(P, (size_t)P.nx * P.ny), dim3(256), 0, s, P, a);
+  if (P.recon == 1)
+    hipLaunchKernelGGL(k_adj_b<true>, cells_grid(P, (size_t)P.nx * P.ny), dim3(256), 0, s, P, a);
+  else
+    hipLaunchKernelGGL(k_adj_b<false>, cells_grid(P, (size_t)P.nx * P.ny), dim3(256), 0, s, P, a);
   return hipGetLastError();
 }
 
@@ -1406,8 +1447,13 @@ hipError_t launch_adjoint(const Params& P, int tile, const AdjArgs& a, hipStream
   return launch_adj_gather(P, a, s);
 }
 
-hipError_t launch_init_state(const Params& P, const double* uv0, double* U, hipStream_t s) {
-  hipLaunchKernelGGL(k_init_state, cells_grid(P, (size_t)P.nx * P.ny), dim3(256), 0, s, P, uv0, U);
+hipError_t launch_background_rows(const Params& P, double* prow, hipStream_t s) {
+  hipLaunchKernelGGL(k_background_rows, dim3(1), dim3(64), 0, s, P, prow);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_state(const Params& P, const double* uv0, double* U, const double* prow, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_state, cells_grid(P, (size_t)P.nx * P.ny), dim3(256), 0, s, P, uv0, U, prow);
   return hipGetLastError();
 }
 

@@ -39,7 +39,7 @@ class RtPhys(ctypes.Structure):
     _fields_ = [("gamma", ctypes.c_double), ("g_y", ctypes.c_double), ("rho_h", ctypes.c_double),
                 ("rho_l", ctypes.c_double), ("y0", ctypes.c_double), ("h", ctypes.c_double),
                 ("p_int", ctypes.c_double), ("cfl", ctypes.c_double), ("comp_mask", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("recon", ctypes.c_int32)]
 
 
 class RtCkptPolicy(ctypes.Structure):
@@ -160,7 +160,8 @@ class Context:
         self.max_steps = int(max_steps)
         L = load()
         grid = RtGrid(cfg.nx, cfg.ny, cfg.batch, 0, cfg.lx, cfg.ly)
-        phys = RtPhys(cfg.gamma, cfg.g_y, cfg.rho_h, cfg.rho_l, cfg.y0, cfg.h, cfg.p_int, cfg.cfl, cfg.comp_mask, 0)
+        phys = RtPhys(cfg.gamma, cfg.g_y, cfg.rho_h, cfg.rho_l, cfg.y0, cfg.h, cfg.p_int, cfg.cfl, cfg.comp_mask,
+                      cfg.recon)
         h = ctypes.c_void_p()
         _check(L.rt_create(ctypes.byref(grid), ctypes.byref(phys), self._stream(), ctypes.byref(h)), "rt_create")
         self._h = h

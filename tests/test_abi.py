@@ -40,6 +40,10 @@ def test_create_rejects_bad_grid_without_gpu():
     p.gamma = 1.0
     assert L.rt_create(ctypes.byref(g), ctypes.byref(p), None, ctypes.byref(h)) == -1
     p.gamma = 1.4
+    p.recon = 2
+    assert L.rt_create(ctypes.byref(g), ctypes.byref(p), None, ctypes.byref(h)) == -1
+    assert b"recon" in L.rt_last_error()
+    p.recon = 0
     assert L.rt_create(ctypes.byref(g), ctypes.byref(p), None, ctypes.byref(h)) == 0
     # calls that need a workspace refuse to run without one
     assert L.rt_kinetic_energy(h, ctypes.c_void_p(8), ctypes.c_void_p(8)) == -5

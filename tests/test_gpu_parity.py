@@ -609,3 +609,68 @@ def test_differentiated_dt_at_full_size_against_fd_of_the_adaptive_march():
     print("adaptive-map FD 256x512: differentiated normwise", max(nrm), "median relative", float(np.median(rel)),
           "| frozen normwise", max(nrm_f), "| |g - g_frozen| / |g|", np.linalg.norm(gh - gfh) / gn)
     assert max(nrm) <= 1e-5, nrm
+
+
+# ------------------------------------------------------ well-balanced variant
+BAL_CASES = [RTConfig(nx=70, ny=37, recon=1), paper_preset(32).with_(recon=1), RTConfig(nx=48, ny=40, batch=3, recon=1)]
+
+
+@pytest.mark.parametrize("cfg", BAL_CASES, ids=["70x37", "paper32", "48x40x3"])
+def test_balanced_variant_matches_oracle(cfg):
+    o = Oracle.from_config(cfg)
+    uv = inputs.seed_batch(cfg, range(cfg.batch), rms=1e-2)
+    r = rt().Context(cfg, max_steps=4096)
+    U0o = o.init_state(uv)
+    U0 = host(r.init_state(uv))
+    assert normwise(U0, U0o) <= 1e-14
+    # 100 steps at the oracle's CFL steps, from the oracle's state
+    U, Uo = torch.from_numpy(U0o).cuda(), U0o
+    for _ in range(100):
+        dt = o.cfl_dt(Uo)
+        Uo = o.step(Uo, dt)
+        U = r.step(U, torch.from_numpy(dt).cuda())
+    assert normwise(host(U), Uo) <= 1e-10
+    # frozen and differentiated gradients
+    T = 0.05
+    Ro, go, no, _ = o.grad_u0(uv, T)
+    R, g, n = r.grad_u0(uv, T, rt().Policy(CKPT_UNIFORM, 5))
+    np.testing.assert_array_equal(host(n), no)
+    np.testing.assert_allclose(host(R), Ro, rtol=1e-12)
+    assert normwise(host(g), go) <= 1e-9
+    # differentiated steps, on white-noise fields (one cell clearly fastest)
+    r.set_dt_mode("differentiated")
+    uw = _white(cfg, [0.05] * cfg.batch, seed=23)
+    Ra, ga, na = o.grad_adaptive(uw, T)
+    R2, g2, n2 = r.grad_u0(uw, T, rt().Policy(CKPT_REVOLVE, 1, pool_bytes=3 * 8 * 4 * cfg.cells * cfg.batch))
+    np.testing.assert_array_equal(host(n2), na)
+    assert normwise(host(g2), ga) <= 1e-9
+
+
+def test_balanced_variant_keeps_the_rest_state_on_gpu():
+    cfg = RTConfig(nx=64, ny=128, recon=1)
+    r = rt().Context(cfg, max_steps=4096)
+    U0 = r.init_state(np.zeros((1, 2, cfg.ny, cfg.nx)))
+    UT, _, n, _ = r.integrate(U0, 2.0)
+    Uh, U0h = host(UT), host(U0)
+    assert int(host(n)[0]) > 1000
+    assert np.max(np.abs(Uh[0, 1:3] / Uh[0, 0])) <= 1e-13
+    for k in (0, 3):
+        assert np.max(np.abs(Uh[0, k] - U0h[0, k])) <= 1e-13 * np.max(np.abs(U0h[0, k]))
+    # the same march with the primitive reconstruction leaves a residual flow
+    r0 = rt().Context(cfg.with_(recon=0), max_steps=4096)
+    U1 = host(r0.integrate(r0.init_state(np.zeros((1, 2, cfg.ny, cfg.nx))), 2.0)[0])
+    assert np.max(np.abs(U1[0, 2] / U1[0, 0])) > 1e-8
+
+
+def test_balanced_variant_tiles_are_bitwise_identical():
+    cfg = RTConfig(nx=70, ny=37, recon=1)
+    uv = inputs.seed_batch(cfg, [2], rms=1e-2)
+    r = rt().Context(cfg, max_steps=1024)
+    out = []
+    for t in ("32x8", "16x16", "8x8w"):
+        r.set_tiles(t, t)
+        R, g, _ = r.grad_u0(uv, 0.05, rt().Policy(CKPT_STORE_ALL, 1))
+        out.append((host(R), host(g)))
+    for R, g in out[1:]:
+        np.testing.assert_array_equal(R, out[0][0])
+        np.testing.assert_array_equal(g, out[0][1])

@@ -22,7 +22,8 @@ HIPCC_FLAGS = [
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-ffp-contract=off",  # every FP64 operation rounds as written: results do not depend on inlining
+    "-ffp-contract=on",  # a*b+c within one expression becomes one fused FP64 FMA, decided per source
+    # expression, so every kernel that evaluates the same expression rounds it the same way
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall",
     "-Wno-unused-function",

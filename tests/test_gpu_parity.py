@@ -422,7 +422,9 @@ def test_ek_field_matches_oracle():
     o = Oracle.from_config(cfg)
     U = o.integrate(o.init_state(inputs.seed_batch(cfg, [0, 1], rms=1e-2)), 0.05)[0]
     r = rt().Context(cfg, max_steps=64)
-    np.testing.assert_array_equal(host(r.ek_field(torch.from_numpy(U))), o.ek_field(U))
+    # the kernels fuse m_x^2 + m_y^2 into one FMA (rounded once), the oracle
+    # rounds each operation: the two agree to an ulp or two
+    np.testing.assert_allclose(host(r.ek_field(torch.from_numpy(U))), o.ek_field(U), rtol=5e-16, atol=0)
 
 
 @pytest.mark.parametrize("cfg,T", [(paper_preset(32), 0.2), (RTConfig(nx=24, ny=30, batch=2), 0.08)],

@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--interval", type=int, default=32)
     ap.add_argument("--tile", default=None, help="tile variant of both kernels (default: the library's choice)")
     ap.add_argument("--tiles", default=None, help="STEP/ADJOINT tile variants (overrides --tile)")
+    ap.add_argument("--fold", type=int, choices=(0, 1), default=None,
+                    help="1: folded reverse sweep (one kernel per adjoint step), 0: two kernels (default: the library's choice)")
     ap.add_argument("--autotune", action="store_true",
                     help="run the kernel autotuner, then keep the fastest of its pick and two fixed pairs on a "
                          "full gradient each (default: the library's measured defaults, so that a profile of "
@@ -118,6 +120,8 @@ def main():
     ctx = Context(cfg, max_steps=16384, tile=args.tile)
     if args.tiles:
         ctx.set_tiles(*args.tiles.split("/"))
+    if args.fold is not None:
+        ctx.set_fold(bool(args.fold))
     cells = cfg.nx * cfg.ny
 
     # seed and step count

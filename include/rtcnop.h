@@ -270,7 +270,8 @@ int rt_get_dt_mode(const rt_ctx* ctx, int32_t* mode);
  * a step with the CFL reduction (as in the march), out[2] one folded
  * adjoint step (one kernel that also completes the previous step's limiter
  * gather), out[3] one rt_step_adjoint (two kernels), out[4] the adjoint step
- * in the sweep's current mode (out[2] or out[3]).  out holds 5 doubles.
+ * in the sweep's current mode (out[2] or out[3]).  The well-balanced variant
+ * has no folded form: there out[2] repeats out[3].  out holds 5 doubles.
  * Synchronises the stream; the workspace serves as scratch. */
 int rt_kernel_times(rt_ctx* ctx, const double* U, int32_t reps, double* out);
 

@@ -256,6 +256,7 @@ def main():
                         f"snapshot every {args.interval} steps, one projected-gradient iteration per step",
             "nx": cfg.nx, "ny": cfg.ny, "batch": 1, "T": T, "nsteps": nt_mean, "tile": ctx.tile,
             "adjoint_folded": ctx.fold,
+            "dt_in_gradient": ctx.dt_mode, "reconstruction": "primitive MC" if cfg.recon == 0 else "well-balanced",
             "sweep_tuning_seconds": {k: round(v, 4) for k, v in tuning.items()},
         },
         "grad_iters_per_s": 1.0 / per_iter,

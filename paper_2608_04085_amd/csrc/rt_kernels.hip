@@ -155,10 +155,6 @@ __device__ void block_argmax(double& s, int& i, double* rs, int* ri) {
   for (int k = 1; k < NT / 64; ++k) argmax_merge(s, i, rs[k], ri[k]);
 }
 
-__device__ __forceinline__ double load_coherent(const double* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 __device__ __forceinline__ double rho0_at(const Params& P, double y) {
   return 0.5 * (P.rho_h + P.rho_l) + 0.5 * (P.rho_h - P.rho_l) * tanh((y - P.y0) / P.h);
 }
@@ -1166,7 +1162,7 @@ __global__ void k_copy_final(Params P, const Ctl* ctl, const double* A, const do
   U[(size_t)b * N4 + idx] = src[(size_t)b * N4 + idx];
 }
 
-__global__ void k_copy_meta(Params P, const Ctl* ctl, double* t_out, int32_t* n_out, const double* ls, int32_t lcap,
+__global__ void k_copy_meta(Params, const Ctl* ctl, double* t_out, int32_t* n_out, const double* ls, int32_t lcap,
                             double* ld, int32_t dcap) {
   const int b = blockIdx.x;
   const int n = ctl[b].nsteps;

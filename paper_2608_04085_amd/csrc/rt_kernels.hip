@@ -192,23 +192,42 @@ __device__ __forceinline__ void tile_of_block(int& bx, int& by) {
 
 // ----------------------------------------------------------------- LDS tile helpers
 // Phase A: primitives of the tile + halo 2.  Returns nonzero on an
-// unphysical interior state.
+// unphysical interior state.  A thread's cells are addressed first and all
+// their loads issued before any is used, so the memory latencies of its
+// passes overlap instead of adding up; halo rows beyond the wall ghosts load
+// a clamped in-range cell that is never used.
 template <int TX, int TY, int NT, class LDS>
 __device__ int tile_prims(const Params& P, const double* U, size_t N, int x0, int y0, LDS& S) {
-  constexpr int AX = TX + 4, AY = TY + 4;
+  constexpr int AX = TX + 4, AY = TY + 4, IT = (AX * AY + NT - 1) / NT;
   int bad = 0;
+  uint32_t c[IT];
 #pragma unroll
-  for (int it = 0; it < (AX * AY + NT - 1) / NT; ++it) {
+  for (int it = 0; it < IT; ++it) {
+    const int k = (int)threadIdx.x + it * NT;
+    const int kk = k < AX * AY ? k : AX * AY - 1;
+    const int lx = kk % AX, ly = kk / AX;
+    const int gx = wrapx(x0 - 2 + lx, P.nx);
+    const int gy = y0 - 2 + ly;
+    const int sy = gy < 0 ? 0 : (gy >= P.ny ? P.ny - 1 : gy);
+    c[it] = (uint32_t)(sy * P.nx + gx);
+  }
+  double r[IT], mx[IT], my[IT], E[IT];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    r[it] = ldg(U, c[it]);
+    mx[it] = ldg(U + N, c[it]);
+    my[it] = ldg(U + 2 * N, c[it]);
+    E[it] = ldg(U + 3 * N, c[it]);
+  }
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
     const int k = (int)threadIdx.x + it * NT;
     if (k >= AX * AY) break;
     const int lx = k % AX, ly = k / AX;
-    const int gx = wrapx(x0 - 2 + lx, P.nx);
     const int gy = y0 - 2 + ly;
     W4 w{1.0, 0.0, 0.0, 1.0, 1.0};
     if (gy >= -1 && gy <= P.ny) {
-      const int sy = gy < 0 ? 0 : (gy >= P.ny ? P.ny - 1 : gy);
-      const uint32_t c = (uint32_t)(sy * P.nx + gx);
-      w = cons_to_prim(P, ldg(U, c), ldg(U + N, c), ldg(U + 2 * N, c), ldg(U + 3 * N, c));
+      w = cons_to_prim(P, r[it], mx[it], my[it], E[it]);
       if (gy >= 0 && gy < P.ny) bad |= unphysical(w);
       if (gy < 0) w = ghost_bottom(P, w);
       else if (gy >= P.ny) w = ghost_top(P, w);

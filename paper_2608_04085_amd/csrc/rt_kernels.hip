@@ -250,42 +250,86 @@ __device__ __forceinline__ W4 ldQ(const LDS& S, int k, int x, int y) {
   return W4{S.Q[4 * k + 0][y][x], S.Q[4 * k + 1][y][x], S.Q[4 * k + 2][y][x], S.Q[4 * k + 3][y][x], 0.0};
 }
 
-// Phase B: slopes and predictor on the cross-shaped halo-1 region.  If
-// codes_out is given, the MC cases of the tile cells are stored there.  BAL:
-// the well-balanced pressure slopes in y (mc_p_balanced).
-template <int TX, int TY, int NT, bool BAL, class LDS>
-__device__ int tile_predict(const Params& P, double dt, int x0, int y0, LDS& S, int32_t* codes_out) {
+// Phase B: slopes and predictor on the cross-shaped halo-1 region.  BAL:
+// the well-balanced pressure slopes in y (mc_p_balanced).  CODES: the MC
+// cases of the tile cells go to codes_out.
+//
+// One position k of the halo-1 region, computed without branches: a corner,
+// a row outside the domain or an index past the region is computed from
+// in-range LDS values (k clamped) and reported as not valid, so the caller
+// stores nothing for it.
+template <int TX, int TY, bool BAL, bool CODES, class LDS>
+__device__ __forceinline__ bool predict_at(const Params& P, const LDS& S, int k, int y0, double hx, double hy,
+                                           double hg, W4& q, W4& sx, W4& sy, int& cx, int& cy) {
   constexpr int QX = TX + 2, QY = TY + 2;
+  const int kc = k < QX * QY ? k : QX * QY - 1;
+  const int lx = kc % QX, ly = kc / QX;
+  const int gy = y0 - 1 + ly;
+  const bool valid = k < QX * QY && !((lx == 0 || lx == QX - 1) && (ly == 0 || ly == QY - 1)) && gy >= 0 &&
+                     gy < P.ny;
+  const W4 wc = ldW(S, lx + 1, ly + 1);
+  sx = mc4<CODES>(P, ldW(S, lx, ly + 1), wc, ldW(S, lx + 2, ly + 1), cx);
+  sy = mc4<CODES>(P, ldW(S, lx + 1, ly), wc, ldW(S, lx + 1, ly + 2), cy);
+  if constexpr (BAL) mc_p_balanced<CODES>(P, ldW(S, lx + 1, ly), wc, ldW(S, lx + 1, ly + 2), sy, cy);
+  q = predict(P, wc, sx, sy, hx, hy, hg);
+  return valid;
+}
+
+// Stores one position's predicted state and slopes (and its MC cases for a
+// tile cell); returns nonzero if a face state would be unphysical.
+template <int TX, int TY, bool CODES, class LDS>
+__device__ __forceinline__ int predict_store(const Params& P, LDS& S, int k, int x0, int y0, const W4& q,
+                                             const W4& sx, const W4& sy, int cx, int cy, int32_t* codes_out) {
+  constexpr int QX = TX + 2;
+  const int lx = k % QX, ly = k / QX;
+  S.Q[0][ly][lx] = q.r;
+  S.Q[1][ly][lx] = q.u;
+  S.Q[2][ly][lx] = q.v;
+  S.Q[3][ly][lx] = q.p;
+  S.Q[4][ly][lx] = sx.r;
+  S.Q[5][ly][lx] = sx.u;
+  S.Q[6][ly][lx] = sx.v;
+  S.Q[7][ly][lx] = sx.p;
+  S.Q[8][ly][lx] = sy.r;
+  S.Q[9][ly][lx] = sy.u;
+  S.Q[10][ly][lx] = sy.v;
+  S.Q[11][ly][lx] = sy.p;
+  if constexpr (CODES) {
+    if (lx >= 1 && lx <= TX && ly >= 1 && ly <= TY) {
+      const int gx = x0 - 1 + lx;
+      if (gx < P.nx) stg(codes_out, (uint32_t)((y0 - 1 + ly) * P.nx + gx), cx | (cy << 8));
+    }
+  }
+  const double hr = 0.5 * fabs(sx.r), hp = 0.5 * fabs(sx.p), vr = 0.5 * fabs(sy.r), vp = 0.5 * fabs(sy.p);
+  return !(q.r - hr > 0.0) || !(q.p - hp > 0.0) || !(q.r - vr > 0.0) || !(q.p - vp > 0.0);
+}
+
+// The region has more positions than the block has threads for the 256-
+// thread tiles, so some wavefronts take two.  With PAIR those compute both
+// positions in one branch-free stretch (their instruction streams
+// interleave and hide each other's latency) instead of one after the
+// other; whether a wavefront has a second position is uniform across it.
+// PAIR costs registers: the step kernel has them to spare, the adjoint
+// kernel would drop to two wavefronts per SIMD.
+template <int TX, int TY, int NT, bool BAL, bool CODES, bool PAIR, class LDS>
+__device__ int tile_predict(const Params& P, double dt, int x0, int y0, LDS& S, int32_t* codes_out) {
+  constexpr int QN = (TX + 2) * (TY + 2);
   const double hx = 0.5 * dt * P.inv_dx, hy = 0.5 * dt * P.inv_dy, hg = 0.5 * dt * P.g_y;
   int bad = 0;
-  for (int k = threadIdx.x; k < QX * QY; k += NT) {
-    const int lx = k % QX, ly = k / QX;
-    if ((lx == 0 || lx == QX - 1) && (ly == 0 || ly == QY - 1)) continue;
-    const int gy = y0 - 1 + ly;
-    if (gy < 0 || gy >= P.ny) continue;
-    const W4 wc = ldW(S, lx + 1, ly + 1);
-    int cx, cy;
-    const W4 sx = mc4<true>(P, ldW(S, lx, ly + 1), wc, ldW(S, lx + 2, ly + 1), cx);
-    W4 sy = mc4<true>(P, ldW(S, lx + 1, ly), wc, ldW(S, lx + 1, ly + 2), cy);
-    if constexpr (BAL) mc_p_balanced<true>(P, ldW(S, lx + 1, ly), wc, ldW(S, lx + 1, ly + 2), sy, cy);
-    const W4 q = predict(P, wc, sx, sy, hx, hy, hg);
-    S.Q[0][ly][lx] = q.r;
-    S.Q[1][ly][lx] = q.u;
-    S.Q[2][ly][lx] = q.v;
-    S.Q[3][ly][lx] = q.p;
-    S.Q[4][ly][lx] = sx.r;
-    S.Q[5][ly][lx] = sx.u;
-    S.Q[6][ly][lx] = sx.v;
-    S.Q[7][ly][lx] = sx.p;
-    S.Q[8][ly][lx] = sy.r;
-    S.Q[9][ly][lx] = sy.u;
-    S.Q[10][ly][lx] = sy.v;
-    S.Q[11][ly][lx] = sy.p;
-    const double hr = 0.5 * fabs(sx.r), hp = 0.5 * fabs(sx.p), vr = 0.5 * fabs(sy.r), vp = 0.5 * fabs(sy.p);
-    bad |= !(q.r - hr > 0.0) || !(q.p - hp > 0.0) || !(q.r - vr > 0.0) || !(q.p - vp > 0.0);
-    if (codes_out && lx >= 1 && lx <= TX && ly >= 1 && ly <= TY) {
-      const int gx = x0 - 1 + lx;
-      if (gx < P.nx) stg(codes_out, (uint32_t)(gy * P.nx + gx), cx | (cy << 8));
+  for (int k = threadIdx.x; k < QN; k += (PAIR ? 2 : 1) * NT) {
+    const int wave_first = k - (int)(threadIdx.x & 63);
+    W4 q, sx, sy;
+    int cx = 0, cy = 0;
+    if (PAIR && wave_first + NT < QN) {
+      W4 q2, sx2, sy2;
+      int cx2 = 0, cy2 = 0;
+      const bool v1 = predict_at<TX, TY, BAL, CODES>(P, S, k, y0, hx, hy, hg, q, sx, sy, cx, cy);
+      const bool v2 = predict_at<TX, TY, BAL, CODES>(P, S, k + NT, y0, hx, hy, hg, q2, sx2, sy2, cx2, cy2);
+      if (v1) bad |= predict_store<TX, TY, CODES>(P, S, k, x0, y0, q, sx, sy, cx, cy, codes_out);
+      if (v2) bad |= predict_store<TX, TY, CODES>(P, S, k + NT, x0, y0, q2, sx2, sy2, cx2, cy2, codes_out);
+    } else {
+      if (predict_at<TX, TY, BAL, CODES>(P, S, k, y0, hx, hy, hg, q, sx, sy, cx, cy))
+        bad |= predict_store<TX, TY, CODES>(P, S, k, x0, y0, q, sx, sy, cx, cy, codes_out);
     }
   }
   return bad;
@@ -390,7 +434,6 @@ __global__ __launch_bounds__(NT) void k_step(Params P, StepArgs a) {
   }
 
   // phase A: primitives of the tile + halo 2
-  constexpr int QX = StepLDS<TX, TY>::QX, QY = StepLDS<TX, TY>::QY;
   int bad = tile_prims<TX, TY, NT>(P, U, N, x0, y0, S);
   if (a.ctl) {
     // the same member for the whole block, so the return is uniform
@@ -409,35 +452,7 @@ __global__ __launch_bounds__(NT) void k_step(Params P, StepArgs a) {
   __syncthreads();
 
   // phase B: slopes and predictor on the cross-shaped halo-1 region
-  {
-    const double hx = 0.5 * dt * P.inv_dx, hy = 0.5 * dt * P.inv_dy, hg = 0.5 * dt * P.g_y;
-    for (int k = tid; k < QX * QY; k += NT) {
-      const int lx = k % QX, ly = k / QX;
-      if ((lx == 0 || lx == QX - 1) && (ly == 0 || ly == QY - 1)) continue;
-      const int qy = y0 - 1 + ly;
-      if (qy < 0 || qy >= ny) continue;
-      const W4 wc = ldW(S, lx + 1, ly + 1);
-      int unused;
-      const W4 sx = mc4<false>(P, ldW(S, lx, ly + 1), wc, ldW(S, lx + 2, ly + 1), unused);
-      W4 sy = mc4<false>(P, ldW(S, lx + 1, ly), wc, ldW(S, lx + 1, ly + 2), unused);
-      if constexpr (BAL) mc_p_balanced<false>(P, ldW(S, lx + 1, ly), wc, ldW(S, lx + 1, ly + 2), sy, unused);
-      const W4 q = predict(P, wc, sx, sy, hx, hy, hg);
-      S.Q[0][ly][lx] = q.r;
-      S.Q[1][ly][lx] = q.u;
-      S.Q[2][ly][lx] = q.v;
-      S.Q[3][ly][lx] = q.p;
-      S.Q[4][ly][lx] = sx.r;
-      S.Q[5][ly][lx] = sx.u;
-      S.Q[6][ly][lx] = sx.v;
-      S.Q[7][ly][lx] = sx.p;
-      S.Q[8][ly][lx] = sy.r;
-      S.Q[9][ly][lx] = sy.u;
-      S.Q[10][ly][lx] = sy.v;
-      S.Q[11][ly][lx] = sy.p;
-      const double hr = 0.5 * fabs(sx.r), hp = 0.5 * fabs(sx.p), vr = 0.5 * fabs(sy.r), vp = 0.5 * fabs(sy.p);
-      bad |= !(q.r - hr > 0.0) || !(q.p - hp > 0.0) || !(q.r - vr > 0.0) || !(q.p - vp > 0.0);
-    }
-  }
+  bad |= tile_predict<TX, TY, NT, BAL, false, true>(P, dt, x0, y0, S, nullptr);
   __syncthreads();
 
   // phase C: every face of the tile once (x faces, then y faces).  The x
@@ -794,7 +809,7 @@ __global__ __launch_bounds__(NT) void k_adj_a(Params P, AdjArgs a) {
     }
   }
   __syncthreads();
-  bad |= tile_predict<TX, TY, NT, BAL>(P, dt, x0, y0, S, a.codes + (size_t)b * N);
+  bad |= tile_predict<TX, TY, NT, BAL, true, false>(P, dt, x0, y0, S, a.codes + (size_t)b * N);
   __syncthreads();
 
   // lambda-tilde (rho entry shifted by the momentum source) at halo-1

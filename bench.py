@@ -99,7 +99,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the independent members of a "
-              f"batch shard across GPUs without communication, see DESIGN.md)", file=sys.stderr)
+              f"batch shard across GPUs without communication)", file=sys.stderr)
         sys.exit(2)
     import torch
 

@@ -66,8 +66,7 @@ def drive(nx: int, ny: int, B: int, K: int, step_tile: str, adj_tile: str):
     else:
         rt.set_tiles(step_tile, adj_tile)
     times = rt.kernel_times(U, reps=K)
-    with open(os.path.join(ROOT, "gpurun_out", f"drive_tiles_{nx}x{ny}x{B}.json"), "w") as f:
-        json.dump({"tiles": rt.tile, "fold": rt.fold, "times_us": times}, f)
+    print(json.dumps({"grid": f"{nx}x{ny}x{B}", "tiles": rt.tile, "fold": rt.fold, "times_us": times}), flush=True)
     n = COPY_BYTES // 8
     a = torch.empty(n, dtype=torch.float64, device="cuda").fill_(1.0)
     flush = torch.empty(n, dtype=torch.float64, device="cuda").fill_(2.0)  # evicts a from the last-level cache

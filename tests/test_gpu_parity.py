@@ -676,3 +676,19 @@ def test_balanced_variant_tiles_are_bitwise_identical():
     for R, g in out[1:]:
         np.testing.assert_array_equal(R, out[0][0])
         np.testing.assert_array_equal(g, out[0][1])
+
+
+def test_balanced_variant_objective_J_with_differentiated_steps_matches_oracle():
+    # the paper's objective on the paper preset with both options on
+    cfg = paper_preset(16).with_(nx=40, ny=24, batch=2, recon=1)
+    T = 0.05
+    o = Oracle.from_config(cfg)
+    uv = _white(cfg, (0.05, 0.02), seed=24)
+    ekb = o.baseline_ek(T)
+    Jo, go, no = o.grad_adaptive(uv, T, ekb)
+    r = rt().Context(cfg, max_steps=1024)
+    r.set_dt_mode("differentiated")
+    J, g, n = r.grad_ek_anomaly(uv, T, torch.from_numpy(ekb), rt().Policy(CKPT_UNIFORM, 4))
+    np.testing.assert_array_equal(host(n), no)
+    np.testing.assert_allclose(host(J), Jo, rtol=1e-9)
+    assert normwise(host(g), go) <= 1e-9

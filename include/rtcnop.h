@@ -105,7 +105,8 @@ enum { RT_SET_SPHERE = 0, RT_SET_BALL = 1 };
 
 /* Create a context for one grid / physics / stream.  Validates the numbers
  * (nx >= 3, ny >= 2, nx * ny < 2^28, batch >= 1, positive lengths,
- * gamma > 1, h > 0, cfl > 0).  No device work. */
+ * gamma > 1, h > 0, cfl > 0, comp_mask 1..3, recon one of RT_RECON_*).  No
+ * device work. */
 int rt_create(const rt_grid* grid, const rt_phys* phys, void* stream, rt_ctx** out);
 int rt_destroy(rt_ctx* ctx);
 int rt_set_stream(rt_ctx* ctx, void* stream);
@@ -119,7 +120,9 @@ int rt_workspace_bytes(const rt_ctx* ctx, int32_t max_steps, size_t* bytes);
 int rt_set_workspace(rt_ctx* ctx, void* dev, size_t bytes, int32_t max_steps);
 
 /* Initial state (Sec. 2.2 and 3.1): U = background + velocity perturbation
- * uv0 ([B][2][ny][nx]) at cell centres; masked components are taken as 0. */
+ * uv0 ([B][2][ny][nx]) at cell centres; masked components are taken as 0.
+ * With RT_RECON_BALANCED the background pressure is the row-balanced one
+ * (see rt_phys). */
 int rt_init_state(rt_ctx* ctx, const double* uv0, double* U);
 
 /* CFL time step of each member's state (unclipped): dt[B] on the device. */
@@ -151,7 +154,8 @@ int rt_step_adjoint(rt_ctx* ctx, const double* U, const double* dt, const double
 /* R[B] = KE(U(T))/KE(U(0)) for the initial perturbation uv0, and its
  * gradient dR/d(u0, v0) ([B][2][ny][nx], Euclidean, with respect to the
  * array entries) by the discrete adjoint with the forward run's time steps
- * held fixed.  nsteps[B] (device, may be NULL) receives the step counts.
+ * held fixed (or differentiated: rt_set_dt_mode).  nsteps[B] (device, may
+ * be NULL) receives the step counts.
  * Synchronises the stream.  RT_ENOMEM if the pool cannot hold the policy's
  * snapshots; RT_EINVAL if KE(0) = 0. */
 int rt_grad_u0(rt_ctx* ctx, const double* uv0, double T, const rt_ckpt_policy* policy, double* R,
@@ -173,8 +177,9 @@ int rt_ek_anomaly(rt_ctx* ctx, const double* U, const double* ek_base, double* J
 
 /* J[B] of Eq. 8 for the perturbation uv0 marched to time T, and its
  * gradient dJ/d(u0, v0) ([B][2][ny][nx]) by the discrete adjoint with the
- * forward run's time steps held fixed (Sec. 3.4), under the same checkpoint
- * policies and with the same kernels as rt_grad_u0.  ek_base is the
+ * forward run's time steps held fixed (Sec. 3.4; or differentiated:
+ * rt_set_dt_mode), under the same checkpoint policies and with the same
+ * kernels as rt_grad_u0.  ek_base is the
  * baseline field (rt_ek_field of the unperturbed march to T).  A zero
  * perturbation is allowed (J and the gradient are then those at the
  * baseline).  Synchronises the stream; errors as rt_grad_u0. */

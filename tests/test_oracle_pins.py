@@ -130,6 +130,24 @@ def test_cfl_step_count_of_the_64x128_workload():
     assert t[0] == 2.0 and 1150 <= n[0] <= 1250
 
 
+def test_stored_long_march_gradient_is_the_oracles():
+    # The stored 64x128 gradient fixture (written by make_oracle_gradients.py
+    # from the oracle) belongs to the oracle as it stands: same step count
+    # and R from a plain forward run; its inner products are those of the
+    # stored sample with each direction's entries there bounded by |g| |d|.
+    ref = _golden("oracle_gradient_64x128_T2.txt")
+    cfg = RTConfig(nx=int(ref["nx"]), ny=int(ref["ny"]))
+    o = Oracle.from_config(cfg)
+    uv = inputs.seed_batch(cfg, [0], rms=1e-3)
+    U0 = o.init_state(uv)
+    UT, t, n, _ = o.integrate(U0, ref["T"])
+    assert int(n[0]) == int(ref["nsteps"])
+    assert (o.kinetic_energy(UT) / o.kinetic_energy(U0))[0] == ref["R"]
+    assert len(ref["gd"]) == len(ref["dir_seeds"]) == 8 and len(ref["idx"]) == len(ref["gval"]) == 64
+    assert np.max(np.abs(ref["gval"])) == ref["gmax"]
+    assert ref["gmax"] <= ref["gnorm"]
+
+
 # ------------------------------------------------------------ whole-step pins
 def test_stationary_contact_and_shear_preserved_exactly():
     cfg = RTConfig(nx=16, ny=16, g_y=0.0)
@@ -413,6 +431,40 @@ def test_step_jacobian_matches_central_differences():
     h = 1e-6
     fd = (o.step(U + h * d, dt) - o.step(U - h * d, dt)) / (2 * h)
     assert np.max(np.abs(fd - jv)) <= 1e-6 * np.max(np.abs(jv))
+
+
+def test_step_adjoint_reaches_two_cells_and_is_local():
+    # Each face's predicted states use the MC slopes of the two cells beside
+    # it, whose stencils reach one cell further, and a cell's update sees its
+    # four faces: the step depends on the box of cells within two of a cell,
+    # walls included (the ghost rows mirror interior rows).  So a cotangent
+    # on a window gives an adjoint supported on the window grown by exactly
+    # two cells, and on a block of the grid with the same spacing the
+    # block's own adjoint equals the grid's around the window.
+    cfg = RTConfig(nx=48, ny=64)
+    o, U = _random_state(cfg, 14)
+    dt = o.cfl_dt(U)
+    size, w = 32, 8
+    x0 = (size - w) // 2
+    for j0, wy0, shift in ((0, 0, 16), (16, 12, -5), (cfg.ny - size, size - w, 3)):
+        Ur = np.ascontiguousarray(np.roll(U, shift, axis=3))
+        lam_next = np.zeros_like(Ur)
+        lam_next[:, :, j0 + wy0 : j0 + wy0 + w, x0 : x0 + w] = np.random.default_rng(j0).standard_normal((1, 4, w, w))
+        lam = o.step_vjp(Ur, dt, lam_next)
+
+        def outside(r):
+            m = np.ones(lam.shape[2:], dtype=bool)
+            m[max(j0 + wy0 - r, 0) : j0 + wy0 + w + r, x0 - r : x0 + w + r] = False
+            return m
+
+        assert np.count_nonzero(lam[:, :, outside(2)]) == 0
+        assert np.count_nonzero(lam[:, :, outside(1)]) > 0
+        sub = cfg.with_(nx=size, ny=size, lx=size * cfg.dx, ly=size * cfg.dy)
+        ref = Oracle.from_config(sub).step_vjp(np.ascontiguousarray(Ur[:, :, j0 : j0 + size, :size]), dt,
+                                               np.ascontiguousarray(lam_next[:, :, j0 : j0 + size, :size]))
+        ya, yb = max(wy0 - 4, 0), min(wy0 + w + 4, size)
+        np.testing.assert_array_equal(lam[:, :, j0 + ya : j0 + yb, x0 - 4 : x0 + w + 4],
+                                      ref[:, :, ya:yb, x0 - 4 : x0 + w + 4])
 
 
 @pytest.mark.parametrize("nx,ny,T", [(8, 16, 0.3), (16, 32, 0.15)])

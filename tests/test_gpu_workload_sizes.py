@@ -1,0 +1,348 @@
+"""GPU parity at the full sizes of the ensemble, CNOP-search and
+high-resolution workloads, in the launch configurations those workloads use
+(default tiles, one launch per step for the whole batch, binomial
+checkpointing under their memory caps): sampled outputs against the oracle
+where it finishes in seconds, and properties that hold at any size where it
+cannot (bitwise agreement of checkpoint policies and of batched and solo
+runs, conservation, central differences of the march).
+
+Tolerances as in test_gpu_parity.py: state 1e-10 after a few steps, KE ratio
+1e-8, adjoint step 1e-12 against the oracle, gradient 1e-9 against the
+oracle's.  Central differences of marches this long are limited by the
+limiter and Riemann-solver decisions they straddle: they are held to 1e-4
+normwise here (1e-5 for the 256 x 512 gradient workload in
+test_gpu_parity.py).
+"""
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+import torch
+
+from oracle.rto import Oracle, lib
+from paper_2608_04085_amd import inputs
+from paper_2608_04085_amd.config import CKPT_REVOLVE, CKPT_UNIFORM, RTConfig
+
+pytestmark = pytest.mark.gpu
+
+
+def rt():
+    from paper_2608_04085_amd import rtcnop
+    return rtcnop
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def normwise(a, b):
+    return max(np.max(np.abs(a[:, k] - b[:, k])) / max(np.max(np.abs(b[:, k])), 1e-300) for k in range(a.shape[1]))
+
+
+@pytest.fixture(autouse=True)
+def _oracle_loaded_and_cache_released():
+    lib()  # load the oracle once before any test calls it from threads
+    yield
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+def revolve_pool(r, budget_bytes):
+    """A checkpoint pool of as many whole states as fit in budget_bytes."""
+    state = 8 * 4 * r.cfg.cells * r.cfg.batch
+    return torch.empty(max(2, budget_bytes // state) * state + 256, dtype=torch.uint8, device=r.device)
+
+
+def frozen_fd(cfg, members, logs, steps):
+    """KE(T)/KE(0) of each row of `members` marched with the step sizes of
+    the run it perturbs: logs[i] (length steps[i]), then dt = 0, which leaves
+    a state unchanged, until the longest schedule ends."""
+    cb = cfg.with_(batch=len(members))
+    rb = rt().Context(cb, max_steps=8)
+    nmax = int(max(steps))
+    dts = np.zeros((nmax, cb.batch))
+    for i, (lg, n) in enumerate(zip(logs, steps)):
+        dts[:n, i] = lg[:n]
+    dts = torch.from_numpy(dts).to(rb.device)
+    U = rb.init_state(np.stack(members))
+    ke0 = rb.kinetic_energy(U)
+    Un = torch.empty_like(U)
+    for k in range(nmax):
+        rb.step(U, dts[k], out=Un)
+        U, Un = Un, U
+    return host(rb.kinetic_energy(U) / ke0)
+
+
+def fd_error(g, d, Rp, Rm, h):
+    """|FD - <g,d>| / (|g| |d|) for the central difference (Rp - Rm) / 2h."""
+    an = float(np.sum(g * d))
+    return abs((Rp - Rm) / (2 * h) - an) / (np.linalg.norm(g) * np.linalg.norm(d))
+
+
+def window_adjoint(r, cfg, U, dt, j0, wy0, shift, size=64, w=16, seed=0):
+    """One adjoint step at full size with lambda^{n+1} nonzero only on a
+    w x w window, against the oracle's adjoint of the same step on the
+    size x size block of the grid around it.  The block has the grid's
+    spacing; its own edges (periodic in x, walls in y) differ from the full
+    grid only where they are not the full grid's walls, and the adjoint
+    there reaches 2 cells, so cells within w + 2r of the window's centre
+    agree.  Coordinates are taken after rolling x by `shift` (the scheme is
+    periodic in x), so that a window can straddle the seam.  Returns the
+    normwise difference on the window grown by 4 cells and the number of
+    nonzero entries of the full-grid result outside the window grown by 3."""
+    Ur = np.ascontiguousarray(np.roll(U, shift, axis=3))
+    lam_next = np.zeros_like(Ur)
+    x0 = (size - w) // 2
+    rng = np.random.default_rng(seed)
+    lam_next[:, :, j0 + wy0 : j0 + wy0 + w, x0 : x0 + w] = rng.standard_normal((1, 4, w, w))
+    lam = host(r.step_adjoint(torch.from_numpy(Ur), torch.from_numpy(dt), torch.from_numpy(lam_next)))
+    sub = cfg.with_(nx=size, ny=size, lx=size * cfg.dx, ly=size * cfg.dy, batch=1)
+    assert sub.dx == cfg.dx and sub.dy == cfg.dy
+    ref = Oracle.from_config(sub).step_vjp(np.ascontiguousarray(Ur[:, :, j0 : j0 + size, :size]), dt,
+                                           np.ascontiguousarray(lam_next[:, :, j0 : j0 + size, :size]))
+    ya, yb = max(wy0 - 4, 0), min(wy0 + w + 4, size)
+    err = normwise(lam[:, :, j0 + ya : j0 + yb, x0 - 4 : x0 + w + 4], ref[:, :, ya:yb, x0 - 4 : x0 + w + 4])
+    outside = np.ones(lam.shape[2:], dtype=bool)
+    outside[max(j0 + wy0 - 3, 0) : j0 + wy0 + w + 3, x0 - 3 : x0 + w + 3] = False
+    return err, int(np.count_nonzero(lam[:, :, outside]))
+
+
+def test_ensemble_128x256x64_matches_oracle_and_solo_runs():
+    # 64 members (32 Gaussian seeds, 32 single Fourier modes) at velocity L2
+    # norm 1e-3, T = 2, all members in one launch per step.
+    cfg = RTConfig(nx=128, ny=256, batch=64)
+    uv = inputs.ensemble_batch(cfg, 1e-3)
+    r = rt().Context(cfg, max_steps=4096)
+    U0 = r.init_state(uv)
+    UT, t, n, log = r.integrate(U0, 2.0, log_cap=4096)
+    R = host(r.kinetic_energy(UT) / r.kinetic_energy(U0))
+    assert np.all(host(t) == 2.0)
+
+    # every member: mass, x momentum and E + rho*phi (phi = -g_y y) are
+    # conserved by the walls-and-gravity scheme to round-off
+    y = (torch.arange(cfg.ny, dtype=torch.float64, device=UT.device) + 0.5) * cfg.dy
+    phi = (-cfg.g_y * y)[:, None]
+
+    def invariants(U):
+        return torch.stack([U[:, 0].sum((1, 2)), U[:, 1].sum((1, 2)), (U[:, 3] + U[:, 0] * phi).sum((1, 2))])
+
+    I0, I1 = host(invariants(U0)), host(invariants(UT))
+    print("ensemble invariants: mass", np.max(np.abs(I1[0] - I0[0]) / I0[0]),
+          "m_x", np.max(np.abs(I1[1] - I0[1]) / I0[0]), "energy", np.max(np.abs(I1[2] - I0[2]) / I0[2]))
+    assert np.max(np.abs(I1[0] - I0[0]) / I0[0]) <= 1e-12
+    assert np.max(np.abs(I1[1] - I0[1]) / I0[0]) <= 1e-12
+    assert np.max(np.abs(I1[2] - I0[2]) / I0[2]) <= 1e-12
+
+    # sampled members against the oracle (one Gaussian, one Fourier mode
+    # kx = 7 at phase pi/2) and against solo GPU runs
+    o = Oracle.from_config(cfg.with_(batch=1))
+    solo = rt().Context(cfg.with_(batch=1), max_steps=4096)
+    sampled = (3, 45)
+    with ThreadPoolExecutor(len(sampled)) as ex:  # the oracle's C calls release the GIL
+        runs = list(ex.map(lambda b: o.integrate(o.init_state(uv[b : b + 1]), 2.0, cap=4096), sampled))
+    for b, (UoT, to, no, logo) in zip(sampled, runs):
+        Uo0 = o.init_state(uv[b : b + 1])
+        Ro = o.kinetic_energy(UoT) / o.kinetic_energy(Uo0)
+        err_state = normwise(host(UT)[b : b + 1], UoT)
+        print(f"ensemble member {b}: steps {int(no[0])} R {Ro[0]:.6g} rel {abs(R[b] - Ro[0]) / abs(Ro[0]):.3g} "
+              f"state {err_state:.3g}")
+        assert int(host(n)[b]) == int(no[0])
+        np.testing.assert_allclose(host(log)[b, : no[0]], logo[0, : no[0]], rtol=1e-10)
+        assert abs(R[b] - Ro[0]) / abs(Ro[0]) <= 1e-8
+        assert err_state <= 1e-9
+        Us, _, ns, _ = solo.integrate(solo.init_state(uv[b : b + 1]), 2.0)
+        np.testing.assert_array_equal(host(Us)[0], host(UT)[b])
+        assert int(host(ns)[0]) == int(host(n)[b])
+
+
+def test_cnop_512x1024x8_steps_match_oracle():
+    # the CNOP search's batch of 8 restarts (velocity L2 norm 1e-3)
+    cfg = RTConfig(nx=512, ny=1024, batch=8)
+    uv = inputs.seed_batch(cfg, range(8), l2=1e-3)
+    o = Oracle.from_config(cfg.with_(batch=1))
+    r = rt().Context(cfg, max_steps=64)
+    U = r.init_state(uv)
+    for _ in range(5):
+        U = r.step(U)
+
+    def oracle_member(b):
+        Uo = o.init_state(uv[b : b + 1])
+        for _ in range(5):
+            Uo = o.step(Uo, o.cfl_dt(Uo))
+        return Uo
+
+    with ThreadPoolExecutor(8) as ex:
+        Uo = np.concatenate(list(ex.map(oracle_member, range(8))))
+    err = normwise(host(U), Uo)
+    print("512x1024x8, 5 steps: normwise", err)
+    assert err <= 1e-10
+
+
+def test_cnop_512x1024x8_gradient_revolve_uniform_and_fd():
+    # T = 1 with binomial checkpointing under 16 GiB (128 states of the
+    # batch), as the search runs it; the same gradient from snapshots every
+    # 32 steps and the two-stream sweep must agree to the bit; then one
+    # seeded direction per restart by central differences.
+    cfg = RTConfig(nx=512, ny=1024, batch=8)
+    T = 1.0
+    delta = 1e-3
+    uv = inputs.seed_batch(cfg, range(8), l2=delta)
+    r = rt().Context(cfg, max_steps=8192)
+    UT, _, n_fwd, log = r.integrate(r.init_state(uv), T, log_cap=8192)
+    steps = host(n_fwd)
+    # the adjoint of one step on a restart's state at T (developed
+    # interface), sampled on windows at the interface and the bottom wall
+    o1 = Oracle.from_config(cfg.with_(batch=1))
+    r1 = rt().Context(cfg.with_(batch=1), max_steps=8)
+    U3 = host(UT)[3:4]
+    dt3 = o1.cfl_dt(U3)
+    for j0, wy0, shift in ((cfg.ny // 2 - 32, 24, -100), (cfg.ny // 2 - 64, 40, 7), (0, 0, 200)):
+        e, stray = window_adjoint(r1, cfg.with_(batch=1), U3, dt3, j0, wy0, shift, seed=j0 + 1)
+        print(f"512x1024 restart 3 at T: adjoint window rows {j0 + wy0}..{j0 + wy0 + 15}: {e:.3g}, stray {stray}")
+        assert e <= 1e-12
+        assert stray == 0
+    del UT
+    pool = revolve_pool(r, 16 * 2**30)
+    R, g, n = r.grad_u0(uv, T, rt().Policy(CKPT_REVOLVE, 1), pool=pool)
+    del pool
+    np.testing.assert_array_equal(host(n), steps)
+    nmax = int(steps.max())
+    upool = torch.empty(r.pool_bytes(CKPT_UNIFORM, 32, nmax) + 256, dtype=torch.uint8, device=r.device)
+    R2, g2, _ = r.grad_u0(uv, T, rt().Policy(CKPT_UNIFORM, 32), pool=upool)
+    del upool
+    np.testing.assert_array_equal(host(R2), host(R))
+    np.testing.assert_array_equal(host(g2), host(g))
+
+    gh = host(g)
+    logs = host(log)
+    hs = (1e-5, 1e-6, 1e-7)
+    dirs = [inputs.direction_batch(cfg.with_(batch=1), [2000 + b], delta)[0] for b in range(8)]
+    members, mlogs, msteps = [], [], []
+    for b in range(8):
+        for h in hs:
+            for sg in (1.0, -1.0):
+                members.append(uv[b] + sg * h * dirs[b])
+                mlogs.append(logs[b])
+                msteps.append(int(steps[b]))
+    Rb = frozen_fd(cfg, members, mlogs, msteps)
+    per_h = np.array([[fd_error(gh[b], dirs[b], Rb[2 * len(hs) * b + 2 * j], Rb[2 * len(hs) * b + 2 * j + 1], h)
+                       for j, h in enumerate(hs)] for b in range(8)])
+    errs = per_h.min(axis=1).tolist()
+    print("512x1024x8 T=1: steps", steps.tolist(), "R", host(R).tolist())
+    print("FD normwise per restart and h", per_h.tolist())
+    # The march takes ~1e12 limiter and Riemann-solver decisions here, so a
+    # central difference straddles case boundaries at every step size (its
+    # error falls with h down to the round-off floor); the best of the three
+    # steps lies between 1e-7 and 4e-5 over these restarts.
+    assert max(errs) <= 1e-4, errs
+
+
+def test_grad_1024x2048_T3_steps_adjoint_and_fd():
+    cfg = RTConfig(nx=1024, ny=2048)
+    T = 3.0
+    uv = inputs.seed_batch(cfg, [0], rms=1e-3)
+    o = Oracle.from_config(cfg)
+    r = rt().Context(cfg, max_steps=32768)
+
+    # a few steps against the oracle at full size
+    Uo = o.init_state(uv)
+    U = r.init_state(uv)
+    for _ in range(4):
+        Uo = o.step(Uo, o.cfl_dt(Uo))
+        U = r.step(U)
+    err = normwise(host(U), Uo)
+    print("1024x2048, 4 steps: normwise", err)
+    assert err <= 1e-10
+
+    # one adjoint step at full size, sampled on windows at the bottom wall
+    # across the periodic seam, at the interface and at the top wall
+    dt = o.cfl_dt(Uo)
+    for j0, wy0, shift in ((0, 0, 32), (cfg.ny // 2 - 32, 24, -500), (cfg.ny - 64, 48, -777)):
+        e, stray = window_adjoint(r, cfg, Uo, dt, j0, wy0, shift, seed=j0)
+        print(f"1024x2048 adjoint window rows {j0 + wy0}..{j0 + wy0 + 15}: normwise {e:.3g}, stray {stray}")
+        assert e <= 1e-12
+        assert stray == 0
+
+    # the gradient under a 64 GiB binomial-checkpointing budget (1024
+    # states); its objective is the forward run's, to the bit
+    U0 = r.init_state(uv)
+    UT, _, n_fwd, log = r.integrate(U0, T, log_cap=32768)
+    R_fwd = host(r.kinetic_energy(UT) / r.kinetic_energy(U0))
+    steps = int(host(n_fwd)[0])
+    pool = revolve_pool(r, 64 * 2**30)
+    R, g, n = r.grad_u0(uv, T, rt().Policy(CKPT_REVOLVE, 1), pool=pool)
+    del pool
+    assert int(host(n)[0]) == steps
+    np.testing.assert_array_equal(host(R), R_fwd)
+    UTh = host(UT)
+    del UT, U0
+    dtT = o.cfl_dt(UTh)
+    for j0, wy0, shift in ((cfg.ny // 2 - 32, 24, 300), (cfg.ny // 2 - 96, 40, -3), (cfg.ny - 64, 48, 0)):
+        e, stray = window_adjoint(r, cfg, UTh, dtT, j0, wy0, shift, seed=j0 + 2)
+        print(f"1024x2048 at T: adjoint window rows {j0 + wy0}..{j0 + wy0 + 15}: normwise {e:.3g}, stray {stray}")
+        assert e <= 1e-12
+        assert stray == 0
+
+    # one seeded direction by central differences of the frozen schedule
+    delta = float(np.sqrt(np.sum(uv * uv) * cfg.dx * cfg.dy))
+    d = inputs.direction_batch(cfg, [3000], delta)[0]
+    hs = (1e-5, 1e-6, 1e-7)
+    gh = host(g)[0]
+    members = [uv[0] + sg * h * d for h in hs for sg in (1.0, -1.0)]
+    lg = host(log)[0]
+    Rb = frozen_fd(cfg, members, [lg] * len(members), [steps] * len(members))
+    errs = [fd_error(gh, d, Rb[2 * j], Rb[2 * j + 1], h) for j, h in enumerate(hs)]
+    print("1024x2048 T=3: steps", steps, "R", float(host(R)[0]), "FD normwise per h", errs,
+          "<g,d>/(|g||d|)", float(np.sum(gh * d) / (np.linalg.norm(gh) * np.linalg.norm(d))))
+    # 29k steps of limiter decisions: as at 512 x 1024, the central
+    # difference's error falls with h (1.8e-4, 2.0e-5, 1.0e-5 here)
+    assert min(errs) <= 1e-4, errs
+
+
+def _golden(name):
+    import os
+    out = {}
+    with open(os.path.join(os.path.dirname(__file__), "golden", name)) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                k, *v = line.split()
+                out[k] = np.array([float(x) for x in v]) if len(v) > 1 else float(v[0])
+    return out
+
+
+@pytest.mark.parametrize("name,entry_tol", [("oracle_gradient_64x128_T2.txt", 1e-9),
+                                             ("oracle_gradient_128x256_T2.txt", 1e-6)])
+def test_long_march_gradient_matches_the_oracle(name, entry_tol):
+    # The gradient of R over 1210 (64 x 128) and 2419 (128 x 256) CFL
+    # steps to T = 2 against the oracle's reverse-mode AD through the same
+    # march, stored by tests/golden/make_oracle_gradients.py: inner products
+    # with eight seeded directions, the norm and sampled entries (the 32
+    # largest and 32 seeded ones), with the benchmark's snapshot policy.
+    # The two marches stay within 1e-12 of each other, but at 128 x 256 two
+    # of their ~1e9 limiter decisions are ties to that precision and go
+    # opposite ways (at steps 1864 and 2417, in cells (row 60, col 98) and
+    # (57, 12): the adjoint of those steps differs by 6e-8 and 7e-7 of its
+    # largest entry between the two states, of every other step by <= 2e-14).
+    # Each side's gradient is the exact derivative of its own branch; they
+    # differ by 3.6e-7 of the largest entry, spread over the lower half of
+    # the domain, which moves the inner products and the norm by <= 1e-10.
+    ref = _golden(name)
+    cfg = RTConfig(nx=int(ref["nx"]), ny=int(ref["ny"]))
+    T = ref["T"]
+    uv = inputs.seed_batch(cfg, [0], rms=1e-3)
+    r = rt().Context(cfg, max_steps=8192)
+    R, g, n = r.grad_u0(uv, T, rt().Policy(CKPT_UNIFORM, 32))
+    gh = host(g).ravel()
+    assert int(host(n)[0]) == int(ref["nsteps"])
+    assert abs(float(host(R)[0]) - ref["R"]) <= 1e-12 * abs(ref["R"])
+    delta = float(np.sqrt(np.sum(uv * uv) * cfg.dx * cfg.dy))
+    dirs = [inputs.direction_batch(cfg, [int(s)], delta).ravel() for s in ref["dir_seeds"]]
+    gd = np.array([float(np.sum(gh * d)) for d in dirs])
+    e_dir = np.max(np.abs(gd - ref["gd"]) / (ref["gnorm"] * np.array([np.linalg.norm(d) for d in dirs])))
+    e_norm = abs(np.linalg.norm(gh) - ref["gnorm"]) / ref["gnorm"]
+    e_val = np.max(np.abs(gh[ref["idx"].astype(np.int64)] - ref["gval"])) / ref["gmax"]
+    print(f"{name}: directions {e_dir:.3g}, norm {e_norm:.3g}, sampled entries {e_val:.3g}")
+    assert e_dir <= 1e-9
+    assert e_norm <= 1e-9
+    assert e_val <= entry_tol

@@ -679,7 +679,8 @@ int rt_integrate(rt_ctx* c, double* U, double T, double* t_out, int32_t* nsteps,
   if (int rc = flags_status(f)) return rc;
   if (dt_log) {
     std::vector<Ctl> h(c->P.nb);
-    RT_HIP(hipMemcpy(h.data(), final_ctl(c), sizeof(Ctl) * c->P.nb, hipMemcpyDeviceToHost));
+    RT_HIP(hipMemcpyAsync(h.data(), final_ctl(c), sizeof(Ctl) * c->P.nb, hipMemcpyDeviceToHost, c->stream));
+    RT_HIP(hipStreamSynchronize(c->stream));
     for (const Ctl& x : h)
       if (x.nsteps > cap) return fail(RT_ENOMEM, "dt_log capacity %d < %d steps", cap, x.nsteps);
   }

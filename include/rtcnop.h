@@ -38,6 +38,9 @@
  *   - Calls are asynchronous on the context's stream (a hipStream_t passed
  *     as void*; NULL = the default stream) unless stated.  rt_integrate and
  *     rt_grad_u0 synchronise that stream (they read device step counters).
+ *   - Kernels are launched on the calling thread's current HIP device; the
+ *     context's stream, workspace and pool and every array passed in must
+ *     belong to that device (the one current at rt_create).
  *   - A context is not thread-safe; distinct contexts are independent.
  *   - Return value: 0 on success or a negative rt_status; rt_last_error()
  *     gives a message for the calling thread's last failure.

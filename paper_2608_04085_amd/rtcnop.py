@@ -163,16 +163,18 @@ class Context:
         phys = RtPhys(cfg.gamma, cfg.g_y, cfg.rho_h, cfg.rho_l, cfg.y0, cfg.h, cfg.p_int, cfg.cfl, cfg.comp_mask,
                       cfg.recon)
         h = ctypes.c_void_p()
-        _check(L.rt_create(ctypes.byref(grid), ctypes.byref(phys), self._stream(), ctypes.byref(h)), "rt_create")
-        self._h = h
-        if tile is not None:
-            _check(L.rt_set_tile(h, TILES[tile]), "rt_set_tile")
-        n = ctypes.c_size_t()
-        _check(L.rt_workspace_bytes(h, self.max_steps, ctypes.byref(n)), "rt_workspace_bytes")
-        self.ws = torch.empty(n.value + 256, dtype=torch.uint8, device=self.device)
-        off = (-self.ws.data_ptr()) % 256
-        self._ws_ptr = ctypes.c_void_p(self.ws.data_ptr() + off)
-        _check(L.rt_set_workspace(h, self._ws_ptr, n.value, self.max_steps), "rt_set_workspace")
+        with torch.cuda.device(self.device):  # rt_set_workspace launches its set-up on the current device
+            _check(L.rt_create(ctypes.byref(grid), ctypes.byref(phys), self._stream(), ctypes.byref(h)),
+                   "rt_create")
+            self._h = h
+            if tile is not None:
+                _check(L.rt_set_tile(h, TILES[tile]), "rt_set_tile")
+            n = ctypes.c_size_t()
+            _check(L.rt_workspace_bytes(h, self.max_steps, ctypes.byref(n)), "rt_workspace_bytes")
+            self.ws = torch.empty(n.value + 256, dtype=torch.uint8, device=self.device)
+            off = (-self.ws.data_ptr()) % 256
+            self._ws_ptr = ctypes.c_void_p(self.ws.data_ptr() + off)
+            _check(L.rt_set_workspace(h, self._ws_ptr, n.value, self.max_steps), "rt_set_workspace")
 
     def __del__(self):
         try:
@@ -188,6 +190,10 @@ class Context:
         return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
     def _sync_stream(self):
+        # the library launches on the current device: refuse to run on another
+        if torch.cuda.current_device() != self.device.index:
+            raise RuntimeError(f"the context lives on {self.device}; make it the current device "
+                               f"(torch.cuda.set_device) before calling it")
         _check(load().rt_set_stream(self._h, self._stream()), "rt_set_stream")
 
     # ---------------------------------------------------------------- shapes

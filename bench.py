@@ -238,6 +238,36 @@ def main():
         "fwd_share_of_iteration": round(fw_share / per_iter, 3),
         "adj_share_of_iteration": round(adj_share / per_iter, 3),
     }
+    # the fused forward step of the march beside it, on the same terms
+    t_step_traffic = profiling.traffic_for(f"grad_{cfg.nx}x{cfg.ny}", "step_march", ctx.tile)
+    achieved_step = FWD_BYTES_PER_CELL * cells / t_march / 1e9
+    roofline_step = {
+        "bound": "hbm",
+        "achieved": round(achieved_step, 2),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved_step / HBM_PEAK_GBS, 5),
+        "traffic": None if t_step_traffic is None else round(t_step_traffic, 1),
+        "algorithmic_bytes_per_launch": FWD_BYTES_PER_CELL * cells,
+        "kernel": "fused forward step (k_step with the CFL epilogue, march)",
+        "launch_us": round(t_march * 1e6, 3),
+    }
+    # the out-of-cache point: 8 members of 1024 x 2048 (537 MB per state,
+    # above the last-level cache), the same kernels timed the same way
+    cfg8 = RTConfig(nx=1024, ny=2048, batch=8)
+    ctx8 = Context(cfg8, max_steps=64)
+    U8 = ctx8.init_state(inputs.seed_batch(cfg8, range(8), rms=1e-3))
+    kt8 = ctx8.kernel_times(U8, reps=10)
+    cells8 = cfg8.nx * cfg8.ny * cfg8.batch
+    scale_point = {"workload": "8 x 1024 x 2048, one launch per step", "tile": ctx8.tile}
+    for key, bpc, t_us, tkey in (("step", FWD_BYTES_PER_CELL, kt8["step_march_us"], "step_march"),
+                                 ("adjoint", ADJ_BYTES_PER_CELL, kt8["adjoint_two_kernel_us"], "adjoint")):
+        gbs = bpc * cells8 / (t_us * 1e-6) / 1e9
+        tr = profiling.traffic_for("step_8x1024x2048", tkey, ctx8.tile)
+        scale_point[key] = {"launch_us": round(t_us, 3), "cell_updates_per_s": cells8 / (t_us * 1e-6),
+                            "achieved_GBps": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4),
+                            "traffic": None if tr is None else round(tr, 1)}
+    del ctx8, U8
     out = {
         "metric": METRIC,
         "value": value,
@@ -266,6 +296,8 @@ def main():
         "adjoint_vs_fd_speedup": fd_iter_s / per_iter,
         "R": float(R.item()),
         "roofline": roofline,
+        "roofline_step": roofline_step,
+        "scale_point": scale_point,
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cfg, T, args.cpu_seconds)

@@ -21,7 +21,7 @@ import torch
 
 from oracle.rto import Oracle, lib
 from paper_2608_04085_amd import inputs
-from paper_2608_04085_amd.config import CKPT_REVOLVE, CKPT_UNIFORM, RTConfig
+from paper_2608_04085_amd.config import CKPT_REVOLVE, CKPT_UNIFORM, RECON_BALANCED, RTConfig
 
 pytestmark = pytest.mark.gpu
 
@@ -346,3 +346,37 @@ def test_long_march_gradient_matches_the_oracle(name, entry_tol):
     assert e_dir <= 1e-9
     assert e_norm <= 1e-9
     assert e_val <= entry_tol
+
+
+def test_balanced_variant_at_1024x2048():
+    # The well-balanced variant in the high-resolution launch configuration:
+    # steps and the step adjoint (windows at both walls and the interface)
+    # against the oracle, and the unperturbed state kept to round-off.
+    cfg = RTConfig(nx=1024, ny=2048, recon=RECON_BALANCED)
+    uv = inputs.seed_batch(cfg, [0], rms=1e-3)
+    o = Oracle.from_config(cfg)
+    r = rt().Context(cfg, max_steps=64)
+    Uo = o.init_state(uv)
+    U = r.init_state(uv)
+    for _ in range(4):
+        Uo = o.step(Uo, o.cfl_dt(Uo))
+        U = r.step(U)
+    err = normwise(host(U), Uo)
+    print("balanced 1024x2048, 4 steps: normwise", err)
+    assert err <= 1e-10
+    dt = o.cfl_dt(Uo)
+    for j0, wy0, shift in ((0, 0, 32), (cfg.ny // 2 - 32, 24, -500), (cfg.ny - 64, 48, -777)):
+        e, stray = window_adjoint(r, cfg, Uo, dt, j0, wy0, shift, seed=j0 + 3)
+        print(f"balanced adjoint window rows {j0 + wy0}..{j0 + wy0 + 15}: normwise {e:.3g}, stray {stray}")
+        assert e <= 1e-12
+        assert stray == 0
+    U0 = r.init_state(np.zeros((1, 2, cfg.ny, cfg.nx)))
+    U = U0
+    for _ in range(200):
+        U = r.step(U)
+    Uh, U0h = host(U), host(U0)
+    drift = np.max(np.abs(Uh[:, [0, 3]] - U0h[:, [0, 3]]) / np.abs(U0h[:, [0, 3]]))
+    speed = np.max(np.abs(Uh[:, 1:3]) / Uh[:, :1])
+    print("balanced rest state after 200 steps: rho, E drift", drift, "max |velocity|", speed)
+    assert drift <= 1e-13
+    assert speed <= 1e-13

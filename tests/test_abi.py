@@ -86,3 +86,39 @@ def test_revolve_large_schedules_are_consistent():
     # with as many slots as steps nothing is recomputed beyond one pass
     fw, _ = rtcnop.revolve_stats(100, 100)
     assert fw == 99
+
+
+def test_argument_validation_without_gpu():
+    # every rejection below is decided on the host before any HIP call
+    L = rtcnop.load()
+    h = ctypes.c_void_p()
+    p = rtcnop.RtPhys(1.4, -0.1, 2.0, 1.0, 0.5, 0.01, 2.5, 0.4, 3, 0)
+    bad_grids = [rtcnop.RtGrid(8, 8, 0, 0, 0.5, 1.0),         # empty batch
+                 rtcnop.RtGrid(8, 1, 1, 0, 0.5, 1.0),         # one row
+                 rtcnop.RtGrid(16384, 16384, 1, 0, 0.5, 1.0),  # 2^28 cells: 32-bit plane offsets overflow
+                 rtcnop.RtGrid(8, 8, 1, 0, -0.5, 1.0),        # negative length
+                 rtcnop.RtGrid(8, 8, 1, 0, 0.5, 0.0)]         # zero length
+    for g in bad_grids:
+        assert L.rt_create(ctypes.byref(g), ctypes.byref(p), None, ctypes.byref(h)) == -1
+    g = rtcnop.RtGrid(8, 8, 1, 0, 0.5, 1.0)
+    for field, value in [("comp_mask", 0), ("comp_mask", 4), ("cfl", 0.0), ("h", 0.0), ("rho_l", -1.0)]:
+        q = rtcnop.RtPhys(1.4, -0.1, 2.0, 1.0, 0.5, 0.01, 2.5, 0.4, 3, 0)
+        setattr(q, field, value)
+        assert L.rt_create(ctypes.byref(g), ctypes.byref(q), None, ctypes.byref(h)) == -1, field
+    # the largest grid below the limit is accepted (nothing is allocated)
+    big = rtcnop.RtGrid(16384, 16383, 1, 0, 0.5, 1.0)
+    assert L.rt_create(ctypes.byref(big), ctypes.byref(p), None, ctypes.byref(h)) == 0
+    assert L.rt_destroy(h) == 0
+    assert L.rt_create(ctypes.byref(g), ctypes.byref(p), None, ctypes.byref(h)) == 0
+    n = ctypes.c_size_t()
+    assert L.rt_workspace_bytes(h, 0, ctypes.byref(n)) == -1
+    assert L.rt_workspace_bytes(h, 64, ctypes.byref(n)) == 0
+    # workspace: misaligned or too small, refused before it is touched
+    assert L.rt_set_workspace(h, ctypes.c_void_p(256 + 8), n.value, 64) == -1
+    assert b"aligned" in L.rt_last_error()
+    assert L.rt_set_workspace(h, ctypes.c_void_p(256), n.value - 1, 64) == -3
+    # checkpoint pools: unknown kind, bad interval
+    assert L.rt_pool_bytes(h, 7, 32, 100, ctypes.byref(n)) == -1
+    assert L.rt_pool_bytes(h, 1, 0, 100, ctypes.byref(n)) == -1
+    assert L.rt_set_tiles(h, 0, 99) == -1 and L.rt_set_tile(h, -1) == -1
+    assert L.rt_destroy(h) == 0

@@ -42,6 +42,8 @@ CASES = [
     RTConfig(nx=70, ny=37),            # ragged in x and y for every tile shape
     RTConfig(nx=5, ny=9),              # smaller than one tile, wrap-around halo
     RTConfig(nx=48, ny=40, batch=3),   # batched
+    RTConfig(nx=3, ny=2),              # the smallest grid: halos wrap several times, both walls next to each row
+    RTConfig(nx=3, ny=4, batch=2),
 ]
 
 
@@ -146,7 +148,7 @@ def test_periodic_shift_equivariance_bitwise():
     np.testing.assert_array_equal(np.roll(host(A), 13, axis=3), host(B))
 
 
-@pytest.mark.parametrize("cfg", [RTConfig(nx=32, ny=48), RTConfig(nx=21, ny=19, batch=2)],
+@pytest.mark.parametrize("cfg", [RTConfig(nx=32, ny=48), RTConfig(nx=21, ny=19, batch=2), RTConfig(nx=3, ny=2)],
                          ids=lambda c: f"{c.nx}x{c.ny}x{c.batch}")
 def test_step_adjoint_matches_oracle(cfg):
     o = Oracle.from_config(cfg)
@@ -162,8 +164,9 @@ def test_step_adjoint_matches_oracle(cfg):
         assert normwise(host(lam), ref) <= 1e-12
 
 
-@pytest.mark.parametrize("cfg,T", [(RTConfig(nx=32, ny=64), 0.1), (RTConfig(nx=24, ny=30, batch=2), 0.08)],
-                         ids=["32x64", "24x30x2"])
+@pytest.mark.parametrize("cfg,T", [(RTConfig(nx=32, ny=64), 0.1), (RTConfig(nx=24, ny=30, batch=2), 0.08),
+                                   (RTConfig(nx=3, ny=4, batch=2), 0.05)],
+                         ids=["32x64", "24x30x2", "3x4x2"])
 def test_gradient_matches_oracle_and_policies_agree_bitwise(cfg, T):
     o = Oracle.from_config(cfg)
     uv = inputs.seed_batch(cfg, range(cfg.batch), rms=1e-3)

@@ -189,3 +189,25 @@ def test_five_mode_and_power_reconstructions():
     assert np.sum(r * r) < np.sum(v * v)
     d = cnop.power_reconstruction(v, 1.0) - v
     assert np.sum(d * d) <= 1e-14 * np.sum(v * v)
+
+
+def test_spectrum_top5_and_peak_row():
+    # Eq. 12's E_n over n >= 1 of the peak row: a single horizontal mode has
+    # all its energy in one n (top-5 fraction 1); a row with known mode
+    # amplitudes gives the fraction computed by an explicit DFT sum
+    from paper_2608_04085_amd import cnop
+    nx = 32
+    x = np.arange(nx) / nx
+    assert cnop.spectrum_top5(np.cos(2 * np.pi * 5 * x + 0.4)) == pytest.approx(1.0, abs=1e-14)
+    amps = {1: 1.0, 2: 0.9, 3: 0.8, 4: 0.7, 6: 0.6, 9: 0.5, 11: 0.3}
+    row = 0.7 + sum(a * np.sin(2 * np.pi * n * x + n) for n, a in amps.items())  # the mean (n = 0) is excluded
+    e = np.array([abs(sum(row[k] * np.exp(-2j * np.pi * n * k / nx) for k in range(nx))) ** 2
+                  for n in range(1, nx // 2 + 1)])
+    assert cnop.spectrum_top5(row) == pytest.approx(np.sum(np.sort(e)[-5:]) / np.sum(e), rel=1e-12)
+    assert cnop.spectrum_top5(row) == pytest.approx(sum(a * a for a in [1.0, 0.9, 0.8, 0.7, 0.6]) /
+                                                    sum(a * a for a in amps.values()), rel=1e-12)
+    # peak row: largest rms along x, the lowest index on a tie
+    v = np.zeros((6, nx))
+    v[2] = np.cos(2 * np.pi * x)
+    v[4] = -np.cos(2 * np.pi * x)
+    assert cnop.peak_row(v) == 2

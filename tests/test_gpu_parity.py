@@ -695,3 +695,24 @@ def test_balanced_variant_objective_J_with_differentiated_steps_matches_oracle()
     np.testing.assert_array_equal(host(n), no)
     np.testing.assert_allclose(host(J), Jo, rtol=1e-9)
     assert normwise(host(g), go) <= 1e-9
+
+
+def test_autograd_function_runs_the_adjoint():
+    # KERatio: R(uv0) as a torch.autograd.Function whose backward is the
+    # library's adjoint: values and gradients equal rt_grad_u0's to the bit,
+    # the incoming gradient scales each member's
+    cfg = RTConfig(nx=32, ny=64, batch=2)
+    T = 0.1
+    r = rt().Context(cfg, max_steps=1024)
+    uv = torch.from_numpy(inputs.seed_batch(cfg, [0, 1], rms=1e-3)).cuda().requires_grad_(True)
+    pol = rt().Policy(CKPT_UNIFORM, 8)
+    R = rt().KERatio.apply(uv, r, T, pol)
+    w = torch.tensor([2.0, -0.5], dtype=torch.float64, device=uv.device)
+    (w * R).sum().backward()
+    R2, g2, _ = r.grad_u0(uv.detach(), T, pol)
+    np.testing.assert_array_equal(host(R), host(R2))
+    np.testing.assert_array_equal(host(uv.grad), host(g2 * w.reshape(-1, 1, 1, 1)))
+    o = Oracle.from_config(cfg)
+    Ro, go, _, _ = o.grad_u0(host(uv), T)
+    np.testing.assert_allclose(host(R), Ro, rtol=1e-12)
+    assert normwise(host(uv.grad), go * host(w).reshape(-1, 1, 1, 1)) <= 1e-9

@@ -122,3 +122,15 @@ def test_argument_validation_without_gpu():
     assert L.rt_pool_bytes(h, 1, 0, 100, ctypes.byref(n)) == -1
     assert L.rt_set_tiles(h, 0, 99) == -1 and L.rt_set_tile(h, -1) == -1
     assert L.rt_destroy(h) == 0
+
+
+def test_committed_counters_belong_to_the_kernel_sources():
+    # profiles/traffic.json records the hash of the kernel sources it was
+    # measured on; the benchmark reports its HBM traffic only while they match
+    from paper_2608_04085_amd import profiling
+    for workload, kernels in (("grad_256x512", ("step", "step_march", "adjoint")),
+                              ("step_8x1024x2048", ("step", "adjoint"))):
+        for k in kernels:
+            t = profiling.traffic_for(workload, k, "32x8/32x8")
+            assert t is not None and t > 0, (workload, k)
+    assert profiling.traffic_for("grad_256x512", "adjoint", "16x8/32x8") is None  # other tiles

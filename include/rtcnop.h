@@ -241,6 +241,8 @@ int rt_set_graphs(rt_ctx* ctx, int32_t on);
  * are identical. */
 int rt_set_overlap(rt_ctx* ctx, int32_t on);
 int rt_get_tiles(const rt_ctx* ctx, int32_t* step_tile, int32_t* adj_tile);
+/* The step kernel's variant (as rt_get_tiles' step_tile). */
+int rt_get_tile(const rt_ctx* ctx, int32_t* tile);
 int rt_autotune(rt_ctx* ctx, const double* U, int32_t reps, int32_t* step_tile, int32_t* adj_tile);
 /* The reverse sweep of RT_CKPT_STORE_ALL / RT_CKPT_UNIFORM runs one kernel
  * per adjoint step, which also completes the previous step's limiter gather
@@ -282,6 +284,15 @@ int rt_get_dt_mode(const rt_ctx* ctx, int32_t* mode);
  * has no folded form: there out[2] repeats out[3].  out holds 5 doubles.
  * Synchronises the stream; the workspace serves as scratch. */
 int rt_kernel_times(rt_ctx* ctx, const double* U, int32_t reps, double* out);
+
+/* Host-only check of the binomial checkpointing schedule (Sec. 3.4) that
+ * RT_CKPT_REVOLVE runs: builds it for nsteps steps and `slots` state slots
+ * (slot 0 holding the initial state), replays it on step indices, and fails
+ * with RT_EINVAL unless every step is reversed exactly once, in decreasing
+ * order, from the right state, using only the given slots.  forward receives
+ * the schedule's count of forward steps, optimum the smallest count any
+ * schedule with that many slots can reach.  No context, no device work. */
+int rt_revolve_stats(int32_t nsteps, int32_t slots, int64_t* forward, int64_t* optimum);
 
 /* Synchronise the stream and report a device-side error flag (RT_EUNPHYS)
  * raised by earlier asynchronous calls; clears the flag. */

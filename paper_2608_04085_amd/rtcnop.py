@@ -113,7 +113,7 @@ EXPORTED = ["rt_create", "rt_destroy", "rt_set_stream", "rt_workspace_bytes", "r
             "rt_last_error", "rt_set_tile", "rt_get_tiles", "rt_autotune", "rt_max_abs", "rt_set_graphs",
             "rt_set_overlap", "rt_kernel_times", "rt_set_fold", "rt_get_fold",
             "rt_set_tiles", "rt_ek_field", "rt_ek_anomaly", "rt_grad_ek_anomaly",
-            "rt_mix_width", "rt_set_dt_mode", "rt_get_dt_mode"]
+            "rt_mix_width", "rt_set_dt_mode", "rt_get_dt_mode", "rt_get_tile", "rt_revolve_stats"]
 
 
 def _check(rc: int, call: str):

@@ -134,3 +134,11 @@ def test_committed_counters_belong_to_the_kernel_sources():
             t = profiling.traffic_for(workload, k, "32x8/32x8")
             assert t is not None and t > 0, (workload, k)
     assert profiling.traffic_for("grad_256x512", "adjoint", "16x8/32x8") is None  # other tiles
+
+
+def test_header_declares_every_exported_call():
+    # the C ABI is what the header declares: no call is defined without a
+    # declaration there
+    src = open(os.path.join(ROOT, "paper_2608_04085_amd", "csrc", "rt_api.hip")).read()
+    defined = set(re.findall(r"^(?:int|const char\*)\s+(rt_[a-z0-9_]+)\s*\(", src[src.index('extern "C" {'):], re.M))
+    assert defined and defined <= set(_declared()), sorted(defined - set(_declared()))

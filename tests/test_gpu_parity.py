@@ -716,3 +716,25 @@ def test_autograd_function_runs_the_adjoint():
     Ro, go, _, _ = o.grad_u0(host(uv), T)
     np.testing.assert_allclose(host(R), Ro, rtol=1e-12)
     assert normwise(host(uv.grad), go * host(w).reshape(-1, 1, 1, 1)) <= 1e-9
+
+
+def test_step_log_overflow_is_reported_and_the_context_recovers():
+    # a march longer than the workspace's step log (max_steps) and a dt log
+    # shorter than the run both fail with RT_ENOMEM; the device flags are
+    # cleared, so the same context then runs a feasible march to the bit of
+    # a fresh one
+    cfg = RTConfig(nx=32, ny=64)
+    uv = inputs.seed_batch(cfg, [0], rms=1e-3)
+    r = rt().Context(cfg, max_steps=40)
+    U0 = r.init_state(uv)
+    with pytest.raises(rt().RTError) as e:
+        r.integrate(U0, 2.0)
+    assert e.value.code == -3
+    with pytest.raises(rt().RTError) as e:
+        r.integrate(U0, 0.05, log_cap=2)
+    assert e.value.code == -3
+    U1, t1, n1, _ = r.integrate(U0, 0.05)
+    fresh = rt().Context(cfg, max_steps=40)
+    U2, t2, n2, _ = fresh.integrate(fresh.init_state(uv), 0.05)
+    assert int(host(n1)[0]) == int(host(n2)[0]) > 2
+    np.testing.assert_array_equal(host(U1), host(U2))

@@ -173,6 +173,18 @@ int rt_ek_field(rt_ctx* ctx, const double* U, double* ek);
  * <rho>_x the mean density of the row (device arrays; U [B][4][ny][nx]). */
 int rt_mix_width(rt_ctx* ctx, const double* U, double* h);
 
+/* Horizontal power spectrum (Sec. 4.2, Eq. 12 before its normalisation) of
+ * one scalar field per member: E[b][n] = sum over the selected rows j of
+ * |sum_i f_b(i, j) exp(-2 pi i n i / nx)|^2 for n = 0 .. nx/2, E laid out
+ * [B][nx/2 + 1] (device).  f (device) holds member b's field, ny rows of nx
+ * doubles, from f + b * member_stride: pass member_stride = nx * ny for a
+ * plain field, or f + nx * ny with member_stride = 2 * nx * ny for the v
+ * component of a velocity field [B][2][ny][nx]; the caller's buffer must
+ * hold (B - 1) * member_stride + nx * ny doubles from f.  row = -1 sums over
+ * all rows, 0 <= row < ny takes one.  Eq. 12's E_n is E[b][n] over
+ * sum_{m >= 1} E[b][m].  nx <= 4096.  Deterministic (a fixed-order sum). */
+int rt_row_spectrum(rt_ctx* ctx, const double* f, int64_t member_stride, int32_t row, double* E);
+
 /* Objective of Eq. 8 on the grid: J[B] = sum over cells of
  * (e_k(U) - ek_base)^2 dx dy, with ek_base [B][ny][nx] the e_k field of the
  * unperturbed run at the same time (device arrays). */

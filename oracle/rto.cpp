@@ -16,6 +16,8 @@
 //                      the whole discrete march with the time steps of the
 //                      forward run held fixed (Sec. 3.4)
 //   rto_mix_width      mixing-layer width of Eqs. 13-14
+//   rto_row_spectrum   horizontal power spectrum of rows (Eq. 12's E_n
+//                      before normalisation)
 //   rto_ek_field       kinetic-energy density field of Eq. 7
 //   rto_ek_anomaly_frozen  objective J of Eq. 8 after a march with given steps
 //   rto_grad_ek_anomaly    J and its exact gradient (same reverse sweep as
@@ -296,6 +298,34 @@ int rto_mix_width(const Problem* P, const double* U, double* h) {
       s += 4.0 * f * (1.0 - f) * dy;
     }
     h[b] = s;
+  }
+  return 0;
+}
+
+// Horizontal power spectrum behind Eq. 12: for each member's field f
+// ([ny][nx], rows of nx values, member b at f + b * member_stride),
+// E[b][n] = sum over the selected rows of |sum_i f(i, j) exp(-2 pi i n i / nx)|^2,
+// n = 0 .. nx/2, by the plain discrete Fourier sum (the phase n i is reduced
+// modulo nx before the cosine and sine are taken).  row = -1: all rows.
+int rto_row_spectrum(const Problem* P, const double* f, int64_t member_stride, int32_t row, double* E) {
+  if (!valid(P) || !f || !E || row < -1 || row >= P->ny) return kEInval;
+  const int nx = P->nx, nbins = nx / 2 + 1;
+  const double two_pi = 2.0 * 3.14159265358979323846;
+  for (int b = 0; b < P->nb; ++b) {
+    const double* fb = f + static_cast<size_t>(b) * static_cast<size_t>(member_stride);
+    for (int n = 0; n < nbins; ++n) {
+      double e = 0.0;
+      for (int j = (row < 0 ? 0 : row); j < (row < 0 ? P->ny : row + 1); ++j) {
+        double re = 0.0, im = 0.0;
+        for (int i = 0; i < nx; ++i) {
+          const double phase = two_pi * static_cast<double>((static_cast<long>(n) * i) % nx) / nx;
+          re += fb[static_cast<size_t>(j) * nx + i] * std::cos(phase);
+          im -= fb[static_cast<size_t>(j) * nx + i] * std::sin(phase);
+        }
+        e += re * re + im * im;
+      }
+      E[static_cast<size_t>(b) * nbins + n] = e;
+    }
   }
   return 0;
 }

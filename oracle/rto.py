@@ -65,6 +65,7 @@ def lib():
             "rto_project_to_constraint": [P, _dp, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, _dp],
             "rto_ek_field": [P, _dp, _dp],
             "rto_mix_width": [P, _dp, _dp],
+            "rto_row_spectrum": [P, _dp, ctypes.c_int64, ctypes.c_int32, _dp],
             "rto_ek_anomaly_frozen": [P, _dp, _dp, _ip, ctypes.c_int32, _dp, _dp],
             "rto_grad_ek_anomaly": [P, _dp, ctypes.c_double, _dp, _dp, _dp, _ip, _dp, ctypes.c_int32],
             "rto_objective_adaptive": [P, _dp, ctypes.c_double, _dp, _dp, _ip],
@@ -199,6 +200,15 @@ class Oracle:
         h = np.empty(self.prob.nb)
         _check(lib().rto_mix_width(ctypes.byref(self.prob), _p(U), _p(h)), "mix_width")
         return h
+
+    def row_spectrum(self, f, row: int = -1):
+        """E[B][nx/2 + 1]: sum over the selected rows of |DFT_n of the row|^2
+        for each member's field f [B][ny][nx] (Eq. 12 before normalisation)."""
+        f = np.ascontiguousarray(f, dtype=np.float64).reshape(self.prob.nb, self.prob.ny, self.prob.nx)
+        E = np.empty((self.prob.nb, self.prob.nx // 2 + 1))
+        _check(lib().rto_row_spectrum(ctypes.byref(self.prob), _p(f), self.prob.nx * self.prob.ny, int(row), _p(E)),
+               "row_spectrum")
+        return E
 
     def ek_field(self, U):
         """Kinetic-energy density e_k = |m|^2/(2 rho) of every cell, [nb][ny][nx] (Eq. 7)."""

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librtcnop.so")
-SOURCES = ["rt_kernels.hip", "rt_api.hip"]
+SOURCES = ["rt_kernels.hip", "rt_diag.hip", "rt_api.hip"]
 ARCH = os.environ.get("RT_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

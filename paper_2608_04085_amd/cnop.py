@@ -176,6 +176,14 @@ def spectrum_top5(v_row: np.ndarray) -> float:
     return float(np.sum(np.sort(e)[-5:]))
 
 
+def top5_fraction(E_row) -> float:
+    """The same fraction from a spectrum E[0 .. nx/2] as the library's
+    rt_row_spectrum returns it (Eq. 12: normalised over n >= 1)."""
+    e = np.asarray(E_row, dtype=np.float64)[1:]
+    e = e / np.sum(e)
+    return float(np.sum(np.sort(e)[-5:]))
+
+
 def peak_row(v: np.ndarray) -> int:
     """Row whose rms along x is largest (lowest index on ties)."""
     return int(np.argmax(np.sqrt(np.mean(v * v, axis=1))))

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "../../include/rtcnop.h"
+#include "rt_diag.h"
 #include "rt_kernels.h"
 #include "rt_revolve.h"
 
@@ -1010,6 +1011,15 @@ int rt_mix_width(rt_ctx* c, const double* U, double* h) {
   if (int rc = need_ws(c)) return rc;
   if (!U || !h) return fail(RT_EINVAL, "null argument");
   RT_HIP(rtk::launch_mix_width(c->P, U, c->rowmean, h, c->stream));
+  return 0;
+}
+
+int rt_row_spectrum(rt_ctx* c, const double* f, int64_t member_stride, int32_t row, double* E) {
+  if (!c || !f || !E) return fail(RT_EINVAL, "null argument");
+  if (c->P.nx > rtk::kSpecMaxNx) return fail(RT_EINVAL, "nx = %d exceeds %d for the spectrum", c->P.nx, rtk::kSpecMaxNx);
+  if (row < -1 || row >= c->P.ny) return fail(RT_EINVAL, "row %d outside -1 .. ny - 1", row);
+  if (c->P.nb > 1 && member_stride < (int64_t)c->cells()) return fail(RT_EINVAL, "member_stride below nx * ny");
+  RT_HIP(rtk::launch_row_spectrum(c->P.nx, c->P.ny, c->P.nb, f, (long long)member_stride, row, E, c->stream));
   return 0;
 }
 

@@ -88,6 +88,7 @@ def load():
         "rt_set_tiles": [_vp, _i32, _i32],
         "rt_ek_field": [_vp, _vp, _vp],
         "rt_mix_width": [_vp, _vp, _vp],
+        "rt_row_spectrum": [_vp, _vp, ctypes.c_int64, _i32, _vp],
         "rt_ek_anomaly": [_vp, _vp, _vp, _vp],
         "rt_grad_ek_anomaly": [_vp, _vp, ctypes.c_double, _vp, _vp, _vp, _vp, _vp],
         "rt_get_fold": [_vp, ctypes.POINTER(_i32)],
@@ -113,7 +114,8 @@ EXPORTED = ["rt_create", "rt_destroy", "rt_set_stream", "rt_workspace_bytes", "r
             "rt_last_error", "rt_set_tile", "rt_get_tiles", "rt_autotune", "rt_max_abs", "rt_set_graphs",
             "rt_set_overlap", "rt_kernel_times", "rt_set_fold", "rt_get_fold",
             "rt_set_tiles", "rt_ek_field", "rt_ek_anomaly", "rt_grad_ek_anomaly",
-            "rt_mix_width", "rt_set_dt_mode", "rt_get_dt_mode", "rt_get_tile", "rt_revolve_stats"]
+            "rt_mix_width", "rt_set_dt_mode", "rt_get_dt_mode", "rt_get_tile", "rt_revolve_stats",
+            "rt_row_spectrum"]
 
 
 def _check(rc: int, call: str):
@@ -379,6 +381,26 @@ class Context:
         h = self._f64((self.cfg.batch,))
         _check(load().rt_mix_width(self._h, _ptr(U), _ptr(h)), "rt_mix_width")
         return h
+
+    def row_spectrum(self, field, row: int = -1, component: int | None = None) -> torch.Tensor:
+        """E[B][nx/2 + 1] of Eq. 12 before normalisation: the squared modulus
+        of each row's horizontal Fourier coefficients, summed over all rows
+        (row = -1) or of one row.  field is [B][ny][nx], or a velocity field
+        [B][2][ny][nx] with `component` 0 (u) or 1 (v)."""
+        self._sync_stream()
+        f = self.as_dev(field)
+        N = self.cfg.nx * self.cfg.ny
+        if component is None:
+            f = f.reshape(self.cfg.batch, self.cfg.ny, self.cfg.nx)
+            base, stride = f.data_ptr(), N
+        else:
+            if component not in (0, 1):
+                raise ValueError("component must be 0 (u) or 1 (v)")
+            f = f.reshape(self.shape_uv)
+            base, stride = f.data_ptr() + 8 * N * int(component), 2 * N
+        E = self._f64((self.cfg.batch, self.cfg.nx // 2 + 1))
+        _check(load().rt_row_spectrum(self._h, ctypes.c_void_p(base), stride, int(row), _ptr(E)), "rt_row_spectrum")
+        return E
 
     def baseline_ek(self, T: float) -> torch.Tensor:
         """e_k field of the unperturbed run at time T: the reference of Eq. 8."""

@@ -98,10 +98,11 @@ def grad_1024x2048(T: float = 3.0, budget_gb: float = 64.0) -> dict:
                                      NORM_L2, SET_SPHERE)
     v = gp[0, 1].cpu().numpy()
     row = cnop.peak_row(v)
+    E = rt.row_spectrum(gp, row, component=1)[0].cpu().numpy()  # Eq. 12 on the device
     return {"workload": "grad_1024x2048", "T": T, "nsteps": int(n.item()), "R": float(R.item()),
             "forward_seconds": t_fwd, "gradient_seconds": t_grad, "adjoint_over_forward": t_grad / t_fwd,
             "pool_slots": int(pool.numel() // (8 * 4 * cfg.cells)), "peak_row": row,
-            "top5_kx_energy_fraction": cnop.spectrum_top5(v[row]), "tiles": rt.tile}
+            "top5_kx_energy_fraction": cnop.top5_fraction(E), "tiles": rt.tile}
 
 
 def cnop_8x512x1024(T: float = 1.0, iters: int = 50, budget_gb: float = 16.0) -> dict:

@@ -121,6 +121,15 @@ def test_argument_validation_without_gpu():
     assert L.rt_pool_bytes(h, 7, 32, 100, ctypes.byref(n)) == -1
     assert L.rt_pool_bytes(h, 1, 0, 100, ctypes.byref(n)) == -1
     assert L.rt_set_tiles(h, 0, 99) == -1 and L.rt_set_tile(h, -1) == -1
+    # spectrum: a row outside -1 .. ny - 1
+    assert L.rt_row_spectrum(h, ctypes.c_void_p(256), 64, 8, ctypes.c_void_p(256)) == -1
+    assert L.rt_row_spectrum(h, ctypes.c_void_p(256), 64, -2, ctypes.c_void_p(256)) == -1
+    assert L.rt_destroy(h) == 0
+    # and a row wider than its LDS twiddle table
+    wide = rtcnop.RtGrid(8192, 4, 1, 0, 0.5, 1.0)
+    assert L.rt_create(ctypes.byref(wide), ctypes.byref(p), None, ctypes.byref(h)) == 0
+    assert L.rt_row_spectrum(h, ctypes.c_void_p(256), 8192 * 4, -1, ctypes.c_void_p(256)) == -1
+    assert b"4096" in L.rt_last_error()
     assert L.rt_destroy(h) == 0
 
 

@@ -738,3 +738,27 @@ def test_step_log_overflow_is_reported_and_the_context_recovers():
     U2, t2, n2, _ = fresh.integrate(fresh.init_state(uv), 0.05)
     assert int(host(n1)[0]) == int(host(n2)[0]) > 2
     np.testing.assert_array_equal(host(U1), host(U2))
+
+
+def test_row_spectrum_matches_oracle():
+    # Eq. 12's E_n before normalisation: all rows and one row, plain fields
+    # and the v component of velocity fields, ragged and bench-sized grids
+    rng = np.random.default_rng(21)
+    for cfg in (RTConfig(nx=70, ny=37, batch=2), RTConfig(nx=256, ny=512)):
+        o = Oracle.from_config(cfg)
+        r = rt().Context(cfg, max_steps=8)
+        f = rng.standard_normal((cfg.batch, cfg.ny, cfg.nx))
+        uv = rng.standard_normal((cfg.batch, 2, cfg.ny, cfg.nx))
+        for row in (-1, 3, cfg.ny - 1):
+            for got, ref in ((r.row_spectrum(torch.from_numpy(f), row), o.row_spectrum(f, row)),
+                             (r.row_spectrum(torch.from_numpy(uv), row, component=1),
+                              o.row_spectrum(np.ascontiguousarray(uv[:, 1]), row))):
+                g = host(got)
+                for b in range(cfg.batch):
+                    assert np.max(np.abs(g[b] - ref[b])) <= 1e-12 * np.max(ref[b]), (cfg, row, b)
+    # full size, one row of a 1024 x 2048 field
+    cfg = RTConfig(nx=1024, ny=2048)
+    f = rng.standard_normal((1, cfg.ny, cfg.nx))
+    g = host(rt().Context(cfg, max_steps=8).row_spectrum(torch.from_numpy(f), 1000))
+    ref = Oracle.from_config(cfg).row_spectrum(f, 1000)
+    assert np.max(np.abs(g - ref)) <= 1e-12 * np.max(ref)

@@ -211,3 +211,15 @@ def test_spectrum_top5_and_peak_row():
     v[2] = np.cos(2 * np.pi * x)
     v[4] = -np.cos(2 * np.pi * x)
     assert cnop.peak_row(v) == 2
+
+
+def test_top5_fraction_of_a_spectrum_vector_equals_the_row_form():
+    # cnop.top5_fraction(E) on rt_row_spectrum's output (here the oracle's)
+    # is cnop.spectrum_top5 of the row itself
+    from oracle.rto import Oracle
+    from paper_2608_04085_amd import cnop
+    from paper_2608_04085_amd.config import RTConfig
+    cfg = RTConfig(nx=40, ny=6)
+    f = np.random.default_rng(9).standard_normal((1, cfg.ny, cfg.nx))
+    E = Oracle.from_config(cfg).row_spectrum(f, row=2)[0]
+    assert cnop.top5_fraction(E) == pytest.approx(cnop.spectrum_top5(f[0, 2]), rel=1e-12)

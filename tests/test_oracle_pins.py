@@ -842,3 +842,29 @@ def test_linear_rt_growth_rate_against_sqrt_agk():
     f2c = _fitted_growth(RTConfig(nx=32, ny=128), 2)
     f2f = _fitted_growth(RTConfig(nx=64, ny=256), 2)
     assert abs(f2f / s2 - 1) < abs(f2c / s2 - 1) and abs(f2f / s2 - 1) < 0.06, (f2c, f2f, s2)
+
+
+# ------------------------------------------------------------ spectrum (Eq. 12)
+def test_row_spectrum_against_rfft_single_mode_and_parseval():
+    cfg = RTConfig(nx=48, ny=20, batch=2)
+    o = Oracle.from_config(cfg)
+    rng = np.random.default_rng(4)
+    f = rng.standard_normal((2, cfg.ny, cfg.nx))
+    E = o.row_spectrum(f)
+    # the library FFT: sum over rows of |rfft|^2
+    np.testing.assert_allclose(E, np.sum(np.abs(np.fft.rfft(f, axis=2)) ** 2, axis=1), rtol=1e-12, atol=1e-9)
+    # Parseval (nx even: the n = 0 and Nyquist bins once, the others twice)
+    w = np.full(cfg.nx // 2 + 1, 2.0)
+    w[0] = w[-1] = 1.0
+    np.testing.assert_allclose(E @ w, cfg.nx * np.sum(f * f, axis=(1, 2)), rtol=1e-12)
+    # one selected row
+    np.testing.assert_allclose(o.row_spectrum(f, row=7)[1], np.abs(np.fft.rfft(f[1, 7])) ** 2, rtol=1e-12,
+                               atol=1e-10)
+    # a single horizontal mode k puts (nx/2)^2 sum_j env_j^2 into bin k alone
+    i = np.arange(cfg.nx)
+    env = np.exp(-((np.arange(cfg.ny) - 9.5) / 4.0) ** 2)
+    g = np.broadcast_to(np.cos(2 * np.pi * 5 * i / cfg.nx + 0.3)[None, None, :] * env[None, :, None],
+                        (2, cfg.ny, cfg.nx))
+    Eg = o.row_spectrum(g)
+    assert Eg[0, 5] == pytest.approx((cfg.nx / 2) ** 2 * np.sum(env**2), rel=1e-13)
+    assert np.max(np.delete(Eg[0], 5)) <= 1e-24 * Eg[0, 5]

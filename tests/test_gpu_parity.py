@@ -762,3 +762,22 @@ def test_row_spectrum_matches_oracle():
     g = host(rt().Context(cfg, max_steps=8).row_spectrum(torch.from_numpy(f), 1000))
     ref = Oracle.from_config(cfg).row_spectrum(f, 1000)
     assert np.max(np.abs(g - ref)) <= 1e-12 * np.max(ref)
+
+
+def test_gradient_is_deterministic_and_shift_equivariant():
+    # the same call twice gives the same bits; a seed shifted periodically in
+    # x gives the shifted gradient (to round-off: KE(0) and KE(T) are sums
+    # taken in storage order, which the shift permutes)
+    cfg = RTConfig(nx=48, ny=64)
+    T = 0.3
+    uv = inputs.seed_batch(cfg, [6], rms=1e-3)
+    r = rt().Context(cfg, max_steps=1024)
+    pol = rt().Policy(CKPT_UNIFORM, 16)
+    R1, g1, n1 = r.grad_u0(uv, T, pol)
+    R2, g2, n2 = r.grad_u0(uv, T, pol)
+    np.testing.assert_array_equal(host(g1), host(g2))
+    np.testing.assert_array_equal(host(R1), host(R2))
+    Rs, gs, ns = r.grad_u0(np.roll(uv, 11, axis=3), T, pol)
+    assert int(host(ns)[0]) == int(host(n1)[0])
+    assert abs(float(host(Rs)[0]) - float(host(R1)[0])) <= 1e-14 * float(host(R1)[0])
+    assert normwise(host(gs), np.roll(host(g1), 11, axis=3)) <= 1e-13

@@ -347,11 +347,14 @@ def test_projection_dot_axpy_match_oracle():
     np.testing.assert_allclose(z, uv * np.array([1.5, -1.0])[:, None, None, None], rtol=1e-15)
 
 
-def test_unphysical_state_is_reported():
+@pytest.mark.parametrize("var,value", [(3, -1.0), (0, -0.5), (0, float("nan")), (2, float("inf"))],
+                         ids=["negative-energy", "negative-density", "nan-density", "inf-momentum"])
+def test_unphysical_state_is_reported(var, value):
+    # forced from the host into one cell of the state
     cfg = RTConfig(nx=32, ny=32)
     r = rt().Context(cfg, max_steps=64)
     U = r.init_state(inputs.seed_batch(cfg, [0]))
-    U[0, 3, 10, 10] = -1.0  # negative energy -> negative pressure, forced from the host
+    U[0, var, 10, 10] = value
     with pytest.raises(rt().RTError) as e:
         r.integrate(U, 0.01)
     assert e.value.code == -4

@@ -780,7 +780,7 @@ int grad_objective(rt_ctx* c, const double* uv0, double T, const rt_ckpt_policy*
   RT_HIP(hipStreamSynchronize(s));
   if (!ek_base)
     for (double k : hke0)
-      if (!(k > 0.0)) return fail(RT_EINVAL, "KE(0) = %g: the perturbation is zero", k);
+      if (!(k > 0.0) || !std::isfinite(k)) return fail(RT_EINVAL, "KE(0) = %g: the perturbation is zero or not finite", k);
   const int nmax = *std::max_element(hn.begin(), hn.end());
 
   // terminal adjoint lambda^N into L0 (from U^N in L1)

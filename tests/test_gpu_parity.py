@@ -373,6 +373,11 @@ def test_pool_too_small_and_zero_perturbation_are_rejected():
     with pytest.raises(rt().RTError) as e:
         r.grad_u0(np.zeros_like(uv), 0.1)
     assert e.value.code == -1
+    bad = uv.copy()
+    bad[0, 1, 5, 5] = np.nan
+    with pytest.raises(rt().RTError) as e:
+        r.grad_u0(bad, 0.1)
+    assert e.value.code in (-1, -4)
 
 
 def test_graph_replays_match_eager_launches_bitwise():

@@ -53,6 +53,10 @@ def parse():
                     help="run the kernel autotuner, then keep the fastest of its pick and two fixed pairs on a "
                          "full gradient each (default: the library's measured defaults, so that a profile of "
                          "this command sees the same kernels)")
+    ap.add_argument("--dt-mode", choices=("frozen", "differentiated"), default="frozen",
+                    help="time steps in the gradient: held at the forward run's (default) or differentiated")
+    ap.add_argument("--recon", choices=("primitive", "balanced"), default="primitive",
+                    help="reconstruction: primitive MC (default) or the well-balanced variant")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--kernel-launches", type=int, default=300)
@@ -115,13 +119,18 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    cfg = RTConfig(nx=args.nx, ny=args.ny)
+    from paper_2608_04085_amd.config import RECON_BALANCED, RECON_PRIMITIVE
+
+    cfg = RTConfig(nx=args.nx, ny=args.ny, recon=RECON_BALANCED if args.recon == "balanced" else RECON_PRIMITIVE)
+    # the committed counter runs cover the default kernels only
+    counters_apply = args.dt_mode == "frozen" and args.recon == "primitive"
     T = args.T
     ctx = Context(cfg, max_steps=16384, tile=args.tile)
     if args.tiles:
         ctx.set_tiles(*args.tiles.split("/"))
     if args.fold is not None:
         ctx.set_fold(bool(args.fold))
+    ctx.set_dt_mode(args.dt_mode)
     cells = cfg.nx * cfg.ny
 
     # seed and step count
@@ -223,7 +232,8 @@ def main():
     achieved = dom["bytes_per_cell"] * cells / dom["t"] / 1e9
     from paper_2608_04085_amd import profiling
 
-    traffic = profiling.traffic_for(f"grad_{cfg.nx}x{cfg.ny}", dom["traffic_key"], ctx.tile)
+    traffic = (profiling.traffic_for(f"grad_{cfg.nx}x{cfg.ny}", dom["traffic_key"], ctx.tile)
+               if counters_apply else None)
     roofline = {
         "bound": "hbm",
         "achieved": round(achieved, 2),
@@ -235,11 +245,15 @@ def main():
         "kernel": dom["kernel"],
         "launch_us": round(dom["t"] * 1e6, 3),
         "kernel_times_us": {k: round(v, 3) for k, v in kt.items()},
+        **({} if args.dt_mode == "frozen" else
+           {"note": "launch_us and kernel_times_us time the frozen-step kernels; the differentiated sweep adds its "
+                    "step-size partial sums to kernel A and one small kernel per step"}),
         "fwd_share_of_iteration": round(fw_share / per_iter, 3),
         "adj_share_of_iteration": round(adj_share / per_iter, 3),
     }
     # the fused forward step of the march beside it, on the same terms
-    t_step_traffic = profiling.traffic_for(f"grad_{cfg.nx}x{cfg.ny}", "step_march", ctx.tile)
+    t_step_traffic = (profiling.traffic_for(f"grad_{cfg.nx}x{cfg.ny}", "step_march", ctx.tile)
+                      if counters_apply else None)
     achieved_step = FWD_BYTES_PER_CELL * cells / t_march / 1e9
     roofline_step = {
         "bound": "hbm",

@@ -21,7 +21,8 @@ import torch
 
 from oracle.rto import Oracle, lib
 from paper_2608_04085_amd import inputs
-from paper_2608_04085_amd.config import CKPT_REVOLVE, CKPT_UNIFORM, RECON_BALANCED, RTConfig, paper_preset
+from paper_2608_04085_amd.config import (CKPT_REVOLVE, CKPT_UNIFORM, NORM_L2, NORM_RHO_KE, NORM_RMS, RECON_BALANCED,
+                                         SET_BALL, SET_SPHERE, RTConfig, paper_preset)
 
 pytestmark = pytest.mark.gpu
 
@@ -132,6 +133,10 @@ def test_ensemble_128x256x64_matches_oracle_and_solo_runs():
     assert np.max(np.abs(I1[0] - I0[0]) / I0[0]) <= 1e-12
     assert np.max(np.abs(I1[1] - I0[1]) / I0[0]) <= 1e-12
     assert np.max(np.abs(I1[2] - I0[2]) / I0[2]) <= 1e-12
+    # the mixing width (Eqs. 13-14) of every member's final state
+    h = host(r.mix_width(UT))
+    ho = Oracle.from_config(cfg).mix_width(host(UT))
+    np.testing.assert_allclose(h, ho, rtol=1e-13)
 
     # sampled members against the oracle (one Gaussian, one Fourier mode
     # kx = 7 at phase pi/2) and against solo GPU runs
@@ -176,6 +181,33 @@ def test_cnop_512x1024x8_steps_match_oracle():
     err = normwise(host(U), Uo)
     print("512x1024x8, 5 steps: normwise", err)
     assert err <= 1e-10
+
+
+def test_cnop_512x1024x8_search_arithmetic_matches_oracle():
+    # Eq. 11 on the search's batch in every norm and set, and the inner
+    # products, largest magnitude and axpy of the SPG step
+    cfg = RTConfig(nx=512, ny=1024, batch=8)
+    o = Oracle.from_config(cfg)
+    r = rt().Context(cfg, max_steps=8)
+    uv = inputs.seed_batch(cfg, range(8), rms=1.0)
+    for norm in (NORM_L2, NORM_RMS, NORM_RHO_KE):
+        for kind in (SET_SPHERE, SET_BALL):
+            delta = 1e-6 if norm == NORM_RHO_KE else 1e-3
+            out, m = r.project_to_constraint(uv, delta, norm, kind)
+            outo, mo = o.project_to_constraint(uv, delta, norm, kind)
+            # the norms are sums of 2^20 terms taken in different orders
+            # (a two-pass tree against the oracle's running sum), whose
+            # rounding differs by about sqrt(2^20) eps ~ 1e-13: they and the
+            # scale factors are held to 5e-13
+            np.testing.assert_allclose(host(m), mo, rtol=5e-13)
+            assert normwise(host(out), outo) <= 5e-13, (norm, kind)
+    w = uv[::-1].copy()
+    np.testing.assert_allclose(host(r.dot(uv, w)), np.sum(uv * w, axis=(1, 2, 3)), rtol=1e-12)
+    np.testing.assert_array_equal(host(r.max_abs(uv)), np.max(np.abs(uv), axis=(1, 2, 3)))
+    alpha = np.linspace(-2.0, 2.0, 8)
+    # one fused multiply-add against numpy's two roundings: within 2 eps of |x| + |alpha y|
+    aw = alpha[:, None, None, None] * w
+    assert np.all(np.abs(host(r.axpy(uv, alpha, w)) - (uv + aw)) <= 2.3e-16 * (np.abs(uv) + np.abs(aw)))
 
 
 def test_cnop_512x1024x8_gradient_revolve_uniform_and_fd():

@@ -345,11 +345,12 @@ def _golden(name):
 
 @pytest.mark.parametrize("name,entry_tol", [("oracle_gradient_64x128_T2.txt", 1e-9),
                                              ("oracle_gradient_128x256_T2.txt", 1e-6),
-                                             ("oracle_gradient_J_paper128_T2.txt", 1e-9)])
+                                             ("oracle_gradient_J_paper128_T2.txt", 1e-9),
+                                             ("oracle_gradient_J_paper256_T2.txt", 1e-7)])
 def test_long_march_gradient_matches_the_oracle(name, entry_tol):
     # The gradient of R over 1210 (64 x 128) and 2419 (128 x 256) CFL
     # steps to T = 2, and of the paper's J (Eq. 8) on its physics at
-    # 128 x 128 to T = 2, against the oracle's reverse-mode AD through the
+    # 128 x 128 and 256 x 256 to T = 2, against the oracle's reverse-mode AD through the
     # same march, stored by tests/golden/make_oracle_gradients.py: inner
     # products with eight seeded directions, the norm and sampled entries
     # (the 32 largest and 32 seeded ones), with the benchmark's snapshot
@@ -362,6 +363,10 @@ def test_long_march_gradient_matches_the_oracle(name, entry_tol):
     # Each side's gradient is the exact derivative of its own branch; they
     # differ by 3.6e-7 of the largest entry, spread over the lower half of
     # the domain, which moves the inner products and the norm by <= 1e-10.
+    # The paper's J at 256 x 256 (3091 steps) has such ties at steps 171-172
+    # and 268 in the quiescent heavy fluid (rows 217 and 232, where the
+    # limiter's tie tolerance decides) and two smaller ones later; sampled
+    # entries differ by 5.4e-9 of the largest, inner products by 5e-14.
     ref = _golden(name)
     T = ref["T"]
     paper = "_J_paper" in name

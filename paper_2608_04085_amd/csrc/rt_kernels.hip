@@ -311,11 +311,30 @@ __device__ __forceinline__ int predict_store(const Params& P, LDS& S, int k, int
 // other; whether a wavefront has a second position is uniform across it.
 // PAIR costs registers: the step kernel has them to spare, the adjoint
 // kernel would drop to two wavefronts per SIMD.
-template <int TX, int TY, int NT, bool BAL, bool CODES, bool PAIR, class LDS>
+//
+// ALIAS: the predicted states overwrite the primitive tile they are computed
+// from (one LDS region serves both): every thread computes its positions
+// (two at most) into registers, the block waits until all have read the
+// primitives, then the results are stored.
+template <int TX, int TY, int NT, bool BAL, bool CODES, bool PAIR, bool ALIAS = false, class LDS>
 __device__ int tile_predict(const Params& P, double dt, int x0, int y0, LDS& S, int32_t* codes_out) {
   constexpr int QN = (TX + 2) * (TY + 2);
   const double hx = 0.5 * dt * P.inv_dx, hy = 0.5 * dt * P.inv_dy, hg = 0.5 * dt * P.g_y;
   int bad = 0;
+  if constexpr (ALIAS) {
+    static_assert(PAIR && !CODES && QN <= 2 * NT, "one pass of at most two positions per thread");
+    const int k = threadIdx.x;
+    const int wave_first = k - (int)(threadIdx.x & 63);
+    W4 q, sx, sy, q2 = W4{}, sx2 = W4{}, sy2 = W4{};
+    int cx = 0, cy = 0, cx2 = 0, cy2 = 0;
+    const bool v1 = predict_at<TX, TY, BAL, CODES>(P, S, k, y0, hx, hy, hg, q, sx, sy, cx, cy);
+    bool v2 = false;
+    if (wave_first + NT < QN) v2 = predict_at<TX, TY, BAL, CODES>(P, S, k + NT, y0, hx, hy, hg, q2, sx2, sy2, cx2, cy2);
+    __syncthreads();  // the primitives are read: their space takes the predicted states
+    if (v1) bad |= predict_store<TX, TY, CODES>(P, S, k, x0, y0, q, sx, sy, cx, cy, codes_out);
+    if (v2) bad |= predict_store<TX, TY, CODES>(P, S, k + NT, x0, y0, q2, sx2, sy2, cx2, cy2, codes_out);
+    return bad;
+  }
   for (int k = threadIdx.x; k < QN; k += (PAIR ? 2 : 1) * NT) {
     const int wave_first = k - (int)(threadIdx.x & 63);
     W4 q, sx, sy;
@@ -358,10 +377,60 @@ __device__ __forceinline__ FS yface_bottom_of(const LDS& S, int x, int y) {
             S.Q[3][y][x] - 0.5 * S.Q[11][y][x]};
 }
 
+// Flux of face item k of the step's phase C (x faces first, padded to NXP
+// items, then y faces) from the predicted states; returns 1 for an x face,
+// 2 for a y face, 0 for padding or a face outside the domain.
+template <int TX, int TY, class LDS>
+__device__ __forceinline__ int step_face_flux(const Params& P, const LDS& S, int k, int y0, double out[4]) {
+  constexpr int NXF = (TX + 1) * TY, NXP = (NXF + 63) / 64 * 64, NYF = TX * (TY + 1);
+  if (k < NXP) {
+    if (k >= NXF) return 0;
+    const int fx = k % (TX + 1), fy = k / (TX + 1);
+    if (y0 + fy >= P.ny) return 0;
+    const int l = fx, r = fx + 1, y = fy + 1;
+    const FS L{S.Q[0][y][l] + 0.5 * S.Q[4][y][l], S.Q[1][y][l] + 0.5 * S.Q[5][y][l],
+               S.Q[2][y][l] + 0.5 * S.Q[6][y][l], S.Q[3][y][l] + 0.5 * S.Q[7][y][l]};
+    const FS R{S.Q[0][y][r] - 0.5 * S.Q[4][y][r], S.Q[1][y][r] - 0.5 * S.Q[5][y][r],
+               S.Q[2][y][r] - 0.5 * S.Q[6][y][r], S.Q[3][y][r] - 0.5 * S.Q[7][y][r]};
+    hllc(P, L, R, out);
+    return 1;
+  }
+  const int kk = k - NXP;
+  if (kk >= NYF) return 0;
+  const int fx = kk % TX, fy = kk / TX;
+  const int j = y0 + fy;
+  if (j > P.ny) return 0;
+  const int x = fx + 1, d = fy, u = fy + 1;
+  out[0] = 0.0;
+  out[1] = 0.0;
+  out[3] = 0.0;
+  if (j == 0) {
+    const FS A{S.Q[0][u][x] - 0.5 * S.Q[8][u][x], S.Q[2][u][x] - 0.5 * S.Q[10][u][x],
+               S.Q[1][u][x] - 0.5 * S.Q[9][u][x], S.Q[3][u][x] - 0.5 * S.Q[11][u][x]};
+    out[2] = wall_pressure(P, A, false);
+  } else if (j == P.ny) {
+    const FS Bs{S.Q[0][d][x] + 0.5 * S.Q[8][d][x], S.Q[2][d][x] + 0.5 * S.Q[10][d][x],
+                S.Q[1][d][x] + 0.5 * S.Q[9][d][x], S.Q[3][d][x] + 0.5 * S.Q[11][d][x]};
+    out[2] = wall_pressure(P, Bs, true);
+  } else {
+    const FS Bs{S.Q[0][d][x] + 0.5 * S.Q[8][d][x], S.Q[2][d][x] + 0.5 * S.Q[10][d][x],
+                S.Q[1][d][x] + 0.5 * S.Q[9][d][x], S.Q[3][d][x] + 0.5 * S.Q[11][d][x]};
+    const FS A{S.Q[0][u][x] - 0.5 * S.Q[8][u][x], S.Q[2][u][x] - 0.5 * S.Q[10][u][x],
+               S.Q[1][u][x] - 0.5 * S.Q[9][u][x], S.Q[3][u][x] - 0.5 * S.Q[11][u][x]};
+    double f[4];
+    hllc(P, Bs, A, f);
+    out[0] = f[0];
+    out[1] = f[2];
+    out[2] = f[1];
+    out[3] = f[3];
+  }
+  return 2;
+}
+
 // ----------------------------------------------------------------- step
 // LDS of the step kernel: the flux arrays reuse the primitive tile, which is
 // dead once the predictor has run.
-template <int TX, int TY>
+template <int TX, int TY, bool ALIAS = false>
 struct StepLDS {
   static constexpr int AX = TX + 4, AY = TY + 4;
   static constexpr int QX = TX + 2, QY = TY + 2;
@@ -374,11 +443,26 @@ struct StepLDS {
   };
   double Q[12][QY][QX];
 };
+// ALIAS: one region by phase (primitives, then predicted states and slopes,
+// then fluxes), for a fourth resident block per CU on large grids.
+template <int TX, int TY>
+struct StepLDS<TX, TY, true> {
+  static constexpr int AX = TX + 4, AY = TY + 4;
+  static constexpr int QX = TX + 2, QY = TY + 2;
+  union {
+    double W[5][AY][AX];
+    double Q[12][QY][QX];
+    struct {
+      double F[4][TY][TX + 1];
+      double G[4][TY + 1][TX];
+    } fg;
+  };
+};
 
-template <int TX, int TY, int NT, bool BAL>
+template <int TX, int TY, int NT, bool BAL, bool ALIAS = false>
 __global__ __launch_bounds__(NT) void k_step(Params P, StepArgs a) {
   static_assert(NT >= TX * TY && NT % 64 == 0, "one thread per tile cell at least");
-  __shared__ StepLDS<TX, TY> S;
+  __shared__ StepLDS<TX, TY, ALIAS> S;
   __shared__ double sRed[NT / 64];
 
   const int b = blockIdx.z;
@@ -452,7 +536,7 @@ __global__ __launch_bounds__(NT) void k_step(Params P, StepArgs a) {
   __syncthreads();
 
   // phase B: slopes and predictor on the cross-shaped halo-1 region
-  bad |= tile_predict<TX, TY, NT, BAL, false, true>(P, dt, x0, y0, S, nullptr);
+  bad |= tile_predict<TX, TY, NT, BAL, false, true, ALIAS>(P, dt, x0, y0, S, nullptr);
   __syncthreads();
 
   // phase C: every face of the tile once (x faces, then y faces).  The x
@@ -460,7 +544,34 @@ __global__ __launch_bounds__(NT) void k_step(Params P, StepArgs a) {
   // x and the y branch (which would put two flux evaluations in series).
   constexpr int NXF = (TX + 1) * TY, NYF = TX * (TY + 1);
   constexpr int NXP = (NXF + 63) / 64 * 64;
-  for (int k = tid; k < NXP + NYF; k += NT) {
+  if constexpr (ALIAS) {
+    // the fluxes overwrite the predicted states: all faces of this thread
+    // first, then the stores once every thread has read its states
+    constexpr int FMAX = (NXP + NYF + NT - 1) / NT;
+    double fl[FMAX][4];
+    int kind[FMAX];
+#pragma unroll
+    for (int it = 0; it < FMAX; ++it) kind[it] = step_face_flux<TX, TY>(P, S, tid + it * NT, y0, fl[it]);
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < FMAX; ++it) {
+      const int k = tid + it * NT;
+      if (kind[it] == 1) {
+        const int fx = k % (TX + 1), fy = k / (TX + 1);
+        S.fg.F[0][fy][fx] = fl[it][0];
+        S.fg.F[1][fy][fx] = fl[it][1];
+        S.fg.F[2][fy][fx] = fl[it][2];
+        S.fg.F[3][fy][fx] = fl[it][3];
+      } else if (kind[it] == 2) {
+        const int kk = k - NXP, fx = kk % TX, fy = kk / TX;
+        S.fg.G[0][fy][fx] = fl[it][0];
+        S.fg.G[1][fy][fx] = fl[it][1];
+        S.fg.G[2][fy][fx] = fl[it][2];
+        S.fg.G[3][fy][fx] = fl[it][3];
+      }
+    }
+  }
+  for (int k = tid; !ALIAS && k < NXP + NYF; k += NT) {
     if (k < NXP) {
       if (k >= NXF) continue;
       const int fx = k % (TX + 1), fy = k / (TX + 1);
@@ -1396,13 +1507,25 @@ int step_blocks(const Params& P, int tile) {
   return ((P.nx + tx - 1) / tx) * ((P.ny + ty - 1) / ty);
 }
 
+#ifndef RT_ALIAS_MODE
+#define RT_ALIAS_MODE 2
+#endif
 template <int TX, int TY, int NT>
 static hipError_t launch_step_t(const Params& P, const StepArgs& a, hipStream_t s) {
   dim3 grid((P.nx + TX - 1) / TX, (P.ny + TY - 1) / TY, P.nb);
-  if (P.recon == 1)
-    hipLaunchKernelGGL((k_step<TX, TY, NT, true>), grid, dim3(NT), 0, s, P, a);
-  else
-    hipLaunchKernelGGL((k_step<TX, TY, NT, false>), grid, dim3(NT), 0, s, P, a);
+  const long blocks = (long)grid.x * grid.y * grid.z;
+  const bool alias = RT_ALIAS_MODE == 1 || (RT_ALIAS_MODE == 2 && blocks > 3L * 256);
+  if (P.recon == 1) {
+    if (alias)
+      hipLaunchKernelGGL((k_step<TX, TY, NT, true, true>), grid, dim3(NT), 0, s, P, a);
+    else
+      hipLaunchKernelGGL((k_step<TX, TY, NT, true, false>), grid, dim3(NT), 0, s, P, a);
+  } else {
+    if (alias)
+      hipLaunchKernelGGL((k_step<TX, TY, NT, false, true>), grid, dim3(NT), 0, s, P, a);
+    else
+      hipLaunchKernelGGL((k_step<TX, TY, NT, false, false>), grid, dim3(NT), 0, s, P, a);
+  }
   return hipGetLastError();
 }
 

@@ -789,3 +789,24 @@ def test_gradient_is_deterministic_and_shift_equivariant():
     assert int(host(ns)[0]) == int(host(n1)[0])
     assert abs(float(host(Rs)[0]) - float(host(R1)[0])) <= 1e-14 * float(host(R1)[0])
     assert normwise(host(gs), np.roll(host(g1), 11, axis=3)) <= 1e-13
+
+
+def test_both_step_layouts_give_the_same_bits_on_every_tile():
+    # A batch of 8 members at 256 x 128 launches more blocks than three per
+    # CU hold on every tile shape, so the step kernel shares one LDS region
+    # between its phases; each member alone launches few blocks and takes
+    # the separate-buffer form.  Same arithmetic, so the same bits.
+    cfg = RTConfig(nx=256, ny=128, batch=8)
+    uv = inputs.seed_batch(cfg, range(8), rms=1e-2)
+    solo_cfg = cfg.with_(batch=1)
+    ref = []
+    solo = rt().Context(solo_cfg, max_steps=512, tile="32x8")
+    for b in (0, 5):
+        U, _, n, _ = solo.integrate(solo.init_state(uv[b : b + 1]), 0.05)
+        ref.append((host(U)[0], int(host(n)[0])))
+    for tile in TILE_NAMES:
+        r = rt().Context(cfg, max_steps=512, tile=tile)
+        U, _, n, _ = r.integrate(r.init_state(uv), 0.05)
+        for (Us, ns), b in zip(ref, (0, 5)):
+            assert int(host(n)[b]) == ns
+            np.testing.assert_array_equal(host(U)[b], Us, err_msg=tile)

@@ -30,6 +30,9 @@
 //                      included
 //   rto_project_to_constraint  scaling onto the constraint set (Eq. 11)
 //   rto_hllc, rto_wall_pressure  single-face fluxes for unit tests
+//   rto_mc_slope, rto_slopes, rto_predict  one limited slope (with its
+//                      derivatives), the four slopes of a cell, and the
+//                      MUSCL-Hancock half step of one cell, for unit tests
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -39,8 +42,10 @@
 #include "rto_scheme.hpp"
 
 namespace rto {
+// One tape per thread, so that independent reverse-mode calls (the adjoints
+// of separate members or blocks) may run on separate threads.
 Tape& tape() {
-  static Tape t;
+  static thread_local Tape t;
   return t;
 }
 }  // namespace rto
@@ -56,7 +61,7 @@ constexpr int kEUnphys = -4;
 
 bool valid(const Problem* P) {
   return P && P->nx >= 3 && P->ny >= 2 && P->nb >= 1 && P->lx > 0 && P->ly > 0 && P->gamma > 1.0 &&
-         P->h > 0 && P->cfl > 0 && (P->recon == 0 || P->recon == 1);
+         P->h > 0 && P->cfl > 0 && (P->recon == 0 || P->recon == 1) && P->tie_tol >= 0.0 && P->tie_tol < 1e-3;
 }
 size_t cells(const Problem* P) { return static_cast<size_t>(P->nx) * P->ny; }
 
@@ -585,10 +590,11 @@ int rto_project_to_constraint(const Problem* P, double* uv, double delta, int32_
 
 // Single-face HLLC flux in face-normal order (mass, normal momentum,
 // tangential momentum, energy); states are (rho, normal vel., tangential
-// vel., p).
+// vel., p).  The workloads' tie tolerance (1e-10) applies.
 int rto_hllc(double gamma, const double* L, const double* Rr, double* flux) {
   Problem P{};
   P.gamma = gamma;
+  P.tie_tol = 1e-10;
   const std::array<double, 4> f =
       rto::hllc<double>(P, rto::FaceState<double>{L[0], L[1], L[2], L[3]},
                         rto::FaceState<double>{Rr[0], Rr[1], Rr[2], Rr[3]});
@@ -599,7 +605,53 @@ int rto_hllc(double gamma, const double* L, const double* Rr, double* flux) {
 double rto_wall_pressure(double gamma, const double* w, int32_t interior_left) {
   Problem P{};
   P.gamma = gamma;
+  P.tie_tol = 1e-10;
   return rto::wall_pressure<double>(P, rto::FaceState<double>{w[0], w[1], w[2], w[3]}, interior_left != 0);
+}
+
+// One monotonized-central limited slope from the differences a, b, with
+// differences of magnitude <= tol counting as zero: out[0] the slope,
+// out[1] = d slope / d a and out[2] = d slope / d b on the selected case
+// (forward-mode AD of mc_slope).
+int rto_mc_slope(double a, double b, double tol, double* out) {
+  if (!out || !(tol >= 0.0)) return kEInval;
+  auto small = [tol](double d) { return std::fabs(d) <= tol; };
+  const Dual sa = rto::mc_slope(Dual(a, 1.0), Dual(b, 0.0), small);
+  const Dual sb = rto::mc_slope(Dual(a, 0.0), Dual(b, 1.0), small);
+  out[0] = sa.v;
+  out[1] = sa.d;
+  out[2] = sb.d;
+  return 0;
+}
+
+// The limited slopes (rho, u, v, p) of the cell w between its neighbours wm
+// (below / left) and wp (above / right), with the problem's tie tolerance
+// scaled by the cell's density, pressure and sound speed; balanced != 0 takes
+// the y slopes of the well-balanced variant.  Arrays of 4 primitives.
+int rto_slopes(const Problem* P, const double* wm, const double* w, const double* wp, int32_t balanced,
+               double* s) {
+  if (!valid(P) || !wm || !w || !wp || !s) return kEInval;
+  const rto::Prim<double> a{wm[0], wm[1], wm[2], wm[3]}, c{w[0], w[1], w[2], w[3]}, b{wp[0], wp[1], wp[2], wp[3]};
+  const rto::Prim<double> r = balanced ? rto::mc_slope_y_balanced(*P, a, c, b) : rto::mc_slope(*P, a, c, b);
+  s[0] = r.r;
+  s[1] = r.u;
+  s[2] = r.v;
+  s[3] = r.p;
+  return 0;
+}
+
+// The MUSCL-Hancock half step of one cell: primitives w, slopes sx and sy
+// (per cell width), step dt; q receives W^{n+1/2}.
+int rto_predict(const Problem* P, const double* w, const double* sx, const double* sy, double dt, double* q) {
+  if (!valid(P) || !w || !sx || !sy || !q) return kEInval;
+  const rto::Prim<double> r = rto::predict_half_step(
+      *P, rto::Prim<double>{w[0], w[1], w[2], w[3]}, rto::Prim<double>{sx[0], sx[1], sx[2], sx[3]},
+      rto::Prim<double>{sy[0], sy[1], sy[2], sy[3]}, dt);
+  q[0] = r.r;
+  q[1] = r.u;
+  q[2] = r.v;
+  q[3] = r.p;
+  return 0;
 }
 
 // Background profiles at the cell centres of row j (Eq. 5 and the

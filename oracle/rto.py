@@ -22,6 +22,11 @@ _ip = ctypes.POINTER(ctypes.c_int32)
 
 ERRORS = {-1: "invalid argument", -3: "capacity too small", -4: "unphysical state"}
 
+# Relative tie tolerance of the scheme's discrete decisions used by the
+# workloads (Problem.tie_tol; 0 gives the plain limiter and Riemann-solver
+# decisions).
+TIE_TOL = 1e-10
+
 
 class Problem(ctypes.Structure):
     """Mirror of the oracle's ``rto::Problem`` (plain numbers only)."""
@@ -35,6 +40,7 @@ class Problem(ctypes.Structure):
         ("y0", ctypes.c_double), ("h", ctypes.c_double),
         ("p_int", ctypes.c_double), ("cfl", ctypes.c_double),
         ("recon", ctypes.c_int32), ("pad", ctypes.c_int32),
+        ("tie_tol", ctypes.c_double),
     ]
 
 
@@ -71,6 +77,9 @@ def lib():
             "rto_objective_adaptive": [P, _dp, ctypes.c_double, _dp, _dp, _ip],
             "rto_grad_adaptive": [P, _dp, ctypes.c_double, _dp, _dp, _dp, _ip],
             "rto_hllc": [ctypes.c_double, _dp, _dp, _dp],
+            "rto_mc_slope": [ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp],
+            "rto_slopes": [P, _dp, _dp, _dp, ctypes.c_int32, _dp],
+            "rto_predict": [P, _dp, _dp, _dp, ctypes.c_double, _dp],
             "rto_background": [P, _dp, _dp],
         }
         for name, args in sig.items():
@@ -105,11 +114,14 @@ class Oracle:
     prob: Problem
 
     @classmethod
-    def from_config(cls, cfg, nb: int | None = None):
+    def from_config(cls, cfg, nb: int | None = None, tie_tol: float | None = None):
+        """The oracle for an RTConfig; tie_tol None takes the workloads'
+        tolerance TIE_TOL, 0 the plain decisions (see rto_scheme.hpp)."""
         p = Problem(
             nx=cfg.nx, ny=cfg.ny, nb=cfg.batch if nb is None else nb, comp_mask=cfg.comp_mask,
             lx=cfg.lx, ly=cfg.ly, gamma=cfg.gamma, g_y=cfg.g_y, rho_h=cfg.rho_h, rho_l=cfg.rho_l,
             y0=cfg.y0, h=cfg.h, p_int=cfg.p_int, cfl=cfg.cfl, recon=getattr(cfg, "recon", 0),
+            tie_tol=TIE_TOL if tie_tol is None else float(tie_tol),
         )
         return cls(p)
 
@@ -305,3 +317,30 @@ def hllc(gamma, left, right):
 def wall_pressure(gamma, state, interior_left: bool):
     s = np.ascontiguousarray(state, dtype=np.float64)
     return lib().rto_wall_pressure(float(gamma), _p(s), 1 if interior_left else 0)
+
+
+def mc_slope(a, b, tol=0.0):
+    """(slope, d slope/d a, d slope/d b) of the monotonized-central limiter
+    for the differences a, b; |d| <= tol counts as zero."""
+    out = np.empty(3)
+    _check(lib().rto_mc_slope(float(a), float(b), float(tol), _p(out)), "mc_slope")
+    return out[0], out[1], out[2]
+
+
+def _w4(x):
+    return np.ascontiguousarray(np.asarray(x, dtype=np.float64).reshape(4))
+
+
+def slopes(o: "Oracle", wm, w, wp, balanced: bool = False):
+    """Limited slopes (rho, u, v, p) of the cell w between wm and wp."""
+    s = np.empty(4)
+    _check(lib().rto_slopes(ctypes.byref(o.prob), _p(_w4(wm)), _p(_w4(w)), _p(_w4(wp)), 1 if balanced else 0,
+                            _p(s)), "slopes")
+    return s
+
+
+def predict(o: "Oracle", w, sx, sy, dt):
+    """MUSCL-Hancock half step W^{n+1/2} of one cell (primitives, slopes per cell width)."""
+    q = np.empty(4)
+    _check(lib().rto_predict(ctypes.byref(o.prob), _p(_w4(w)), _p(_w4(sx)), _p(_w4(sy)), float(dt), _p(q)), "predict")
+    return q

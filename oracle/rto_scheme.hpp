@@ -16,8 +16,9 @@
 //     gravity source (Sec. 2.3).  The paper names neither the reconstruction
 //     nor the time integrator; this is the unsplit primitive-variable
 //     MUSCL-Hancock scheme with piecewise-linear, monotonized-central (MC)
-//     limited slopes (differences below 1e-10 of the local scale count as
-//     zero), and the plain HLLC flux with Davis wave-speed bounds
+//     limited slopes (differences below a relative tolerance of the local
+//     scale count as zero, 1e-10 for the workloads; Problem::tie_tol), and the
+//     plain HLLC flux with Davis wave-speed bounds
 //     (the "hybrid" qualifier in Sec. 2.3 is not explained there, so no HLL
 //     switch is applied).
 //   * Gravity source, second order in time and chosen so that total energy
@@ -57,6 +58,7 @@ struct Problem {
   double p_int;               // pressure at the interface height y0
   double cfl;
   int recon, pad;             // recon 1: well-balanced variant (see above)
+  double tie_tol;             // relative tie tolerance of the discrete decisions (see below); 0: none
 };
 
 inline double dx_of(const Problem& P) { return P.lx / P.nx; }
@@ -121,15 +123,17 @@ bool bad_state(const Prim<T>& w) {
   return !(r > 0.0) || !(p > 0.0) || !std::isfinite(val(w.u)) || !std::isfinite(val(w.v));
 }
 
-// Relative tolerance below which a difference counts as zero when the scheme
-// takes a discrete decision (limiter case, upwind side, wave-speed choice).
-// Decisions on differences at the level of round-off would otherwise be
-// taken at random and make the discrete derivative of the march erratic:
-// the linearisation of the compressive limiter branches amplifies grid-scale
-// perturbations, so two correct implementations that differ by one ulp in a
-// quiescent region would produce different gradients.  The forward state
-// changes by at most this tolerance, relative.
-constexpr double kTieTol = 1e-10;
+// Problem::tie_tol is the relative tolerance below which a difference counts
+// as zero when the scheme takes a discrete decision (limiter case, upwind
+// side, wave-speed choice).  With 0 the decisions are the plain ones (MC
+// with a*b <= 0 as the only zero case, Davis min/max, the sign of S*).  The
+// workloads use 1e-10: decisions on differences at the level of round-off
+// would otherwise be taken at random and make the discrete derivative of
+// the march erratic (the linearisation of the compressive limiter branches
+// amplifies grid-scale perturbations, so two correct implementations that
+// differ by one ulp in a quiescent region would produce different
+// gradients).  A slope or speed that the tolerance zeroes or switches was
+// itself within that relative distance of zero or of the other case.
 
 // Monotonized-central limited slope of one variable from its backward and
 // forward differences a, b: zero at an extremum (a*b <= 0) or when either
@@ -146,14 +150,14 @@ T mc_slope(const T& a, const T& b, Small small) {
   return 2.0 * b;
 }
 
-// Slopes of the four primitives.  A difference is negligible below kTieTol
+// Slopes of the four primitives.  A difference is negligible below tie_tol
 // times the cell's own density (density slope), pressure (pressure slope)
 // or sound speed c = sqrt(gamma p / rho) (velocity slopes; compared as
-// d^2 rho <= kTieTol^2 gamma p).
+// d^2 rho <= tie_tol^2 gamma p).
 template <class T>
 Prim<T> mc_slope(const Problem& P, const Prim<T>& wm, const Prim<T>& w, const Prim<T>& wp) {
-  const double r = val(w.r), p = val(w.p);
-  const double tr = kTieTol * r, tp = kTieTol * p, tv2 = kTieTol * kTieTol * P.gamma * p;
+  const double r = val(w.r), p = val(w.p), tol = P.tie_tol;
+  const double tr = tol * r, tp = tol * p, tv2 = tol * tol * P.gamma * p;
   auto small_r = [tr](double d) { return std::fabs(d) <= tr; };
   auto small_p = [tp](double d) { return std::fabs(d) <= tp; };
   auto small_v = [tv2, r](double d) { return d * d * r <= tv2; };
@@ -167,7 +171,7 @@ Prim<T> mc_slope(const Problem& P, const Prim<T>& wm, const Prim<T>& w, const Pr
 template <class T>
 Prim<T> mc_slope_y_balanced(const Problem& P, const Prim<T>& wm, const Prim<T>& w, const Prim<T>& wp) {
   Prim<T> s = mc_slope(P, wm, w, wp);
-  const double tp = kTieTol * val(w.p);
+  const double tp = P.tie_tol * val(w.p);
   auto small_p = [tp](double d) { return std::fabs(d) <= tp; };
   const T h = w.r * (P.g_y * dy_of(P));
   s.p = h + mc_slope((w.p - wm.p) - h, (wp.p - w.p) - h, small_p);
@@ -190,8 +194,8 @@ std::array<T, 4> hllc(const Problem& P, const FaceState<T>& L, const FaceState<T
   const double gm = P.gamma;
   const T cL = sqrt(gm * L.p / L.r);
   const T cR = sqrt(gm * R.p / R.r);
-  // Near-ties (within kTieTol of the sound speeds) resolve to the left state.
-  const double tie = kTieTol * (val(cL) + val(cR));
+  // Near-ties (within tie_tol of the sound speeds) resolve to the left state.
+  const double tie = P.tie_tol * (val(cL) + val(cR));
   const T aL = L.n - cL, bL = R.n - cR;
   const T SL = val(aL) <= val(bL) + tie ? aL : bL;
   const T aR = L.n + cL, bR = R.n + cR;
@@ -231,9 +235,26 @@ template <class T>
 T wall_pressure(const Problem& P, const FaceState<T>& w, bool interior_left) {
   const T c = sqrt(P.gamma * w.p / w.r);
   // |n|, with normal speeds within the tie tolerance of zero taken as >= 0
-  const T an = val(w.n) < -kTieTol * val(c) ? -w.n : w.n;
+  const T an = val(w.n) < -P.tie_tol * val(c) ? -w.n : w.n;
   if (interior_left) return w.p + w.r * w.n * (an + c + w.n);
   return w.p - w.r * w.n * (an + c - w.n);
+}
+
+// MUSCL-Hancock half step of one cell in primitive variables: the
+// quasi-linear form W_t + A_x(W) W_x + A_y(W) W_y = (0, 0, g_y, 0) of Eqs. 1-4
+// advanced by dt/2 with the limited slopes sx, sy (per cell width) standing
+// in for dx W_x, dy W_y:
+//   A_x dW = (u dr + r du, u du + dp/r, u dv, gamma p du + u dp),
+//   A_y dW = (v dr + r dv, v du, v dv + dp/r, gamma p dv + v dp).
+template <class T, class D>
+Prim<T> predict_half_step(const Problem& P, const Prim<T>& w, const Prim<T>& sx, const Prim<T>& sy, D dt) {
+  const D hx = 0.5 * dt / dx_of(P), hy = 0.5 * dt / dy_of(P);
+  Prim<T> q;
+  q.r = w.r - hx * (w.u * sx.r + w.r * sx.u) - hy * (w.v * sy.r + w.r * sy.v);
+  q.u = w.u - hx * (w.u * sx.u + sx.p / w.r) - hy * (w.v * sy.u);
+  q.v = w.v - hx * (w.u * sx.v) - hy * (w.v * sy.v + sy.p / w.r) + 0.5 * dt * P.g_y;
+  q.p = w.p - hx * (P.gamma * w.p * sx.u + w.u * sx.p) - hy * (P.gamma * w.p * sy.v + w.v * sy.p);
+  return q;
 }
 
 // ------------------------------------------------------------------ one step
@@ -272,12 +293,7 @@ int step_member(const Problem& P, const T* U, T* Un, D dt) {
       const Prim<T> sx = mc_slope(P, Wat((i + nx - 1) % nx, j), w, Wat((i + 1) % nx, j));
       const Prim<T> sy = P.recon == 1 ? mc_slope_y_balanced(P, Wat(i, j - 1), w, Wat(i, j + 1))
                                       : mc_slope(P, Wat(i, j - 1), w, Wat(i, j + 1));
-      const D hx = 0.5 * dt / dx, hy = 0.5 * dt / dy;
-      Prim<T> q;
-      q.r = w.r - hx * (w.u * sx.r + w.r * sx.u) - hy * (w.v * sy.r + w.r * sy.v);
-      q.u = w.u - hx * (w.u * sx.u + sx.p / w.r) - hy * (w.v * sy.u);
-      q.v = w.v - hx * (w.u * sx.v) - hy * (w.v * sy.v + sy.p / w.r) + 0.5 * dt * g;
-      q.p = w.p - hx * (P.gamma * w.p * sx.u + w.u * sx.p) - hy * (P.gamma * w.p * sy.v + w.v * sy.p);
+      const Prim<T> q = predict_half_step(P, w, sx, sy, dt);
       const int c = j * nx + i;
       xl[c] = Prim<T>{q.r - 0.5 * sx.r, q.u - 0.5 * sx.u, q.v - 0.5 * sx.v, q.p - 0.5 * sx.p};
       xr[c] = Prim<T>{q.r + 0.5 * sx.r, q.u + 0.5 * sx.u, q.v + 0.5 * sx.v, q.p + 0.5 * sx.p};

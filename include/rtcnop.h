@@ -94,7 +94,8 @@ typedef struct rt_ctx rt_ctx;
 /* Checkpoint policy of rt_grad_u0 (Sec. 3.4: checkpoints re-computed from a
  * sparse set of saved states).  kind: 0 store every state, 1 a snapshot every
  * `interval` steps with re-computation inside each interval, 2 binomial
- * (revolve) schedule using as many snapshots as `pool_bytes` holds.  The pool
+ * (revolve) checkpointing using as many snapshots as `pool_bytes` holds, in
+ * two levels (see rt_revolve_plan_stats; `interval` is not read).  The pool
  * is caller-owned device memory. */
 typedef struct rt_ckpt_policy {
   int32_t kind, interval;
@@ -148,6 +149,13 @@ int rt_integrate(rt_ctx* ctx, double* U, double T, double* t_out, int32_t* nstep
 
 /* Kinetic energy of each member, ke[B] (device). */
 int rt_kinetic_energy(rt_ctx* ctx, const double* U, double* ke);
+
+/* Growth ratio of the kinetic energy (the objective of Eq. 10 in the
+ * workloads' form): R[b] = KE(UT_b) / KE(U0_b) for the states U0 and UT
+ * ([B][4][ny][nx], device; typically the initial state and the state the
+ * march reached at T).  R[B] is device memory.  A member with KE(U0) = 0
+ * gets inf or NaN; the call does not check it (rt_grad_u0 does). */
+int rt_ke_ratio(rt_ctx* ctx, const double* U0, const double* UT, double* R);
 
 /* Adjoint of one step: lam = (d Phi_dt / dU)(U)^T lam_next with dt[B]
  * (device) held fixed.  Arrays are states [B][4][ny][nx]; lam must not
@@ -305,6 +313,23 @@ int rt_kernel_times(rt_ctx* ctx, const double* U, int32_t reps, double* out);
  * the schedule's count of forward steps, optimum the smallest count any
  * schedule with that many slots can reach.  No context, no device work. */
 int rt_revolve_stats(int32_t nsteps, int32_t slots, int64_t* forward, int64_t* optimum);
+
+/* Host-only check of the plan RT_CKPT_REVOLVE runs (Sec. 3.4's binomial
+ * checkpointing, in two levels): the forward march that evaluates the
+ * objective also leaves a snapshot every `interval` steps, an interval the
+ * library picks from the step count n_est that the initial CFL step
+ * suggests (so that 1.25 n_est steps fit in slots - 1 slots, at the least
+ * re-computation); the reverse sweep then reverses each segment, last
+ * first, with the binomial schedule on the slots left free.  If the march
+ * needs more snapshots than fit, or one binomial schedule over the whole
+ * march from U^0 re-computes less, that schedule runs instead.  For a march
+ * of nsteps steps with `slots` slots: forward receives all forward steps of
+ * the gradient (the objective's march included), interval the level-1
+ * interval, two_level 1 if the two-level plan runs.  Replays the plan as
+ * rt_revolve_stats does (RT_EINVAL if inconsistent).  nsteps >= 1,
+ * slots >= 2, n_est >= 1.  No context, no device work. */
+int rt_revolve_plan_stats(int32_t nsteps, int32_t slots, int32_t n_est, int64_t* forward, int32_t* interval,
+                          int32_t* two_level);
 
 /* Synchronise the stream and report a device-side error flag (RT_EUNPHYS)
  * raised by earlier asynchronous calls; clears the flag. */

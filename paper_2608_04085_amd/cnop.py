@@ -48,10 +48,7 @@ def _l2dv(rt: Context, x: torch.Tensor) -> np.ndarray:
 
 def ke_ratio(rt: Context, uv: torch.Tensor, T: float) -> torch.Tensor:
     """R = KE(T)/KE(0) of every member (forward march only)."""
-    U0 = rt.init_state(uv)
-    ke0 = rt.kinetic_energy(U0)
-    UT, _, _, _ = rt.integrate(U0, T)
-    return rt.kinetic_energy(UT) / ke0
+    return rt.objective_ratio(uv, T)
 
 
 def spg(rt: Context, uv0, T: float, delta: float, iters: int, policy: Policy | None = None,

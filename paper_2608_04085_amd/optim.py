@@ -47,33 +47,77 @@ class LBFGSLog:
     grads: int = 0
 
 
-def _two_loop(be, g, pairs):
-    """H g for the ascent problem from the stored pairs (oldest first)."""
-    q = g
-    alphas = []
-    for s, y, rho in reversed(pairs):
-        a = rho * be.dot(s, q)
-        alphas.append(a)
-        q = be.axpy(q, -a, y)
-    s, y, _ = pairs[-1]
-    yy = be.dot(y, y)
-    gamma = np.where(yy > 0.0, be.dot(s, y) / np.where(yy > 0.0, yy, 1.0), 0.0)
-    r = be.axpy(q, gamma - 1.0, q)  # gamma * q
-    for (s, y, rho), a in zip(pairs, reversed(alphas)):
-        b = rho * be.dot(y, r)
-        r = be.axpy(r, a - b, s)
-    return r
+class _Memory:
+    """Curvature pairs of every member, kept apart per member.
 
+    Pairs are stored batched (one field per pair for all members) with a
+    per-member validity mask; a pair that is not valid for a member enters
+    its recursion with rho = 0 and contributes an exact zero.  Each member
+    keeps its own `memory` newest valid pairs (the oldest of its own goes
+    first) and takes H0 from its own newest valid pair, so a member's
+    search direction is the one it would get searching alone."""
 
-def _zero_members(be, pairs, keep):
-    """The pairs with the members where keep is False set to zero (a zero
-    pair drops out of the recursion: rho = 0 and, as the newest pair,
-    gamma = 0, which the direction test turns into a gradient step)."""
-    out = []
-    for s, y, rho in pairs:
-        z = be.axpy(s, -1.0, s)
-        out.append((be.where(keep, s, z), be.where(keep, y, be.axpy(y, -1.0, y)), np.where(keep, rho, 0.0)))
-    return out
+    def __init__(self, memory: int, B: int):
+        self.memory, self.B = memory, B
+        self.pairs = []  # (s, y, rho[B], valid[B], sy[B], yy[B]), oldest first
+
+    def has(self) -> np.ndarray:
+        out = np.zeros(self.B, dtype=bool)
+        for *_, valid, _, _ in self.pairs:
+            out |= valid
+        return out
+
+    def drop(self, members: np.ndarray):
+        """Forget every pair of the members where `members` is True."""
+        for k, (s, y, rho, valid, sy, yy) in enumerate(self.pairs):
+            keep = valid & ~members
+            self.pairs[k] = (s, y, np.where(keep, rho, 0.0), keep, sy, yy)
+        self._compact()
+
+    def push(self, be, s, y, good: np.ndarray, sy: np.ndarray, yy: np.ndarray):
+        """Append (s, y) for the members where good is True (the other
+        members' entries are stored as zeros)."""
+        if self.memory <= 0 or not good.any():
+            return
+        s = be.where(good, s, be.axpy(s, -1.0, s))
+        y = be.where(good, y, be.axpy(y, -1.0, y))
+        self.pairs.append((s, y, np.where(good, 1.0 / np.where(good, sy, 1.0), 0.0), good.copy(), sy, yy))
+        count = np.zeros(self.B, dtype=int)
+        for *_, valid, _, _ in self.pairs:
+            count += valid
+        for k, (s_, y_, rho, valid, sy_, yy_) in enumerate(self.pairs):
+            over = valid & (count > self.memory)  # this member's oldest pair beyond its memory
+            if over.any():
+                self.pairs[k] = (s_, y_, np.where(over, 0.0, rho), valid & ~over, sy_, yy_)
+                count -= over
+        self._compact()
+
+    def _compact(self):
+        self.pairs = [p for p in self.pairs if p[3].any()]
+
+    def gamma(self) -> np.ndarray:
+        """H0 = <s, y>/<y, y> of each member's newest valid pair (0 without)."""
+        g = np.zeros(self.B)
+        seen = np.zeros(self.B, dtype=bool)
+        for *_, valid, sy, yy in reversed(self.pairs):
+            new = valid & ~seen
+            g = np.where(new, sy / np.where(yy > 0.0, yy, 1.0) * (yy > 0.0), g)
+            seen |= valid
+        return g
+
+    def two_loop(self, be, g):
+        """H g for the ascent problem (two-loop recursion, newest pair first)."""
+        q = g
+        alphas = []
+        for s, y, rho, *_ in reversed(self.pairs):
+            a = rho * be.dot(s, q)
+            alphas.append(a)
+            q = be.axpy(q, -a, y)
+        r = be.axpy(q, self.gamma() - 1.0, q)  # gamma * q
+        for (s, y, rho, *_), a in zip(self.pairs, reversed(alphas)):
+            b = rho * be.dot(y, r)
+            r = be.axpy(r, a - b, s)
+        return r
 
 
 def lbfgs_max(be, x0, iters: int, memory: int = 10, nonmonotone: int = 10, c_armijo: float = 1e-4,
@@ -94,16 +138,16 @@ def lbfgs_max(be, x0, iters: int, memory: int = 10, nonmonotone: int = 10, c_arm
     log.grads += 1
     B = len(f)
     hist = [f.copy()]
-    pairs = []
+    mem = _Memory(memory, B)
     gn = np.maximum(np.sqrt(be.dot(g, g)), 1e-300)
     xn = np.sqrt(be.dot(x, x))
     step0 = np.where(xn > 0.0, 0.1 * xn, 1.0) / gn
-    have = np.zeros(B, dtype=bool)  # member has curvature pairs in memory
     for it in range(iters):
         d = be.axpy(g, step0 - 1.0, g)  # step0 * g
         reset = np.zeros(B, dtype=bool)
-        if pairs and have.any():
-            dq = _two_loop(be, g, pairs)
+        have = mem.has()  # member has curvature pairs in memory
+        if have.any():
+            dq = mem.two_loop(be, g)
             ok = have & (be.dot(g, be.axpy(be.project(be.axpy(x, 1.0, dq)), -1.0, x)) > 0.0)
             reset = have & ~ok
             d = be.where(ok, dq, d)
@@ -135,15 +179,8 @@ def lbfgs_max(be, x0, iters: int, memory: int = 10, nonmonotone: int = 10, c_arm
         good = accepted & (sy > 1e-12 * np.sqrt(ss * yy))
         drop = reset | failed
         if drop.any():
-            pairs = _zero_members(be, pairs, ~drop)
-            have &= ~drop
-        if good.any():
-            zs = be.axpy(s, -1.0, s)
-            pairs.append((be.where(good, s, zs), be.where(good, y, be.axpy(y, -1.0, y)),
-                          np.where(good, 1.0 / np.where(good, sy, 1.0), 0.0)))
-            if len(pairs) > memory:
-                pairs.pop(0)
-            have |= good
+            mem.drop(drop)
+        mem.push(be, s, y, good, sy, yy)
         # Barzilai-Borwein length for the next gradient step
         gn2 = np.sqrt(be.dot(g2, g2))
         base = np.sqrt(be.dot(x_new, x_new)) / np.maximum(gn2, 1e-300)

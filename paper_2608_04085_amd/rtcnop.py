@@ -8,6 +8,7 @@ raises :class:`RTError` on a non-zero status.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 from dataclasses import dataclass
 
@@ -75,6 +76,7 @@ def load():
         "rt_step": [_vp, _vp, _vp, _vp, _vp],
         "rt_integrate": [_vp, _vp, ctypes.c_double, _vp, _vp, _vp, _i32],
         "rt_kinetic_energy": [_vp, _vp, _vp],
+        "rt_ke_ratio": [_vp, _vp, _vp, _vp],
         "rt_step_adjoint": [_vp, _vp, _vp, _vp, _vp],
         "rt_grad_u0": [_vp, _vp, ctypes.c_double, ctypes.POINTER(RtCkptPolicy), _vp, _vp, _vp],
         "rt_pool_bytes": [_vp, _i32, _i32, _i32, ctypes.POINTER(ctypes.c_size_t)],
@@ -97,6 +99,8 @@ def load():
         "rt_axpy": [_vp, _vp, _vp, _vp, _vp],
         "rt_check_error": [_vp],
         "rt_revolve_stats": [_i32, _i32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
+        "rt_revolve_plan_stats": [_i32, _i32, _i32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(_i32),
+                                  ctypes.POINTER(_i32)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -115,7 +119,7 @@ EXPORTED = ["rt_create", "rt_destroy", "rt_set_stream", "rt_workspace_bytes", "r
             "rt_set_overlap", "rt_kernel_times", "rt_set_fold", "rt_get_fold",
             "rt_set_tiles", "rt_ek_field", "rt_ek_anomaly", "rt_grad_ek_anomaly",
             "rt_mix_width", "rt_set_dt_mode", "rt_get_dt_mode", "rt_get_tile", "rt_revolve_stats",
-            "rt_row_spectrum"]
+            "rt_row_spectrum", "rt_ke_ratio", "rt_revolve_plan_stats"]
 
 
 def _check(rc: int, call: str):
@@ -141,6 +145,19 @@ def revolve_stats(nsteps: int, slots: int):
     return fw.value, opt.value
 
 
+def revolve_plan_stats(nsteps: int, slots: int, n_est: int):
+    """(forward steps of the whole gradient, level-1 interval, two-level
+    plan used) of RT_CKPT_REVOLVE for a march of nsteps steps with `slots`
+    slots when the initial CFL step suggested n_est steps; the plan is also
+    checked for consistency (host only, no GPU)."""
+    fw = ctypes.c_int64()
+    iv = ctypes.c_int32()
+    two = ctypes.c_int32()
+    _check(load().rt_revolve_plan_stats(nsteps, slots, n_est, ctypes.byref(fw), ctypes.byref(iv), ctypes.byref(two)),
+           "rt_revolve_plan_stats")
+    return fw.value, iv.value, bool(two.value)
+
+
 @dataclass
 class Policy:
     kind: int = CKPT_UNIFORM
@@ -160,6 +177,7 @@ class Context:
             dev = torch.device("cuda", torch.cuda.current_device())
         self.device = dev
         self.max_steps = int(max_steps)
+        self._own_pool = None  # checkpoint pool of gradient calls made without one
         L = load()
         grid = RtGrid(cfg.nx, cfg.ny, cfg.batch, 0, cfg.lx, cfg.ly)
         phys = RtPhys(cfg.gamma, cfg.g_y, cfg.rho_h, cfg.rho_l, cfg.y0, cfg.h, cfg.p_int, cfg.cfl, cfg.comp_mask,
@@ -327,6 +345,22 @@ class Context:
         _check(load().rt_kinetic_energy(self._h, _ptr(U), _ptr(ke)), "rt_kinetic_energy")
         return ke
 
+    def ke_ratio(self, U0, UT) -> torch.Tensor:
+        """R[B] = KE(UT)/KE(U0) (the library's rt_ke_ratio)."""
+        self._sync_stream()
+        U0 = self.as_dev(U0)
+        UT = self.as_dev(UT)
+        R = self._f64((self.cfg.batch,))
+        _check(load().rt_ke_ratio(self._h, _ptr(U0), _ptr(UT), _ptr(R)), "rt_ke_ratio")
+        return R
+
+    def objective_ratio(self, uv0, T: float) -> torch.Tensor:
+        """R = KE(U(T))/KE(U(0)) of every member for the perturbation uv0
+        (forward march only)."""
+        U0 = self.init_state(uv0)
+        UT, _, _, _ = self.integrate(U0, T)
+        return self.ke_ratio(U0, UT)
+
     def step_adjoint(self, U, dt, lam_next, out: torch.Tensor | None = None) -> torch.Tensor:
         self._sync_stream()
         U = self.as_dev(U)
@@ -342,10 +376,15 @@ class Context:
         return n.value
 
     def grad_u0(self, uv0, T: float, policy: Policy | None = None, pool: torch.Tensor | None = None):
-        """(R[B], grad[B][2][ny][nx], nsteps[B]) on the device."""
+        """(R[B], grad[B][2][ny][nx], nsteps[B]) on the device.  Without a
+        pool the context sizes one for the run (see _pool) and keeps it."""
         self._sync_stream()
         policy = policy or Policy()
         uv0 = self.as_dev(uv0).reshape(self.shape_uv)
+        if pool is None:
+            return self._with_own_pool(policy, uv0, T, lambda pl, pol: load().rt_grad_u0(
+                self._h, _ptr(uv0), float(T), ctypes.byref(pol), _ptr(pl[0]), _ptr(pl[1]), _ptr(pl[2])),
+                "rt_grad_u0")
         pool, pol = self._pool(policy, pool)
         R = self._f64((self.cfg.batch,))
         g = self._f64(self.shape_uv)
@@ -353,6 +392,35 @@ class Context:
         _check(load().rt_grad_u0(self._h, _ptr(uv0), float(T), ctypes.byref(pol), _ptr(R), _ptr(g), _ptr(n)),
                "rt_grad_u0")
         return R, g, n
+
+    def _step_estimate(self, uv0, T: float) -> int:
+        """Steps a march of uv0 to T will take, with room to spare: 1.25 T /
+        dt0 + 64 from the CFL step dt0 of the initial state (the signal
+        speeds of these runs are set by the background's sound speed, so
+        dt changes little along the march)."""
+        dt0 = float(self.cfl_dt(self.init_state(uv0)).min())
+        return min(self.max_steps, int(math.ceil(1.25 * T / dt0)) + 64)
+
+    def _with_own_pool(self, policy, uv0, T, call, name):
+        """Run a gradient call with a pool the context sizes and keeps:
+        policy.pool_bytes if given, else what the policy needs for the
+        estimated step count; on RT_ENOMEM (more steps than estimated) once
+        more with the exact count from a forward march."""
+        out = (self._f64((self.cfg.batch,)), self._f64(self.shape_uv),
+               torch.empty((self.cfg.batch,), dtype=torch.int32, device=self.device))
+        need = policy.pool_bytes or self.pool_bytes(policy.kind, policy.interval, self._step_estimate(uv0, T))
+        for attempt in range(2):
+            if self._own_pool is None or self._own_pool.numel() < need + 256:
+                self._own_pool = None
+                self._own_pool = torch.empty(need + 256, dtype=torch.uint8, device=self.device)
+            _, pol = self._pool(policy, self._own_pool)
+            rc = call(out, pol)
+            if rc != -3 or attempt == 1 or policy.pool_bytes:
+                _check(rc, name)
+                return out
+            _, _, n, _ = self.integrate(self.init_state(uv0), T)
+            need = self.pool_bytes(policy.kind, policy.interval, int(n.max().item()))
+        return out
 
     def _pool(self, policy, pool):
         if pool is None:
@@ -424,6 +492,10 @@ class Context:
         policy = policy or Policy()
         uv0 = self.as_dev(uv0).reshape(self.shape_uv)
         ekb = self.as_dev(ek_base).expand(self.cfg.batch, self.cfg.ny, self.cfg.nx).contiguous()
+        if pool is None:
+            return self._with_own_pool(policy, uv0, T, lambda pl, pol: load().rt_grad_ek_anomaly(
+                self._h, _ptr(uv0), float(T), ctypes.byref(pol), _ptr(ekb), _ptr(pl[0]), _ptr(pl[1]),
+                _ptr(pl[2])), "rt_grad_ek_anomaly")
         pool, pol = self._pool(policy, pool)
         J = self._f64((self.cfg.batch,))
         g = self._f64(self.shape_uv)
@@ -471,22 +543,23 @@ class Context:
 
 class KERatio(torch.autograd.Function):
     """R = KE(U(T)) / KE(U(0)) as a differentiable function of the initial
-    velocity perturbation; backward runs the library's discrete adjoint."""
+    velocity perturbation.  When a gradient is wanted, forward runs the
+    library's rt_grad_u0 (one march with checkpoints, then the discrete
+    adjoint) and keeps dR/duv0; backward only scales it by grad_output.
+    Otherwise forward marches once (rt_integrate, rt_ke_ratio)."""
 
     @staticmethod
     def forward(fctx, uv0: torch.Tensor, rt: Context, T: float, policy: Policy | None = None):
-        U0 = rt.init_state(uv0)
-        ke0 = rt.kinetic_energy(U0)
-        UT, _, _, _ = rt.integrate(U0, T)
-        keT = rt.kinetic_energy(UT)
-        fctx.save_for_backward(uv0)
-        fctx.rt, fctx.T, fctx.policy = rt, T, policy
-        return keT / ke0
+        if fctx.needs_input_grad[0]:
+            R, g, _ = rt.grad_u0(uv0, T, policy)
+            fctx.save_for_backward(g)
+            return R
+        fctx.save_for_backward(None)
+        return rt.objective_ratio(uv0, T)
 
     @staticmethod
     def backward(fctx, gout):
-        (uv0,) = fctx.saved_tensors
-        _, g, _ = fctx.rt.grad_u0(uv0, fctx.T, fctx.policy)
+        (g,) = fctx.saved_tensors
         return g * gout.reshape(-1, 1, 1, 1), None, None, None
 
 

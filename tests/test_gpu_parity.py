@@ -810,3 +810,62 @@ def test_both_step_layouts_give_the_same_bits_on_every_tile():
         for (Us, ns), b in zip(ref, (0, 5)):
             assert int(host(n)[b]) == ns
             np.testing.assert_array_equal(host(U)[b], Us, err_msg=tile)
+
+
+def test_ke_ratio_matches_the_kinetic_energies_and_the_oracle():
+    # rt_ke_ratio (Eq. 10's ratio in the workloads' form): the quotient of
+    # rt_kinetic_energy's values to the bit, and the oracle's R
+    cfg = RTConfig(nx=48, ny=40, batch=3)
+    uv = inputs.seed_batch(cfg, range(3), rms=1e-3)
+    r = rt().Context(cfg, max_steps=1024)
+    U0 = r.init_state(uv)
+    UT, _, _, _ = r.integrate(U0, 0.2)
+    R = host(r.ke_ratio(U0, UT))
+    np.testing.assert_array_equal(R, host(r.kinetic_energy(UT)) / host(r.kinetic_energy(U0)))
+    o = Oracle.from_config(cfg)
+    Uo0 = o.init_state(uv)
+    UoT, _, _, _ = o.integrate(Uo0, 0.2)
+    np.testing.assert_allclose(R, o.kinetic_energy(UoT) / o.kinetic_energy(Uo0), rtol=1e-10)
+    np.testing.assert_array_equal(host(r.objective_ratio(uv, 0.2)), R)
+
+
+def test_autograd_function_without_gradient_and_gradient_without_pool():
+    # KERatio marches once when no gradient is wanted, and its value is the
+    # gradient call's R to the bit; a gradient call without a pool sizes one
+    # for the run (not for max_steps) and keeps it
+    cfg = RTConfig(nx=32, ny=64, batch=2)
+    T = 0.1
+    uv = torch.from_numpy(inputs.seed_batch(cfg, [0, 1], rms=1e-3)).cuda()
+    r = rt().Context(cfg, max_steps=65536)
+    pol = rt().Policy(CKPT_UNIFORM, 8)
+    R0 = rt().KERatio.apply(uv, r, T, pol)
+    R1, g1, n1 = r.grad_u0(uv, T, pol)
+    np.testing.assert_array_equal(host(R0), host(R1))
+    assert r._own_pool is not None
+    full = r.pool_bytes(CKPT_UNIFORM, 8, 65536)
+    assert r._own_pool.numel() < full / 20
+    pool = torch.empty(r.pool_bytes(CKPT_UNIFORM, 8, int(host(n1).max())) + 256, dtype=torch.uint8, device="cuda")
+    R2, g2, _ = r.grad_u0(uv, T, pol, pool=pool)
+    np.testing.assert_array_equal(host(R2), host(R1))
+    np.testing.assert_array_equal(host(g2), host(g1))
+
+
+@pytest.mark.parametrize("cfg,T", [(RTConfig(nx=64, ny=128), 0.05), (RTConfig(nx=256, ny=256), 0.02)],
+                         ids=["64x128", "256x256"])
+def test_autotune_pick_reproduces_the_default_gradient_bitwise(cfg, T):
+    # rt_autotune times every tile variant and the two adjoint forms on the
+    # caller's state and keeps the fastest; all variants give the same bits,
+    # so the gradient after tuning equals the default one to the bit
+    uv = inputs.seed_batch(cfg, [0], rms=1e-3)
+    r = rt().Context(cfg, max_steps=4096)
+    pol = rt().Policy(CKPT_UNIFORM, 16)
+    R0, g0, n0 = r.grad_u0(uv, T, pol)
+    before = (r.tile, r.fold)
+    picked = r.autotune(r.init_state(uv), reps=5)
+    step_tile, adj_tile = picked.split("/")
+    assert step_tile in rt().TILES and adj_tile in rt().TILES
+    R1, g1, n1 = r.grad_u0(uv, T, pol)
+    np.testing.assert_array_equal(host(n1), host(n0))
+    np.testing.assert_array_equal(host(R1), host(R0))
+    np.testing.assert_array_equal(host(g1), host(g0))
+    print("autotune", cfg.nx, cfg.ny, "default", before, "picked", picked, "fold", r.fold)

@@ -223,3 +223,60 @@ def test_top5_fraction_of_a_spectrum_vector_equals_the_row_form():
     f = np.random.default_rng(9).standard_normal((1, cfg.ny, cfg.nx))
     E = Oracle.from_config(cfg).row_spectrum(f, row=2)[0]
     assert cnop.top5_fraction(E) == pytest.approx(cnop.spectrum_top5(f[0, 2]), rel=1e-12)
+
+
+class MixedCurvature(QuadBall):
+    """Member 0 concave (its maximum at the origin), member 1 indefinite
+    with a few directions of positive curvature (its maximum on the
+    boundary): along a step a curvature pair can pass the test for one
+    member and fail it for the other while the other still holds pairs."""
+
+    def __init__(self, n, seed, frac_pos):
+        rng = np.random.default_rng(seed)
+        M = rng.standard_normal((n, n))
+        neg = -(M @ M.T / n + 0.1 * np.eye(n))
+        Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+        ev = -np.abs(rng.standard_normal(n)) - 0.05
+        k = max(1, int(frac_pos * n))
+        ev[:k] = 0.3 * np.abs(ev[:k])
+        super().__init__(np.stack([neg, Q @ np.diag(ev) @ Q.T]), np.ones(n), 1.0)
+        self.x0 = self.project(3.0 * np.sqrt(2.0) * rng.standard_normal((2, n)))
+
+
+class Solo:
+    """Member b of a batched backend as a batch of one."""
+
+    def __init__(self, be, b):
+        self.be, self.b = be, b
+
+    def __getattr__(self, name):
+        return getattr(self.be, name)
+
+    def _embed(self, x):
+        X = np.zeros((self.be.A.shape[0], x.shape[1]))
+        X[self.b] = x[0]
+        return X
+
+    def value(self, x):
+        return self.be.value(self._embed(x))[self.b: self.b + 1]
+
+    def value_and_grad(self, x):
+        f, g = self.be.value_and_grad(self._embed(x))
+        return f[self.b: self.b + 1], g[self.b: self.b + 1]
+
+
+@pytest.mark.parametrize("seed,frac_pos", [(0, 0.1), (0, 0.3), (1, 0.5), (2, 0.1), (4, 0.3), (11, 0.5)])
+def test_members_with_mixed_curvature_match_their_solo_runs(seed, frac_pos):
+    # Restarts are independent (Sec. 3.4 runs them separately): the pairs a
+    # member keeps, its memory limit and its initial Hessian scale are its
+    # own, so each batched member takes exactly the iterates of its solo run.
+    # (With one shared pair list, a pair that passed the curvature test for
+    # one member entered the other's memory as a zero pair: it reset that
+    # member's initial Hessian scale and evicted its real pairs early.)
+    be = MixedCurvature(12, seed, frac_pos)
+    x, f, _, log = optim.lbfgs_max(be, be.x0, iters=25)
+    for b in range(2):
+        xs, fs, _, logs = optim.lbfgs_max(Solo(be, b), be.x0[b: b + 1], iters=25)
+        np.testing.assert_array_equal(x[b], xs[0])
+        assert f[b] == fs[0]
+        assert [row[b] for row in log.f] == [row[0] for row in logs.f]

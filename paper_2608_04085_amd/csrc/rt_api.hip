@@ -84,6 +84,9 @@ struct rt_ctx {
   int32_t* dtd_imax = nullptr;
   int32_t dtd_stride = 0;
   double* bg_p = nullptr;  // [ny] background pressure rows of the well-balanced variant
+  // the last binomial-checkpointing gradient: two-level plan, level-1 interval
+  bool rev_last_two_level = false;
+  int rev_last_interval = 0;
   ~rt_ctx() {
     if (chunk_exec) (void)hipGraphExecDestroy(chunk_exec);
     if (capture_stream) (void)hipStreamDestroy(capture_stream);
@@ -94,7 +97,7 @@ struct rt_ctx {
   Flags* flags = nullptr;
   double* dt_log = nullptr;
   int32_t* nsteps = nullptr;
-  double* scal = nullptr;  // [8][B]: 0 max speed, 1 ke0, 2 keN, 3 dt, 4 norm, 5 dot
+  double* scal = nullptr;  // [8][B]: 0 max speed, 1 ke0, 2 keN, 3 dt, 4 norm, 5 dot, 6-7 rt_ke_ratio
   size_t cells() const { return (size_t)P.nx * P.ny; }
   size_t state_elems() const { return 4 * cells() * P.nb; }
   double* sc(int k) const { return scal + (size_t)k * P.nb; }
@@ -166,6 +169,7 @@ int read_flags(rt_ctx* c, Flags* host, bool clear) {
   if (clear && (host->err_unphys || host->err_overflow)) {
     RT_HIP(rtk::launch_fill_i32(reinterpret_cast<int32_t*>(c->flags), 0, 2, c->stream));
   }
+  if (clear && host->snap_overflow) RT_HIP(rtk::launch_fill_i32(&c->flags->snap_overflow, 0, 1, c->stream));
   return 0;
 }
 
@@ -194,6 +198,10 @@ rtk::StepArgs adaptive_args(rt_ctx* c, const double* src, double* dst, long laun
 
 // Control records after the last march.
 const Ctl* final_ctl(const rt_ctx* c) { return c->ctl + (size_t)(c->last_launch & 1) * c->P.nb; }
+
+// Level-1 snapshots of the binomial checkpointing cover this multiple of the
+// step count the initial CFL step suggests.
+constexpr double kRevolveMargin = 1.25;
 
 // Steps per captured graph: a multiple of 6 so that the launch index enters
 // the kernels only through L mod 2 and L mod 3.
@@ -262,7 +270,9 @@ int march(rt_ctx* c, double T, double* pool, int interval, int slots) {
     if (int rc = ensure_chunk_graph(c, pool, interval, slots)) return rc;
   }
   long launched = 0;
-  long target = nest;
+  // the first round stops where the step log would overflow, so that a T
+  // beyond max_steps is refused after at most one round past the limit
+  long target = std::min<long>(nest, (long)c->max_steps + kGraphChunk + 2);
   Flags f{};
   for (;;) {
     while (launched < target) {
@@ -695,6 +705,15 @@ int rt_kinetic_energy(rt_ctx* c, const double* U, double* ke) {
   return 0;
 }
 
+int rt_ke_ratio(rt_ctx* c, const double* U0, const double* UT, double* R) {
+  if (int rc = need_ws(c)) return rc;
+  if (!U0 || !UT || !R) return fail(RT_EINVAL, "null argument");
+  RT_HIP(rtk::launch_reduce(c->P, 1, U0, nullptr, c->partial, c->red_blocks, c->sc(6), c->stream));
+  RT_HIP(rtk::launch_reduce(c->P, 1, UT, nullptr, c->partial, c->red_blocks, c->sc(7), c->stream));
+  RT_HIP(rtk::launch_ratio(c->P.nb, c->sc(7), c->sc(6), R, c->stream));
+  return 0;
+}
+
 int rt_step_adjoint(rt_ctx* c, const double* U, const double* dt, const double* lam_next, double* lam) {
   if (int rc = need_ws(c)) return rc;
   if (!U || !dt || !lam_next || !lam || lam == lam_next) return fail(RT_EINVAL, "bad argument");
@@ -751,6 +770,7 @@ int grad_objective(rt_ctx* c, const double* uv0, double T, const rt_ckpt_policy*
 
   int interval = 1;
   size_t snap_slots = 0;
+  int rev_slots = 0;
   if (pol->kind == RT_CKPT_STORE_ALL || pol->kind == RT_CKPT_UNIFORM) {
     interval = pol->kind == RT_CKPT_STORE_ALL ? 1 : pol->interval;
     if (interval < 1) return fail(RT_EINVAL, "interval must be >= 1");
@@ -759,16 +779,31 @@ int grad_objective(rt_ctx* c, const double* uv0, double T, const rt_ckpt_policy*
     if (int rc = march(c, T, pool, interval, (int)std::min<size_t>(snap_slots, 1u << 30))) return rc;
   } else if (pol->kind == RT_CKPT_REVOLVE) {
     if (slots_total < 2) return fail(RT_ENOMEM, "revolve needs a pool of at least 2 states");
-    // Counting pass: the step count decides the binomial schedule.  The
-    // initial state is kept in slot 0 for the restart.
-    RT_HIP(rtk::launch_copy(c->S0, state_slot(0), se, s));
-    if (int rc = march(c, T, nullptr, 1, 0)) return rc;
+    // The objective's forward march also leaves level-1 snapshots, every
+    // `interval` steps, in slots 0 .. rev_slots - 2 (slot 0: U^0); the
+    // interval comes from the step count the initial CFL step suggests.
+    rev_slots = (int)std::min<size_t>(slots_total, 1u << 20);
+    RT_HIP(rtk::launch_reduce(P, 0, c->S0, nullptr, c->partial, c->red_blocks, c->sc(0), s));
+    std::vector<double> ms(P.nb);
+    RT_HIP(hipMemcpyAsync(ms.data(), c->sc(0), sizeof(double) * P.nb, hipMemcpyDeviceToHost, s));
+    RT_HIP(hipStreamSynchronize(s));
+    const double msmax = *std::max_element(ms.begin(), ms.end());
+    const double est = std::ceil(T * msmax / P.cfl);
+    const int n_est = !(est < 1e8) ? 100000000 : std::max(1, (int)est);
+    interval = rtrev::level1_interval(n_est, rev_slots, kRevolveMargin);
+    if (int rc = march(c, T, pool, interval, std::max(1, rev_slots - 1))) return rc;
   } else {
     return fail(RT_EINVAL, "unknown checkpoint kind %d", pol->kind);
   }
   Flags f{};
   if (int rc = read_flags(c, &f, true)) return rc;
   if (int rc = flags_status(f)) return rc;
+  // Level-1 snapshots beyond the pool: the uniform policies cannot go on;
+  // revolve falls back to one binomial schedule over the whole march from
+  // U^0 in slot 0 (the march it just ran then served to count the steps).
+  const bool snaps_fit = !f.snap_overflow;
+  if (!snaps_fit && pol->kind != RT_CKPT_REVOLVE)
+    return fail(RT_ENOMEM, "checkpoint pool of %zu states overflowed", slots_total);
 
   // step counts and final state
   RT_HIP(rtk::launch_copy_final(P, final_ctl(c), c->S0, c->S1, c->L1, nullptr, c->nsteps, nullptr, 0, nullptr, 0, s));
@@ -946,11 +981,20 @@ int grad_objective(rt_ctx* c, const double* uv0, double T, const rt_ckpt_policy*
       RT_HIP(hipStreamWaitEvent(s, c->aux_done, 0));
     }
   } else {
-    // Binomial checkpointing over slots [0, slots_total): slot 0 holds U^0.
-    const int snaps = (int)std::min<size_t>(slots_total, 1u << 20);
-    std::vector<rtrev::Action> plan = rtrev::schedule(nmax, snaps);
-    std::vector<int> slot_step(snaps, -1);
+    // Binomial checkpointing over slots [0, rev_slots).  Two-level: the
+    // segments between the level-1 snapshots, last first (slot k holds
+    // U^{k interval}); single level if that is cheaper or the snapshots did
+    // not fit (slot 0 holds U^0 either way).
+    const bool two = snaps_fit && rtrev::two_level_cost(nmax, interval, rev_slots) <=
+                                      rtrev::min_forward_steps(nmax, rev_slots);
+    std::vector<rtrev::Action> plan = two ? rtrev::two_level_plan(nmax, interval, rev_slots)
+                                          : rtrev::schedule(nmax, rev_slots);
+    std::vector<int> slot_step(rev_slots, -1);
     slot_step[0] = 0;
+    if (two)
+      for (int k = 0; (long)k * interval < nmax; ++k) slot_step[k] = k * interval;
+    c->rev_last_two_level = two;
+    c->rev_last_interval = interval;
     double* cur = c->S0;   // working state of the schedule
     int cur_step = 0;
     RT_HIP(rtk::launch_copy(state_slot(0), cur, se, s));
@@ -961,7 +1005,12 @@ int grad_objective(rt_ctx* c, const double* uv0, double T, const rt_ckpt_policy*
           slot_step[act.slot] = cur_step;
           break;
         case rtrev::Action::RESTORE:
-          RT_HIP(rtk::launch_copy(state_slot(act.slot), cur, se, s));
+          // the working state always holds step cur_step: no copy is needed
+          // when the slot holds that same step
+          if (cur_step != slot_step[act.slot]) {
+            cur = c->S0;
+            RT_HIP(rtk::launch_copy(state_slot(act.slot), cur, se, s));
+          }
           cur_step = slot_step[act.slot];
           break;
         case rtrev::Action::ADVANCE:
@@ -1066,23 +1115,19 @@ int rt_check_error(rt_ctx* c) {
   return flags_status(f);
 }
 
-// Host-only check of the binomial schedule (no GPU): builds the schedule for
-// nsteps steps and `slots` slots, replays it on step indices and verifies that
-// every step is reversed exactly once, in decreasing order, from the right
-// state, using only slots [0, slots).  Returns its forward-step count and
-// the closed-form minimum.
-int rt_revolve_stats(int32_t nsteps, int32_t slots, int64_t* forward, int64_t* optimum) {
-  if (nsteps < 1 || slots < 1 || !forward || !optimum) return fail(RT_EINVAL, "bad argument");
-  const std::vector<rtrev::Action> plan = rtrev::schedule(nsteps, slots);
-  std::vector<int> slot_step(slots, -1);
-  slot_step[0] = 0;
+namespace {
+// Replays a reverse-sweep plan on step indices: every step reversed exactly
+// once, in decreasing order, from the right state, using only slots
+// [0, slots) whose steps slot_step gives at the start.  Adds its forward
+// steps to *fw.
+int replay_plan(const std::vector<rtrev::Action>& plan, int nsteps, int slots, std::vector<int> slot_step,
+                int64_t* fw) {
   int cur = 0, next_rev = nsteps - 1;
-  int64_t fw = 0;
   for (const rtrev::Action& a : plan) {
     switch (a.kind) {
       case rtrev::Action::ADVANCE:
         if (a.to < cur) return fail(RT_EINVAL, "schedule advances backwards");
-        fw += a.to - cur;
+        *fw += a.to - cur;
         cur = a.to;
         break;
       case rtrev::Action::TAKESHOT:
@@ -1100,8 +1145,50 @@ int rt_revolve_stats(int32_t nsteps, int32_t slots, int64_t* forward, int64_t* o
     }
   }
   if (next_rev != -1) return fail(RT_EINVAL, "schedule left %d steps unreversed", next_rev + 1);
+  return 0;
+}
+}  // namespace
+
+// Host-only check of the binomial schedule (no GPU): builds the schedule for
+// nsteps steps and `slots` slots, replays it on step indices and verifies that
+// every step is reversed exactly once, in decreasing order, from the right
+// state, using only slots [0, slots).  Returns its forward-step count and
+// the closed-form minimum.
+int rt_revolve_stats(int32_t nsteps, int32_t slots, int64_t* forward, int64_t* optimum) {
+  if (nsteps < 1 || slots < 1 || !forward || !optimum) return fail(RT_EINVAL, "bad argument");
+  std::vector<int> slot_step(slots, -1);
+  slot_step[0] = 0;
+  int64_t fw = 0;
+  if (int rc = replay_plan(rtrev::schedule(nsteps, slots), nsteps, slots, slot_step, &fw)) return rc;
   *forward = fw;
   *optimum = rtrev::min_forward_steps(nsteps, slots);
+  return 0;
+}
+
+// Host-only check of what RT_CKPT_REVOLVE runs for a march of nsteps steps
+// with `slots` pool slots when the initial CFL step suggested n_est steps:
+// the level-1 interval, then the two-level plan if its snapshots fit in
+// slots - 1 slots and it is no dearer than one binomial schedule, else that
+// schedule.  Replays and checks the plan as rt_revolve_stats does; forward
+// receives every forward step of the gradient (the objective's march
+// included), interval and two_level what was chosen.
+int rt_revolve_plan_stats(int32_t nsteps, int32_t slots, int32_t n_est, int64_t* forward, int32_t* interval,
+                          int32_t* two_level) {
+  if (nsteps < 1 || slots < 2 || n_est < 1 || !forward || !interval || !two_level)
+    return fail(RT_EINVAL, "bad argument");
+  const int I = rtrev::level1_interval(n_est, slots, kRevolveMargin);
+  const bool fit = (nsteps + (int64_t)I - 1) / I <= slots - 1;
+  const bool two = fit && rtrev::two_level_cost(nsteps, I, slots) <= rtrev::min_forward_steps(nsteps, slots);
+  std::vector<int> slot_step(slots, -1);
+  slot_step[0] = 0;
+  if (two)
+    for (int k = 0; (int64_t)k * I < nsteps; ++k) slot_step[k] = k * I;
+  int64_t fw = nsteps;  // the objective's forward march
+  const std::vector<rtrev::Action> plan = two ? rtrev::two_level_plan(nsteps, I, slots) : rtrev::schedule(nsteps, slots);
+  if (int rc = replay_plan(plan, nsteps, slots, slot_step, &fw)) return rc;
+  *forward = fw;
+  *interval = I;
+  *two_level = two ? 1 : 0;
   return 0;
 }
 

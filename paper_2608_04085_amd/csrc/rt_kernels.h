@@ -23,10 +23,10 @@ struct Ctl {
 
 // Flags shared by all members (device).
 struct Flags {
-  int32_t err_unphys;   // a state or face state was unphysical
-  int32_t err_overflow; // step log or snapshot pool overflow
-  int32_t n_active;     // members not done
-  int32_t pad;
+  int32_t err_unphys;    // a state or face state was unphysical
+  int32_t err_overflow;  // step log overflow (stops the march)
+  int32_t n_active;      // members not done
+  int32_t snap_overflow; // a snapshot fell beyond the pool's slots (the march goes on)
 };
 
 // Arguments of the fused step kernel.

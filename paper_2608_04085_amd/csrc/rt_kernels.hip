@@ -648,7 +648,7 @@ __global__ __launch_bounds__(NT) void k_step(Params P, StepArgs a) {
         stg(sp + 2 * N, c, u2);
         stg(sp + 3 * N, c, u3);
       } else {
-        bad |= 2;  // overflow, reported below
+        bad |= 4;  // snapshot beyond the pool, reported below
       }
     }
     if (need_speed) {
@@ -659,7 +659,7 @@ __global__ __launch_bounds__(NT) void k_step(Params P, StepArgs a) {
       smax = sx > sy ? sx : sy;
     }
   }
-  if (bad & 2) atomicOr(&a.flags->err_overflow, 1);
+  if (bad & 4) atomicOr(&a.flags->snap_overflow, 1);
   if (bad & 1) atomicOr(&a.flags->err_unphys, 1);
   if (!need_speed) return;
 

@@ -16,6 +16,7 @@
 #pragma once
 #include <algorithm>
 #include <cstdint>
+#include <limits>
 #include <vector>
 
 namespace rtrev {
@@ -91,6 +92,62 @@ inline std::vector<Action> schedule(int nsteps, int slots) {
   for (int k = slots - 1; k >= 1; --k) free_slots.push_back(k);
   detail::rev(0, nsteps, std::max(1, slots), 0, free_slots, out);
   return out;
+}
+
+// Two-level plan.  The forward march that evaluates the objective (and
+// finds the step count) also leaves the state of every step k * interval in
+// slot k, k < K = ceil(nsteps / interval): those snapshots cost no extra
+// forward steps.  The reverse sweep then takes the segments from the last
+// to the first and reverses each with the binomial schedule above, starting
+// from its own snapshot and using the slots no level-1 snapshot holds plus
+// those of the segments already reversed.  The returned actions are the
+// reverse sweep only, with the level-1 snapshots taken as present.
+inline std::vector<Action> two_level_plan(int nsteps, int interval, int slots) {
+  std::vector<Action> out;
+  const int K = (nsteps + interval - 1) / interval;
+  std::vector<int> free_slots;
+  for (int k = slots - 1; k >= K; --k) free_slots.push_back(k);
+  for (int k = K - 1; k >= 0; --k) {
+    const int start = k * interval, l = std::min(interval, nsteps - start);
+    detail::rev(start, l, 1 + (int)free_slots.size(), k, free_slots, out);
+    free_slots.push_back(k);  // its segment is done: the slot is free
+  }
+  return out;
+}
+
+// Forward steps of the reverse sweep of two_level_plan (the level-1 march's
+// nsteps steps not included), from the closed-form optimum of each segment.
+inline int64_t two_level_cost(int nsteps, int interval, int slots) {
+  const int K = (nsteps + interval - 1) / interval;
+  if (K > slots) return std::numeric_limits<int64_t>::max();
+  int64_t t = 0;
+  int nfree = slots - K;
+  for (int k = K - 1; k >= 0; --k) {
+    const int l = std::min(interval, nsteps - k * interval);
+    t += min_forward_steps(l, 1 + nfree);
+    ++nfree;
+  }
+  return t;
+}
+
+// Level-1 interval for a march expected to take about n_est steps: the
+// cheapest by two_level_cost among those whose snapshots of margin * n_est
+// steps fit in slots - 1 slots (one slot stays free).
+inline int level1_interval(int n_est, int slots, double margin) {
+  n_est = std::max(n_est, 1);
+  const int usable = std::max(slots - 1, 1);
+  const int lo = std::max(1, (int)((margin * n_est + usable - 1) / usable));
+  int best = lo;
+  int64_t best_cost = two_level_cost(n_est, lo, slots);
+  const int hi = std::min(n_est, 64 * lo);
+  for (int I = lo + 1; I <= hi; ++I) {
+    const int64_t t = two_level_cost(n_est, I, slots);
+    if (t < best_cost) {
+      best_cost = t;
+      best = I;
+    }
+  }
+  return best;
 }
 
 // Forward steps a schedule performs (each ADVANCE from the current step).

@@ -88,6 +88,54 @@ def test_revolve_large_schedules_are_consistent():
     assert fw == 99
 
 
+@functools.lru_cache(maxsize=None)
+def _dp_cost(l, c):
+    # the same brute force, for the segments of the two-level plan
+    return _dp(l, c)
+
+
+@pytest.mark.parametrize("n,c,n_est", [(1, 2, 1), (7, 2, 7), (40, 3, 40), (40, 5, 20), (120, 6, 100),
+                                       (37, 4, 37), (200, 6, 30)])
+def test_two_level_revolve_plan_is_consistent_and_segmentwise_optimal(n, c, n_est):
+    # The plan of RT_CKPT_REVOLVE: the objective's march leaves snapshots
+    # every I steps; each segment is reversed by a binomial schedule on the
+    # free slots.  The replay inside the call checks that every step is
+    # reversed once, in order, from the right state.  Its forward steps are
+    # the march's n plus, per segment (last first), the brute-force optimum
+    # for its length and the slots free then -- or, when that is dearer or
+    # the snapshots do not fit, n plus the single binomial schedule.
+    fw, I, two = rtcnop.revolve_plan_stats(n, c, n_est)
+    K = -(-n // I)
+    if two:
+        free, seg = c - K, 0
+        for k in range(K - 1, -1, -1):
+            seg += _dp_cost(min(I, n - k * I), 1 + free)
+            free += 1
+        assert fw == n + seg
+        assert K <= c - 1
+    else:
+        assert fw == n + _dp(n, c)
+    assert fw <= n + _dp(n, c)
+
+
+def test_two_level_revolve_at_the_workload_sizes():
+    # The binomial checkpointing workloads (8 x 512 x 1024 under 16 GB: 119
+    # states; 1024 x 2048 under 64 GB: 1024 states).  Against counting the
+    # steps first and then one binomial schedule (n + t(n, c)), the two-level
+    # plan saves re-computation, and an underestimated step count falls back
+    # to that schedule.
+    for n, c in [(4838, 119), (19350, 119), (29025, 1024), (1210, 8)]:
+        fw, I, two = rtcnop.revolve_plan_stats(n, c, n)
+        _, opt = rtcnop.revolve_stats(n, c)
+        assert two and fw < n + opt, (n, c, fw, n + opt)
+        print(f"revolve n={n} c={c}: interval {I}, forward steps {fw} ({fw / n:.2f} n) "
+              f"against {n + opt} ({(n + opt) / n:.2f} n) counting first")
+    # estimate far below the actual count: the snapshots overflow, fall back
+    fw, I, two = rtcnop.revolve_plan_stats(4838, 119, 1000)
+    _, opt = rtcnop.revolve_stats(4838, 119)
+    assert not two and fw == 4838 + opt
+
+
 def test_argument_validation_without_gpu():
     # every rejection below is decided on the host before any HIP call
     L = rtcnop.load()

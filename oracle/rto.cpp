@@ -30,6 +30,7 @@
 //                      included
 //   rto_project_to_constraint  scaling onto the constraint set (Eq. 11)
 //   rto_hllc, rto_wall_pressure  single-face fluxes for unit tests
+//   rto_count_flops    algorithmic flops of one step (measurement only)
 //   rto_mc_slope, rto_slopes, rto_predict  one limited slope (with its
 //                      derivatives), the four slopes of a cell, and the
 //                      MUSCL-Hancock half step of one cell, for unit tests
@@ -39,6 +40,7 @@
 #include <vector>
 
 #include "rto_ad.hpp"
+#include "rto_count.hpp"
 #include "rto_scheme.hpp"
 
 namespace rto {
@@ -652,6 +654,58 @@ int rto_predict(const Problem* P, const double* w, const double* sx, const doubl
   q[2] = r.v;
   q[3] = r.p;
   return 0;
+}
+
+// Algorithmic floating-point work of one step of one member U ([4][ny][nx])
+// at step dt (measurement only): out[0] the flops of the step (rto_count.hpp:
+// every operation on state-dependent values as the scheme writes it), out[1]
+// those of the largest signal speed of the new state (the CFL reduction),
+// out[2] the edges of the step's computational graph (a reverse-mode
+// adjoint does one multiply-add per edge after recomputing the step),
+// out[3..6] the step's additions, multiplications, divisions and square
+// roots.  Totals over the member's cells.
+int rto_count_flops(const Problem* P, const double* U, double dt, double* out) {
+  if (!valid(P) || !U || !out) return kEInval;
+  const size_t n4 = 4 * cells(P);
+  rto::FlopCount& fc = rto::flop_count();
+  std::vector<rto::Cnt> x(n4), y(n4);
+  for (size_t k = 0; k < n4; ++k) x[k] = rto::Cnt(U[k]);
+  fc = rto::FlopCount{};
+  const int bad = rto::step_member<rto::Cnt>(*P, x.data(), y.data(), dt);
+  const rto::FlopCount step = fc;
+  fc = rto::FlopCount{};
+  (void)rto::max_signal_speed<rto::Cnt>(*P, y.data());
+  const uint64_t cfl = fc.total();
+  // edges of the step's graph, from the reverse-mode tape
+  rto::Tape& tp = rto::tape();
+  tp.clear();
+  std::vector<Rev> xr(n4), yr(n4);
+  for (size_t k = 0; k < n4; ++k) xr[k] = Rev::leaf(U[k]);
+  (void)rto::step_member<Rev>(*P, xr.data(), yr.data(), dt);
+  uint64_t edges = 0;
+  for (const rto::Tape::Node& nd : tp.nodes) edges += (nd.a >= 0) + (nd.b >= 0);
+  tp.clear();
+  out[0] = (double)step.total();
+  out[1] = (double)cfl;
+  out[2] = (double)edges;
+  out[3] = (double)step.add;
+  out[4] = (double)step.mul;
+  out[5] = (double)step.div;
+  out[6] = (double)step.sqrt;
+  return bad ? kEUnphys : 0;
+}
+
+// Threads over the rows of the double-precision forward step (timing only;
+// results are the same for any count).  Returns the count in force: 1 if
+// the library was built without OpenMP.
+int rto_set_threads(int32_t n) {
+  if (n < 1) return kEInval;
+#ifdef _OPENMP
+  rto::omp_threads() = n;
+  return n;
+#else
+  return 1;
+#endif
 }
 
 // Background profiles at the cell centres of row j (Eq. 5 and the

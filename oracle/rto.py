@@ -80,6 +80,8 @@ def lib():
             "rto_mc_slope": [ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp],
             "rto_slopes": [P, _dp, _dp, _dp, ctypes.c_int32, _dp],
             "rto_predict": [P, _dp, _dp, _dp, ctypes.c_double, _dp],
+            "rto_set_threads": [ctypes.c_int32],
+            "rto_count_flops": [P, _dp, ctypes.c_double, _dp],
             "rto_background": [P, _dp, _dp],
         }
         for name, args in sig.items():
@@ -344,3 +346,22 @@ def predict(o: "Oracle", w, sx, sy, dt):
     q = np.empty(4)
     _check(lib().rto_predict(ctypes.byref(o.prob), _p(_w4(w)), _p(_w4(sx)), _p(_w4(sy)), float(dt), _p(q)), "predict")
     return q
+
+
+def set_threads(n: int) -> int:
+    """Threads over the rows of the oracle's forward step (timing only;
+    results do not depend on it).  Returns the count in force."""
+    return int(lib().rto_set_threads(int(n)))
+
+
+def count_flops(o: "Oracle", U, dt):
+    """Algorithmic work of one step of member 0 of U at step dt, per cell:
+    {"step": flops of the step, "cfl": flops of the signal speed of the new
+    state, "edges": edges of the step's computational graph, "add", "mul",
+    "div", "sqrt": the step's operations by kind} (see rto_count.hpp)."""
+    U = np.ascontiguousarray(np.asarray(U, dtype=np.float64)[:1])
+    out = np.empty(7)
+    _check(lib().rto_count_flops(ctypes.byref(o.prob), _p(U), float(np.asarray(dt).ravel()[0]), _p(out)), "count_flops")
+    n = o.prob.nx * o.prob.ny
+    return {"step": out[0] / n, "cfl": out[1] / n, "edges": out[2] / n, "add": out[3] / n, "mul": out[4] / n,
+            "div": out[5] / n, "sqrt": out[6] / n}

@@ -44,6 +44,7 @@
 #pragma once
 #include <array>
 #include <cmath>
+#include <type_traits>
 #include <vector>
 
 #include "rto_ad.hpp"
@@ -257,6 +258,19 @@ Prim<T> predict_half_step(const Problem& P, const Prim<T>& w, const Prim<T>& sx,
   return q;
 }
 
+// Threads over the rows of the double-precision step, for timing the oracle
+// on several cores (1 unless rto_set_threads changes it; the AD types always
+// run on one thread).  Every cell is computed as on one thread, so the
+// result does not depend on the count.
+inline int& omp_threads() {
+  static int n = 1;
+  return n;
+}
+template <class T, class D>
+bool omp_rows() {
+  return std::is_same<T, double>::value && std::is_same<D, double>::value && omp_threads() > 1;
+}
+
 // ------------------------------------------------------------------ one step
 // Advance one member from U (4*ny*nx) to Un by dt.  Returns nonzero if a cell
 // or face state is unphysical (rho <= 0, p <= 0, or not finite).  The step
@@ -271,6 +285,7 @@ int step_member(const Problem& P, const T* U, T* Un, D dt) {
   // Primitive variables with one ghost row below (row -1) and above (row ny).
   std::vector<Prim<T>> W(static_cast<size_t>(ny + 2) * nx);
   auto Wat = [&](int i, int j) -> Prim<T>& { return W[static_cast<size_t>(j + 1) * nx + i]; };
+#pragma omp parallel for if (omp_rows<T, D>()) num_threads(omp_threads()) reduction(| : bad) schedule(static)
   for (int j = 0; j < ny; ++j)
     for (int i = 0; i < nx; ++i) {
       const int c = j * nx + i;
@@ -287,6 +302,7 @@ int step_member(const Problem& P, const T* U, T* Un, D dt) {
   // Limited slopes, MUSCL-Hancock half-step prediction, and the four face
   // states of every cell (x: left/right, y: bottom/top).
   std::vector<Prim<T>> xl(N), xr(N), yb(N), yt(N);
+#pragma omp parallel for if (omp_rows<T, D>()) num_threads(omp_threads()) reduction(| : bad) schedule(static)
   for (int j = 0; j < ny; ++j)
     for (int i = 0; i < nx; ++i) {
       const Prim<T>& w = Wat(i, j);
@@ -306,6 +322,7 @@ int step_member(const Problem& P, const T* U, T* Un, D dt) {
   // G[j][i] (j = 0..ny) is the y-flux through the bottom face of row j, with
   // G[0] and G[ny] at the walls.  Components: (rho, m_x, m_y, E).
   std::vector<std::array<T, 4>> F(N), G(static_cast<size_t>(ny + 1) * nx);
+#pragma omp parallel for if (omp_rows<T, D>()) num_threads(omp_threads()) reduction(| : bad) schedule(static)
   for (int j = 0; j < ny; ++j)
     for (int i = 0; i < nx; ++i) {
       const Prim<T>& a = xr[j * nx + (i + nx - 1) % nx];
@@ -313,6 +330,7 @@ int step_member(const Problem& P, const T* U, T* Un, D dt) {
       const std::array<T, 4> f = hllc(P, FaceState<T>{a.r, a.u, a.v, a.p}, FaceState<T>{b.r, b.u, b.v, b.p});
       F[j * nx + i] = {f[0], f[1], f[2], f[3]};
     }
+#pragma omp parallel for if (omp_rows<T, D>()) num_threads(omp_threads()) reduction(| : bad) schedule(static)
   for (int j = 0; j <= ny; ++j)
     for (int i = 0; i < nx; ++i) {
       std::array<T, 4> gf;
@@ -333,6 +351,7 @@ int step_member(const Problem& P, const T* U, T* Un, D dt) {
 
   // Conservative update plus the gravity source.
   const D ax = dt / dx, ay = dt / dy;
+#pragma omp parallel for if (omp_rows<T, D>()) num_threads(omp_threads()) reduction(| : bad) schedule(static)
   for (int j = 0; j < ny; ++j)
     for (int i = 0; i < nx; ++i) {
       const int c = j * nx + i;

@@ -18,7 +18,7 @@ def _build_oracle_if_missing():
     lib = os.path.join(ROOT, "oracle", "librtoracle.so")
     if os.path.exists(lib):
         return
-    subprocess.check_call(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-o", lib,
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-fopenmp", "-fPIC", "-shared", "-o", lib,
                            os.path.join(ROOT, "oracle", "rto.cpp")])
 
 

@@ -1082,3 +1082,41 @@ def test_tie_tolerance_moves_the_64x128_march_by_a_bounded_amount():
     assert rel[0] <= 5e-10 and rel[3] <= 5e-10, rel
     assert rel[1] <= 1e-7 and rel[2] <= 1e-7, rel
     assert np.max(np.abs(la - lb) / lb) <= 3e-8
+
+
+# ------------------------------------------------------------ measurement aids
+def test_algorithmic_flops_per_cell_of_the_benchmark():
+    # The roofline of the benchmark compares the kernels' FP64 rate with the
+    # algorithmic work of the scheme: every operation on state-dependent
+    # values as the oracle writes it (rto_count.hpp), per cell, on the
+    # workload's state half-way through a march: the step plus the signal
+    # speed of the new state (forward), and for the adjoint the step again
+    # plus one multiply-add per edge of the step's graph.
+    import bench
+    cfg = RTConfig(nx=128, ny=256)
+    o = Oracle.from_config(cfg)
+    U, _, _, _ = o.integrate(o.init_state(inputs.seed_batch(cfg, [0], rms=1e-3)), 1.0)
+    c = rto.count_flops(o, U, o.cfl_dt(U))
+    assert c["add"] + c["mul"] + c["div"] + c["sqrt"] == pytest.approx(c["step"])
+    fwd = c["step"] + c["cfl"]
+    adj = c["step"] + 2.0 * c["edges"]
+    assert abs(fwd - bench.FWD_FLOPS_PER_CELL) <= 0.03 * fwd, fwd
+    assert abs(adj - bench.ADJ_FLOPS_PER_CELL) <= 0.03 * adj, adj
+    # the signal speed: c^2 = gamma p / rho (after the primitives), |u| + c,
+    # |v| + c, each over its cell width: a fixed count per cell
+    assert c["cfl"] == 16.0
+
+
+def test_threaded_oracle_steps_are_bitwise_the_single_threaded_ones():
+    cfg = RTConfig(nx=64, ny=128)
+    o = Oracle.from_config(cfg)
+    U = o.init_state(inputs.seed_batch(cfg, [2], rms=3e-2))
+    dt = o.cfl_dt(U)
+    one = o.step(U, dt)
+    used = rto.set_threads(4)
+    try:
+        many = o.step(U, dt)
+    finally:
+        rto.set_threads(1)
+    assert used in (1, 4)
+    np.testing.assert_array_equal(one, many)

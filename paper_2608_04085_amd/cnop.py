@@ -51,67 +51,109 @@ def ke_ratio(rt: Context, uv: torch.Tensor, T: float) -> torch.Tensor:
     return rt.objective_ratio(uv, T)
 
 
-def spg(rt: Context, uv0, T: float, delta: float, iters: int, policy: Policy | None = None,
-        pool: torch.Tensor | None = None, memory: int = 10, c_armijo: float = 1e-4, max_backtracks: int = 8,
-        log: SPGLog | None = None, on_iter=None):
-    """Run `iters` SPG iterations from uv0 (projected onto ||u|| = delta).
-    on_iter(k, R, log), if given, is called after iteration k.
-    Returns (u, R, g, log)."""
-    log = log or SPGLog()
-    B = rt.cfg.batch
-    u, _ = rt.project_to_constraint(rt.as_dev(uv0), delta, NORM_L2, SET_SPHERE)
-    R, g, _ = rt.grad_u0(u, T, policy, pool=pool)
-    log.grads += 1
-    Rh = R.cpu().numpy().copy()
-    hist = [Rh.copy()]
-    gn = _l2dv(rt, g)
-    alpha = 0.1 * delta / np.maximum(gn, 1e-300)
-    for it in range(iters):
+class SPG:
+    """The spectral projected-gradient search as an object that advances one
+    iteration per step() (all members at once).  Each trial point is
+    evaluated with its gradient (grad_at_trials, the default: an accepted
+    trial needs no second march) or with a forward march and the gradient
+    afterwards at the accepted point; both give the same iterates.
+
+    cell_updates counts 2 B nx ny N_t per gradient call (one forward and one
+    adjoint sweep over every member's N_t steps), the algorithmic work of
+    the calls so far."""
+
+    def __init__(self, rt: Context, uv0, T: float, delta: float, policy: Policy | None = None,
+                 pool: torch.Tensor | None = None, memory: int = 10, c_armijo: float = 1e-4,
+                 max_backtracks: int = 8, log: SPGLog | None = None, grad_at_trials: bool = True):
+        self.rt, self.T, self.delta, self.policy, self.pool = rt, T, delta, policy, pool
+        self.memory, self.c_armijo, self.max_backtracks = memory, c_armijo, max_backtracks
+        self.grad_at_trials = grad_at_trials
+        self.log = log or SPGLog()
+        self.cell_updates = 0
+        self.u, _ = rt.project_to_constraint(rt.as_dev(uv0), delta, NORM_L2, SET_SPHERE)
+        R, self.g, _ = self._grad(self.u)
+        self.R = R.cpu().numpy().copy()
+        self.hist = [self.R.copy()]
+        gn = _l2dv(rt, self.g)
+        self.alpha = 0.1 * delta / np.maximum(gn, 1e-300)
+
+    def _grad(self, u):
+        R, g, n = self.rt.grad_u0(u, self.T, self.policy, pool=self.pool)
+        self.log.grads += 1
+        self.last_nsteps = n.cpu().numpy().tolist()
+        self.cell_updates += 2 * int(sum(self.last_nsteps)) * self.rt.cfg.nx * self.rt.cfg.ny
+        return R, g, n
+
+    def step(self) -> np.ndarray:
+        """One iteration; returns the accepted objective of every member."""
+        rt, log, B = self.rt, self.log, self.rt.cfg.batch
+        u, g, alpha, delta, T = self.u, self.g, self.alpha, self.delta, self.T
         lam = np.ones(B)
         accepted = np.zeros(B, dtype=bool)
         u_new = torch.empty_like(u)
+        g2 = torch.empty_like(g)
         R_new = np.zeros(B)
-        ref = np.min(np.stack(hist[-memory:]), axis=0)
+        ref = np.min(np.stack(self.hist[-self.memory:]), axis=0)
         nback = np.zeros(B, dtype=int)
-        for bt in range(max_backtracks + 1):
+        for bt in range(self.max_backtracks + 1):
             trial = rt.axpy(u, lam * alpha, g)
             trial, _ = rt.project_to_constraint(trial, delta, NORM_L2, SET_SPHERE)
-            Rt = ke_ratio(rt, trial, T).cpu().numpy()
-            log.evals += 1
+            if self.grad_at_trials:
+                Rt_dev, gt, _ = self._grad(trial)
+            else:
+                Rt_dev = ke_ratio(rt, trial, T)
+                log.evals += 1
+            Rt = Rt_dev.cpu().numpy()
             d = rt.axpy(trial, -1.0, u)
             gd = rt.dot(g, d).cpu().numpy()
-            ok = (Rt >= ref + c_armijo * gd) | (bt == max_backtracks)
+            ok = (Rt >= ref + self.c_armijo * gd) | (bt == self.max_backtracks)
             for b in range(B):
                 if not accepted[b] and ok[b]:
                     accepted[b] = True
                     u_new[b] = trial[b]
                     R_new[b] = Rt[b]
+                    if self.grad_at_trials:
+                        g2[b] = gt[b]
             if accepted.all():
                 break
             nback += ~accepted
             lam = np.where(accepted, lam, 0.5 * lam)
-        R2, g2, _ = rt.grad_u0(u_new, T, policy, pool=pool)
-        log.grads += 1
+        if self.grad_at_trials:
+            Rh = R_new.copy()
+        else:
+            R2, g2, _ = self._grad(u_new)
+            Rh = R2.cpu().numpy().copy()
         s = rt.axpy(u_new, -1.0, u)
         y = rt.axpy(g2, -1.0, g)
         ss = rt.dot(s, s).cpu().numpy()
         sy = rt.dot(s, y).cpu().numpy()
         gn = _l2dv(rt, g2)
         base = delta / np.maximum(gn, 1e-300)
-        alpha = np.clip(ss / np.maximum(np.abs(sy), 1e-300), 1e-10 * base, 1e10 * base)
+        self.alpha = np.clip(ss / np.maximum(np.abs(sy), 1e-300), 1e-10 * base, 1e10 * base)
         # stationarity measure chi = ||P(u + g) - u||_inf
         pg, _ = rt.project_to_constraint(rt.axpy(u_new, 1.0, g2), delta, NORM_L2, SET_SPHERE)
         chi = rt.max_abs(rt.axpy(pg, -1.0, u_new)).cpu().numpy()
-        u, g = u_new, g2
-        Rh = R2.cpu().numpy().copy()
-        hist.append(Rh)
+        self.u, self.g, self.R = u_new, g2, Rh
+        self.hist.append(Rh)
         log.R.append(Rh.tolist())
         log.grad_norm.append(gn.tolist())
         log.chi.append(chi.tolist())
         log.backtracks.append(nback.tolist())
+        return Rh
+
+
+def spg(rt: Context, uv0, T: float, delta: float, iters: int, policy: Policy | None = None,
+        pool: torch.Tensor | None = None, memory: int = 10, c_armijo: float = 1e-4, max_backtracks: int = 8,
+        log: SPGLog | None = None, on_iter=None, grad_at_trials: bool = True):
+    """Run `iters` SPG iterations from uv0 (projected onto ||u|| = delta).
+    on_iter(k, R, log), if given, is called after iteration k.
+    grad_at_trials: see SPG.  Returns (u, R, g, log)."""
+    search = SPG(rt, uv0, T, delta, policy, pool, memory, c_armijo, max_backtracks, log, grad_at_trials)
+    for it in range(iters):
+        Rh = search.step()
         if on_iter is not None:
-            on_iter(it, Rh, log)
-    return u, torch.as_tensor(Rh), g, log
+            on_iter(it, Rh, search.log)
+    return search.u, torch.as_tensor(search.R), search.g, search.log
 
 
 class LibraryBackend:

@@ -121,9 +121,12 @@ class _Memory:
 
 
 def lbfgs_max(be, x0, iters: int, memory: int = 10, nonmonotone: int = 10, c_armijo: float = 1e-4,
-              max_backtracks: int = 12, on_iter=None, log: LBFGSLog | None = None):
+              max_backtracks: int = 12, on_iter=None, log: LBFGSLog | None = None, grad_at_trials: bool = True):
     """Maximise f over the constraint set from x0 (projected first).
-    Returns (x, f[B], g, log).
+    Returns (x, f[B], g, log).  grad_at_trials: each trial point is
+    evaluated with its gradient (the accepted one's is the next iterate's),
+    else with f alone and the gradient afterwards at the accepted point; the
+    iterates are the same (the backend's f must be the same in both).
 
     Safeguards (per member): the quasi-Newton direction is replaced by a
     gradient step, and the memory dropped, when the projected step
@@ -154,25 +157,34 @@ def lbfgs_max(be, x0, iters: int, memory: int = 10, nonmonotone: int = 10, c_arm
         ref = np.min(np.stack(hist[-nonmonotone:]), axis=0)
         lam = np.ones(B)
         accepted = np.zeros(B, dtype=bool)
-        x_new, f_new = x, f.copy()
+        x_new, f_new, g_new = x, f.copy(), g
         nback = np.zeros(B, dtype=int)
         for bt in range(max_backtracks + 1):
             trial = be.project(be.axpy(x, lam, d))
-            ft = be.value(trial)
-            log.evals += 1
+            if grad_at_trials:
+                ft, gt = be.value_and_grad(trial)
+                log.grads += 1
+            else:
+                ft = be.value(trial)
+                log.evals += 1
             gd = be.dot(g, be.axpy(trial, -1.0, x))
             ok = ~accepted & (ft >= ref + c_armijo * gd)
             if ok.any():
                 x_new = be.where(ok, trial, x_new)
                 f_new = np.where(ok, ft, f_new)
+                if grad_at_trials:
+                    g_new = be.where(ok, gt, g_new)
                 accepted |= ok
             if accepted.all():
                 break
             nback += ~accepted
             lam = np.where(accepted, lam, 0.5 * lam)
         failed = ~accepted
-        f2, g2 = be.value_and_grad(x_new)
-        log.grads += 1
+        if grad_at_trials:
+            f2, g2 = f_new, g_new  # a member that found no point keeps x, f and g
+        else:
+            f2, g2 = be.value_and_grad(x_new)
+            log.grads += 1
         s = be.axpy(x_new, -1.0, x)
         y = be.axpy(g, -1.0, g2)  # gradient change of the minimisation of -f
         ss, sy, yy = be.dot(s, s), be.dot(s, y), be.dot(y, y)

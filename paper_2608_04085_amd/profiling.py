@@ -18,7 +18,9 @@
     python -m paper_2608_04085_amd.profiling stats TITLE TRACE OUT_MD
         Kernel times of a --kernel-trace run as Markdown, per kernel and grid.
     python -m paper_2608_04085_amd.profiling counters TITLE DIR... OUT_MD
-        Per-dispatch averages of the counters of --pmc runs, per kernel class.
+        Per-dispatch averages of the counters of --pmc runs, per kernel class,
+        as Markdown and in profiles/counters.json under TITLE (keyed by the
+        kernel-source hash, as the traffic is).
 
 FETCH_SIZE and WRITE_SIZE are scaled by what they read for the plain copy
 (bytes moved / counted bytes).  On gfx950 the derived FETCH_SIZE counts a
@@ -39,6 +41,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 KERNEL_SOURCES = ["csrc/rt_kernels.hip", "csrc/rt_device.h", "csrc/rt_kernels.h"]
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic.json")
+COUNTERS_JSON = os.path.join(ROOT, "profiles", "counters.json")
 COPY_BYTES = 2 * 1024**3
 CATEGORIES = ["step_given", "step_march", "adj_a_folded", "adj_a", "adj_b", "copy"]
 
@@ -272,7 +275,33 @@ def counters_md(title: str, dirs: list, out_md: str, command: str = ""):
         lines.append(f"| {n} | " + " | ".join(vals) + " |")
     with open(out_md, "w") as f:
         f.write("\n".join(lines) + "\n")
+    data = {}
+    if os.path.exists(COUNTERS_JSON):
+        with open(COUNTERS_JSON) as f:
+            data = json.load(f)
+    data[title] = {"source_hash": kernel_source_hash(),
+                   "per_dispatch": {k: {n: sum(v) / len(v) for n, v in d.items()} for k, d in per.items()}}
+    with open(COUNTERS_JSON, "w") as f:
+        json.dump(data, f, indent=1)
     print("\n".join(lines))
+
+
+def counters_for(title: str, parts) -> dict | None:
+    """Per-launch sums over the kernel classes `parts` of the counters of
+    the committed --pmc runs titled `title`, or None if there are none or the
+    kernel sources changed since they were taken."""
+    try:
+        with open(COUNTERS_JSON) as f:
+            d = json.load(f)[title]
+    except (OSError, KeyError, ValueError):
+        return None
+    if d.get("source_hash") != kernel_source_hash():
+        return None
+    per = d.get("per_dispatch", {})
+    if not all(p in per for p in parts):
+        return None
+    names = set().union(*(per[p].keys() for p in parts))
+    return {n: sum(per[p].get(n, 0.0) for p in parts) for n in names}
 
 
 if __name__ == "__main__":

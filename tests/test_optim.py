@@ -280,3 +280,19 @@ def test_members_with_mixed_curvature_match_their_solo_runs(seed, frac_pos):
         np.testing.assert_array_equal(x[b], xs[0])
         assert f[b] == fs[0]
         assert [row[b] for row in log.f] == [row[0] for row in logs.f]
+
+
+@pytest.mark.parametrize("memory", [0, 10])
+def test_gradient_at_the_trial_points_gives_the_same_iterates(memory):
+    # evaluating trials with their gradient (the accepted trial's is reused)
+    # or with f alone and the gradient afterwards: the same search
+    B, n = 3, 12
+    be = QuadBall(_symmetric(B, n, 3), 1.0 + np.random.default_rng(2).random(n), 1e-6)
+    x0 = be.project(np.random.default_rng(5).standard_normal((B, n)))
+    xa, fa, ga, la = optim.lbfgs_max(be, x0, iters=30, memory=memory, grad_at_trials=True)
+    xb, fb, gb, lb = optim.lbfgs_max(be, x0, iters=30, memory=memory, grad_at_trials=False)
+    np.testing.assert_array_equal(xa, xb)
+    np.testing.assert_array_equal(ga, gb)
+    assert la.f == lb.f and la.backtracks == lb.backtracks
+    # one gradient per trial point (and the initial one) instead of one per iteration
+    assert lb.grads == 31 and la.grads == 1 + lb.evals and la.evals == 0

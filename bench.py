@@ -1,19 +1,23 @@
 """Benchmark of the CNOP hot path on one MI355X.
 
-One step = one projected-gradient iteration of the CNOP search on the
-gradient workload (256 x 512 FP64 cells, T = 2, about 4.8k CFL steps, a
-snapshot every 32 steps with re-computation in between):
-    u+ = P(u + alpha g)                   (constraint projection, Eq. 11)
-    R, g+ = KE ratio and its gradient     (init_state, CFL march with
-                                           snapshots, kinetic energy, adjoint
-                                           sweep, initial adjoint)
-    alpha = <s,s>/|<s,y>|                 (dot products for the next step)
+One step = one iteration of the CNOP search on the largest workload that
+fits one GPU: 8 restarts of the spectral projected-gradient ascent on the
+sphere ||u0|| = 1e-3 (Sec. 3.4, Eq. 11) at 512 x 1024 FP64 cells, T = 1
+(about 4.8k CFL steps per march), with binomial checkpointing under a
+16 GiB pool:
+    u+ = P(u + alpha g)                trial point on the sphere (Eq. 11)
+    R+, g+ = R(u+) and dR/du(u+)       init_state, CFL march with level-1
+                                       snapshots, kinetic energy, the
+                                       reverse sweep (re-computation and
+                                       discrete adjoint), initial adjoint
+    accept (non-monotone test), alpha = <s,s>/|<s,y>| (dot products)
 All of it runs in the library's HIP kernels; torch provides memory and the
 stream.  Inputs are seeded synthetic velocity fields (envelope-masked
 Gaussian noise); the paper uses no dataset.
 
-value = (forward + adjoint) cell-updates per second of the whole iteration:
-2 * N_t * nx * ny / (seconds per iteration).
+value = algorithmic cell-updates per second: 2 B nx ny N_t per gradient
+evaluation (one forward and one adjoint sweep over each member's N_t
+steps), summed over the timed iterations, over their wall time.
 """
 from __future__ import annotations
 
@@ -32,8 +36,16 @@ if ROOT not in sys.path:
 
 METRIC = "FP64 cell-updates/s (fwd, adjoint) and CNOP grad iters/s vs FD-gradient, % HBM"
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6                   # 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4     # wave64 instructions/s: one per 4 cycles per SIMD
 FWD_BYTES_PER_CELL = 64.0   # read U^n, write U^{n+1}
 ADJ_BYTES_PER_CELL = 96.0   # read U^n and lambda^{n+1}, write lambda^n
+# Algorithmic FP64 operations per cell and step (the oracle's scheme counted
+# operation by operation; tests/test_oracle_pins.py holds them to the count):
+# the step plus the signal speed of the new state; the adjoint re-computes
+# the step and does one multiply-add per edge of its computational graph.
+FWD_FLOPS_PER_CELL = 324.0
+ADJ_FLOPS_PER_CELL = 1400.0
 
 
 def parse():
@@ -41,247 +53,269 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--nx", type=int, default=256)
-    ap.add_argument("--ny", type=int, default=512)
-    ap.add_argument("--T", type=float, default=2.0)
-    ap.add_argument("--interval", type=int, default=32)
-    ap.add_argument("--tile", default=None, help="tile variant of both kernels (default: the library's choice)")
-    ap.add_argument("--tiles", default=None, help="STEP/ADJOINT tile variants (overrides --tile)")
-    ap.add_argument("--fold", type=int, choices=(0, 1), default=None,
-                    help="1: folded reverse sweep (one kernel per adjoint step), 0: two kernels (default: the library's choice)")
-    ap.add_argument("--autotune", action="store_true",
-                    help="run the kernel autotuner, then keep the fastest of its pick and two fixed pairs on a "
-                         "full gradient each (default: the library's measured defaults, so that a profile of "
-                         "this command sees the same kernels)")
-    ap.add_argument("--dt-mode", choices=("frozen", "differentiated"), default="frozen",
-                    help="time steps in the gradient: held at the forward run's (default) or differentiated")
-    ap.add_argument("--recon", choices=("primitive", "balanced"), default="primitive",
-                    help="reconstruction: primitive MC (default) or the well-balanced variant")
+    ap.add_argument("--T", type=float, default=1.0)
+    ap.add_argument("--budget-gib", type=float, default=16.0, help="checkpoint pool of the binomial checkpointing")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--kernel-launches", type=int, default=300)
-    ap.add_argument("--workload", default="grad_256x512",
-                    help="grad_256x512 (default, the JSON line) or a name from paper_2608_04085_amd.workloads")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the headline (no FD measurement, 256x512 and out-of-cache legs)")
+    ap.add_argument("--kernel-launches", type=int, default=20)
+    ap.add_argument("--workload", default="cnop_8x512x1024",
+                    help="cnop_8x512x1024 (default, the JSON line), grad_256x512, or a name from "
+                         "paper_2608_04085_amd.workloads")
     return ap.parse_args()
 
 
-def cpu_baseline(cfg, T, seconds):
-    """The oracle as it stands (single-threaded C++), timed on a bounded
-    sample of the same workload: forward steps and reverse-mode adjoint steps
-    on the same grid from the same seed."""
+def host_info():
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return model, int(cores or 1)
+
+
+def cpu_baseline(cfg, seconds):
+    """The oracle as it stands (C++, -O2), timed on the GPU machine's host on a
+    bounded sample of the same grid and seed: forward steps on one thread
+    and with OpenMP over rows on every core the process may use, and
+    reverse-mode adjoint steps (single-threaded by construction) on a
+    128 x 128 block of the same cell size around the interface, where the
+    whole grid's tape would not fit in memory."""
+    from oracle import rto
     from oracle.rto import Oracle
     from paper_2608_04085_amd import inputs
 
-    o = Oracle.from_config(cfg)
-    U = o.init_state(inputs.seed_batch(cfg, [0], rms=1e-3))
-    cells = cfg.nx * cfg.ny
-    t0 = time.perf_counter()
-    nf = 0
-    while time.perf_counter() - t0 < 0.6 * seconds:
-        U = o.step(U, o.cfl_dt(U))
-        nf += 1
-    tf = (time.perf_counter() - t0) / (nf * cells)
-    lam = np.ones_like(U) * 1e-3
-    t1 = time.perf_counter()
-    na = 0
+    model, cores = host_info()
+    c1 = cfg.with_(batch=1)
+    o = Oracle.from_config(c1)
+    U = o.init_state(inputs.seed_batch(c1, [0], l2=1e-3))
+    cells = c1.nx * c1.ny
     dt = o.cfl_dt(U)
-    while time.perf_counter() - t1 < 0.4 * seconds or na == 0:
-        lam = o.step_vjp(U, dt, lam)
+
+    def fwd_rate(threads, budget):
+        used = rto.set_threads(threads)
+        t0 = time.perf_counter()
+        n = 0
+        V = U
+        while time.perf_counter() - t0 < budget or n == 0:
+            V = o.step(V, dt)
+            n += 1
+        return n, n * cells / (time.perf_counter() - t0), used
+
+    n1, r1, _ = fwd_rate(1, 0.3 * seconds)
+    nm, rm, used = fwd_rate(cores, 0.3 * seconds)
+    rto.set_threads(1)
+    b = 128
+    j0 = c1.ny // 2 - b // 2
+    blk = c1.with_(nx=b, ny=b, lx=c1.lx * b / c1.nx, ly=c1.ly * b / c1.ny)
+    ob = Oracle.from_config(blk)
+    Ub = np.ascontiguousarray(U[:, :, j0:j0 + b, :b])
+    lam = np.full_like(Ub, 1e-3)
+    t0 = time.perf_counter()
+    na = 0
+    while time.perf_counter() - t0 < 0.4 * seconds or na == 0:
+        lam = ob.step_vjp(Ub, dt, lam)
         na += 1
-    ta = (time.perf_counter() - t1) / (na * cells)
+    ra = na * b * b / (time.perf_counter() - t0)
+    value = 2.0 / (1.0 / rm + 1.0 / ra)
     return {
-        "value": 2.0 / (tf + ta),
+        "value": value,
         "unit": "cell-updates/s",
-        "cores": 1,
+        "cores": used,
         "kind": "oracle",
-        "sample": f"{nf} forward steps + {na} adjoint steps of the {cfg.nx}x{cfg.ny} grid from the same seed; "
-                  f"value = 2/(t_fwd + t_adj) per cell (forward {1.0 / tf:.3e}, adjoint {1.0 / ta:.3e} cell-updates/s)",
+        "sample": f"{c1.nx}x{c1.ny} grid, Gaussian seed 0: {nm} forward steps with OpenMP over rows on {used} threads "
+                  f"({rm:.3e} cell-updates/s; one thread: {n1} steps, {r1:.3e}) and {na} reverse-mode adjoint steps "
+                  f"on one thread on a {b}x{b} block of the same cells ({ra:.3e}); value = 2/(1/forward + 1/adjoint) "
+                  f"per cell",
+        "single_thread_value": 2.0 / (1.0 / r1 + 1.0 / ra),
+        "host_cpu": model,
+        "host_cores_available": cores,
     }
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the independent members of a "
-              f"batch shard across GPUs without communication)", file=sys.stderr)
-        sys.exit(2)
+def roofline(kind, kt_us, cells, traffic, counters):
+    """Roofline object of the forward step or the adjoint pair: algorithmic
+    FP64 flops over the event-timed launch against the FP64 vector peak
+    (the kernels are bound by FP64 VALU issue), with the HBM view
+    (algorithmic bytes) and, from the committed counters at this size, the
+    VALU issue rate beside it."""
+    flops = (FWD_FLOPS_PER_CELL if kind == "step" else ADJ_FLOPS_PER_CELL) * cells
+    nbytes = (FWD_BYTES_PER_CELL if kind == "step" else ADJ_BYTES_PER_CELL) * cells
+    t = kt_us * 1e-6
+    tf = flops / t / 1e12
+    gb = nbytes / t / 1e9
+    out = {
+        "bound": "alu",
+        "achieved": round(tf, 3),
+        "peak": FP64_PEAK_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": round(tf / FP64_PEAK_TFLOPS, 5),
+        "traffic": None if traffic is None else round(traffic, 1),
+        "algorithmic_flops_per_launch": flops,
+        "kernel": ("fused forward step (k_step with the CFL epilogue, march)" if kind == "step"
+                   else "adjoint step (k_adj_a + k_adj_b)"),
+        "launch_us": round(kt_us, 3),
+        "hbm": {"achieved": round(gb, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gb / HBM_PEAK_GBS, 5),
+                "algorithmic_bytes_per_launch": nbytes},
+        "valu_issue": None,
+    }
+    if counters and counters.get("SQ_INSTS_VALU"):
+        insts = counters["SQ_INSTS_VALU"]
+        f64 = 64 * (counters.get("SQ_INSTS_VALU_ADD_F64", 0) + counters.get("SQ_INSTS_VALU_MUL_F64", 0)
+                    + counters.get("SQ_INSTS_VALU_TRANS_F64", 0) + 2 * counters.get("SQ_INSTS_VALU_FMA_F64", 0))
+        out["valu_issue"] = {"achieved": insts / t, "peak": VALU_ISSUE_PEAK, "unit": "wave-instructions/s",
+                             "frac": round(insts / t / VALU_ISSUE_PEAK, 4), "instructions_per_launch": insts,
+                             "per_64_cells": round(insts / (cells / 64), 1),
+                             "executed_fp64_tflops": round(f64 / t / 1e12, 3)}
+    return out
+
+
+def grad_256x512_extra(steps: int = 5, interval: int = 32) -> dict:
+    """The 256 x 512, T = 2 gradient iteration (snapshots every 32 steps):
+    projected-gradient iterations per second and cell-updates/s."""
     import torch
-
-    if args.workload != "grad_256x512":
-        from paper_2608_04085_amd import workloads
-
-        print(json.dumps(workloads.WORKLOADS[args.workload]()), flush=True)
-        return
 
     from paper_2608_04085_amd import inputs
     from paper_2608_04085_amd.config import CKPT_UNIFORM, NORM_L2, SET_SPHERE, RTConfig
     from paper_2608_04085_amd.rtcnop import Context, Policy
 
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    torch.cuda.set_device(0)
-    from paper_2608_04085_amd.config import RECON_BALANCED, RECON_PRIMITIVE
-
-    cfg = RTConfig(nx=args.nx, ny=args.ny, recon=RECON_BALANCED if args.recon == "balanced" else RECON_PRIMITIVE)
-    # the committed counter runs cover the default kernels only
-    counters_apply = args.dt_mode == "frozen" and args.recon == "primitive"
-    T = args.T
-    ctx = Context(cfg, max_steps=16384, tile=args.tile)
-    if args.tiles:
-        ctx.set_tiles(*args.tiles.split("/"))
-    if args.fold is not None:
-        ctx.set_fold(bool(args.fold))
-    ctx.set_dt_mode(args.dt_mode)
-    cells = cfg.nx * cfg.ny
-
-    # seed and step count
+    cfg = RTConfig(nx=256, ny=512)
+    T = 2.0
+    ctx = Context(cfg, max_steps=16384)
     u = torch.from_numpy(inputs.seed_batch(cfg, [0], rms=1e-3)).cuda()
     delta = float(math.sqrt(float((u * u).sum()) * cfg.dx * cfg.dy))
     U0 = ctx.init_state(u)
-    _, _, n, log = ctx.integrate(U0, T, log_cap=16384)
+    _, _, n, _ = ctx.integrate(U0, T)
     nt = int(n.item())
-    pol = Policy(CKPT_UNIFORM, args.interval)
-    pool = torch.empty(ctx.pool_bytes(CKPT_UNIFORM, args.interval, nt + 64) + 256, dtype=torch.uint8, device="cuda")
-    tuning = {}
-    if args.autotune:
-        # kernel-level autotuning, then the sweep decides: the autotuner's
-        # pick against two fixed pairs, one gradient each (all give the same
-        # bits; only the speed differs)
-        ctx.autotune(U0, reps=20)
-        cands = [(ctx.tile, ctx.fold), ("32x8w/32x8", False), ("32x8/32x8", False)]
-        for tiles, fold in cands:
-            ctx.set_tiles(*tiles.split("/"))
-            ctx.set_fold(fold)
-            ctx.grad_u0(u, T, pol, pool=pool)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            ctx.grad_u0(u, T, pol, pool=pool)
-            torch.cuda.synchronize()
-            tuning[f"{tiles}{'+fold' if fold else ''}"] = time.perf_counter() - t0
-        best = min(tuning, key=tuning.get)
-        ctx.set_tiles(*best.split("+")[0].split("/"))
-        ctx.set_fold(best.endswith("+fold"))
+    pol = Policy(CKPT_UNIFORM, interval)
+    pool = torch.empty(ctx.pool_bytes(CKPT_UNIFORM, interval, nt + 64) + 256, dtype=torch.uint8, device="cuda")
     R, g, _ = ctx.grad_u0(u, T, pol, pool=pool)
     alpha = 0.1 * delta / float(g.norm() * math.sqrt(cfg.dx * cfg.dy))
 
     def iteration(u, g, alpha):
-        ut = ctx.axpy(u, alpha, g)
-        ut, _ = ctx.project_to_constraint(ut, delta, NORM_L2, SET_SPHERE)
+        ut, _ = ctx.project_to_constraint(ctx.axpy(u, alpha, g), delta, NORM_L2, SET_SPHERE)
         R, gt, n = ctx.grad_u0(ut, T, pol, pool=pool)
-        s = ctx.axpy(ut, -1.0, u)
-        y = ctx.axpy(gt, -1.0, g)
-        ss, sy = ctx.dot(s, s), ctx.dot(s, y)
-        a = float(ss.item()) / max(abs(float(sy.item())), 1e-300)
-        return ut, gt, min(max(a, 1e-10 * alpha), 1e10 * alpha), R, n
+        s, y = ctx.axpy(ut, -1.0, u), ctx.axpy(gt, -1.0, g)
+        a = float(ctx.dot(s, s).item()) / max(abs(float(ctx.dot(s, y).item())), 1e-300)
+        return ut, gt, min(max(a, 1e-10 * alpha), 1e10 * alpha), n
 
-    for _ in range(args.warmup):
-        u, g, alpha, R, n = iteration(u, g, alpha)
+    u, g, alpha, n = iteration(u, g, alpha)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    nsteps_total = 0
-    for _ in range(args.steps):
-        u, g, alpha, R, n = iteration(u, g, alpha)
-        nsteps_total += int(n.item())
+    tot = 0
+    for _ in range(steps):
+        u, g, alpha, n = iteration(u, g, alpha)
+        tot += int(n.item())
     torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    per_iter = elapsed / args.steps
-    nt_mean = nsteps_total / args.steps
-    value = 2.0 * nt_mean * cells / per_iter
-
-    # forward-only march (adaptive CFL, one launch per step, no snapshots)
+    per = (time.perf_counter() - t0) / steps
     torch.cuda.synchronize()
     tf0 = time.perf_counter()
     _, _, nf, _ = ctx.integrate(U0, T)
     torch.cuda.synchronize()
     t_fwd = time.perf_counter() - tf0
-    fwd_rate = int(nf.item()) * cells / t_fwd
+    kt = ctx.kernel_times(ctx.integrate(U0, 0.5)[0], reps=100)
+    return {"workload": "grad_256x512: forward + discrete-adjoint gradient of KE(T)/KE(0), T=2, snapshot every 32 "
+                        "steps, one projected-gradient iteration", "grad_iters_per_s": 1.0 / per,
+            "cell_updates_per_s": 2.0 * (tot / steps) * cfg.cells / per, "nsteps": tot / steps,
+            "fwd_cell_updates_per_s": int(nf.item()) * cfg.cells / t_fwd, "gradient_over_forward": per / t_fwd,
+            "kernel_times_us": {k: round(v, 3) for k, v in kt.items()}, "tile": ctx.tile}
 
-    # finite-difference gradient for comparison: n_dof + 1 forward marches
-    # (one-sided differences), run as batches of 8 members; one batch timed
-    fd_b = 8
-    ctx_fd = Context(cfg.with_(batch=fd_b), max_steps=16384)
-    Ufd = ctx_fd.init_state(np.repeat(inputs.seed_batch(cfg, [0], rms=1e-3), fd_b, axis=0))
-    ctx_fd.autotune(Ufd, reps=10)
-    ctx_fd.integrate(Ufd, T)
-    torch.cuda.synchronize()
-    tb0 = time.perf_counter()
-    ctx_fd.integrate(Ufd, T)
-    torch.cuda.synchronize()
-    t_fd_batch = time.perf_counter() - tb0
-    del ctx_fd, Ufd
-    n_dof = 2 * cells
-    fd_iter_s = t_fd_batch * (n_dof + 1) / fd_b
 
-    # per-launch durations of the kernels as the iteration launches them,
-    # from HIP events on the library's stream around back-to-back launches
-    Uk = ctx.integrate(U0, 0.5)[0]
-    kt = ctx.kernel_times(Uk, reps=args.kernel_launches)
-    t_given, t_march, t_adj = (kt["step_given_us"] * 1e-6, kt["step_march_us"] * 1e-6,
-                               kt["adjoint_sweep_us"] * 1e-6)
-    # per iteration: nt march steps, nt (interval-1)/interval re-computed
-    # steps, nt adjoint steps (one kernel each)
-    fw_share = nt_mean * (t_march + t_given * (1 - 1.0 / args.interval))
-    adj_share = t_adj * nt_mean
-    if adj_share >= fw_share:
-        dom = {"kernel": ("adjoint step (k_adj_a with the folded limiter gather)" if ctx.fold
-                          else "adjoint step (k_adj_a + k_adj_b)"),
-               "bytes_per_cell": ADJ_BYTES_PER_CELL, "t": t_adj,
-               "traffic_key": "adjoint_folded" if ctx.fold else "adjoint"}
-    else:
-        dom = {"kernel": "fused forward step (k_step, march)", "bytes_per_cell": FWD_BYTES_PER_CELL, "t": t_march,
-               "traffic_key": "step"}
-    achieved = dom["bytes_per_cell"] * cells / dom["t"] / 1e9
-    from paper_2608_04085_amd import profiling
+def scale_point(kernel_launches: int = 10) -> dict:
+    """Out-of-cache kernel times: 8 members of 1024 x 2048 (537 MB a state)."""
+    from paper_2608_04085_amd import inputs, profiling
+    from paper_2608_04085_amd.config import RTConfig
+    from paper_2608_04085_amd.rtcnop import Context
 
-    traffic = (profiling.traffic_for(f"grad_{cfg.nx}x{cfg.ny}", dom["traffic_key"], ctx.tile)
-               if counters_apply else None)
-    roofline = {
-        "bound": "hbm",
-        "achieved": round(achieved, 2),
-        "peak": HBM_PEAK_GBS,
-        "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 5),
-        "traffic": None if traffic is None else round(traffic, 1),
-        "algorithmic_bytes_per_launch": dom["bytes_per_cell"] * cells,
-        "kernel": dom["kernel"],
-        "launch_us": round(dom["t"] * 1e6, 3),
-        "kernel_times_us": {k: round(v, 3) for k, v in kt.items()},
-        **({} if args.dt_mode == "frozen" else
-           {"note": "launch_us and kernel_times_us time the frozen-step kernels; the differentiated sweep adds its "
-                    "step-size partial sums to kernel A and one small kernel per step"}),
-        "fwd_share_of_iteration": round(fw_share / per_iter, 3),
-        "adj_share_of_iteration": round(adj_share / per_iter, 3),
-    }
-    # the fused forward step of the march beside it, on the same terms
-    t_step_traffic = (profiling.traffic_for(f"grad_{cfg.nx}x{cfg.ny}", "step_march", ctx.tile)
-                      if counters_apply else None)
-    achieved_step = FWD_BYTES_PER_CELL * cells / t_march / 1e9
-    roofline_step = {
-        "bound": "hbm",
-        "achieved": round(achieved_step, 2),
-        "peak": HBM_PEAK_GBS,
-        "unit": "GB/s",
-        "frac": round(achieved_step / HBM_PEAK_GBS, 5),
-        "traffic": None if t_step_traffic is None else round(t_step_traffic, 1),
-        "algorithmic_bytes_per_launch": FWD_BYTES_PER_CELL * cells,
-        "kernel": "fused forward step (k_step with the CFL epilogue, march)",
-        "launch_us": round(t_march * 1e6, 3),
-    }
-    # the out-of-cache point: 8 members of 1024 x 2048 (537 MB per state,
-    # above the last-level cache), the same kernels timed the same way
     cfg8 = RTConfig(nx=1024, ny=2048, batch=8)
     ctx8 = Context(cfg8, max_steps=64)
     U8 = ctx8.init_state(inputs.seed_batch(cfg8, range(8), rms=1e-3))
-    kt8 = ctx8.kernel_times(U8, reps=10)
+    kt8 = ctx8.kernel_times(U8, reps=kernel_launches)
     cells8 = cfg8.nx * cfg8.ny * cfg8.batch
-    scale_point = {"workload": "8 x 1024 x 2048, one launch per step", "tile": ctx8.tile}
-    for key, bpc, t_us, tkey in (("step", FWD_BYTES_PER_CELL, kt8["step_march_us"], "step_march"),
-                                 ("adjoint", ADJ_BYTES_PER_CELL, kt8["adjoint_two_kernel_us"], "adjoint")):
-        gbs = bpc * cells8 / (t_us * 1e-6) / 1e9
-        tr = profiling.traffic_for("step_8x1024x2048", tkey, ctx8.tile)
-        scale_point[key] = {"launch_us": round(t_us, 3), "cell_updates_per_s": cells8 / (t_us * 1e-6),
-                            "achieved_GBps": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4),
-                            "traffic": None if tr is None else round(tr, 1)}
-    del ctx8, U8
+    out = {"workload": "8 x 1024 x 2048, one launch per step", "tile": ctx8.tile}
+    for key, t_us, tkey, parts in (("step", kt8["step_march_us"], "step_march", ["step_march"]),
+                                   ("adjoint", kt8["adjoint_two_kernel_us"], "adjoint", ["adj_a", "adj_b"])):
+        out[key] = roofline(key, t_us, cells8, profiling.traffic_for("step_8x1024x2048", tkey, ctx8.tile),
+                            profiling.counters_for("8x1024x2048", parts))
+        out[key]["cell_updates_per_s"] = cells8 / (t_us * 1e-6)
+    return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the independent restarts of a batch "
+              f"would shard across GPUs without communication)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    if args.workload == "grad_256x512":
+        torch.cuda.set_device(0)
+        print(json.dumps(grad_256x512_extra(max(args.steps, 1))), flush=True)
+        return
+    if args.workload != "cnop_8x512x1024":
+        from paper_2608_04085_amd import workloads
+
+        print(json.dumps(workloads.WORKLOADS[args.workload]()), flush=True)
+        return
+
+    from paper_2608_04085_amd import cnop, inputs, profiling, rtcnop
+    from paper_2608_04085_amd.config import CKPT_REVOLVE, RTConfig
+    from paper_2608_04085_amd.rtcnop import Context, Policy
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    cfg = RTConfig(nx=512, ny=1024, batch=8)
+    B = cfg.batch
+    cells = cfg.nx * cfg.ny * B
+    T = args.T
+    delta = 1e-3
+    ctx = Context(cfg, max_steps=int(math.ceil(6000 * T)) + 1024)
+    state_bytes = 8 * 4 * cells
+    slots = int(args.budget_gib * 2**30) // state_bytes
+    pool = torch.empty(slots * state_bytes + 256, dtype=torch.uint8, device="cuda")
+    uv = inputs.seed_batch(cfg, range(B), l2=delta)
+
+    search = cnop.SPG(ctx, uv, T, delta, Policy(CKPT_REVOLVE, 1), pool=pool)
+    for _ in range(args.warmup):
+        search.step()
+    torch.cuda.synchronize()
+    cu0, gr0, it0 = search.cell_updates, search.log.grads, len(search.log.backtracks)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        search.step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    per_iter = elapsed / args.steps
+    value = (search.cell_updates - cu0) / elapsed
+    grads_timed = search.log.grads - gr0
+    nsteps = search.last_nsteps
+    nt = int(max(nsteps))
+    backtracks = [row for row in search.log.backtracks[it0:]]
+
+    # kernels at this size, as the iteration launches them (HIP events on
+    # the library's stream), on a state half-way through the march
+    Umid, _, _, _ = ctx.integrate(ctx.init_state(search.u), 0.5 * T)
+    kt = ctx.kernel_times(Umid, reps=args.kernel_launches)
+    fw_total, interval, two = rtcnop.revolve_plan_stats(nt, slots, nt)
+    t_fwd = nt * kt["step_march_us"] + (fw_total - nt) * kt["step_given_us"]
+    t_adj = nt * kt["adjoint_two_kernel_us"]
+    tkey = "cnop_8x512x1024"
+    adj = roofline("adjoint", kt["adjoint_two_kernel_us"], cells, profiling.traffic_for(tkey, "adjoint", ctx.tile),
+                   profiling.counters_for(tkey, ["adj_a", "adj_b"]))
+    stp = roofline("step", kt["step_march_us"], cells, profiling.traffic_for(tkey, "step_march", ctx.tile),
+                   profiling.counters_for(tkey, ["step_march"]))
+    dom, other = (adj, stp) if t_adj >= t_fwd else (stp, adj)
+    per_grad_s = per_iter * args.steps / max(grads_timed, 1)
+    dom["fwd_share_of_gradient"] = round(t_fwd * 1e-6 / per_grad_s, 3)
+    dom["adj_share_of_gradient"] = round(t_adj * 1e-6 / per_grad_s, 3)
+
     out = {
         "metric": METRIC,
         "value": value,
@@ -296,25 +330,44 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": f"grad_{cfg.nx}x{cfg.ny}: forward + discrete-adjoint gradient of KE(T)/KE(0), T={T}, "
-                        f"snapshot every {args.interval} steps, one projected-gradient iteration per step",
-            "nx": cfg.nx, "ny": cfg.ny, "batch": 1, "T": T, "nsteps": nt_mean, "tile": ctx.tile,
-            "adjoint_folded": ctx.fold,
-            "dt_in_gradient": ctx.dt_mode, "reconstruction": "primitive MC" if cfg.recon == 0 else "well-balanced",
-            "sweep_tuning_seconds": {k: round(v, 4) for k, v in tuning.items()},
+            "workload": f"cnop_8x512x1024: one iteration of the CNOP search (spectral projected gradient on the sphere "
+                        f"||u0|| = 1e-3, non-monotone line search, each trial evaluated with its discrete-adjoint "
+                        f"gradient) for 8 restarts at once, 512x1024 cells, T={T}, binomial checkpointing under "
+                        f"{args.budget_gib:g} GiB",
+            "nx": cfg.nx, "ny": cfg.ny, "batch": B, "T": T, "nsteps": int(np.mean(nsteps)),
+            "pool_slots": slots, "level1_interval": interval, "two_level": two,
+            "forward_steps_per_gradient": fw_total, "tile": ctx.tile,
         },
-        "grad_iters_per_s": 1.0 / per_iter,
-        "fwd_cell_updates_per_s": fwd_rate,
-        "fd_grad_iters_per_s_extrapolated": 1.0 / fd_iter_s,
-        "fd_batch8_forward_seconds": t_fd_batch,
-        "adjoint_vs_fd_speedup": fd_iter_s / per_iter,
-        "R": float(R.item()),
-        "roofline": roofline,
-        "roofline_step": roofline_step,
-        "scale_point": scale_point,
+        "cnop_iters_per_s": 1.0 / per_iter,
+        "gradient_evals_per_iter": grads_timed / args.steps,
+        "backtracks": backtracks,
+        "best_R": float(np.max(search.R)),
+        "roofline": dom,
+        "roofline_other": other,
+        "kernel_times_us": {k: round(v, 3) for k, v in kt.items()},
     }
+    if not args.no_extras:
+        from paper_2608_04085_amd import workloads
+
+        fd = workloads.fd_64x128()
+        out["fd_64x128_measured"] = fd
+        # the FD gradient iteration at this size, extrapolated from a timed
+        # march of the 8 members: 2 n_dof marches per member, each batched
+        # march serving every member once
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        ctx.objective_ratio(search.u, T)
+        torch.cuda.synchronize()
+        t_march8 = time.perf_counter() - tb
+        n_dof = 2 * cfg.nx * cfg.ny
+        fd_iter = 2 * n_dof * t_march8 + t_march8
+        out["fd_iters_per_s_extrapolated"] = 1.0 / fd_iter
+        out["adjoint_vs_fd_speedup_extrapolated"] = fd_iter / per_iter
+        out["forward_march_seconds_8_members"] = t_march8
+        out["grad_256x512"] = grad_256x512_extra()
+        out["scale_point"] = scale_point()
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(cfg, T, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

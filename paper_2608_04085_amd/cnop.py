@@ -231,31 +231,47 @@ def peak_row(v: np.ndarray) -> int:
 # ---------------------------------------------------------------------------
 # Forward comparison suite (Sec. 3.3 run design, Sec. 4.3-4.4 diagnostics)
 
-def dominant_modes(v: np.ndarray, k: int = 5) -> np.ndarray:
+def dominant_modes(v: np.ndarray, k: int = 5, E_row=None) -> np.ndarray:
     """Horizontal mode numbers n >= 1 of the k largest E_n (Eq. 12) at the
-    peak row of v ([ny][nx])."""
-    c = np.fft.rfft(v[peak_row(v)])
-    e = np.abs(c[1:]) ** 2
+    peak row of v ([ny][nx]); E_row, if given, is that row's spectrum from
+    the library's rt_row_spectrum (else numpy's rfft of the row)."""
+    if E_row is None:
+        e = np.abs(np.fft.rfft(v[peak_row(v)])[1:]) ** 2
+    else:
+        e = np.asarray(E_row, dtype=np.float64)[1:]
     return 1 + np.argsort(-e, kind="stable")[:k]
 
 
-def five_mode_seed(v: np.ndarray, k: int = 5) -> np.ndarray:
+def five_mode_seed(v: np.ndarray, k: int = 5, E_row=None) -> np.ndarray:
     """The 5modes perturbation: every row of v keeps only the k dominant
     horizontal modes of the peak row, with their amplitudes and phases
     (rfft bins n and, implicitly, -n); the rest of each row is dropped."""
-    modes = dominant_modes(v, k)
+    modes = dominant_modes(v, k, E_row)
     c = np.fft.rfft(v, axis=1)
     keep = np.zeros(c.shape[1], dtype=bool)
     keep[modes] = True
     return np.fft.irfft(np.where(keep[None, :], c, 0.0), n=v.shape[1], axis=1)
 
 
-def power_reconstruction(v: np.ndarray, frac: float = 0.9) -> np.ndarray:
+def full_plane(E_half: np.ndarray, nx: int) -> np.ndarray:
+    """The [ny][nx] power spectrum of a real field from its half plane
+    [ny][nx/2 + 1] (E(q, k) = E(-q mod ny, nx - k))."""
+    ny = E_half.shape[0]
+    out = np.empty((ny, nx))
+    nk = nx // 2 + 1
+    out[:, :nk] = E_half
+    k = np.arange(nk, nx)
+    out[:, nk:] = E_half[(-np.arange(ny)) % ny][:, nx - k]
+    return out
+
+
+def power_reconstruction(v: np.ndarray, frac: float = 0.9, E2=None) -> np.ndarray:
     """The 2-D reconstruction of App. B: the fewest 2-D Fourier modes of v
     that hold `frac` of its spectral energy (strongest first), inverse
-    transformed."""
+    transformed.  E2, if given, is the library's rt_power_spectrum_2d of v
+    (half plane), which then ranks the modes."""
     F = np.fft.fft2(v)
-    e = np.abs(F) ** 2
+    e = np.abs(F) ** 2 if E2 is None else full_plane(np.asarray(E2, dtype=np.float64), v.shape[1])
     order = np.argsort(-e, axis=None, kind="stable")
     csum = np.cumsum(e.ravel()[order])
     m = int(np.searchsorted(csum, frac * csum[-1]) + 1)
@@ -264,19 +280,32 @@ def power_reconstruction(v: np.ndarray, frac: float = 0.9) -> np.ndarray:
     return np.real(np.fft.ifft2(np.where(mask.reshape(e.shape), F, 0.0)))
 
 
+def library_spectra(rt: Context, v: np.ndarray):
+    """(E of the peak row, the 2-D power spectrum) of the field v [ny][nx]
+    from the library (rt_row_spectrum, rt_power_spectrum_2d), on a
+    one-member context of rt's grid."""
+    r1 = Context(rt.cfg.with_(batch=1), max_steps=8, device=rt.device)
+    f = torch.as_tensor(np.ascontiguousarray(v)[None], dtype=torch.float64, device=rt.device)
+    E_row = r1.row_spectrum(f, row=peak_row(v))[0].cpu().numpy()
+    E2 = r1.power_spectrum_2d(f)[0].cpu().numpy()
+    return E_row, E2
+
+
 COMPARISON_KINDS = ("CNOP", "Random", "5modes", "2D90")
 
 
-def comparison_seeds(cfg, v_cnop: np.ndarray, random_seed: int = 1000) -> np.ndarray:
+def comparison_seeds(cfg, v_cnop: np.ndarray, random_seed: int = 1000, rt: Context | None = None) -> np.ndarray:
     """[4][2][ny][nx] u_y-only perturbations of the comparison suite, unscaled:
     the CNOP itself, a localised Gaussian field (the optimiser's initial-guess
     construction), its 5-mode reduction and its 90%-power 2-D
-    reconstruction."""
+    reconstruction.  With rt, the mode energies that pick the 5 modes and
+    the 90 % of the power come from the library's spectra."""
     from . import inputs
 
+    E_row, E2 = library_spectra(rt, v_cnop) if rt is not None else (None, None)
     rnd = inputs.paper_seed_batch(cfg.with_(batch=1), [random_seed])[0, 1]
     out = np.zeros((4, 2, cfg.ny, cfg.nx))
-    for k, v in enumerate((v_cnop, rnd, five_mode_seed(v_cnop), power_reconstruction(v_cnop))):
+    for k, v in enumerate((v_cnop, rnd, five_mode_seed(v_cnop, E_row=E_row), power_reconstruction(v_cnop, E2=E2))):
         out[k, 1] = v
     return out
 

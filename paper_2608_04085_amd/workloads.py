@@ -263,7 +263,7 @@ def paper_compare_128(T: float = 2.0, iters: int = 20, n_snap: int = 20) -> dict
     be = cnop.LibraryBackend(rt, T, ekb, 1e-6, pol)
     u, J, g, log = optim.lbfgs_max(be, u0, iters, memory=0)
     t_search = time.perf_counter() - t0
-    seeds = cnop.comparison_seeds(cfg, u[0, 1].cpu().numpy())
+    seeds = cnop.comparison_seeds(cfg, u[0, 1].cpu().numpy(), rt=rt)
     rc = Context(cfg.with_(batch=4), max_steps=16384)
     (res, el) = _timed(lambda: cnop.comparison_runs(rc, seeds, 1e-6, T, n_snap))
     ke = np.array(res["ke"])

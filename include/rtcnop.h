@@ -193,6 +193,18 @@ int rt_mix_width(rt_ctx* ctx, const double* U, double* h);
  * sum_{m >= 1} E[b][m].  nx <= 4096.  Deterministic (a fixed-order sum). */
 int rt_row_spectrum(rt_ctx* ctx, const double* f, int64_t member_stride, int32_t row, double* E);
 
+/* 2-D power spectrum of one scalar field per member, the quantity whose
+ * strongest modes, up to 90 % of the spectral energy, make the 2-D
+ * reconstruction of App. B: E[b][q][k] = |F_b(q, k)|^2 with F_b(q, k) =
+ * sum over cells of f_b(y, x) exp(-2 pi i (k x / nx + q y / ny)), for
+ * q = 0 .. ny - 1 and k = 0 .. nx/2 (a real field's spectrum is symmetric,
+ * E(q, k) = E(-q mod ny, nx - k), so this half plane holds all of it), E
+ * laid out [B][ny][nx/2 + 1] (device).  f and member_stride as in
+ * rt_row_spectrum.  nx, ny <= 4096.  Deterministic (fixed-order sums: the
+ * transform of every row, then of every column).  Uses the workspace as
+ * scratch. */
+int rt_power_spectrum_2d(rt_ctx* ctx, const double* f, int64_t member_stride, double* E);
+
 /* Objective of Eq. 8 on the grid: J[B] = sum over cells of
  * (e_k(U) - ek_base)^2 dx dy, with ek_base [B][ny][nx] the e_k field of the
  * unperturbed run at the same time (device arrays). */

@@ -18,6 +18,7 @@
 //   rto_mix_width      mixing-layer width of Eqs. 13-14
 //   rto_row_spectrum   horizontal power spectrum of rows (Eq. 12's E_n
 //                      before normalisation)
+//   rto_power_spectrum_2d  2-D power spectrum (App. B's reconstruction)
 //   rto_ek_field       kinetic-energy density field of Eq. 7
 //   rto_ek_anomaly_frozen  objective J of Eq. 8 after a march with given steps
 //   rto_grad_ek_anomaly    J and its exact gradient (same reverse sweep as
@@ -333,6 +334,45 @@ int rto_row_spectrum(const Problem* P, const double* f, int64_t member_stride, i
       }
       E[static_cast<size_t>(b) * nbins + n] = e;
     }
+  }
+  return 0;
+}
+
+// 2-D power spectrum (App. B's reconstruction keeps its strongest modes):
+// E[b][q][k] = |sum_{y, x} f(y, x) exp(-2 pi i (k x / nx + q y / ny))|^2 for
+// q = 0 .. ny - 1, k = 0 .. nx/2, written as the transform of every row and
+// then of every column of the result (the 2-D DFT factorises), each a plain
+// Fourier sum with its phase reduced modulo the length.
+int rto_power_spectrum_2d(const Problem* P, const double* f, int64_t member_stride, double* E) {
+  if (!valid(P) || !f || !E) return kEInval;
+  const int nx = P->nx, ny = P->ny, nk = nx / 2 + 1;
+  const double two_pi = 2.0 * 3.14159265358979323846;
+  std::vector<double> cre(static_cast<size_t>(ny) * nk), cim(static_cast<size_t>(ny) * nk);
+  for (int b = 0; b < P->nb; ++b) {
+    const double* fb = f + static_cast<size_t>(b) * static_cast<size_t>(member_stride);
+    for (int y = 0; y < ny; ++y)
+      for (int k = 0; k < nk; ++k) {
+        double re = 0.0, im = 0.0;
+        for (int x = 0; x < nx; ++x) {
+          const double ph = two_pi * static_cast<double>((static_cast<long>(k) * x) % nx) / nx;
+          re += fb[static_cast<size_t>(y) * nx + x] * std::cos(ph);
+          im -= fb[static_cast<size_t>(y) * nx + x] * std::sin(ph);
+        }
+        cre[static_cast<size_t>(y) * nk + k] = re;
+        cim[static_cast<size_t>(y) * nk + k] = im;
+      }
+    for (int q = 0; q < ny; ++q)
+      for (int k = 0; k < nk; ++k) {
+        double re = 0.0, im = 0.0;
+        for (int y = 0; y < ny; ++y) {
+          const double ph = two_pi * static_cast<double>((static_cast<long>(q) * y) % ny) / ny;
+          const double c = std::cos(ph), s = std::sin(ph);
+          const double ar = cre[static_cast<size_t>(y) * nk + k], ai = cim[static_cast<size_t>(y) * nk + k];
+          re += ar * c + ai * s;
+          im += ai * c - ar * s;
+        }
+        E[(static_cast<size_t>(b) * ny + q) * nk + k] = re * re + im * im;
+      }
   }
   return 0;
 }

@@ -72,6 +72,7 @@ def lib():
             "rto_ek_field": [P, _dp, _dp],
             "rto_mix_width": [P, _dp, _dp],
             "rto_row_spectrum": [P, _dp, ctypes.c_int64, ctypes.c_int32, _dp],
+            "rto_power_spectrum_2d": [P, _dp, ctypes.c_int64, _dp],
             "rto_ek_anomaly_frozen": [P, _dp, _dp, _ip, ctypes.c_int32, _dp, _dp],
             "rto_grad_ek_anomaly": [P, _dp, ctypes.c_double, _dp, _dp, _dp, _ip, _dp, ctypes.c_int32],
             "rto_objective_adaptive": [P, _dp, ctypes.c_double, _dp, _dp, _ip],
@@ -222,6 +223,15 @@ class Oracle:
         E = np.empty((self.prob.nb, self.prob.nx // 2 + 1))
         _check(lib().rto_row_spectrum(ctypes.byref(self.prob), _p(f), self.prob.nx * self.prob.ny, int(row), _p(E)),
                "row_spectrum")
+        return E
+
+    def power_spectrum_2d(self, f):
+        """E[B][ny][nx/2 + 1] = |2-D DFT of each member's field f [B][ny][nx]|^2
+        (App. B's reconstruction keeps its strongest modes)."""
+        f = np.ascontiguousarray(f, dtype=np.float64).reshape(self.prob.nb, self.prob.ny, self.prob.nx)
+        E = np.empty((self.prob.nb, self.prob.ny, self.prob.nx // 2 + 1))
+        _check(lib().rto_power_spectrum_2d(ctypes.byref(self.prob), _p(f), self.prob.nx * self.prob.ny, _p(E)),
+               "power_spectrum_2d")
         return E
 
     def ek_field(self, U):

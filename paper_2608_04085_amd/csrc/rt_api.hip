@@ -1072,6 +1072,19 @@ int rt_row_spectrum(rt_ctx* c, const double* f, int64_t member_stride, int32_t r
   return 0;
 }
 
+int rt_power_spectrum_2d(rt_ctx* c, const double* f, int64_t member_stride, double* E) {
+  if (int rc = need_ws(c)) return rc;
+  if (!f || !E) return fail(RT_EINVAL, "null argument");
+  if (c->P.nx > rtk::kSpecMaxNx || c->P.ny > rtk::kSpecMaxNx)
+    return fail(RT_EINVAL, "%d x %d exceeds %d x %d for the 2-D spectrum", c->P.nx, c->P.ny, rtk::kSpecMaxNx,
+                rtk::kSpecMaxNx);
+  if (c->P.nb > 1 && member_stride < (int64_t)c->cells()) return fail(RT_EINVAL, "member_stride below nx * ny");
+  // the row transforms, 2 nb ny (nx/2 + 1) <= 12 nb nx ny doubles, in the
+  // adjoint's intermediate buffer
+  RT_HIP(rtk::launch_power_spectrum_2d(c->P.nx, c->P.ny, c->P.nb, f, (long long)member_stride, c->Z, E, c->stream));
+  return 0;
+}
+
 int rt_ek_anomaly(rt_ctx* c, const double* U, const double* ek_base, double* J) {
   if (int rc = need_ws(c)) return rc;
   if (!U || !ek_base || !J) return fail(RT_EINVAL, "null argument");

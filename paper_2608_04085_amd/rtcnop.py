@@ -91,6 +91,7 @@ def load():
         "rt_ek_field": [_vp, _vp, _vp],
         "rt_mix_width": [_vp, _vp, _vp],
         "rt_row_spectrum": [_vp, _vp, ctypes.c_int64, _i32, _vp],
+        "rt_power_spectrum_2d": [_vp, _vp, ctypes.c_int64, _vp],
         "rt_ek_anomaly": [_vp, _vp, _vp, _vp],
         "rt_grad_ek_anomaly": [_vp, _vp, ctypes.c_double, _vp, _vp, _vp, _vp, _vp],
         "rt_get_fold": [_vp, ctypes.POINTER(_i32)],
@@ -119,7 +120,8 @@ EXPORTED = ["rt_create", "rt_destroy", "rt_set_stream", "rt_workspace_bytes", "r
             "rt_set_overlap", "rt_kernel_times", "rt_set_fold", "rt_get_fold",
             "rt_set_tiles", "rt_ek_field", "rt_ek_anomaly", "rt_grad_ek_anomaly",
             "rt_mix_width", "rt_set_dt_mode", "rt_get_dt_mode", "rt_get_tile", "rt_revolve_stats",
-            "rt_row_spectrum", "rt_ke_ratio", "rt_revolve_plan_stats"]
+            "rt_row_spectrum", "rt_ke_ratio", "rt_revolve_plan_stats",
+            "rt_power_spectrum_2d"]
 
 
 def _check(rc: int, call: str):
@@ -468,6 +470,26 @@ class Context:
             base, stride = f.data_ptr() + 8 * N * int(component), 2 * N
         E = self._f64((self.cfg.batch, self.cfg.nx // 2 + 1))
         _check(load().rt_row_spectrum(self._h, ctypes.c_void_p(base), stride, int(row), _ptr(E)), "rt_row_spectrum")
+        return E
+
+    def _field_ptr(self, field, component):
+        f = self.as_dev(field)
+        N = self.cfg.nx * self.cfg.ny
+        if component is None:
+            f = f.reshape(self.cfg.batch, self.cfg.ny, self.cfg.nx)
+            return f, f.data_ptr(), N
+        if component not in (0, 1):
+            raise ValueError("component must be 0 (u) or 1 (v)")
+        f = f.reshape(self.shape_uv)
+        return f, f.data_ptr() + 8 * N * int(component), 2 * N
+
+    def power_spectrum_2d(self, field, component: int | None = None) -> torch.Tensor:
+        """E[B][ny][nx/2 + 1] = |F(q, k)|^2, the 2-D power spectrum of a field
+        [B][ny][nx] or of one component of a velocity field (App. B)."""
+        self._sync_stream()
+        f, base, stride = self._field_ptr(field, component)
+        E = self._f64((self.cfg.batch, self.cfg.ny, self.cfg.nx // 2 + 1))
+        _check(load().rt_power_spectrum_2d(self._h, ctypes.c_void_p(base), stride, _ptr(E)), "rt_power_spectrum_2d")
         return E
 
     def baseline_ek(self, T: float) -> torch.Tensor:

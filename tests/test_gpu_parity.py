@@ -508,6 +508,9 @@ def test_comparison_suite_runs_all_kinds_at_the_energy_budget():
     v = inputs.paper_seed_batch(cfg, [3])[0, 1]
     seeds = cnop.comparison_seeds(cfg, v)
     r = rt().Context(cfg.with_(batch=4), max_steps=2048)
+    # the mode energies from the library's spectra (Eq. 12's row spectrum
+    # and App. B's 2-D spectrum) pick the same modes as numpy's transforms
+    np.testing.assert_array_equal(cnop.comparison_seeds(cfg, v, rt=r), seeds)
     res = cnop.comparison_runs(r, seeds, 1e-6, 0.3, 3)
     assert len(res["t"]) == 4 and abs(res["t"][-1] - 0.3) < 1e-15
     u, C = r.project_to_constraint(torch.from_numpy(seeds), 1e-6, NORM_RHO_KE, SET_SPHERE)
@@ -869,3 +872,18 @@ def test_autotune_pick_reproduces_the_default_gradient_bitwise(cfg, T):
     np.testing.assert_array_equal(host(R1), host(R0))
     np.testing.assert_array_equal(host(g1), host(g0))
     print("autotune", cfg.nx, cfg.ny, "default", before, "picked", picked, "fold", r.fold)
+
+
+def test_power_spectrum_2d_matches_oracle():
+    # App. B's 2-D power spectrum on the device: plain fields and the v
+    # component of velocity fields, ragged and bench-sized grids
+    rng = np.random.default_rng(31)
+    for cfg in (RTConfig(nx=70, ny=37, batch=2), RTConfig(nx=128, ny=128), RTConfig(nx=3, ny=2)):
+        o = Oracle.from_config(cfg)
+        r = rt().Context(cfg, max_steps=8)
+        f = rng.standard_normal((cfg.batch, cfg.ny, cfg.nx))
+        uv = rng.standard_normal((cfg.batch, 2, cfg.ny, cfg.nx))
+        for field, comp, ref_field in ((f, None, f), (uv, 1, uv[:, 1])):
+            E = host(r.power_spectrum_2d(torch.from_numpy(np.ascontiguousarray(field)), component=comp))
+            Eo = o.power_spectrum_2d(np.ascontiguousarray(ref_field))
+            assert np.max(np.abs(E - Eo)) <= 1e-12 * np.max(Eo), (cfg, comp)

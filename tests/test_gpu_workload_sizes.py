@@ -395,6 +395,50 @@ def test_long_march_gradient_matches_the_oracle(name, entry_tol):
     assert e_val <= entry_tol
 
 
+def test_long_march_gradient_on_the_gpus_own_branch_matches_the_oracle_to_1e9():
+    # The exact discrete gradient (Sec. 2.3, 3.4) over the 2419 steps of the
+    # 128 x 256 march to T = 2, on one branch: the oracle's reverse-mode
+    # adjoint of every step, taken at the GPU's own states and step sizes
+    # (the store-all pool of the GPU's gradient call holds every U^n), with
+    # the closed-form terminal and initial adjoints, against the GPU's
+    # gradient entry by entry.  (The oracle's own march takes two round-off
+    # ties at this size the other way, so its gradient is that of another
+    # branch; see test_long_march_gradient_matches_the_oracle.)
+    import os
+
+    import oracle_chain
+    from paper_2608_04085_amd.config import CKPT_STORE_ALL
+    cfg = RTConfig(nx=128, ny=256)
+    T = 2.0
+    uv = inputs.seed_batch(cfg, [0], rms=1e-3)
+    r = rt().Context(cfg, max_steps=8192)
+    U0 = r.init_state(uv)
+    UT, _, n, log = r.integrate(U0, T, log_cap=4096)
+    N = int(host(n)[0])
+    dts = host(log)[0, :N]
+    pool = torch.empty(r.pool_bytes(CKPT_STORE_ALL, 1, N) + 256, dtype=torch.uint8, device="cuda")
+    R, g, ng = r.grad_u0(uv, T, rt().Policy(CKPT_STORE_ALL, 1), pool=pool)
+    assert int(host(ng)[0]) == N == 2419
+    se = 8 * 4 * cfg.cells
+    off = (-pool.data_ptr()) % 256
+    states = pool[off: off + N * se].view(torch.float64).view(N, 1, 4, cfg.ny, cfg.nx).cpu().numpy()
+    np.testing.assert_array_equal(states[0], host(U0))
+    o = Oracle.from_config(cfg)
+    ke0 = float(o.kinetic_energy(host(U0))[0])
+    UTh = host(UT)
+    Rh = float(o.kinetic_energy(UTh)[0]) / ke0
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    lam0 = oracle_chain.adjoint_chain(o, lambda k: states[k], dts, oracle_chain.terminal_adjoint_R(o, UTh, ke0),
+                                      workers=workers, band=8)
+    go = oracle_chain.initial_adjoint_R(o, uv, lam0, Rh, ke0)
+    gh = host(g)
+    err = np.max(np.abs(gh - go)) / np.max(np.abs(go))
+    print(f"128x256 T=2, {N} steps on the GPU's branch: |R - R_oracle|/R {abs(float(host(R)[0]) - Rh) / Rh:.3g}, "
+          f"gradient max|dg|/max|g| {err:.3g}")
+    assert abs(float(host(R)[0]) - Rh) <= 1e-13 * Rh
+    assert err <= 1e-9
+
+
 def test_balanced_variant_at_1024x2048():
     # The well-balanced variant in the high-resolution launch configuration:
     # steps and the step adjoint (windows at both walls and the interface)

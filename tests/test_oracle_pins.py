@@ -1120,3 +1120,60 @@ def test_threaded_oracle_steps_are_bitwise_the_single_threaded_ones():
         rto.set_threads(1)
     assert used in (1, 4)
     np.testing.assert_array_equal(one, many)
+
+
+@pytest.mark.parametrize("nx,ny,band", [(48, 64, 16), (20, 33, 8), (16, 12, 3)])
+def test_banded_step_adjoint_is_the_whole_grids_to_the_bit(nx, ny, band):
+    # the helper behind the long-march GPU check: each step's adjoint on row
+    # bands (each band's block grown by four rows, walls where the grid has
+    # them) equals the whole grid's adjoint exactly
+    import oracle_chain
+    cfg = RTConfig(nx=nx, ny=ny)
+    o, U = _random_state(cfg, 21)
+    dt = o.cfl_dt(U)
+    lam_next = np.random.default_rng(5).standard_normal(U.shape)
+    whole = o.step_vjp(U, dt, lam_next)
+    np.testing.assert_array_equal(oracle_chain.banded_vjp(o, U, float(dt[0]), lam_next, band=band), whole)
+    # and the closed-form terminal and initial adjoints are the oracle's own
+    uv = inputs.seed_batch(cfg, [3], rms=1e-3)
+    U0 = o.init_state(uv)
+    UT, _, n, log = o.integrate(U0, 0.05, cap=256)
+    ke0 = float(o.kinetic_energy(U0)[0])
+    R = float(o.kinetic_energy(UT)[0]) / ke0
+    states, V = [], U0
+    for k in range(int(n[0])):
+        states.append(V)
+        V = o.step(V, log[0, k])
+    lam0 = oracle_chain.adjoint_chain(o, lambda k: states[k], log[0, : int(n[0])],
+                                      oracle_chain.terminal_adjoint_R(o, UT, ke0), workers=3, band=band)
+    g = oracle_chain.initial_adjoint_R(o, uv, lam0, R, ke0)
+    Ro, go, _, _ = o.grad_u0(uv, 0.05)
+    assert abs(R - Ro[0]) <= 1e-15 * abs(Ro[0])
+    assert np.max(np.abs(g - go)) <= 1e-12 * np.max(np.abs(go))
+
+
+@pytest.mark.parametrize("nx,ny", [(16, 12), (15, 9), (8, 32)])
+def test_power_spectrum_2d_against_rfft2_parseval_and_a_single_mode(nx, ny):
+    # App. B's 2-D reconstruction keeps the strongest 2-D Fourier modes; the
+    # oracle's spectrum is |2-D DFT|^2 on the half plane k = 0 .. nx/2
+    cfg = RTConfig(nx=nx, ny=ny, batch=2)
+    o = Oracle.from_config(cfg)
+    f = np.random.default_rng(nx * ny).standard_normal((2, ny, nx))
+    E = o.power_spectrum_2d(f)
+    ref = np.abs(np.fft.rfft2(f)) ** 2  # numpy: full transform along y, half along x
+    np.testing.assert_allclose(E, ref, rtol=1e-12, atol=1e-12 * ref.max())
+    # Parseval: the full plane (the half plane with its mirror) holds
+    # nx ny sum f^2
+    w = np.full(nx // 2 + 1, 2.0)
+    w[0] = 1.0
+    if nx % 2 == 0:
+        w[-1] = 1.0
+    np.testing.assert_allclose((E * w).sum(axis=(1, 2)), nx * ny * (f * f).sum(axis=(1, 2)), rtol=1e-12)
+    # a single 2-D mode cos(2 pi (3 x / nx + 2 y / ny)) lands in one bin of
+    # the half plane with |F| = nx ny / 2
+    x, y = np.arange(nx), np.arange(ny)
+    m = np.cos(2 * np.pi * (3 * x[None, :] / nx + 2 * y[:, None] / ny))
+    E1 = Oracle.from_config(cfg.with_(batch=1)).power_spectrum_2d(m[None])[0]
+    assert E1[2, 3] == pytest.approx((nx * ny / 2) ** 2, rel=1e-12)
+    E1[2, 3] = 0.0
+    assert np.max(E1) <= 1e-20 * (nx * ny) ** 2

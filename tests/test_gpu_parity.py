@@ -887,3 +887,58 @@ def test_power_spectrum_2d_matches_oracle():
             E = host(r.power_spectrum_2d(torch.from_numpy(np.ascontiguousarray(field)), component=comp))
             Eo = o.power_spectrum_2d(np.ascontiguousarray(ref_field))
             assert np.max(np.abs(E - Eo)) <= 1e-12 * np.max(Eo), (cfg, comp)
+
+
+class _OracleBackend:
+    """The field operations of optim.lbfgs_max on the oracle (numpy arrays
+    [B][2][ny][nx]): J of Eq. 8 after the adaptive march and its
+    frozen-step gradient, the projection of Eq. 11 onto the ball C <= eps of
+    Eq. 9."""
+
+    def __init__(self, o, T, ek_base, eps):
+        self.o, self.T, self.ekb, self.eps = o, T, ek_base, eps
+
+    def dot(self, a, b):
+        return np.sum(a * b, axis=(1, 2, 3))
+
+    def axpy(self, x, alpha, y):
+        return x + np.asarray(alpha, dtype=float).reshape(-1, 1, 1, 1) * y
+
+    def project(self, x):
+        return self.o.project_to_constraint(x, self.eps, NORM_RHO_KE, SET_BALL)[0]
+
+    def max_abs(self, x):
+        return np.max(np.abs(x), axis=(1, 2, 3))
+
+    def where(self, mask, a, b):
+        return np.where(np.asarray(mask).reshape(-1, 1, 1, 1), a, b)
+
+    def value(self, x):
+        return self.o.objective_adaptive(x, self.T, self.ekb)[0]
+
+    def value_and_grad(self, x):
+        J, g, _, _ = self.o.grad_ek_anomaly(x, self.T, self.ekb)
+        return J, g
+
+
+def test_paper_lbfgs_search_on_the_library_matches_the_oracle_backend():
+    # The paper's search (Sec. 3.4: projected L-BFGS, m = 10, non-monotone
+    # Armijo line search) for J of Eq. 8 on its physics at 32x32, two
+    # restarts, three iterations, from the same start with the same baseline
+    # field: the host driver is shared, so the J history, the line-search
+    # decisions and the iterates differ only by the backends' arithmetic
+    from paper_2608_04085_amd import cnop, optim
+    cfg = paper_preset(32, batch=2)
+    T, eps = 1.0, 1e-6
+    o = Oracle.from_config(cfg)
+    ekb = o.baseline_ek(T)
+    x0, _ = o.project_to_constraint(inputs.paper_seed_batch(cfg, [0, 1]), eps, NORM_RHO_KE, SET_SPHERE)
+    xo, fo, go, lo = optim.lbfgs_max(_OracleBackend(o, T, ekb, eps), x0, iters=3)
+    r = rt().Context(cfg, max_steps=8192)
+    be = cnop.LibraryBackend(r, T, torch.from_numpy(ekb), eps, rt().Policy(CKPT_UNIFORM, 16))
+    xl, fl, gl, ll = optim.lbfgs_max(be, torch.from_numpy(x0).cuda(), iters=3)
+    assert ll.backtracks == lo.backtracks and ll.resets == lo.resets
+    np.testing.assert_allclose(np.array(ll.f), np.array(lo.f), rtol=1e-8)
+    assert normwise(host(xl), xo) <= 1e-8
+    assert normwise(host(gl), go) <= 1e-8
+    print("paper L-BFGS 32x32: J history", lo.f, "backtracks", lo.backtracks)

@@ -157,6 +157,24 @@ int rt_kinetic_energy(rt_ctx* ctx, const double* U, double* ke);
  * gets inf or NaN; the call does not check it (rt_grad_u0 does). */
 int rt_ke_ratio(rt_ctx* ctx, const double* U0, const double* UT, double* R);
 
+/* rt_ke_ratio for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * kernels and the same result to the bit, with their scratch (the
+ * reductions' partial sums and the two kinetic energies) in a static device
+ * array of the library, 512 KiB per GPU, held until the process ends, in
+ * place of the context's workspace; no workspace needs to be set.  The call
+ * allocates nothing; its first call on a device looks up that device's copy
+ * of the array (make that first call before any graph capture).  Limit:
+ * (red_blocks + 2) * batch <= 65536 doubles, where red_blocks = min(256,
+ * max(1, nx * ny / 2048)): at most 254 members for grids of 2^19 cells or
+ * more; beyond it RT_ENOMEM, decided on the host before any device work.
+ * All calls on one GPU share the array: calls that overlap on one GPU
+ * (other streams, other threads, other contexts) race, so the caller
+ * serialises them.  Nothing in the array has to start at zero (every
+ * partial is written before it is read).  Asynchronous on the context's
+ * stream; U0, UT and R as rt_ke_ratio. */
+int rt_ke_ratio_noalloc(rt_ctx* ctx, const double* U0, const double* UT, double* R);
+
 /* Adjoint of one step: lam = (d Phi_dt / dU)(U)^T lam_next with dt[B]
  * (device) held fixed.  Arrays are states [B][4][ny][nx]; lam must not
  * overlap lam_next. */

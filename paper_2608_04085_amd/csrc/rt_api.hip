@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -711,6 +712,64 @@ int rt_ke_ratio(rt_ctx* c, const double* U0, const double* UT, double* R) {
   RT_HIP(rtk::launch_reduce(c->P, 1, U0, nullptr, c->partial, c->red_blocks, c->sc(6), c->stream));
   RT_HIP(rtk::launch_reduce(c->P, 1, UT, nullptr, c->partial, c->red_blocks, c->sc(7), c->stream));
   RT_HIP(rtk::launch_ratio(c->P.nb, c->sc(7), c->sc(6), R, c->stream));
+  return 0;
+}
+
+namespace {
+// Scratch of rt_ke_ratio_noalloc: a file-scope device array, one copy per
+// GPU, held until the process ends.  Host code reaches it only through the
+// device address hipGetSymbolAddress returns (the array's name is a host-side
+// stand-in, not a device address), taken once per device on that entry
+// point's first call there.
+constexpr size_t kNoAllocScratchDoubles = 65536;  // 512 KiB
+__device__ __align__(256) double scratch[kNoAllocScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on the current device, or null (with the
+// error recorded) if it cannot be had.
+double* scratch_on_current_device() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    fail(RT_EHIP, "no current HIP device (or device id beyond %d)", kMaxDevices - 1);
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      fail(RT_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+      return nullptr;
+    }
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  return g_scratch_ptr[dev];
+}
+}  // namespace
+
+int rt_ke_ratio_noalloc(rt_ctx* c, const double* U0, const double* UT, double* R) {
+  if (!c) return fail(RT_EINVAL, "null context");
+  if (!U0 || !UT || !R) return fail(RT_EINVAL, "null argument");
+  // partials of the two reductions (red_blocks per member, reused) and the
+  // two kinetic energies of every member
+  const size_t need = (size_t)c->red_blocks * c->P.nb + 2 * (size_t)c->P.nb;
+  if (need > kNoAllocScratchDoubles)
+    return fail(RT_ENOMEM, "rt_ke_ratio_noalloc: batch %d needs %zu doubles of scratch, the static array holds %zu "
+                "(at most %zu members)", c->P.nb, need, kNoAllocScratchDoubles,
+                kNoAllocScratchDoubles / ((size_t)c->red_blocks + 2));
+  double* sp = scratch_on_current_device();
+  if (!sp) return RT_EHIP;
+  double* partial = sp;
+  double* ke0 = sp + (size_t)c->red_blocks * c->P.nb;
+  double* keT = ke0 + c->P.nb;
+  // every partial and both energies are written before they are read:
+  // nothing has to start at zero
+  RT_HIP(rtk::launch_reduce(c->P, 1, U0, nullptr, partial, c->red_blocks, ke0, c->stream));
+  RT_HIP(rtk::launch_reduce(c->P, 1, UT, nullptr, partial, c->red_blocks, keT, c->stream));
+  RT_HIP(rtk::launch_ratio(c->P.nb, keT, ke0, R, c->stream));
   return 0;
 }
 

@@ -77,6 +77,7 @@ def load():
         "rt_integrate": [_vp, _vp, ctypes.c_double, _vp, _vp, _vp, _i32],
         "rt_kinetic_energy": [_vp, _vp, _vp],
         "rt_ke_ratio": [_vp, _vp, _vp, _vp],
+        "rt_ke_ratio_noalloc": [_vp, _vp, _vp, _vp],
         "rt_step_adjoint": [_vp, _vp, _vp, _vp, _vp],
         "rt_grad_u0": [_vp, _vp, ctypes.c_double, ctypes.POINTER(RtCkptPolicy), _vp, _vp, _vp],
         "rt_pool_bytes": [_vp, _i32, _i32, _i32, ctypes.POINTER(ctypes.c_size_t)],
@@ -120,7 +121,7 @@ EXPORTED = ["rt_create", "rt_destroy", "rt_set_stream", "rt_workspace_bytes", "r
             "rt_set_overlap", "rt_kernel_times", "rt_set_fold", "rt_get_fold",
             "rt_set_tiles", "rt_ek_field", "rt_ek_anomaly", "rt_grad_ek_anomaly",
             "rt_mix_width", "rt_set_dt_mode", "rt_get_dt_mode", "rt_get_tile", "rt_revolve_stats",
-            "rt_row_spectrum", "rt_ke_ratio", "rt_revolve_plan_stats",
+            "rt_row_spectrum", "rt_ke_ratio", "rt_revolve_plan_stats", "rt_ke_ratio_noalloc",
             "rt_power_spectrum_2d"]
 
 
@@ -355,6 +356,14 @@ class Context:
         R = self._f64((self.cfg.batch,))
         _check(load().rt_ke_ratio(self._h, _ptr(U0), _ptr(UT), _ptr(R)), "rt_ke_ratio")
         return R
+
+    def ke_ratio_noalloc(self, U0, UT, out: torch.Tensor) -> torch.Tensor:
+        """rt_ke_ratio_noalloc: R[B] into `out` (device, [B]) with the
+        library's static scratch; U0 and UT must already be contiguous
+        float64 device tensors (nothing is allocated)."""
+        self._sync_stream()
+        _check(load().rt_ke_ratio_noalloc(self._h, _ptr(U0), _ptr(UT), _ptr(out)), "rt_ke_ratio_noalloc")
+        return out
 
     def objective_ratio(self, uv0, T: float) -> torch.Tensor:
         """R = KE(U(T))/KE(U(0)) of every member for the perturbation uv0

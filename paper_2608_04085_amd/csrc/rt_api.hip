@@ -482,7 +482,7 @@ int time_kernels(rt_ctx* c, const double* U, int step_tile, int adj_tile, int re
     return e;
   };
   hipError_t e = rtk::launch_step(P, step_tile, a, s);
-  if (e == hipSuccess) e = rtk::launch_adjoint(P, adj_tile, j, s);  // fills Z, codes for the fold
+  if (e == hipSuccess) e = rtk::launch_adjoint(P, adj_tile, j, s, false);  // fills Z, codes for the fold
   if (e == hipSuccess) e = timed([&](int) { return rtk::launch_step(P, step_tile, a, s); }, &out[0]);
   if (e == hipSuccess) e = rtk::launch_copy(U, c->S0, se, s);
   if (e == hipSuccess) e = rtk::launch_reduce(P, 0, c->S0, nullptr, c->partial, c->red_blocks, c->sc(0), s);
@@ -1054,32 +1054,37 @@ int grad_objective(rt_ctx* c, const double* uv0, double T, const rt_ckpt_policy*
       for (int k = 0; (long)k * interval < nmax; ++k) slot_step[k] = k * interval;
     c->rev_last_two_level = two;
     c->rev_last_interval = interval;
-    double* cur = c->S0;   // working state of the schedule
+    // The working state (cur) always holds step cur_step and is only ever
+    // read: a restore points it at the pool slot, and an advance that a
+    // snapshot follows writes its last step straight into that slot, so the
+    // schedule needs no state copies (a snapshot of an unadvanced state, if
+    // a plan had one, is copied).
+    const double* cur = state_slot(0);
     int cur_step = 0;
-    RT_HIP(rtk::launch_copy(state_slot(0), cur, se, s));
-    for (const rtrev::Action& act : plan) {
+    for (size_t ai = 0; ai < plan.size(); ++ai) {
+      const rtrev::Action& act = plan[ai];
       switch (act.kind) {
         case rtrev::Action::TAKESHOT:
-          RT_HIP(rtk::launch_copy(cur, state_slot(act.slot), se, s));
+          if (cur != state_slot(act.slot)) RT_HIP(rtk::launch_copy(cur, state_slot(act.slot), se, s));
           slot_step[act.slot] = cur_step;
+          cur = state_slot(act.slot);
           break;
         case rtrev::Action::RESTORE:
-          // the working state always holds step cur_step: no copy is needed
-          // when the slot holds that same step
-          if (cur_step != slot_step[act.slot]) {
-            cur = c->S0;
-            RT_HIP(rtk::launch_copy(state_slot(act.slot), cur, se, s));
-          }
+          cur = state_slot(act.slot);
           cur_step = slot_step[act.slot];
           break;
-        case rtrev::Action::ADVANCE:
+        case rtrev::Action::ADVANCE: {
+          double* shot = (ai + 1 < plan.size() && plan[ai + 1].kind == rtrev::Action::TAKESHOT)
+                             ? state_slot(plan[ai + 1].slot)
+                             : nullptr;
           for (int n = cur_step; n < act.to; ++n) {
-            double* dst = (cur == c->S0) ? c->S1 : c->S0;
+            double* dst = (n == act.to - 1 && shot) ? shot : (cur == c->S0 ? c->S1 : c->S0);
             if (int rc = step_given(cur, dst, n, s)) return rc;
             cur = dst;
           }
           cur_step = act.to;
           break;
+        }
         case rtrev::Action::REVERSE:
           if (int rc = adjoint(cur, cur_step)) return rc;
           break;

@@ -284,9 +284,11 @@ def test_gradient_matches_finite_differences_on_gpu():
 def test_gradient_at_full_size_against_16_fd_directions():
     # The gradient workload at its full size (256 x 512, T = 2, ~4.8k CFL
     # steps, snapshots every 32 steps, two-stream sweep) against central
-    # differences of the frozen-schedule march along 16 seeded directions.
-    # The 64 perturbed runs (16 directions x 2 signs x 2 step sizes) advance
-    # as one batch with the unperturbed run's steps.
+    # differences of the frozen-schedule march along 16 seeded directions
+    # and 4 directions along the gradient itself (g/|g| plus envelope noise,
+    # where the plain relative error |FD - <g,d>| / |<g,d>| means what it
+    # says).  The perturbed runs (20 directions x 2 signs x 5 step sizes)
+    # advance as one batch with the unperturbed run's steps.
     cfg = RTConfig(nx=256, ny=512)
     T = 2.0
     r = rt().Context(cfg, max_steps=8192)
@@ -295,38 +297,52 @@ def test_gradient_at_full_size_against_16_fd_directions():
     _, _, n2, log = r.integrate(r.init_state(uv), T, log_cap=8192)
     steps = int(host(n2)[0])
     assert steps == int(host(n)[0])
-    delta = float(np.sqrt(np.sum(uv * uv) * cfg.dx * cfg.dy))
+    gh = host(g)
+    dV = cfg.dx * cfg.dy
+    delta = float(np.sqrt(np.sum(uv * uv) * dV))
     dirs = [inputs.direction_batch(cfg, [s], delta)[0] for s in range(1000, 1016)]
-    hs = (1e-5, 1e-6)
+    for s in range(2000, 2004):
+        noise = inputs.direction_batch(cfg, [s], delta)[0]
+        d = gh[0] / np.sqrt(np.sum(gh[0] ** 2) * dV) * delta + 0.1 * noise
+        dirs.append(d * delta / np.sqrt(np.sum(d * d) * dV))
+    hs = (1e-5, 1e-6, 1e-7, 1e-8, 1e-9)
     members = [uv[0] + sg * h * d for d in dirs for h in hs for sg in (1.0, -1.0)]
     cb = cfg.with_(batch=len(members))
     rb = rt().Context(cb, max_steps=8)
     U = rb.init_state(np.stack(members))
-    ke0 = rb.kinetic_energy(U)
+    U0 = U.clone()
     Un = torch.empty_like(U)
     dts = log[0, :steps].unsqueeze(1).expand(steps, cb.batch).contiguous()
     for k in range(steps):
         rb.step(U, dts[k], out=Un)
         U, Un = Un, U
-    Rb = host(rb.kinetic_energy(U) / ke0)
-    gh = host(g)
+    Rb = host(rb.ke_ratio(U0, U))
     gn = np.linalg.norm(gh)
-    rel, nrm = [], []
+    rel, nrm, along = [], [], []
     for i, d in enumerate(dirs):
         an = float(np.sum(gh * d))
-        errs = []
-        for j, h in enumerate(hs):
-            k = 4 * i + 2 * j
-            errs.append(abs((Rb[k] - Rb[k + 1]) / (2 * h) - an))
-        rel.append(min(errs) / abs(an))
-        nrm.append(min(errs) / (gn * np.linalg.norm(d)))
-    print("FD 256x512 T=2: normwise", max(nrm), "relative median", float(np.median(rel)), "max", max(rel))
-    # |<g,d>| / (|g| |d|) is about 1e-2 for these directions, so the plain
-    # relative error is the normwise one magnified about 100 times; the
-    # difference quotients of a march over ~1e9 limiter decisions straddle
-    # case boundaries at every step size.
+        k0 = 2 * len(hs) * i
+        fd = [(Rb[k0 + 2 * j] - Rb[k0 + 2 * j + 1]) / (2 * h) for j, h in enumerate(hs)]
+        errs = [abs(x - an) for x in fd]
+        if i >= 16:
+            print("along g, FD / <g,d> - 1 at h =", hs, ":", ["%.2e" % (x / an - 1) for x in fd])
+            along.append(min(errs) / abs(an))
+        else:
+            rel.append(min(errs) / abs(an))
+            nrm.append(min(errs) / (gn * np.linalg.norm(d)))
+    print("FD 256x512 T=2: random directions normwise max", max(nrm), "relative median", float(np.median(rel)),
+          "max", max(rel), "; along g relative", along)
+    # The march is piecewise smooth: every limiter, wave-speed and star-side
+    # decision is a kink, and over ~1e9 of them some fall inside +-h, so the
+    # difference quotients converge slowly and unevenly.  Along g the plain
+    # relative error was 6e-4, 4e-4, 3e-4 and 1.2e-5 at h = 1e-5 .. 1e-8
+    # (with the oracle alone, its own reverse-mode gradient and frozen march
+    # at 64 x 128, T = 2: 3e-4, 1.5e-4, 5e-5, 4e-5, 6e-5 at h = 1e-4 .. 1e-8).
+    # The random directions, whose |<g,d>| is about 1e-2 |g| |d|, sit under
+    # the normwise bar.
     assert max(nrm) <= 1e-5, nrm
     assert float(np.median(rel)) <= 1e-3, rel
+    assert max(along) <= 2.5e-5, along
 
 
 def test_projection_dot_axpy_match_oracle():

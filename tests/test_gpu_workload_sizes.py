@@ -345,11 +345,13 @@ def _golden(name):
 
 @pytest.mark.parametrize("name,entry_tol", [("oracle_gradient_64x128_T2.txt", 1e-9),
                                              ("oracle_gradient_128x256_T2.txt", 1e-6),
+                                             ("oracle_gradient_256x512_T2.txt", 5e-7),
                                              ("oracle_gradient_J_paper128_T2.txt", 1e-9),
                                              ("oracle_gradient_J_paper256_T2.txt", 1e-7)])
 def test_long_march_gradient_matches_the_oracle(name, entry_tol):
-    # The gradient of R over 1210 (64 x 128) and 2419 (128 x 256) CFL
-    # steps to T = 2, and of the paper's J (Eq. 8) on its physics at
+    # The gradient of R over 1210 (64 x 128), 2419 (128 x 256) and 4838
+    # (256 x 512, the gradient workload's size) CFL steps to T = 2, and of
+    # the paper's J (Eq. 8) on its physics at
     # 128 x 128 and 256 x 256 to T = 2, against the oracle's reverse-mode AD through the
     # same march, stored by tests/golden/make_oracle_gradients.py: inner
     # products with eight seeded directions, the norm and sampled entries
@@ -367,6 +369,10 @@ def test_long_march_gradient_matches_the_oracle(name, entry_tol):
     # and 268 in the quiescent heavy fluid (rows 217 and 232, where the
     # limiter's tie tolerance decides) and two smaller ones later; sampled
     # entries differ by 5.4e-9 of the largest, inner products by 5e-14.
+    # At 256 x 512 the sampled entries differ by 5.1e-8 of the largest, the
+    # inner products by 1.2e-12 and the norm by 1.3e-10: ties again, which
+    # the same-branch comparison at 128 x 256 shows to be branches of the
+    # march, not an error of either gradient.
     ref = _golden(name)
     T = ref["T"]
     paper = "_J_paper" in name

@@ -341,11 +341,11 @@ int rt_create(const rt_grid* grid, const rt_phys* phys, void* stream, rt_ctx** o
   // Defaults from measurements on MI355X.  Tiny grids (one partial round of
   // blocks) are bound by one block's critical path: single-pass 8x8 tiles
   // and the folded adjoint (one kernel per step) win.  From 2^16 cells on,
-  // 32x8 tiles of 256 threads and the two-kernel adjoint win, in the
-  // two-stream reverse sweep too, where their LDS footprints let the
-  // re-computation share the CUs.  rt_autotune measures instead.
+  // the step takes 32x16 tiles of 512 threads (the least halo work per
+  // cell) and the adjoint 32x8 tiles of 256 threads in the two-kernel form.
+  // rt_autotune measures instead.
   const bool tiny = (size_t)P.nx * P.ny * P.nb < ((size_t)1 << 16);
-  c->tile = tiny ? rtk::TILE_8x8W : rtk::TILE_32x8;
+  c->tile = tiny ? rtk::TILE_8x8W : rtk::TILE_32x16;
   c->tile_adj = tiny ? rtk::TILE_8x8W : rtk::TILE_32x8;
   c->fold = tiny;
   const size_t n = c->cells();
@@ -1054,42 +1054,142 @@ int grad_objective(rt_ctx* c, const double* uv0, double T, const rt_ckpt_policy*
       for (int k = 0; (long)k * interval < nmax; ++k) slot_step[k] = k * interval;
     c->rev_last_two_level = two;
     c->rev_last_interval = interval;
-    // The working state (cur) always holds step cur_step and is only ever
-    // read: a restore points it at the pool slot, and an advance that a
-    // snapshot follows writes its last step straight into that slot, so the
-    // schedule needs no state copies (a snapshot of an unadvanced state, if
-    // a plan had one, is copied).
-    const double* cur = state_slot(0);
-    int cur_step = 0;
+    // The restarts split over two streams when the batch has two or more
+    // members: [0, h) on the caller's stream, [h, B) on the auxiliary one,
+    // each group running the whole plan on its own slice of every buffer
+    // (states, pool slots, lambda, Z, cases, step logs).  Members are
+    // independent, so each gets the same kernels and bits as unsplit; the
+    // second group starts one action later, so that one group's gather
+    // (bound by HBM) and steps overlap the other's kernel A (bound by VALU
+    // issue) instead of running in lockstep with it.
+    const bool split = c->overlap && P.nb >= 2;
+    const int ng = split ? 2 : 1;
+    const size_t N = (size_t)P.nx * P.ny, sm = 4 * N;
+    const size_t h = split ? (size_t)P.nb / 2 : (size_t)P.nb;
+    struct Group {
+      Params P;
+      size_t b0;
+      hipStream_t st;
+      const double* cur;  // holds step cur_step; only ever read
+      int cur_step;
+      double* lam;
+      double* lam_other;
+    } g[2];
+    for (int k = 0; k < ng; ++k) {
+      Group& G = g[k];
+      G.b0 = k == 0 ? 0 : h;
+      G.P = P;
+      G.P.nb = (int)(k == 0 ? h : (size_t)P.nb - h);
+      G.cur = state_slot(0) + G.b0 * sm;
+      G.cur_step = 0;
+      G.lam = lam + G.b0 * sm;
+      G.lam_other = lam_other + G.b0 * sm;
+    }
+    g[0].st = s;
+    if (split) {
+      if (int rc = ensure_aux(c)) return rc;
+      g[1].st = c->aux_stream;
+      RT_HIP(hipEventRecord(c->seg_ready[0], s));  // the march and the terminal adjoint
+      RT_HIP(hipStreamWaitEvent(c->aux_stream, c->seg_ready[0], 0));
+    }
+    auto gslot = [&](const Group& G, int slot) { return state_slot((size_t)slot) + G.b0 * sm; };
+    auto gstep = [&](const Group& G, const double* src, double* dst, int n) -> int {
+      rtk::StepArgs a{};
+      a.U = src;
+      a.Un = dst;
+      a.dt = c->dt_log + G.b0 * (size_t)c->max_steps;
+      a.dt_stride = c->max_steps;
+      a.dt_index = n;
+      a.nsteps_limit = c->nsteps + G.b0;
+      a.flags = c->flags;
+      RT_HIP(rtk::launch_step(G.P, c->tile, a, G.st));
+      return 0;
+    };
+    auto gadjoint = [&](Group& G, const double* Un, int n) -> int {
+      rtk::AdjArgs a{};
+      a.U = Un;
+      a.lam_next = G.lam;
+      a.lam = G.lam_other;
+      a.Z = c->Z + G.b0 * 12 * N;
+      a.codes = c->codes + G.b0 * N;
+      a.dt = c->dt_log + G.b0 * (size_t)c->max_steps;
+      a.dt_stride = c->max_steps;
+      a.dt_index = n;
+      a.nsteps_limit = c->nsteps + G.b0;
+      a.flags = c->flags;
+      if (dtd) {
+        a.dtd.mu = c->dtd_mu + G.b0 * (size_t)c->dtd_stride;
+        a.dtd.smax = c->dtd_smax + G.b0 * (size_t)c->dtd_stride;
+        a.dtd.imax = c->dtd_imax + G.b0 * (size_t)c->dtd_stride;
+        a.dtd.stride = c->dtd_stride;
+        a.dtd.count = rtk::step_blocks(G.P, c->tile_adj);
+        a.dtd.mu_last = c->dtd_mu_last + G.b0;
+      }
+      RT_HIP(rtk::launch_adjoint(G.P, c->tile_adj, a, G.st));
+      if (dtd) RT_HIP(rtk::launch_dt_correct(G.P, a, G.st));  // updates lambda^n (a.lam) in place
+      std::swap(G.lam, G.lam_other);
+      return 0;
+    };
+    // The working state of each group always holds step cur_step and is
+    // only ever read: a restore points it at the pool slot, and an advance
+    // that a snapshot follows writes its last step straight into that slot,
+    // so the schedule needs no state copies (a snapshot of an unadvanced
+    // state, if a plan had one, is copied).
+    bool skew = split;
     for (size_t ai = 0; ai < plan.size(); ++ai) {
       const rtrev::Action& act = plan[ai];
-      switch (act.kind) {
-        case rtrev::Action::TAKESHOT:
-          if (cur != state_slot(act.slot)) RT_HIP(rtk::launch_copy(cur, state_slot(act.slot), se, s));
-          slot_step[act.slot] = cur_step;
-          cur = state_slot(act.slot);
-          break;
-        case rtrev::Action::RESTORE:
-          cur = state_slot(act.slot);
-          cur_step = slot_step[act.slot];
-          break;
-        case rtrev::Action::ADVANCE: {
-          double* shot = (ai + 1 < plan.size() && plan[ai + 1].kind == rtrev::Action::TAKESHOT)
-                             ? state_slot(plan[ai + 1].slot)
-                             : nullptr;
-          for (int n = cur_step; n < act.to; ++n) {
-            double* dst = (n == act.to - 1 && shot) ? shot : (cur == c->S0 ? c->S1 : c->S0);
-            if (int rc = step_given(cur, dst, n, s)) return rc;
-            cur = dst;
+      for (int k = 0; k < ng; ++k) {
+        Group& G = g[k];
+        bool launched = false;
+        switch (act.kind) {
+          case rtrev::Action::TAKESHOT:
+            if (G.cur != gslot(G, act.slot)) {
+              RT_HIP(rtk::launch_copy(G.cur, gslot(G, act.slot), (size_t)G.P.nb * sm, G.st));
+              launched = true;
+            }
+            if (k == 0) slot_step[act.slot] = G.cur_step;
+            G.cur = gslot(G, act.slot);
+            break;
+          case rtrev::Action::RESTORE:
+            G.cur = gslot(G, act.slot);
+            G.cur_step = slot_step[act.slot];
+            break;
+          case rtrev::Action::ADVANCE: {
+            double* shot = (ai + 1 < plan.size() && plan[ai + 1].kind == rtrev::Action::TAKESHOT)
+                               ? gslot(G, plan[ai + 1].slot)
+                               : nullptr;
+            double* s0 = c->S0 + G.b0 * sm;
+            double* s1 = c->S1 + G.b0 * sm;
+            for (int n = G.cur_step; n < act.to; ++n) {
+              double* dst = (n == act.to - 1 && shot) ? shot : (G.cur == s0 ? s1 : s0);
+              if (int rc = gstep(G, G.cur, dst, n)) return rc;
+              G.cur = dst;
+              launched = true;
+            }
+            G.cur_step = act.to;
+            break;
           }
-          cur_step = act.to;
-          break;
+          case rtrev::Action::REVERSE:
+            if (int rc = gadjoint(G, G.cur, G.cur_step)) return rc;
+            launched = true;
+            break;
         }
-        case rtrev::Action::REVERSE:
-          if (int rc = adjoint(cur, cur_step)) return rc;
-          break;
+        if (k == 0 && skew && launched) {
+          // the second group waits for the first group's first kernels
+          RT_HIP(hipEventRecord(c->seg_ready[1], s));
+          RT_HIP(hipStreamWaitEvent(c->aux_stream, c->seg_ready[1], 0));
+          skew = false;
+        }
       }
     }
+    if (split) {
+      RT_HIP(hipEventRecord(c->aux_done, c->aux_stream));
+      RT_HIP(hipStreamWaitEvent(s, c->aux_done, 0));
+    }
+    // every group reversed the same steps, so its lambda^0 sits in the same
+    // buffer of the pair
+    lam = g[0].lam;
+    lam_other = g[0].lam_other;
   }
 
   // initial adjoint -> R, gradient

@@ -103,8 +103,9 @@ struct AdjArgs {
 };
 
 // Tile shapes of the fused step / adjoint kernels: TX x TY cells with 256
-// threads, or with 576 threads ("W" variants: one pass per phase).  All
-// variants produce bitwise-identical results.
+// threads, with 576 threads ("W" variants: one pass per phase), or 32 x 16
+// cells with 512 threads (less halo work per cell).  All variants produce
+// bitwise-identical results.
 enum TileId {
   TILE_16x16 = 0,
   TILE_32x8 = 1,
@@ -115,7 +116,8 @@ enum TileId {
   TILE_8x8 = 6,
   TILE_16x8W = 7,
   TILE_8x8W = 8,
-  TILE_COUNT = 9
+  TILE_32x16 = 9,
+  TILE_COUNT = 10
 };
 void tile_dims(int tile, int* tx, int* ty, int* nt);
 int step_blocks(const Params& P, int tile);  // blocks per member

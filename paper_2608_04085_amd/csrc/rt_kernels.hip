@@ -377,54 +377,75 @@ __device__ __forceinline__ FS yface_bottom_of(const LDS& S, int x, int y) {
             S.Q[3][y][x] - 0.5 * S.Q[11][y][x]};
 }
 
-// Flux of face item k of the step's phase C (x faces first, padded to NXP
-// items, then y faces) from the predicted states; returns 1 for an x face,
-// 2 for a y face, 0 for padding or a face outside the domain.
+// Phase C's face items: k < NXF are the x faces (TX + 1 per tile row, TY
+// rows), the next NYF the y faces (TX per face row, TY + 1 rows), with no
+// gap, so a wavefront may hold both kinds.  Both kinds run one instruction
+// stream: the face's two predicted states are read through per-lane LDS
+// offsets (which planes hold the normal and the tangential velocity and
+// their slopes, and whether the right state is the next column or the next
+// row), and the flux comes back in face-normal order.  Only y faces on a
+// wall branch off.
+template <int TX, int TY>
+struct FaceItems {
+  static constexpr int QX = TX + 2, PS = (TX + 2) * (TY + 2);
+  static constexpr int NXF = (TX + 1) * TY, NYF = TX * (TY + 1), N = NXF + NYF;
+};
+
+// Flux of face item k in face-normal order; returns 1 for an x face, 2 for a
+// y face, 0 past the items or for a face outside the domain.  Every lane
+// runs the same instructions (an item past the end reads the last item's
+// states, a face outside the domain reads whatever its rows hold, and a
+// wall face's HLLC result is replaced), so a wavefront never takes two
+// paths except for the wall faces of the first and last tile rows.
 template <int TX, int TY, class LDS>
-__device__ __forceinline__ int step_face_flux(const Params& P, const LDS& S, int k, int y0, double out[4]) {
-  constexpr int NXF = (TX + 1) * TY, NXP = (NXF + 63) / 64 * 64, NYF = TX * (TY + 1);
-  if (k < NXP) {
-    if (k >= NXF) return 0;
-    const int fx = k % (TX + 1), fy = k / (TX + 1);
-    if (y0 + fy >= P.ny) return 0;
-    const int l = fx, r = fx + 1, y = fy + 1;
-    const FS L{S.Q[0][y][l] + 0.5 * S.Q[4][y][l], S.Q[1][y][l] + 0.5 * S.Q[5][y][l],
-               S.Q[2][y][l] + 0.5 * S.Q[6][y][l], S.Q[3][y][l] + 0.5 * S.Q[7][y][l]};
-    const FS R{S.Q[0][y][r] - 0.5 * S.Q[4][y][r], S.Q[1][y][r] - 0.5 * S.Q[5][y][r],
-               S.Q[2][y][r] - 0.5 * S.Q[6][y][r], S.Q[3][y][r] - 0.5 * S.Q[7][y][r]};
-    hllc(P, L, R, out);
-    return 1;
-  }
-  const int kk = k - NXP;
-  if (kk >= NYF) return 0;
-  const int fx = kk % TX, fy = kk / TX;
+__device__ __forceinline__ int step_face_flux(const Params& P, const LDS& S, int k, int y0, double f[4]) {
+  using FI = FaceItems<TX, TY>;
+  const int kc = k < FI::N ? k : FI::N - 1;
+  const bool xf = kc < FI::NXF;
+  const int kk = kc - FI::NXF;
+  const int fy = xf ? kc / (TX + 1) : kk / TX;
+  const int fx = xf ? kc - (kc / (TX + 1)) * (TX + 1) : kk % TX;
   const int j = y0 + fy;
-  if (j > P.ny) return 0;
-  const int x = fx + 1, d = fy, u = fy + 1;
-  out[0] = 0.0;
-  out[1] = 0.0;
-  out[3] = 0.0;
-  if (j == 0) {
-    const FS A{S.Q[0][u][x] - 0.5 * S.Q[8][u][x], S.Q[2][u][x] - 0.5 * S.Q[10][u][x],
-               S.Q[1][u][x] - 0.5 * S.Q[9][u][x], S.Q[3][u][x] - 0.5 * S.Q[11][u][x]};
-    out[2] = wall_pressure(P, A, false);
-  } else if (j == P.ny) {
-    const FS Bs{S.Q[0][d][x] + 0.5 * S.Q[8][d][x], S.Q[2][d][x] + 0.5 * S.Q[10][d][x],
-                S.Q[1][d][x] + 0.5 * S.Q[9][d][x], S.Q[3][d][x] + 0.5 * S.Q[11][d][x]};
-    out[2] = wall_pressure(P, Bs, true);
-  } else {
-    const FS Bs{S.Q[0][d][x] + 0.5 * S.Q[8][d][x], S.Q[2][d][x] + 0.5 * S.Q[10][d][x],
-                S.Q[1][d][x] + 0.5 * S.Q[9][d][x], S.Q[3][d][x] + 0.5 * S.Q[11][d][x]};
-    const FS A{S.Q[0][u][x] - 0.5 * S.Q[8][u][x], S.Q[2][u][x] - 0.5 * S.Q[10][u][x],
-               S.Q[1][u][x] - 0.5 * S.Q[9][u][x], S.Q[3][u][x] - 0.5 * S.Q[11][u][x]};
-    double f[4];
-    hllc(P, Bs, A, f);
-    out[0] = f[0];
-    out[1] = f[2];
-    out[2] = f[1];
-    out[3] = f[3];
+  // left state: the right face of cell (fx, fy + 1) or the top face of
+  // cell (fx + 1, fy) of the predictor region; right state one column or
+  // one row further
+  const int l = xf ? (fy + 1) * FI::QX + fx : fy * FI::QX + fx + 1;
+  const int r = l + (xf ? 1 : FI::QX);
+  const int pn = xf ? FI::PS : 2 * FI::PS, pt = xf ? 2 * FI::PS : FI::PS;  // velocity planes
+  const int sb = xf ? 4 * FI::PS : 8 * FI::PS;                             // slope planes
+  const double* q = &S.Q[0][0][0];
+  const FS L{q[l] + 0.5 * q[sb + l], q[pn + l] + 0.5 * q[sb + pn + l], q[pt + l] + 0.5 * q[sb + pt + l],
+             q[3 * FI::PS + l] + 0.5 * q[sb + 3 * FI::PS + l]};
+  const FS R{q[r] - 0.5 * q[sb + r], q[pn + r] - 0.5 * q[sb + pn + r], q[pt + r] - 0.5 * q[sb + pt + r],
+             q[3 * FI::PS + r] - 0.5 * q[sb + 3 * FI::PS + r]};
+  hllc(P, L, R, f);
+  if (!xf && (j == 0 || j == P.ny)) {
+    f[1] = j == 0 ? wall_pressure(P, R, false) : wall_pressure(P, L, true);
+    f[0] = 0.0;
+    f[2] = 0.0;
+    f[3] = 0.0;
   }
-  return 2;
+  const bool inside = k < FI::N && (xf ? j < P.ny : j <= P.ny);
+  return inside ? (xf ? 1 : 2) : 0;
+}
+
+// Stores the flux of face item k (kind from step_face_flux) into F or G.
+template <int TX, int TY, class LDS>
+__device__ __forceinline__ void step_face_store(LDS& S, int k, int kind, const double f[4]) {
+  using FI = FaceItems<TX, TY>;
+  if (kind == 1) {
+    const int fx = k % (TX + 1), fy = k / (TX + 1);
+    S.fg.F[0][fy][fx] = f[0];
+    S.fg.F[1][fy][fx] = f[1];
+    S.fg.F[2][fy][fx] = f[2];
+    S.fg.F[3][fy][fx] = f[3];
+  } else if (kind == 2) {
+    const int kk = k - FI::NXF, fx = kk % TX, fy = kk / TX;
+    S.fg.G[0][fy][fx] = f[0];
+    S.fg.G[1][fy][fx] = f[2];
+    S.fg.G[2][fy][fx] = f[1];
+    S.fg.G[3][fy][fx] = f[3];
+  }
 }
 
 // ----------------------------------------------------------------- step
@@ -539,85 +560,27 @@ __global__ __launch_bounds__(NT) void k_step(Params P, StepArgs a) {
   bad |= tile_predict<TX, TY, NT, BAL, false, true, ALIAS>(P, dt, x0, y0, S, nullptr);
   __syncthreads();
 
-  // phase C: every face of the tile once (x faces, then y faces).  The x
-  // faces are padded to whole wavefronts so that no wavefront runs both the
-  // x and the y branch (which would put two flux evaluations in series).
-  constexpr int NXF = (TX + 1) * TY, NYF = TX * (TY + 1);
-  constexpr int NXP = (NXF + 63) / 64 * 64;
+  // phase C: every face of the tile once
+  constexpr int NF = FaceItems<TX, TY>::N;
   if constexpr (ALIAS) {
     // the fluxes overwrite the predicted states: all faces of this thread
     // first, then the stores once every thread has read its states
-    constexpr int FMAX = (NXP + NYF + NT - 1) / NT;
+    constexpr int FMAX = (NF + NT - 1) / NT;
     double fl[FMAX][4];
     int kind[FMAX];
 #pragma unroll
-    for (int it = 0; it < FMAX; ++it) kind[it] = step_face_flux<TX, TY>(P, S, tid + it * NT, y0, fl[it]);
+    for (int it = 0; it < FMAX; ++it) {
+      kind[it] = 0;
+      if ((tid & ~63) + it * NT < NF) kind[it] = step_face_flux<TX, TY>(P, S, tid + it * NT, y0, fl[it]);
+    }
     __syncthreads();
 #pragma unroll
-    for (int it = 0; it < FMAX; ++it) {
-      const int k = tid + it * NT;
-      if (kind[it] == 1) {
-        const int fx = k % (TX + 1), fy = k / (TX + 1);
-        S.fg.F[0][fy][fx] = fl[it][0];
-        S.fg.F[1][fy][fx] = fl[it][1];
-        S.fg.F[2][fy][fx] = fl[it][2];
-        S.fg.F[3][fy][fx] = fl[it][3];
-      } else if (kind[it] == 2) {
-        const int kk = k - NXP, fx = kk % TX, fy = kk / TX;
-        S.fg.G[0][fy][fx] = fl[it][0];
-        S.fg.G[1][fy][fx] = fl[it][1];
-        S.fg.G[2][fy][fx] = fl[it][2];
-        S.fg.G[3][fy][fx] = fl[it][3];
-      }
-    }
-  }
-  for (int k = tid; !ALIAS && k < NXP + NYF; k += NT) {
-    if (k < NXP) {
-      if (k >= NXF) continue;
-      const int fx = k % (TX + 1), fy = k / (TX + 1);
-      if (y0 + fy >= ny) continue;
-      const int l = fx, r = fx + 1, y = fy + 1;
-      const FS L{S.Q[0][y][l] + 0.5 * S.Q[4][y][l], S.Q[1][y][l] + 0.5 * S.Q[5][y][l],
-                 S.Q[2][y][l] + 0.5 * S.Q[6][y][l], S.Q[3][y][l] + 0.5 * S.Q[7][y][l]};
-      const FS R{S.Q[0][y][r] - 0.5 * S.Q[4][y][r], S.Q[1][y][r] - 0.5 * S.Q[5][y][r],
-                 S.Q[2][y][r] - 0.5 * S.Q[6][y][r], S.Q[3][y][r] - 0.5 * S.Q[7][y][r]};
-      double F[4];
-      hllc(P, L, R, F);
-      S.fg.F[0][fy][fx] = F[0];
-      S.fg.F[1][fy][fx] = F[1];
-      S.fg.F[2][fy][fx] = F[2];
-      S.fg.F[3][fy][fx] = F[3];
-    } else {
-      const int kk = k - NXP;
-      const int fx = kk % TX, fy = kk / TX;
-      const int j = y0 + fy;
-      if (j > ny) continue;
-      const int x = fx + 1, d = fy, u = fy + 1;  // halo-1 cells below / above the face
-      double G0 = 0.0, G1 = 0.0, G2, G3 = 0.0;
-      if (j == 0) {
-        const FS A{S.Q[0][u][x] - 0.5 * S.Q[8][u][x], S.Q[2][u][x] - 0.5 * S.Q[10][u][x],
-                   S.Q[1][u][x] - 0.5 * S.Q[9][u][x], S.Q[3][u][x] - 0.5 * S.Q[11][u][x]};
-        G2 = wall_pressure(P, A, false);
-      } else if (j == ny) {
-        const FS Bs{S.Q[0][d][x] + 0.5 * S.Q[8][d][x], S.Q[2][d][x] + 0.5 * S.Q[10][d][x],
-                    S.Q[1][d][x] + 0.5 * S.Q[9][d][x], S.Q[3][d][x] + 0.5 * S.Q[11][d][x]};
-        G2 = wall_pressure(P, Bs, true);
-      } else {
-        const FS Bs{S.Q[0][d][x] + 0.5 * S.Q[8][d][x], S.Q[2][d][x] + 0.5 * S.Q[10][d][x],
-                    S.Q[1][d][x] + 0.5 * S.Q[9][d][x], S.Q[3][d][x] + 0.5 * S.Q[11][d][x]};
-        const FS A{S.Q[0][u][x] - 0.5 * S.Q[8][u][x], S.Q[2][u][x] - 0.5 * S.Q[10][u][x],
-                   S.Q[1][u][x] - 0.5 * S.Q[9][u][x], S.Q[3][u][x] - 0.5 * S.Q[11][u][x]};
-        double f[4];
-        hllc(P, Bs, A, f);
-        G0 = f[0];
-        G1 = f[2];
-        G2 = f[1];
-        G3 = f[3];
-      }
-      S.fg.G[0][fy][fx] = G0;
-      S.fg.G[1][fy][fx] = G1;
-      S.fg.G[2][fy][fx] = G2;
-      S.fg.G[3][fy][fx] = G3;
+    for (int it = 0; it < FMAX; ++it) step_face_store<TX, TY>(S, tid + it * NT, kind[it], fl[it]);
+  } else {
+    for (int k = tid; (k & ~63) < NF; k += NT) {
+      double f[4];
+      const int kind = step_face_flux<TX, TY>(P, S, k, y0, f);
+      step_face_store<TX, TY>(S, k, kind, f);
     }
   }
   __syncthreads();
@@ -1494,6 +1457,7 @@ void tile_dims(int tile, int* tx, int* ty, int* nt) {
     case TILE_8x8: a = 8; b = 8; t = 64; break;
     case TILE_16x8W: b = 8; t = 320; break;
     case TILE_8x8W: a = 8; b = 8; t = 192; break;
+    case TILE_32x16: a = 32; b = 16; t = 512; break;
     default: break;
   }
   *tx = a;
@@ -1514,7 +1478,9 @@ template <int TX, int TY, int NT>
 static hipError_t launch_step_t(const Params& P, const StepArgs& a, hipStream_t s) {
   dim3 grid((P.nx + TX - 1) / TX, (P.ny + TY - 1) / TY, P.nb);
   const long blocks = (long)grid.x * grid.y * grid.z;
-  const bool alias = RT_ALIAS_MODE == 1 || (RT_ALIAS_MODE == 2 && blocks > 3L * 256);
+  // the separate-buffer layout fits min(3, 160 KiB / its size) blocks per CU
+  const long per_cu = std::min(3L, 163840L / (long)sizeof(StepLDS<TX, TY, false>));
+  const bool alias = RT_ALIAS_MODE == 1 || (RT_ALIAS_MODE == 2 && blocks > per_cu * 256);
   if (P.recon == 1) {
     if (alias)
       hipLaunchKernelGGL((k_step<TX, TY, NT, true, true>), grid, dim3(NT), 0, s, P, a);
@@ -1539,6 +1505,7 @@ hipError_t launch_step(const Params& P, int tile, const StepArgs& a, hipStream_t
     case TILE_8x8: return launch_step_t<8, 8, 64>(P, a, s);
     case TILE_16x8W: return launch_step_t<16, 8, 320>(P, a, s);
     case TILE_8x8W: return launch_step_t<8, 8, 192>(P, a, s);
+    case TILE_32x16: return launch_step_t<32, 16, 512>(P, a, s);
     default: return launch_step_t<16, 16, 256>(P, a, s);
   }
 }
@@ -1590,6 +1557,7 @@ static hipError_t launch_adj_a(const Params& P, int tile, const AdjArgs& a, hipS
     case TILE_8x8: return launch_adj_t<8, 8, 64>(P, a, s);
     case TILE_16x8W: return launch_adj_t<16, 8, 320>(P, a, s);
     case TILE_8x8W: return launch_adj_t<8, 8, 192>(P, a, s);
+    case TILE_32x16: return launch_adj_t<32, 16, 512>(P, a, s);
     default: return launch_adj_t<16, 16, 256>(P, a, s);
   }
 }

@@ -188,7 +188,7 @@ def test_committed_counters_belong_to_the_kernel_sources():
     for workload, kernels in (("grad_256x512", ("step", "step_march", "adjoint")),
                               ("step_8x1024x2048", ("step", "adjoint"))):
         for k in kernels:
-            t = profiling.traffic_for(workload, k, "32x8/32x8")
+            t = profiling.traffic_for(workload, k, "32x16/32x8")
             assert t is not None and t > 0, (workload, k)
     assert profiling.traffic_for("grad_256x512", "adjoint", "16x8/32x8") is None  # other tiles
 

@@ -213,6 +213,36 @@ def test_two_stream_and_folded_sweeps_match_bitwise():
     np.testing.assert_array_equal(host(Rr), out[True][0])
 
 
+@pytest.mark.parametrize("dt_mode", ["frozen", "differentiated"])
+def test_binomial_sweep_split_over_two_streams_is_bitwise_equal(dt_mode):
+    # Binomial checkpointing splits the batch over two streams (members
+    # [0, B/2) and [B/2, B), the second group one action behind).  Each
+    # member runs the kernels of the one-stream sweep, so R, the gradient
+    # and the step counts are equal to the bit: an odd batch whose second
+    # group's members take different step counts, a grid above the
+    # folded-adjoint size, and a pool small enough that the plan restores
+    # and takes snapshots.
+    cfg = RTConfig(nx=128, ny=176, batch=3)
+    uv = inputs.seed_batch(cfg, [7, 8, 9], rms=1e-3)
+    uv[1] *= 40.0
+    r = rt().Context(cfg, max_steps=4096)
+    r.set_dt_mode(dt_mode)
+    pol = rt().Policy(CKPT_REVOLVE, 1, pool_bytes=5 * 8 * 4 * cfg.cells * cfg.batch)
+    out = {}
+    for on in (True, False):
+        r.set_overlap(on)
+        R, g, n = r.grad_u0(uv, 0.3, pol)
+        out[on] = (host(R), host(g), host(n))
+    r.set_overlap(True)
+    assert out[True][2][1] != out[True][2][2], out[True][2]  # the second group's members differ
+    for k in range(3):
+        np.testing.assert_array_equal(out[True][k], out[False][k])
+    Rs, gs, ns = r.grad_u0(uv, 0.3, rt().Policy(CKPT_STORE_ALL, 1))
+    np.testing.assert_array_equal(host(ns), out[True][2])
+    np.testing.assert_array_equal(host(Rs), out[True][0])
+    np.testing.assert_array_equal(host(gs), out[True][1])
+
+
 @pytest.mark.parametrize("slack", [0, 1, 7, 64])
 def test_two_stream_sweep_with_pool_sized_to_the_run(slack):
     # pools sized from the actual step count (plus some slack) put both

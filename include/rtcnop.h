@@ -282,13 +282,16 @@ int rt_set_tiles(rt_ctx* ctx, int32_t step_tile, int32_t adj_tile);
 /* The adaptive march replays captured HIP graphs of 48 steps (on = 1, the
  * default) or launches step by step (on = 0); results are identical. */
 int rt_set_graphs(rt_ctx* ctx, int32_t on);
-/* The reverse sweep of RT_CKPT_UNIFORM re-computes segment k-1 on a second
- * stream of the context (default priority, created on first use on the
- * current device) while the adjoint of segment k runs on the context's
- * stream, if the pool holds two segment buffers beside the snapshots (the
- * size rt_pool_bytes returns) and on = 1 (the default); on = 0, or a pool
- * with room for one segment buffer, runs the sweep on one stream.  Results
- * are identical. */
+/* Second stream of the reverse sweep (default priority, created on first
+ * use on the current device), on = 1 (the default) or 0.  RT_CKPT_UNIFORM
+ * re-computes segment k-1 on it while the adjoint of segment k runs on the
+ * context's stream, if the pool holds two segment buffers beside the
+ * snapshots (the size rt_pool_bytes returns); with room for one, the sweep
+ * runs on one stream.  RT_CKPT_REVOLVE with two or more members runs the
+ * binomial plan for members [0, B/2) on the context's stream and for
+ * [B/2, B) on the second one, one action later, each on its own slice of
+ * every buffer.  Results are identical either way; on = 0 runs everything
+ * on the context's stream. */
 int rt_set_overlap(rt_ctx* ctx, int32_t on);
 int rt_get_tiles(const rt_ctx* ctx, int32_t* step_tile, int32_t* adj_tile);
 /* The step kernel's variant (as rt_get_tiles' step_tile). */

@@ -286,7 +286,8 @@ class Context:
         _check(load().rt_set_dt_mode(self._h, DT_MODES[mode]), "rt_set_dt_mode")
 
     def set_overlap(self, on: bool):
-        """Two-stream reverse sweep of the UNIFORM policy (default on); results are identical."""
+        """Second stream in the reverse sweep (default on): the UNIFORM policy re-computes the next segment on
+        it, REVOLVE runs half of the members on it; results are identical."""
         _check(load().rt_set_overlap(self._h, 1 if on else 0), "rt_set_overlap")
 
     def autotune(self, U, reps: int = 20) -> str:

@@ -46,6 +46,11 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 }  // namespace
 
+// Member groups of the split binomial sweep: at most this many streams.
+constexpr int kMaxGroups = 4;
+// Groups the sweep uses (fewer if the batch has fewer members).
+constexpr int kSplitGroups = 2;
+
 struct rt_ctx {
   Params P;
   hipStream_t stream;
@@ -74,6 +79,11 @@ struct rt_ctx {
   // states while the adjoint of the current one runs (default priority).
   hipStream_t aux_stream = nullptr;
   hipEvent_t seg_ready[2] = {nullptr, nullptr}, seg_free[2] = {nullptr, nullptr}, aux_done = nullptr;
+  // Streams of member groups 2.. of the split binomial sweep (group 0 runs
+  // on the context's stream, group 1 on aux_stream; entries 0 and 1 stay
+  // null) and the events that stagger and join the groups.
+  hipStream_t group_stream[kMaxGroups] = {};
+  hipEvent_t group_ev[kMaxGroups] = {};
   bool overlap = true;
   // Reverse sweep with the limiter gather folded into the next step's kernel
   // (one kernel per step) or as its own kernel (two per step).
@@ -93,6 +103,10 @@ struct rt_ctx {
     if (capture_stream) (void)hipStreamDestroy(capture_stream);
     for (hipEvent_t e : {seg_ready[0], seg_ready[1], seg_free[0], seg_free[1], aux_done})
       if (e) (void)hipEventDestroy(e);
+    for (int k = 0; k < kMaxGroups; ++k) {
+      if (group_ev[k]) (void)hipEventDestroy(group_ev[k]);
+      if (group_stream[k]) (void)hipStreamDestroy(group_stream[k]);
+    }
     if (aux_stream) (void)hipStreamDestroy(aux_stream);
   }
   Flags* flags = nullptr;
@@ -440,6 +454,18 @@ int ensure_aux(rt_ctx* c) {
   RT_HIP(hipStreamCreateWithFlags(&c->aux_stream, hipStreamNonBlocking));
   for (hipEvent_t* e : {&c->seg_ready[0], &c->seg_ready[1], &c->seg_free[0], &c->seg_free[1], &c->aux_done})
     RT_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
+  return 0;
+}
+
+// Streams and events of member groups 0 .. ng-1 of the split sweep (group 0
+// runs on the context's stream, group 1 on aux_stream), created on first use
+// on the current device, default priority.
+int ensure_groups(rt_ctx* c, int ng) {
+  if (int rc = ensure_aux(c)) return rc;
+  for (int k = 0; k < ng; ++k) {
+    if (k >= 2 && !c->group_stream[k]) RT_HIP(hipStreamCreateWithFlags(&c->group_stream[k], hipStreamNonBlocking));
+    if (!c->group_ev[k]) RT_HIP(hipEventCreateWithFlags(&c->group_ev[k], hipEventDisableTiming));
+  }
   return 0;
 }
 }  // namespace
@@ -1054,18 +1080,18 @@ int grad_objective(rt_ctx* c, const double* uv0, double T, const rt_ckpt_policy*
       for (int k = 0; (long)k * interval < nmax; ++k) slot_step[k] = k * interval;
     c->rev_last_two_level = two;
     c->rev_last_interval = interval;
-    // The restarts split over two streams when the batch has two or more
-    // members: [0, h) on the caller's stream, [h, B) on the auxiliary one,
-    // each group running the whole plan on its own slice of every buffer
-    // (states, pool slots, lambda, Z, cases, step logs).  Members are
-    // independent, so each gets the same kernels and bits as unsplit; the
-    // second group starts one action later, so that one group's gather
-    // (bound by HBM) and steps overlap the other's kernel A (bound by VALU
-    // issue) instead of running in lockstep with it.
+    // The restarts split over streams when the batch has two or more
+    // members: group k takes members [k B / ng, (k + 1) B / ng) and runs the
+    // whole plan on its own slice of every buffer (states, pool slots,
+    // lambda, Z, cases, step logs), group 0 on the caller's stream and the
+    // others on streams of their own.  Members are independent, so each gets
+    // the same kernels and bits as unsplit; group k starts once group k - 1
+    // has launched its first kernels, so that one group's gather (bound by
+    // HBM) and steps overlap another's kernel A (bound by VALU issue)
+    // instead of running in lockstep with it.
     const bool split = c->overlap && P.nb >= 2;
-    const int ng = split ? 2 : 1;
+    const int ng = split ? std::min(P.nb, kSplitGroups) : 1;
     const size_t N = (size_t)P.nx * P.ny, sm = 4 * N;
-    const size_t h = split ? (size_t)P.nb / 2 : (size_t)P.nb;
     struct Group {
       Params P;
       size_t b0;
@@ -1074,23 +1100,23 @@ int grad_objective(rt_ctx* c, const double* uv0, double T, const rt_ckpt_policy*
       int cur_step;
       double* lam;
       double* lam_other;
-    } g[2];
+    } g[kMaxGroups];
+    if (split)
+      if (int rc = ensure_groups(c, ng)) return rc;
     for (int k = 0; k < ng; ++k) {
       Group& G = g[k];
-      G.b0 = k == 0 ? 0 : h;
+      G.b0 = (size_t)P.nb * k / ng;
       G.P = P;
-      G.P.nb = (int)(k == 0 ? h : (size_t)P.nb - h);
+      G.P.nb = (int)((size_t)P.nb * (k + 1) / ng - G.b0);
+      G.st = k == 0 ? s : (k == 1 ? c->aux_stream : c->group_stream[k]);
       G.cur = state_slot(0) + G.b0 * sm;
       G.cur_step = 0;
       G.lam = lam + G.b0 * sm;
       G.lam_other = lam_other + G.b0 * sm;
     }
-    g[0].st = s;
     if (split) {
-      if (int rc = ensure_aux(c)) return rc;
-      g[1].st = c->aux_stream;
-      RT_HIP(hipEventRecord(c->seg_ready[0], s));  // the march and the terminal adjoint
-      RT_HIP(hipStreamWaitEvent(c->aux_stream, c->seg_ready[0], 0));
+      RT_HIP(hipEventRecord(c->group_ev[0], s));  // the march and the terminal adjoint
+      for (int k = 1; k < ng; ++k) RT_HIP(hipStreamWaitEvent(g[k].st, c->group_ev[0], 0));
     }
     auto gslot = [&](const Group& G, int slot) { return state_slot((size_t)slot) + G.b0 * sm; };
     auto gstep = [&](const Group& G, const double* src, double* dst, int n) -> int {
@@ -1135,7 +1161,7 @@ int grad_objective(rt_ctx* c, const double* uv0, double T, const rt_ckpt_policy*
     // that a snapshot follows writes its last step straight into that slot,
     // so the schedule needs no state copies (a snapshot of an unadvanced
     // state, if a plan had one, is copied).
-    bool skew = split;
+    int skew = split ? 1 : ng;  // the next group still to be staggered
     for (size_t ai = 0; ai < plan.size(); ++ai) {
       const rtrev::Action& act = plan[ai];
       for (int k = 0; k < ng; ++k) {
@@ -1174,17 +1200,17 @@ int grad_objective(rt_ctx* c, const double* uv0, double T, const rt_ckpt_policy*
             launched = true;
             break;
         }
-        if (k == 0 && skew && launched) {
-          // the second group waits for the first group's first kernels
-          RT_HIP(hipEventRecord(c->seg_ready[1], s));
-          RT_HIP(hipStreamWaitEvent(c->aux_stream, c->seg_ready[1], 0));
-          skew = false;
+        if (k + 1 == skew && skew < ng && launched) {
+          // group k + 1 waits for group k's first kernels
+          RT_HIP(hipEventRecord(c->group_ev[skew], G.st));
+          RT_HIP(hipStreamWaitEvent(g[skew].st, c->group_ev[skew], 0));
+          ++skew;
         }
       }
     }
-    if (split) {
-      RT_HIP(hipEventRecord(c->aux_done, c->aux_stream));
-      RT_HIP(hipStreamWaitEvent(s, c->aux_done, 0));
+    for (int k = 1; k < ng; ++k) {
+      RT_HIP(hipEventRecord(c->group_ev[k], g[k].st));
+      RT_HIP(hipStreamWaitEvent(s, c->group_ev[k], 0));
     }
     // every group reversed the same steps, so its lambda^0 sits in the same
     // buffer of the pair

@@ -68,7 +68,7 @@ struct AdjArgs {
   const double* U;         // U^n
   const double* lam_next;  // lambda^{n+1}
   double* lam;             // lambda^n
-  double* Z;               // [B][12][ny][nx] predictor-adjoint output
+  double* Z;               // [B][12][ny][nx] kernel A's output for the gather (direct part, slope cotangents)
   int32_t* codes;          // [B][ny][nx] MC cases
   const double* dt;        // dt[b * dt_stride + dt_index]
   int32_t dt_stride, dt_index;

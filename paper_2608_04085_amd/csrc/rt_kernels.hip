@@ -17,9 +17,11 @@
 //            the member's next CFL step (no extra launch, no host sync).
 // Adjoint of one step (frozen dt): kernel A recomputes phases A-C, runs the
 // HLLC / wall-flux adjoints on every face of the tile and the predictor
-// adjoint of every tile cell; kernel B gathers the limiter adjoints of the
-// five slope stencils touching a cell and applies the primitive-variable
-// adjoint and the direct (identity + gravity) terms.
+// adjoint of every tile cell, and forms each cell's direct part of lambda^n
+// (its own primitive cotangent through the primitive-variable adjoint, plus
+// the identity and gravity terms); kernel B gathers the limiter adjoints of
+// the five slope stencils touching a cell, maps them through the
+// primitive-variable adjoint and adds the direct part.
 #include <hip/hip_runtime.h>
 
 #include "rt_kernels.h"
@@ -671,19 +673,20 @@ __device__ __forceinline__ void add_slope_terms(double sb[4], int code, double s
 
 // Outputs of kernel A for one step n of one member, read by the gather.
 struct GatherSrc {
-  const double* Z;        // [12][ny][nx]
+  const double* Z;        // [12][ny][nx]: planes 0..3 the cell's direct part of lambda^n (conservative),
+                          // 4..7 and 8..11 the cotangents of its x and y slopes (primitive)
   const int32_t* codes;   // [ny][nx]
   const double* U;        // U^n, [4][ny][nx]
-  const double* lam_next; // lambda^{n+1}, [4][ny][nx]
-  double dt;
+  const double* lam_next; // lambda^{n+1}, [4][ny][nx] (read for finished members only)
   bool pass;              // member finished before step n: lambda^n = lambda^{n+1}
 };
 
 // lambda^n at cell (i, j): the limiter gather of the slope cotangents of
-// the cell and its four neighbours through the MC cases, the wall ghost
-// terms, the adjoint of the primitive map at U^n, plus the identity and
-// gravity-source terms of the update.  BAL: the well-balanced pressure
-// slopes' dependence on the cell's density.
+// the cell and its four neighbours through the MC cases and the wall ghost
+// terms, mapped by the adjoint of the primitive map at U^n, plus the direct
+// part kernel A left in Z (the cell's own primitive cotangent mapped the
+// same way, and the identity and gravity-source terms of the update).  BAL:
+// the well-balanced pressure slopes' dependence on the cell's density.
 template <bool BAL>
 __device__ __forceinline__ void lambda_at(const Params& P, const GatherSrc& g, int i, int j, double out[4]) {
   const int nx = P.nx, ny = P.ny;
@@ -700,7 +703,7 @@ __device__ __forceinline__ void lambda_at(const Params& P, const GatherSrc& g, i
   const double* Z = g.Z;
   const int32_t* codes = g.codes;
   const double* U = g.U;
-  double wb[4] = {ldg(Z, idx), ldg(Z + N, idx), ldg(Z + 2 * N, idx), ldg(Z + 3 * N, idx)};
+  double wb[4] = {0.0, 0.0, 0.0, 0.0};
   // x slopes at d = c-1, c, c+1
   {
     const uint32_t cm = (uint32_t)(j * nx + (i == 0 ? nx - 1 : i - 1));
@@ -750,11 +753,10 @@ __device__ __forceinline__ void lambda_at(const Params& P, const GatherSrc& g, i
   const W4 w = cons_to_prim(P, ldg(U, idx), ldg(U + N, idx), ldg(U + 2 * N, idx), ldg(U + 3 * N, idx));
   double ub[4];
   prim_adj(P, w, W4{wb[0], wb[1], wb[2], wb[3]}, ub);
-  const double l0 = ldg(Lm, idx), l1 = ldg(Lm + N, idx), l2 = ldg(Lm + 2 * N, idx), l3 = ldg(Lm + 3 * N, idx);
-  out[0] = ub[0] + l0 + g.dt * P.g_y * l2;
-  out[1] = ub[1] + l1;
-  out[2] = ub[2] + l2;
-  out[3] = ub[3] + l3;
+  out[0] = ldg(Z, idx) + ub[0];
+  out[1] = ldg(Z + N, idx) + ub[1];
+  out[2] = ldg(Z + 2 * N, idx) + ub[2];
+  out[3] = ldg(Z + 3 * N, idx) + ub[3];
 }
 
 // ----------------------------------------------------------------- adjoint A
@@ -858,7 +860,6 @@ __global__ __launch_bounds__(NT) void k_adj_a(Params P, AdjArgs a) {
     g.U = a.fold.U + (size_t)b * 4 * N;
     g.lam_next = a.fold.lam_next + (size_t)b * 4 * N;
     g.pass = a.nsteps_limit && a.fold.dt_index >= a.nsteps_limit[b];
-    g.dt = g.pass ? 0.0 : a.dt[(size_t)b * a.dt_stride + a.fold.dt_index];
     double* lam_out = a.fold.lam_out + (size_t)b * 4 * N;
     for (int k = tid; k < QX * QY; k += NT) {
       const int lx = k % QX, ly = k / QX;
@@ -876,7 +877,7 @@ __global__ __launch_bounds__(NT) void k_adj_a(Params P, AdjArgs a) {
           stg(lam_out + 3 * N, cc, l[3]);
         }
       }
-      S.L[0][ly][lx] = l[0] + hdtg * l[2];
+      S.L[0][ly][lx] = l[0];
       S.L[1][ly][lx] = l[1];
       S.L[2][ly][lx] = l[2];
       S.L[3][ly][lx] = l[3];
@@ -890,7 +891,7 @@ __global__ __launch_bounds__(NT) void k_adj_a(Params P, AdjArgs a) {
   // position (lx, ly) of the tile; rows outside the domain are never asked
   auto lam = [&](int lx, int ly, double l[4]) {
     if constexpr (FOLD) {
-      l[0] = S.L[0][ly][lx];
+      l[0] = S.L[0][ly][lx] + hdtg * S.L[2][ly][lx];
       l[1] = S.L[1][ly][lx];
       l[2] = S.L[2][ly][lx];
       l[3] = S.L[3][ly][lx];
@@ -1022,11 +1023,30 @@ __global__ __launch_bounds__(NT) void k_adj_a(Params P, AdjArgs a) {
       mu += P.g_y * l[2] * u0 - 0.5 * P.inv_dx * (qb.r * axr + qb.u * axu + qb.v * axv + qb.p * axp) -
             0.5 * P.inv_dy * (qb.r * ayr + qb.u * ayu + qb.v * ayv + qb.p * ayp) + 0.5 * P.g_y * qb.v;
     }
+    // planes 0..3: the part of lambda^n the gather does not touch, in
+    // conservative variables -- the primitive-map adjoint of this cell's
+    // own primitive cotangent plus the identity and gravity terms of the
+    // update (the map is linear in the cotangent, so the gather maps only
+    // its slope terms and adds these)
+    double ln[4];
+    if constexpr (FOLD) {
+      ln[0] = S.L[0][ly][lx];
+      ln[1] = S.L[1][ly][lx];
+      ln[2] = S.L[2][ly][lx];
+      ln[3] = S.L[3][ly][lx];
+    } else {
+      ln[0] = ldg(Lm, c);
+      ln[1] = ldg(Lm + N, c);
+      ln[2] = ldg(Lm + 2 * N, c);
+      ln[3] = ldg(Lm + 3 * N, c);
+    }
+    double ud[4];
+    prim_adj(P, w, wb, ud);
     double* Z = a.Z + (size_t)b * 12 * N;
-    stg(Z, c, wb.r);
-    stg(Z + N, c, wb.u);
-    stg(Z + 2 * N, c, wb.v);
-    stg(Z + 3 * N, c, wb.p);
+    stg(Z, c, ud[0] + ln[0] + dt * P.g_y * ln[2]);
+    stg(Z + N, c, ud[1] + ln[1]);
+    stg(Z + 2 * N, c, ud[2] + ln[2]);
+    stg(Z + 3 * N, c, ud[3] + ln[3]);
     stg(Z + 4 * N, c, sxb.r);
     stg(Z + 5 * N, c, sxb.u);
     stg(Z + 6 * N, c, sxb.v);
@@ -1072,7 +1092,6 @@ __global__ __launch_bounds__(256) void k_adj_b(Params P, AdjArgs a) {
   g.U = a.U + (size_t)b * 4 * N;
   g.lam_next = a.lam_next + (size_t)b * 4 * N;
   g.pass = a.nsteps_limit && a.dt_index >= a.nsteps_limit[b];
-  g.dt = g.pass ? 0.0 : a.dt[(size_t)b * a.dt_stride + a.dt_index];
   double l[4];
   lambda_at<BAL>(P, g, (int)(idx % nx), (int)(idx / nx), l);
   double* Lo = a.lam + (size_t)b * 4 * N;

@@ -370,9 +370,15 @@ def test_long_march_gradient_matches_the_oracle(name, entry_tol):
     # limiter's tie tolerance decides) and two smaller ones later; sampled
     # entries differ by 5.4e-9 of the largest, inner products by 5e-14.
     # At 256 x 512 the sampled entries differ by 5.1e-8 of the largest, the
-    # inner products by 1.2e-12 and the norm by 1.3e-10: ties again, which
-    # the same-branch comparison at 128 x 256 shows to be branches of the
-    # march, not an error of either gradient.
+    # inner products by 1.2e-12 and the norm by 1.3e-10.  The first tie is
+    # at step 147, cell (row 114, col 216): the two states agree to 1.4e-14
+    # there, the adjoint of that step differs by 1.2e-5 of its largest
+    # entry; the marches then part by up to ~1e-10 near the interface and
+    # meet further ties at 279 steps in all (the last at step 4483), and end
+    # 4.4e-12 apart.  On the GPU's own branch (the oracle's reverse sweep
+    # over the GPU's 4838 states) the gradient agrees entry by entry to
+    # 3.2e-14, so the difference is the branch, not an error of either
+    # gradient.
     ref = _golden(name)
     T = ref["T"]
     paper = "_J_paper" in name

@@ -273,6 +273,19 @@ def counters_md(title: str, dirs: list, out_md: str, command: str = ""):
                 v = per[k].get(n)
                 vals.append("" if not v else f"{sum(v) / len(v):.4g}")
         lines.append(f"| {n} | " + " | ".join(vals) + " |")
+    # where the wavefronts' cycles go, when the run has the wait counters
+    fr = ["SQ_ACTIVE_INST_ANY", "SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_SCA", "SQ_ACTIVE_INST_LDS", "SQ_WAIT_INST_ANY",
+          "SQ_WAIT_ANY", "SQ_WAIT_INST_LDS"]
+    ks = [k for k in CATEGORIES if k in per and "SQ_WAVE_CYCLES" in per[k] and "SQ_WAIT_ANY" in per[k]]
+    if ks:
+        lines += ["", "Fractions of SQ_WAVE_CYCLES (per dispatch):", "", "| counter / SQ_WAVE_CYCLES | " + " | ".join(ks) +
+                  " |", "|---|" + "---|" * len(ks)]
+        for n in fr:
+            vals = []
+            for k in ks:
+                v, w = per[k].get(n), per[k]["SQ_WAVE_CYCLES"]
+                vals.append("" if not v else f"{(sum(v) / len(v)) / (sum(w) / len(w)):.3f}")
+            lines.append(f"| {n} | " + " | ".join(vals) + " |")
     with open(out_md, "w") as f:
         f.write("\n".join(lines) + "\n")
     data = {}

@@ -81,7 +81,7 @@ def host_info():
 
 
 def cpu_baseline(cfg, seconds):
-    """The oracle as it stands (C++, -O2), timed on the GPU machine's host on a
+    """The oracle as it stands (C++, -O2), timed on the host CPU beside the GPU on a
     bounded sample of the same grid and seed: forward steps on one thread
     and with OpenMP over rows on every core the process may use, and
     reverse-mode adjoint steps (single-threaded by construction) on a

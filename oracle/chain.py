@@ -1,5 +1,6 @@
-"""Test helper: the oracle's reverse-mode adjoint of a march over given
-states, a step at a time, each step on row bands that run on threads.
+"""Test infrastructure (with the rest of oracle/): the oracle's reverse-mode
+adjoint of a march over given states, a step at a time, each step on row
+bands that run on threads.
 
 A step's adjoint at a cell gathers the cotangents of the outputs within two
 cells, and an output two or more rows inside a block of the grid is computed

@@ -418,7 +418,7 @@ def test_long_march_gradient_on_the_gpus_own_branch_matches_the_oracle_to_1e9():
     # branch; see test_long_march_gradient_matches_the_oracle.)
     import os
 
-    import oracle_chain
+    from oracle import chain as oracle_chain
     from paper_2608_04085_amd.config import CKPT_STORE_ALL
     cfg = RTConfig(nx=128, ny=256)
     T = 2.0

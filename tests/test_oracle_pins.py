@@ -1127,7 +1127,7 @@ def test_banded_step_adjoint_is_the_whole_grids_to_the_bit(nx, ny, band):
     # the helper behind the long-march GPU check: each step's adjoint on row
     # bands (each band's block grown by four rows, walls where the grid has
     # them) equals the whole grid's adjoint exactly
-    import oracle_chain
+    from oracle import chain as oracle_chain
     cfg = RTConfig(nx=nx, ny=ny)
     o, U = _random_state(cfg, 21)
     dt = o.cfl_dt(U)

@@ -1,18 +1,19 @@
 """The benchmark workloads, each returning a dict of measured results.
 
     fwd_64x128            forward march to T = 2 of one RMS-1e-3 Gaussian seed; R and cell-updates/s
-    grad_256x512          forward + adjoint gradient, snapshot every 32 steps, T = 2 (bench.py's step)
     ensemble_64x128x256   64 members (32 Gaussian seeds, 32 single Fourier modes kx = 1..16, two
                           phases), velocity L2 norm 1e-3, T = 2, all members in one launch per step
     cnop_8x512x1024       SPG CNOP search, 8 restarts, T = 1 or 4, binomial checkpointing <= 16 GB
+                          (bench.py's step is one iteration of it)
     grad_1024x2048        forward + adjoint, T = 3, binomial checkpointing <= 64 GB; top-5 horizontal
                           mode energy of the sphere-projected gradient; adjoint/forward time ratio
-    fd_64x128             finite-difference gradient (one-sided, n_dof + 1 batched forwards) vs the adjoint
+    fd_64x128             the full central-difference gradient (2 n_dof batched forwards) vs the adjoint
     paper_cnop_128        the paper's own search on its physics: J of Eq. 8 over C <= 1e-6, projected L-BFGS
                           (m = 10) against the memory-free driver (SPG) at equal gradient budget
     paper_compare_128     the paper's forward comparison suite: CNOP, Random, 5modes and 2-D 90% reconstructions
                           marched together, KE(t) and mixing width h_mix(t)
 
+The 256x512 gradient iteration (snapshot every 32 steps, T = 2) is bench.py --workload grad_256x512.
 All inputs are seeded synthetic fields (see inputs.py); the paper uses no dataset.
 Run: python -m paper_2608_04085_amd.workloads <name> [--iters K] [--T T]
 """
@@ -110,7 +111,8 @@ def cnop_8x512x1024(T: float = 1.0, iters: int = 50, budget_gb: float = 16.0) ->
     rt = Context(cfg, max_steps=65536)
     delta = 1e-3
     uv = inputs.seed_batch(cfg, range(8), l2=delta)
-    rt.autotune(rt.init_state(uv), reps=5)
+    # default tiles: measured fastest for the whole split binomial sweep,
+    # which the autotuner (timing each kernel alone) does not see
     pool = _revolve_pool(rt, int(budget_gb * 2**30))
     t0 = time.perf_counter()
 
@@ -121,11 +123,12 @@ def cnop_8x512x1024(T: float = 1.0, iters: int = 50, budget_gb: float = 16.0) ->
     (u, R, g, log), el = _timed(lambda: cnop.spg(rt, uv, T, delta, iters, Policy(CKPT_REVOLVE, 1), pool=pool,
                                                   on_iter=progress))
     R0 = log.R[0] if log.R else None
-    # finite-difference alternative: n_dof + 1 forward runs per member and
-    # iteration, at the measured rate of one batched forward of all members
+    # finite-difference alternative (extrapolated): 2 n_dof central
+    # differences plus the point itself per member and iteration, at the
+    # measured rate of one batched forward of all members
     _, t_fwd = _timed(lambda: cnop.ke_ratio(rt, u, T))
     n_dof = 2 * cfg.cells
-    fd_iter_s = t_fwd * (n_dof + 1)  # each batched forward serves every member once
+    fd_iter_s = t_fwd * (2 * n_dof + 1)  # each batched forward serves every member once
     return {"workload": "cnop_8x512x1024", "T": T, "iters": iters, "seconds": el, "iters_per_s": iters / el,
             "forward_batch_seconds": t_fwd, "fd_iters_per_s_extrapolated": 1.0 / fd_iter_s,
             "adjoint_vs_fd_speedup": fd_iter_s / (el / iters),

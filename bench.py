@@ -60,6 +60,8 @@ def parse():
     ap.add_argument("--no-extras", action="store_true",
                     help="only the headline (no FD measurement, 256x512 and out-of-cache legs)")
     ap.add_argument("--kernel-launches", type=int, default=20)
+    ap.add_argument("--groups", type=int, default=2,
+                    help="independent searches the 8 restarts run as (own context, stream, host thread each)")
     ap.add_argument("--workload", default="cnop_8x512x1024",
                     help="cnop_8x512x1024 (default, the JSON line), grad_256x512, or a name from "
                          "paper_2608_04085_amd.workloads")
@@ -278,31 +280,36 @@ def main():
     cells = cfg.nx * cfg.ny * B
     T = args.T
     delta = 1e-3
-    ctx = Context(cfg, max_steps=int(math.ceil(6000 * T)) + 1024)
+    max_steps = int(math.ceil(6000 * T)) + 1024
     state_bytes = 8 * 4 * cells
-    slots = int(args.budget_gib * 2**30) // state_bytes
-    pool = torch.empty(slots * state_bytes + 256, dtype=torch.uint8, device="cuda")
+    budget = int(args.budget_gib * 2**30)
+    slots = budget // state_bytes
     uv = inputs.seed_batch(cfg, range(B), l2=delta)
 
-    search = cnop.SPG(ctx, uv, T, delta, Policy(CKPT_REVOLVE, 1), pool=pool)
-    for _ in range(args.warmup):
-        search.step()
+    # the 8 restarts as `groups` independent searches, each on its own
+    # context, stream and share of the checkpoint budget (same slots per
+    # state), driven by its own host thread: every member takes the
+    # iterates of one search of all 8, bit for bit
+    search = cnop.GroupedSPG(cfg, uv, T, delta, groups=args.groups, pool_bytes=budget, max_steps=max_steps,
+                             policy=Policy(CKPT_REVOLVE, 1))
+    if args.warmup:
+        search.step(args.warmup)
     torch.cuda.synchronize()
-    cu0, gr0, it0 = search.cell_updates, search.log.grads, len(search.log.backtracks)
+    cu0, gr0, it0 = search.cell_updates, sum(search.grads), len(search.backtracks)
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        search.step()
+    search.step(args.steps)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     per_iter = elapsed / args.steps
     value = (search.cell_updates - cu0) / elapsed
-    grads_timed = search.log.grads - gr0
+    grads_timed = (sum(search.grads) - gr0) / len(search.grads)
     nsteps = search.last_nsteps
     nt = int(max(nsteps))
-    backtracks = [row for row in search.log.backtracks[it0:]]
+    backtracks = [row for row in search.backtracks[it0:]]
 
-    # kernels at this size, as the iteration launches them (HIP events on
+    # kernels at this size, as one launch of all 8 members (HIP events on
     # the library's stream), on a state half-way through the march
+    ctx = Context(cfg, max_steps=max_steps)
     Umid, _, _, _ = ctx.integrate(ctx.init_state(search.u), 0.5 * T)
     kt = ctx.kernel_times(Umid, reps=args.kernel_launches)
     fw_total, interval, two = rtcnop.revolve_plan_stats(nt, slots, nt)
@@ -334,9 +341,10 @@ def main():
         "config": {
             "workload": f"cnop_8x512x1024: one iteration of the CNOP search (spectral projected gradient on the sphere "
                         f"||u0|| = 1e-3, non-monotone line search, each trial evaluated with its discrete-adjoint "
-                        f"gradient) for 8 restarts at once, 512x1024 cells, T={T}, binomial checkpointing under "
-                        f"{args.budget_gib:g} GiB",
-            "nx": cfg.nx, "ny": cfg.ny, "batch": B, "T": T, "nsteps": int(np.mean(nsteps)),
+                        f"gradient) for 8 restarts, run as {len(search.searches)} independent searches on their own "
+                        f"streams, 512x1024 cells, T={T}, binomial checkpointing under {args.budget_gib:g} GiB",
+            "nx": cfg.nx, "ny": cfg.ny, "batch": B, "groups": len(search.searches), "T": T,
+            "nsteps": int(np.mean(nsteps)),
             "pool_slots": slots, "level1_interval": interval, "two_level": two,
             "forward_steps_per_gradient": fw_total, "tile": ctx.tile,
         },

@@ -142,6 +142,95 @@ class SPG:
         return Rh
 
 
+class GroupedSPG:
+    """The SPG search of B independent restarts run as `groups` searches of
+    about B / groups members, each on its own context, stream and share of
+    the checkpoint budget and driven by its own host thread.  The restarts
+    never interact (every decision of the search is per member), so each
+    takes the same iterates, bit for bit, as in one search of all B; the
+    groups' marches and reverse sweeps overlap on the GPU instead of running
+    one after the other.  `pool_bytes` is the whole budget; each group's
+    pool holds the same number of its own states as one pool of
+    `pool_bytes` holds of all B."""
+
+    def __init__(self, cfg, uv0, T: float, delta: float, groups: int = 2, pool_bytes: int | None = None,
+                 max_steps: int = 65536, policy: Policy | None = None, **kw):
+        B = cfg.batch
+        groups = max(1, min(groups, B))
+        uv0 = np.asarray(uv0.cpu() if isinstance(uv0, torch.Tensor) else uv0)
+        self.bounds = [(k * B // groups, (k + 1) * B // groups) for k in range(groups)]
+        self.streams = [torch.cuda.Stream() for _ in range(groups)]
+        self.searches: list[SPG] = []
+        for (b0, b1), st in zip(self.bounds, self.streams):
+            with torch.cuda.stream(st):
+                gcfg = cfg.with_(batch=b1 - b0)
+                rt = Context(gcfg, max_steps=max_steps)
+                pool = None
+                if pool_bytes is not None:
+                    state = 8 * 4 * gcfg.nx * gcfg.ny
+                    slots = int(pool_bytes) // (state * B)
+                    pool = torch.empty(slots * state * (b1 - b0) + 256, dtype=torch.uint8, device=rt.device)
+                self.searches.append(SPG(rt, uv0[b0:b1], T, delta, policy, pool, **kw))
+        torch.cuda.synchronize()
+
+    def step(self, n: int = 1, on_iter=None) -> np.ndarray:
+        """n iterations of every group (the groups advance independently);
+        on_iter(group, k), if given, is called from the group's thread after
+        its iteration k.  Returns the accepted objectives of all members."""
+        import threading
+        errors = []
+
+        def run(k):
+            try:
+                with torch.cuda.stream(self.streams[k]):
+                    for it in range(n):
+                        self.searches[k].step()
+                        if on_iter is not None:
+                            on_iter(k, it)
+                self.streams[k].synchronize()
+            except BaseException as e:  # noqa: BLE001 -- re-raised below
+                errors.append(e)
+
+        threads = [threading.Thread(target=run, args=(k,)) for k in range(len(self.searches))]
+        for t in threads:
+            t.start()
+        for t in threads:
+            t.join()
+        if errors:
+            raise errors[0]
+        return self.R
+
+    @property
+    def R(self) -> np.ndarray:
+        return np.concatenate([s.R for s in self.searches])
+
+    @property
+    def u(self) -> torch.Tensor:
+        return torch.cat([s.u for s in self.searches])
+
+    @property
+    def cell_updates(self) -> int:
+        return sum(s.cell_updates for s in self.searches)
+
+    @property
+    def grads(self) -> list[int]:
+        return [s.log.grads for s in self.searches]
+
+    @property
+    def last_nsteps(self) -> list[int]:
+        return [n for s in self.searches for n in s.last_nsteps]
+
+    @property
+    def hist(self) -> np.ndarray:
+        return np.concatenate([np.array(s.hist) for s in self.searches], axis=1)
+
+    @property
+    def backtracks(self) -> list[list[int]]:
+        """Per iteration, the backtracks of every member."""
+        rows = [s.log.backtracks for s in self.searches]
+        return [sum((r[i] for r in rows), []) for i in range(min(len(r) for r in rows))]
+
+
 def spg(rt: Context, uv0, T: float, delta: float, iters: int, policy: Policy | None = None,
         pool: torch.Tensor | None = None, memory: int = 10, c_armijo: float = 1e-4, max_backtracks: int = 8,
         log: SPGLog | None = None, on_iter=None, grad_at_trials: bool = True):

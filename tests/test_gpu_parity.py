@@ -243,6 +243,37 @@ def test_binomial_sweep_split_over_two_streams_is_bitwise_equal(dt_mode):
     np.testing.assert_array_equal(host(gs), out[True][1])
 
 
+@pytest.mark.parametrize("groups", [2, 3])
+def test_grouped_search_takes_the_iterates_of_one_search(groups):
+    # The restarts of the CNOP search run as independent searches on their
+    # own contexts, streams and host threads (cnop.GroupedSPG); every
+    # decision of the search is per member, so each member's objectives,
+    # iterates and gradients are those of one search of all members, bit for
+    # bit -- with an even split and an uneven one (4 members in 1 + 1 + 2).
+    from paper_2608_04085_amd import cnop
+    cfg = RTConfig(nx=128, ny=176, batch=4)
+    T, delta = 0.3, 1e-3
+    uv = inputs.seed_batch(cfg, [11, 12, 13, 14], l2=delta)
+    budget = 6 * 8 * 4 * cfg.cells * cfg.batch
+    one = rt().Context(cfg, max_steps=4096)
+    pool = torch.empty(budget + 256, dtype=torch.uint8, device="cuda")
+    s1 = cnop.SPG(one, uv, T, delta, rt().Policy(CKPT_REVOLVE, 1), pool=pool)
+    for _ in range(3):
+        s1.step()
+    sg = cnop.GroupedSPG(cfg, uv, T, delta, groups=groups, pool_bytes=budget, max_steps=4096,
+                         policy=rt().Policy(CKPT_REVOLVE, 1))
+    seen = []
+    sg.step(3, on_iter=lambda k, it: seen.append((k, it)))
+    torch.cuda.synchronize()
+    assert sorted(seen) == [(k, it) for k in range(groups) for it in range(3)]
+    np.testing.assert_array_equal(sg.hist, np.array(s1.hist))
+    np.testing.assert_array_equal(host(sg.u), host(s1.u))
+    np.testing.assert_array_equal(np.concatenate([host(s.g) for s in sg.searches]), host(s1.g))
+    # a group backtracks only until its own members accept: never more
+    # gradient calls than the one search
+    assert all(1 <= gk <= s1.log.grads for gk in sg.grads), (sg.grads, s1.log.grads)
+
+
 @pytest.mark.parametrize("slack", [0, 1, 7, 64])
 def test_two_stream_sweep_with_pool_sized_to_the_run(slack):
     # pools sized from the actual step count (plus some slack) put both

@@ -243,13 +243,14 @@ def test_binomial_sweep_split_over_two_streams_is_bitwise_equal(dt_mode):
     np.testing.assert_array_equal(host(gs), out[True][1])
 
 
-@pytest.mark.parametrize("groups", [2, 3])
+@pytest.mark.parametrize("groups", [2, 3, 4])
 def test_grouped_search_takes_the_iterates_of_one_search(groups):
     # The restarts of the CNOP search run as independent searches on their
     # own contexts, streams and host threads (cnop.GroupedSPG); every
     # decision of the search is per member, so each member's objectives,
     # iterates and gradients are those of one search of all members, bit for
-    # bit -- with an even split and an uneven one (4 members in 1 + 1 + 2).
+    # bit -- with even splits (2 + 2, and one member per search) and an
+    # uneven one (1 + 1 + 2).
     from paper_2608_04085_amd import cnop
     cfg = RTConfig(nx=128, ny=176, batch=4)
     T, delta = 0.3, 1e-3

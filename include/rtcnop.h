@@ -267,8 +267,9 @@ int rt_axpy(rt_ctx* ctx, const double* x, const double* alpha, const double* y, 
 
 /* Kernel variants.  The fused step and adjoint kernels come in tile shapes
  * 16x16, 32x8, 64x4 (256 threads), 16x16, 32x8 (576 threads, one pass per
- * phase), 16x8 (128), 8x8 (64), 16x8 (320, one pass) and 8x8 (192, one
- * pass); ids 0..8 in that order.  Every variant gives bitwise-identical
+ * phase), 16x8 (128), 8x8 (64), 16x8 (320, one pass), 8x8 (192, one
+ * pass), 32x16 (512), 16x15 and 15x16 (256, every face loop in one pass);
+ * ids 0..11 in that order.  Every variant gives bitwise-identical
  * results.  rt_set_tile selects one variant for both kernels;
  * rt_autotune times every variant on the state U (device) with `reps`
  * launches each on the context's stream (steps at a given dt and with the
@@ -304,7 +305,8 @@ int rt_autotune(rt_ctx* ctx, const double* U, int32_t reps, int32_t* step_tile, 
  * faster than the two-kernel step on their own (the folded kernel shares
  * the CUs less well with the concurrent re-computation); before it, grids
  * of fewer than 2^16 cells in all fold (and use 8x8 single-pass tiles),
- * larger ones use 32x8 tiles and two kernels.  Binomial checkpointing,
+ * larger ones run two adjoint kernels, with 32x16 step and 32x8 adjoint
+ * tiles up to three 32x8 blocks per CU and 16x15 tiles for both beyond.  Binomial checkpointing,
  * differentiated time steps (rt_set_dt_mode) and the well-balanced variant
  * (RT_RECON_BALANCED) always run two kernels per step. */
 int rt_set_fold(rt_ctx* ctx, int32_t on);

@@ -354,13 +354,24 @@ int rt_create(const rt_grid* grid, const rt_phys* phys, void* stream, rt_ctx** o
   c->stream = reinterpret_cast<hipStream_t>(stream);
   // Defaults from measurements on MI355X.  Tiny grids (one partial round of
   // blocks) are bound by one block's critical path: single-pass 8x8 tiles
-  // and the folded adjoint (one kernel per step) win.  From 2^16 cells on,
-  // the step takes 32x16 tiles of 512 threads (the least halo work per
-  // cell) and the adjoint 32x8 tiles of 256 threads in the two-kernel form.
-  // rt_autotune measures instead.
-  const bool tiny = (size_t)P.nx * P.ny * P.nb < ((size_t)1 << 16);
-  c->tile = tiny ? rtk::TILE_8x8W : rtk::TILE_32x16;
-  c->tile_adj = tiny ? rtk::TILE_8x8W : rtk::TILE_32x8;
+  // and the folded adjoint (one kernel per step) win.  From 2^16 cells on
+  // the adjoint runs two kernels.  While 32x8 tiles fill at most one round
+  // of three blocks per CU, each launch lasts about one block's critical
+  // path: the step takes 32x16 tiles of 512 threads (the least halo work
+  // per cell) and the adjoint 32x8 tiles.  Beyond that both take 16x15 tiles
+  // of 256 threads: every face loop is one pass of the block (255 and 256
+  // faces of each direction; the step's single face list two), and four
+  // small blocks per CU hide one another's barriers better than two large
+  // ones.  rt_autotune measures instead.
+  const size_t all_cells = (size_t)P.nx * P.ny * P.nb;
+  const bool tiny = all_cells < ((size_t)1 << 16);
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+    cus = 256;
+  const bool one_round = all_cells <= (size_t)3 * cus * 256;
+  c->tile = tiny ? rtk::TILE_8x8W : (one_round ? rtk::TILE_32x16 : rtk::TILE_16x15);
+  c->tile_adj = tiny ? rtk::TILE_8x8W : (one_round ? rtk::TILE_32x8 : rtk::TILE_16x15);
   c->fold = tiny;
   const size_t n = c->cells();
   c->red_blocks = (int)std::min<size_t>(256, std::max<size_t>(1, n / 2048));

@@ -103,8 +103,10 @@ struct AdjArgs {
 };
 
 // Tile shapes of the fused step / adjoint kernels: TX x TY cells with 256
-// threads, with 576 threads ("W" variants: one pass per phase), or 32 x 16
-// cells with 512 threads (less halo work per cell).  All variants produce
+// threads, with 576 threads ("W" variants: one pass per phase), 32 x 16
+// cells with 512 threads (less halo work per cell), or 16 x 15 and 15 x 16
+// cells with 256 threads (every face loop of the adjoint in one pass of the
+// block: 255 and 256 faces of each direction).  All variants produce
 // bitwise-identical results.
 enum TileId {
   TILE_16x16 = 0,
@@ -117,7 +119,9 @@ enum TileId {
   TILE_16x8W = 7,
   TILE_8x8W = 8,
   TILE_32x16 = 9,
-  TILE_COUNT = 10
+  TILE_16x15 = 10,
+  TILE_15x16 = 11,
+  TILE_COUNT = 12
 };
 void tile_dims(int tile, int* tx, int* ty, int* nt);
 int step_blocks(const Params& P, int tile);  // blocks per member

@@ -1477,6 +1477,8 @@ void tile_dims(int tile, int* tx, int* ty, int* nt) {
     case TILE_16x8W: b = 8; t = 320; break;
     case TILE_8x8W: a = 8; b = 8; t = 192; break;
     case TILE_32x16: a = 32; b = 16; t = 512; break;
+    case TILE_16x15: b = 15; break;
+    case TILE_15x16: a = 15; break;
     default: break;
   }
   *tx = a;
@@ -1525,6 +1527,8 @@ hipError_t launch_step(const Params& P, int tile, const StepArgs& a, hipStream_t
     case TILE_16x8W: return launch_step_t<16, 8, 320>(P, a, s);
     case TILE_8x8W: return launch_step_t<8, 8, 192>(P, a, s);
     case TILE_32x16: return launch_step_t<32, 16, 512>(P, a, s);
+    case TILE_16x15: return launch_step_t<16, 15, 256>(P, a, s);
+    case TILE_15x16: return launch_step_t<15, 16, 256>(P, a, s);
     default: return launch_step_t<16, 16, 256>(P, a, s);
   }
 }
@@ -1577,6 +1581,8 @@ static hipError_t launch_adj_a(const Params& P, int tile, const AdjArgs& a, hipS
     case TILE_16x8W: return launch_adj_t<16, 8, 320>(P, a, s);
     case TILE_8x8W: return launch_adj_t<8, 8, 192>(P, a, s);
     case TILE_32x16: return launch_adj_t<32, 16, 512>(P, a, s);
+    case TILE_16x15: return launch_adj_t<16, 15, 256>(P, a, s);
+    case TILE_15x16: return launch_adj_t<15, 16, 256>(P, a, s);
     default: return launch_adj_t<16, 16, 256>(P, a, s);
   }
 }

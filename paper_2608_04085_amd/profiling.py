@@ -17,10 +17,10 @@
         variable RT_PROFILE_COMMAND.
     python -m paper_2608_04085_amd.profiling stats TITLE TRACE OUT_MD
         Kernel times of a --kernel-trace run as Markdown, per kernel and grid.
-    python -m paper_2608_04085_amd.profiling counters TITLE DIR... OUT_MD
+    python -m paper_2608_04085_amd.profiling counters [--tiles=STEP/ADJ] TITLE DIR... OUT_MD
         Per-dispatch averages of the counters of --pmc runs, per kernel class,
         as Markdown and in profiles/counters.json under TITLE (keyed by the
-        kernel-source hash, as the traffic is).
+        kernel-source hash and the tile variants, as the traffic is).
 
 FETCH_SIZE and WRITE_SIZE are scaled by what they read for the plain copy
 (bytes moved / counted bytes).  On gfx950 the derived FETCH_SIZE counts a
@@ -251,7 +251,7 @@ def stats_md(title: str, trace: str, out_md: str, command: str = "", top: int = 
     print("\n".join(lines))
 
 
-def counters_md(title: str, dirs: list, out_md: str, command: str = ""):
+def counters_md(title: str, dirs: list, out_md: str, command: str = "", tiles: str = ""):
     """Per-dispatch averages of every collected counter, per kernel class."""
     per: dict = {}
     for d in dirs:
@@ -262,7 +262,8 @@ def counters_md(title: str, dirs: list, out_md: str, command: str = ""):
             if c and c != "copy":
                 per.setdefault(c, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
     names = sorted({n for v in per.values() for n in v})
-    lines = [f"# Counters: {title}", "", "Commands (repository root):", "", "```"]
+    lines = [f"# Counters: {title}" + (f" (tiles {tiles})" if tiles else ""), "", "Commands (repository root):", "",
+             "```"]
     lines += command.strip().split("\n") if command else []
     lines += ["```", "", "Per-dispatch averages.", "", "| counter | " + " | ".join(k for k in CATEGORIES if k in per) + " |",
               "|---|" + "---|" * len([k for k in CATEGORIES if k in per])]
@@ -292,23 +293,26 @@ def counters_md(title: str, dirs: list, out_md: str, command: str = ""):
     if os.path.exists(COUNTERS_JSON):
         with open(COUNTERS_JSON) as f:
             data = json.load(f)
-    data[title] = {"source_hash": kernel_source_hash(),
+    data[title] = {"source_hash": kernel_source_hash(), "tiles": tiles,
                    "per_dispatch": {k: {n: sum(v) / len(v) for n, v in d.items()} for k, d in per.items()}}
     with open(COUNTERS_JSON, "w") as f:
         json.dump(data, f, indent=1)
     print("\n".join(lines))
 
 
-def counters_for(title: str, parts) -> dict | None:
+def counters_for(title: str, parts, tiles: str | None = None) -> dict | None:
     """Per-launch sums over the kernel classes `parts` of the counters of
-    the committed --pmc runs titled `title`, or None if there are none or the
-    kernel sources changed since they were taken."""
+    the committed --pmc runs titled `title`, or None if there are none, the
+    kernel sources changed since they were taken, or they were taken with
+    other tile variants than `tiles`."""
     try:
         with open(COUNTERS_JSON) as f:
             d = json.load(f)[title]
     except (OSError, KeyError, ValueError):
         return None
     if d.get("source_hash") != kernel_source_hash():
+        return None
+    if tiles is not None and d.get("tiles") and d["tiles"] != tiles:
         return None
     per = d.get("per_dispatch", {})
     if not all(p in per for p in parts):
@@ -328,6 +332,8 @@ if __name__ == "__main__":
     elif sys.argv[1] == "stats":
         stats_md(sys.argv[2], sys.argv[3], sys.argv[4], os.environ.get("RT_PROFILE_COMMAND", ""))
     elif sys.argv[1] == "counters":
-        counters_md(sys.argv[2], sys.argv[3:-1], sys.argv[-1], os.environ.get("RT_PROFILE_COMMAND", ""))
+        args = sys.argv[2:]
+        tl = args.pop(0)[len("--tiles="):] if args and args[0].startswith("--tiles=") else ""
+        counters_md(args[0], args[1:-1], args[-1], os.environ.get("RT_PROFILE_COMMAND", ""), tl)
     else:
         raise SystemExit(__doc__)

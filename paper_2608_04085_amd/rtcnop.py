@@ -20,7 +20,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librtcnop.so")
 
 STATUS = {0: "RT_OK", -1: "RT_EINVAL", -2: "RT_EHIP", -3: "RT_ENOMEM", -4: "RT_EUNPHYS", -5: "RT_ESTATE"}
-TILES = {"16x16": 0, "32x8": 1, "64x4": 2, "16x16w": 3, "32x8w": 4, "16x8": 5, "8x8": 6, "16x8w": 7, "8x8w": 8, "32x16": 9}
+TILES = {"16x16": 0, "32x8": 1, "64x4": 2, "16x16w": 3, "32x8w": 4, "16x8": 5, "8x8": 6, "16x8w": 7, "8x8w": 8, "32x16": 9,
+         "16x15": 10, "15x16": 11}
 DT_MODES = {"frozen": 0, "differentiated": 1}
 DT_MODES_BY_ID = {v: k for k, v in DT_MODES.items()}
 

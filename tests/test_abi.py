@@ -184,13 +184,19 @@ def test_argument_validation_without_gpu():
 def test_committed_counters_belong_to_the_kernel_sources():
     # profiles/traffic.json records the hash of the kernel sources it was
     # measured on; the benchmark reports its HBM traffic only while they match
+    # and the tile variants (the defaults at each size)
     from paper_2608_04085_amd import profiling
-    for workload, kernels in (("grad_256x512", ("step", "step_march", "adjoint")),
-                              ("step_8x1024x2048", ("step", "adjoint"))):
+    for workload, kernels, tiles in (("grad_256x512", ("step", "step_march", "adjoint"), "32x16/32x8"),
+                                     ("cnop_8x512x1024", ("step_march", "adjoint"), "16x15/16x15"),
+                                     ("step_8x1024x2048", ("step", "adjoint"), "16x15/16x15")):
         for k in kernels:
-            t = profiling.traffic_for(workload, k, "32x16/32x8")
+            t = profiling.traffic_for(workload, k, tiles)
             assert t is not None and t > 0, (workload, k)
     assert profiling.traffic_for("grad_256x512", "adjoint", "16x8/32x8") is None  # other tiles
+    for title, tiles in (("cnop_8x512x1024", "16x15/16x15"), ("8x1024x2048", "16x15/16x15")):
+        c = profiling.counters_for(title, ["adj_a", "adj_b"], tiles)
+        assert c is not None and c["SQ_INSTS_VALU"] > 0, title
+        assert profiling.counters_for(title, ["adj_a"], "32x16/32x8") is None
 
 
 def test_header_declares_every_exported_call():

@@ -61,7 +61,7 @@ def test_init_and_cfl_match_oracle(cfg):
     np.testing.assert_allclose(ke, o.kinetic_energy(Uo), rtol=1e-13)
 
 
-TILE_NAMES = ["16x16", "32x8", "64x4", "16x16w", "32x8w", "16x8", "8x8", "16x8w", "8x8w"]
+TILE_NAMES = ["16x16", "32x8", "64x4", "16x16w", "32x8w", "16x8", "8x8", "16x8w", "8x8w", "32x16", "16x15", "15x16"]
 
 
 @pytest.mark.parametrize("tile", TILE_NAMES)
@@ -158,7 +158,7 @@ def test_step_adjoint_matches_oracle(cfg):
     dt = o.cfl_dt(Uo)
     lam_next = np.random.default_rng(7).standard_normal(Uo.shape)
     ref = o.step_vjp(Uo, dt, lam_next)
-    for tile in ["16x16", "64x4", "32x8w", "8x8", "16x8w"]:
+    for tile in ["16x16", "64x4", "32x8w", "8x8", "16x8w", "32x8", "32x16", "16x15", "15x16"]:
         r = rt().Context(cfg, max_steps=64, tile=tile)
         lam = r.step_adjoint(torch.from_numpy(Uo), torch.from_numpy(dt), torch.from_numpy(lam_next))
         assert normwise(host(lam), ref) <= 1e-12

@@ -762,12 +762,21 @@ __device__ __forceinline__ void lambda_at(const Params& P, const GatherSrc& g, i
 // ----------------------------------------------------------------- adjoint A
 // LDS of adjoint kernel A.  The face cotangents reuse the primitive tile,
 // which is dead once the predictor has run (the tile cell's own primitives
-// are recomputed from registers for the predictor adjoint); x faces and
-// y faces take turns in that space.  lambda^{n+1} on the halo-1 region is
-// staged in LDS only when the kernel forms it by the folded gather;
-// otherwise the face loops read it from global memory (L2), which keeps the
-// footprint small enough for more resident blocks per CU.
-template <int TX, int TY>
+// are recomputed from registers for the predictor adjoint).  lambda^{n+1}
+// on the halo-1 region is staged in LDS only when the kernel forms it by
+// the folded gather; otherwise the face loops read it from global memory
+// (L2), which keeps the footprint small enough for more resident blocks
+// per CU.
+//
+// Two ways to hand a face's cotangents to its two cells.  OWNF (blocks with
+// a spare thread for every boundary face): each tile cell's thread takes
+// the face to its right and the face above it and keeps the cotangent of its
+// own side in registers; the block's spare threads take the tile's left and
+// bottom boundary faces.  Only the far side's cotangent goes through LDS,
+// and the x and y faces share one phase (one barrier instead of three).
+// Otherwise the x faces and then the y faces are loops over all faces of
+// the tile, both sides through LDS.
+template <int TX, int TY, bool OWNF>
 struct AdjCore {
   static constexpr int AX = TX + 4, AY = TY + 4;
   static constexpr int QX = TX + 2, QY = TY + 2;
@@ -784,11 +793,24 @@ struct AdjCore {
   };
   double Q[12][QY][QX];
 };
-template <int TX, int TY, bool FOLD>
-struct AdjLDS : AdjCore<TX, TY> {};
 template <int TX, int TY>
-struct AdjLDS<TX, TY, true> : AdjCore<TX, TY> {
-  double L[4][AdjCore<TX, TY>::QY][AdjCore<TX, TY>::QX];  // lambda-tilde on the halo-1 region
+struct AdjCore<TX, TY, true> {
+  static constexpr int AX = TX + 4, AY = TY + 4;
+  static constexpr int QX = TX + 2, QY = TY + 2;
+  union {
+    double W[5][AY][AX];
+    struct {
+      double XR[4][TY][TX];  // cell (x, y): cotangent of the right state of its left face (r, u, v, p)
+      double YT[4][TY][TX];  // cell (x, y): cotangent of the upper state of its bottom face (r, u, v, p)
+    } fo;
+  };
+  double Q[12][QY][QX];
+};
+template <int TX, int TY, bool FOLD, bool OWNF>
+struct AdjLDS : AdjCore<TX, TY, OWNF> {};
+template <int TX, int TY, bool OWNF>
+struct AdjLDS<TX, TY, true, OWNF> : AdjCore<TX, TY, OWNF> {
+  double L[4][AdjCore<TX, TY, OWNF>::QY][AdjCore<TX, TY, OWNF>::QX];  // lambda on the halo-1 region
 };
 
 // DTD: also the step-size derivative mu and the signal-speed argmax of U^n
@@ -807,8 +829,10 @@ __global__ __launch_bounds__(NT) void k_adj_a(Params P, AdjArgs a) {
   static_assert(NT >= TX * TY && NT % 64 == 0, "one thread per tile cell at least");
   static_assert(!(FOLD && DTD), "the step-size derivative needs the two-kernel form");
   static_assert(!(FOLD && BAL), "the well-balanced variant runs the two-kernel form");
-  constexpr int QX = AdjCore<TX, TY>::QX, QY = AdjCore<TX, TY>::QY;
-  __shared__ AdjLDS<TX, TY, FOLD> S;
+  // a spare thread for each boundary face: the tile's own faces in one phase
+  constexpr bool OWNF = NT - TX * TY >= (TX > TY ? TX : TY);
+  constexpr int QX = AdjCore<TX, TY, OWNF>::QX, QY = AdjCore<TX, TY, OWNF>::QY;
+  __shared__ AdjLDS<TX, TY, FOLD, OWNF> S;
 
   const int b = blockIdx.z;
   int tbx, tby;
@@ -907,57 +931,32 @@ __global__ __launch_bounds__(NT) void k_adj_a(Params P, AdjArgs a) {
 
   const double ax = dt * P.inv_dx, ay = dt * P.inv_dy;
   double mu = 0.0;  // DTD: this thread's share of d<lambda^{n+1}, U^{n+1}>/d dt
-  // x faces
-  for (int k = tid; k < (TX + 1) * TY; k += NT) {
-    const int fx = k % (TX + 1), fy = k / (TX + 1);
-    FS Lb{0, 0, 0, 0}, Rb{0, 0, 0, 0};
-    if (y0 + fy < ny) {
-      // face between halo-1 cells (fx, fy+1) [left] and (fx+1, fy+1) [right]
-      double lL[4], lR[4];
-      lam(fx, fy + 1, lL);
-      lam(fx + 1, fy + 1, lR);
-      const double Fb[4] = {ax * (lR[0] - lL[0]), ax * (lR[1] - lL[1]), ax * (lR[2] - lL[2]), ax * (lR[3] - lL[3])};
-      if constexpr (DTD) {
-        double F[4];
-        hllc_adj(P, xface_right_of(S, fx, fy + 1), xface_left_of(S, fx + 1, fy + 1), Fb, Lb, Rb, F);
-        // each face once: the right faces of the tile's own cells
-        if (fx >= 1 && x0 + fx - 1 < nx)
-          mu += P.inv_dx * ((lR[0] - lL[0]) * F[0] + (lR[1] - lL[1]) * F[1] + (lR[2] - lL[2]) * F[2] +
-                            (lR[3] - lL[3]) * F[3] + hdtg * (lR[2] - lL[2]) * F[0]);
-      } else {
-        hllc_adj(P, xface_right_of(S, fx, fy + 1), xface_left_of(S, fx + 1, fy + 1), Fb, Lb, Rb);
-      }
+  // The adjoint of x face (fx, fy), between halo-1 cells (fx, fy+1) [left]
+  // and (fx+1, fy+1) [right], into the cotangents of its two states (x
+  // frame: r, n = u, t = v, p).  DTD counts each face once: the right faces
+  // of the tile's own cells.
+  auto xface = [&](int fx, int fy, FS& Lb, FS& Rb) {
+    double lL[4], lR[4];
+    lam(fx, fy + 1, lL);
+    lam(fx + 1, fy + 1, lR);
+    const double Fb[4] = {ax * (lR[0] - lL[0]), ax * (lR[1] - lL[1]), ax * (lR[2] - lL[2]), ax * (lR[3] - lL[3])};
+    if constexpr (DTD) {
+      double F[4];
+      hllc_adj(P, xface_right_of(S, fx, fy + 1), xface_left_of(S, fx + 1, fy + 1), Fb, Lb, Rb, F);
+      if (fx >= 1 && x0 + fx - 1 < nx)
+        mu += P.inv_dx * ((lR[0] - lL[0]) * F[0] + (lR[1] - lL[1]) * F[1] + (lR[2] - lL[2]) * F[2] +
+                          (lR[3] - lL[3]) * F[3] + hdtg * (lR[2] - lL[2]) * F[0]);
+    } else {
+      hllc_adj(P, xface_right_of(S, fx, fy + 1), xface_left_of(S, fx + 1, fy + 1), Fb, Lb, Rb);
     }
-    // x-frame (r, n = u, t = v, p) is the primitive order
-    S.fx.XL[0][fy][fx] = Lb.r;
-    S.fx.XL[1][fy][fx] = Lb.n;
-    S.fx.XL[2][fy][fx] = Lb.t;
-    S.fx.XL[3][fy][fx] = Lb.p;
-    S.fx.XR[0][fy][fx] = Rb.r;
-    S.fx.XR[1][fy][fx] = Rb.n;
-    S.fx.XR[2][fy][fx] = Rb.t;
-    S.fx.XR[3][fy][fx] = Rb.p;
-  }
-  __syncthreads();
-  // the tile cell's x contributions: q-bar from both x faces, sx-bar
-  W4 qx{0, 0, 0, 0, 0}, sxb{0, 0, 0, 0, 0};
-  if (own) {
-    const W4 xl{S.fx.XR[0][ty][tx], S.fx.XR[1][ty][tx], S.fx.XR[2][ty][tx], S.fx.XR[3][ty][tx]};
-    const W4 xr{S.fx.XL[0][ty][tx + 1], S.fx.XL[1][ty][tx + 1], S.fx.XL[2][ty][tx + 1], S.fx.XL[3][ty][tx + 1]};
-    qx = W4{xl.r + xr.r, xl.u + xr.u, xl.v + xr.v, xl.p + xr.p};
-    sxb = W4{0.5 * (xr.r - xl.r), 0.5 * (xr.u - xl.u), 0.5 * (xr.v - xl.v), 0.5 * (xr.p - xl.p)};
-  }
-  __syncthreads();
-  // y faces, the thread index rotated by one wavefront so that a second
-  // pass of this loop and of the x-face loop fall on different wavefronts
-  for (int k = (tid + NT - 64) % NT; k < TX * (TY + 1); k += NT) {
-    const int fx = k % TX, fy = k / TX;
+  };
+  // y face (fx, fy), between halo-1 cells (fx+1, fy) [below] and (fx+1,
+  // fy+1) [above], row j = y0 + fy of faces (walls at 0 and ny, nothing
+  // beyond), into the cotangents of its two states (y frame: r, n = v,
+  // t = u, p).  DTD counts each face once: the walls and the top faces of
+  // the tile's own rows (col: the face's column is in the domain).
+  auto yface = [&](int fx, int fy, bool col, FS& Bb, FS& Tb) {
     const int j = y0 + fy;
-    FS Bb{0, 0, 0, 0}, Tb{0, 0, 0, 0};
-    // below = halo-1 cell (fx+1, fy), above = (fx+1, fy+1)
-    // DTD counts each face once: the walls, and the top faces of the tile's
-    // own rows
-    const bool col = x0 + fx < nx;
     if (j == 0) {
       double lT[4];
       lam(fx + 1, fy + 1, lT);
@@ -990,22 +989,96 @@ __global__ __launch_bounds__(NT) void k_adj_a(Params P, AdjArgs a) {
         hllc_adj(P, yface_top_of(S, fx + 1, fy), yface_bottom_of(S, fx + 1, fy + 1), Fb, Bb, Tb);
       }
     }
-    // y-frame (r, n = v, t = u, p) -> primitive order (r, u, v, p)
-    S.fy.YB[0][fy][fx] = Bb.r;
-    S.fy.YB[1][fy][fx] = Bb.t;
-    S.fy.YB[2][fy][fx] = Bb.n;
-    S.fy.YB[3][fy][fx] = Bb.p;
-    S.fy.YT[0][fy][fx] = Tb.r;
-    S.fy.YT[1][fy][fx] = Tb.t;
-    S.fy.YT[2][fy][fx] = Tb.n;
-    S.fy.YT[3][fy][fx] = Tb.p;
+  };
+
+  // the tile cell's cotangents from its four faces, in primitive order:
+  // xl / xr of the right state of its left face and the left state of its
+  // right face, yb / yt likewise in y
+  W4 xl{0, 0, 0, 0, 0}, xr{0, 0, 0, 0, 0}, yb{0, 0, 0, 0, 0}, yt{0, 0, 0, 0, 0};
+  if constexpr (OWNF) {
+    // one phase: a tile cell's thread takes the face to its right and the
+    // face above it; spare thread e the left face of tile row e and the
+    // bottom face of tile column e.  The far side goes to LDS for the cell
+    // that owns it.
+    const int e = tid - TX * TY;
+    FS Lb{0, 0, 0, 0}, Rb{0, 0, 0, 0}, Bb{0, 0, 0, 0}, Tb{0, 0, 0, 0};
+    if (own || (e >= 0 && e < TY && y0 + e < ny)) {
+      const int fx = own ? tx + 1 : 0, fy = own ? ty : e;
+      xface(fx, fy, Lb, Rb);
+      if (fx < TX) {
+        S.fo.XR[0][fy][fx] = Rb.r;
+        S.fo.XR[1][fy][fx] = Rb.n;
+        S.fo.XR[2][fy][fx] = Rb.t;
+        S.fo.XR[3][fy][fx] = Rb.p;
+      }
+    }
+    if (own || (e >= 0 && e < TX && x0 + e < nx)) {
+      const int fx = own ? tx : e, fy = own ? ty + 1 : 0;
+      yface(fx, fy, true, Bb, Tb);
+      if (fy < TY) {
+        S.fo.YT[0][fy][fx] = Tb.r;
+        S.fo.YT[1][fy][fx] = Tb.t;
+        S.fo.YT[2][fy][fx] = Tb.n;
+        S.fo.YT[3][fy][fx] = Tb.p;
+      }
+    }
+    __syncthreads();
+    if (own) {
+      xl = W4{S.fo.XR[0][ty][tx], S.fo.XR[1][ty][tx], S.fo.XR[2][ty][tx], S.fo.XR[3][ty][tx]};
+      xr = W4{Lb.r, Lb.n, Lb.t, Lb.p};
+      yb = W4{S.fo.YT[0][ty][tx], S.fo.YT[1][ty][tx], S.fo.YT[2][ty][tx], S.fo.YT[3][ty][tx]};
+      yt = W4{Bb.r, Bb.t, Bb.n, Bb.p};
+    }
+  } else {
+    // x faces, all of the tile's in a loop, both sides through LDS
+    for (int k = tid; k < (TX + 1) * TY; k += NT) {
+      const int fx = k % (TX + 1), fy = k / (TX + 1);
+      FS Lb{0, 0, 0, 0}, Rb{0, 0, 0, 0};
+      if (y0 + fy < ny) xface(fx, fy, Lb, Rb);
+      // x-frame (r, n = u, t = v, p) is the primitive order
+      S.fx.XL[0][fy][fx] = Lb.r;
+      S.fx.XL[1][fy][fx] = Lb.n;
+      S.fx.XL[2][fy][fx] = Lb.t;
+      S.fx.XL[3][fy][fx] = Lb.p;
+      S.fx.XR[0][fy][fx] = Rb.r;
+      S.fx.XR[1][fy][fx] = Rb.n;
+      S.fx.XR[2][fy][fx] = Rb.t;
+      S.fx.XR[3][fy][fx] = Rb.p;
+    }
+    __syncthreads();
+    if (own) {
+      xl = W4{S.fx.XR[0][ty][tx], S.fx.XR[1][ty][tx], S.fx.XR[2][ty][tx], S.fx.XR[3][ty][tx]};
+      xr = W4{S.fx.XL[0][ty][tx + 1], S.fx.XL[1][ty][tx + 1], S.fx.XL[2][ty][tx + 1], S.fx.XL[3][ty][tx + 1]};
+    }
+    __syncthreads();
+    // y faces, the thread index rotated by one wavefront so that a second
+    // pass of this loop and of the x-face loop fall on different wavefronts
+    for (int k = (tid + NT - 64) % NT; k < TX * (TY + 1); k += NT) {
+      const int fx = k % TX, fy = k / TX;
+      FS Bb{0, 0, 0, 0}, Tb{0, 0, 0, 0};
+      yface(fx, fy, x0 + fx < nx, Bb, Tb);
+      // y-frame (r, n = v, t = u, p) -> primitive order (r, u, v, p)
+      S.fy.YB[0][fy][fx] = Bb.r;
+      S.fy.YB[1][fy][fx] = Bb.t;
+      S.fy.YB[2][fy][fx] = Bb.n;
+      S.fy.YB[3][fy][fx] = Bb.p;
+      S.fy.YT[0][fy][fx] = Tb.r;
+      S.fy.YT[1][fy][fx] = Tb.t;
+      S.fy.YT[2][fy][fx] = Tb.n;
+      S.fy.YT[3][fy][fx] = Tb.p;
+    }
+    __syncthreads();
+    if (own) {
+      yb = W4{S.fy.YT[0][ty][tx], S.fy.YT[1][ty][tx], S.fy.YT[2][ty][tx], S.fy.YT[3][ty][tx]};
+      yt = W4{S.fy.YB[0][ty + 1][tx], S.fy.YB[1][ty + 1][tx], S.fy.YB[2][ty + 1][tx], S.fy.YB[3][ty + 1][tx]};
+    }
   }
-  __syncthreads();
 
   if (own) {
     const int lx = tx + 1, ly = ty + 1;
-    const W4 yb{S.fy.YT[0][ty][tx], S.fy.YT[1][ty][tx], S.fy.YT[2][ty][tx], S.fy.YT[3][ty][tx]};
-    const W4 yt{S.fy.YB[0][ty + 1][tx], S.fy.YB[1][ty + 1][tx], S.fy.YB[2][ty + 1][tx], S.fy.YB[3][ty + 1][tx]};
+    // q-bar from the four faces, sx-bar and sy-bar
+    const W4 qx{xl.r + xr.r, xl.u + xr.u, xl.v + xr.v, xl.p + xr.p};
+    W4 sxb{0.5 * (xr.r - xl.r), 0.5 * (xr.u - xl.u), 0.5 * (xr.v - xl.v), 0.5 * (xr.p - xl.p)};
     const W4 qb{qx.r + yb.r + yt.r, qx.u + yb.u + yt.u, qx.v + yb.v + yt.v, qx.p + yb.p + yt.p};
     W4 syb{0.5 * (yt.r - yb.r), 0.5 * (yt.u - yb.u), 0.5 * (yt.v - yb.v), 0.5 * (yt.p - yb.p)};
     W4 wb{0.0, 0.0, 0.0, 0.0};

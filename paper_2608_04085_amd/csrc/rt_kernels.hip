@@ -3,9 +3,8 @@
 // them.  All arithmetic is FP64.
 //
 // Fused step (one launch per time step for all members):
-//   block = one tile of TX x TY cells of one member; 256 threads, or 576
-//            threads so that every phase of a 16x16 or 32x8 tile is a single
-//            pass (shorter critical path when the grid is small);
+//   block = one tile of TX x TY cells of one member (the tile shapes and
+//            thread counts are listed with TileId);
 //   phase A  primitives of the tile plus a 2-cell halo into LDS (x periodic,
 //            y ghost rows from the wall boundary condition);
 //   phase B  MC slopes and the MUSCL-Hancock predictor of the tile plus a
@@ -13,8 +12,10 @@
 //   phase C  HLLC fluxes of every face of the tile, each computed once;
 //   phase D  conservative update with the gravity source, store, optional
 //            snapshot of U^n, and the largest signal speed of U^{n+1};
-//   epilogue per-block maxima -> the last block to finish reduces them into
-//            the member's next CFL step (no extra launch, no host sync).
+//   epilogue the block's largest signal speed goes by an integer atomic max
+//            (on the bit pattern) into one of the member's slots, which the
+//            next launch reduces into its CFL step (no extra launch, no host
+//            sync).
 // Adjoint of one step (frozen dt): kernel A recomputes phases A-C, runs the
 // HLLC / wall-flux adjoints on every face of the tile and the predictor
 // adjoint of every tile cell, and forms each cell's direct part of lambda^n

@@ -954,6 +954,22 @@ def test_autotune_pick_reproduces_the_default_gradient_bitwise(cfg, T):
     print("autotune", cfg.nx, cfg.ny, "default", before, "picked", picked, "fold", r.fold)
 
 
+def test_default_tiles_by_grid_size():
+    # the measured defaults: tiny grids fold on single-pass 8x8 tiles; grids
+    # whose 32x8 tiles fill at most one round of three blocks per CU take
+    # 32x16 / 32x8; larger ones 16x15 for both kernels
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    one_round = 3 * cus * 256
+    for cfg, want, fold in ((RTConfig(nx=64, ny=128), "8x8w/8x8w", True),
+                            (RTConfig(nx=256, ny=512), "32x16/32x8", False),
+                            (RTConfig(nx=512, ny=1024, batch=8), "16x15/16x15", False),
+                            (RTConfig(nx=1024, ny=2048), "16x15/16x15", False)):
+        r = rt().Context(cfg, max_steps=64)
+        cells = cfg.nx * cfg.ny * cfg.batch
+        assert (cells <= one_round) == (want == "32x16/32x8") or cells < 2**16, cfg
+        assert r.tile == want and r.fold == fold, (cfg, r.tile, r.fold)
+
+
 def test_power_spectrum_2d_matches_oracle():
     # App. B's 2-D power spectrum on the device: plain fields and the v
     # component of velocity fields, ragged and bench-sized grids

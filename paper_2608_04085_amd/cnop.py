@@ -182,6 +182,8 @@ class GroupedSPG:
 
         def run(k):
             try:
+                # a new thread starts on device 0: take the group's device first
+                torch.cuda.set_device(self.searches[k].rt.device)
                 with torch.cuda.stream(self.streams[k]):
                     for it in range(n):
                         self.searches[k].step()

@@ -339,6 +339,13 @@ def main():
     per_grad_s = per_iter * args.steps / max(grads_timed, 1)
     dom["fwd_share_of_gradient"] = round(t_fwd * 1e-6 / per_grad_s, 3)
     dom["adj_share_of_gradient"] = round(t_adj * 1e-6 / per_grad_s, 3)
+    # time per phase of one gradient of all 8 restarts, from the kernels'
+    # event times (the executor copies no states); the searches overlap the
+    # phases on the GPU, so they add up to more than the measured gradient
+    phases = {"forward_march_ms": nt * kt["step_march_us"] * 1e-3,
+              "recompute_ms": (fw_total - nt) * kt["step_given_us"] * 1e-3,
+              "adjoint_ms": t_adj * 1e-3, "state_copies_ms": 0.0,
+              "measured_gradient_ms": per_grad_s * 1e3}
 
     out = {
         "metric": METRIC,
@@ -370,6 +377,7 @@ def main():
         "roofline": dom,
         "roofline_other": other,
         "kernel_times_us": {k: round(v, 3) for k, v in kt.items()},
+        "phases_per_gradient": {k: round(v, 1) for k, v in phases.items()},
     }
     if not args.no_extras:
         from paper_2608_04085_amd import workloads
